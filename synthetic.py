@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs for the B-spline cloth hot path: sheets, states, pins and drives.
+
+This module holds none of the method's arithmetic (no basis, quadrature, energy or solver
+code); it only builds inputs. Both the oracle-based tests and the HIP path take their inputs
+from here, so that the two sides see identical data.
+
+Every sheet is a flat rectangle in the plane z = 0 on open uniform quadratic knots
+(0,0,0,1,...,N,N,N). Its rest control points sit at the Greville abscissae of the knots
+(x_i = L (xi_{i+1} + xi_{i+2}) / (2N), 0-based knots), the placement at which the B-spline
+rest map is exactly affine, matching the control-point drawing of the paper's quadrature
+figure. Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
+
+These sheets stand in for the paper's square-sheet benchmarks (upright hanging, drape,
+compression); no benchmark assets are used.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def open_uniform_knots(n: int, spacing: int = 1) -> np.ndarray:
+    """Open uniform quadratic knot vector for n control points (n + 3 entries)."""
+    N = n - 2
+    return spacing * np.concatenate([[0.0, 0.0], np.arange(N + 1, dtype=np.float64), [N, N]])
+
+
+def greville(knots: np.ndarray, n: int) -> np.ndarray:
+    """Greville abscissae (xi_{i+1} + xi_{i+2}) / 2, 0-based knots, i = 0..n-1."""
+    return 0.5 * (knots[1:n + 1] + knots[2:n + 2])
+
+
+@dataclass
+class Material:
+    """membrane: 0 = StVK (young [Pa], poisson, thickness [m]); 1 = FBW (mu_* [N/m]).
+    mu_bend [N m] is the bending stiffness; rho_area [kg/m^2] the rest mass per area."""
+    membrane: int = 0
+    young: float = 1e4
+    poisson: float = 0.3
+    thickness: float = 1e-3
+    mu_st1: float = 0.0
+    mu_st2: float = 0.0
+    mu_sh: float = 0.0
+    mu_bend: float = 0.0
+    rho_area: float = 0.2
+
+
+def plate_bending_stiffness(young: float, poisson: float, thickness: float) -> float:
+    """Kirchhoff plate stiffness D = E t^3 / (12 (1 - nu^2)), used as the bending stiffness."""
+    return young * thickness ** 3 / (12.0 * (1.0 - poisson ** 2))
+
+
+def stvk_material(young=1e4, poisson=0.3, thickness=1e-3, rho_area=0.2, mu_bend=None) -> Material:
+    if mu_bend is None:
+        mu_bend = plate_bending_stiffness(young, poisson, thickness)
+    return Material(0, young, poisson, thickness, 0.0, 0.0, 0.0, mu_bend, rho_area)
+
+
+@dataclass
+class Scene:
+    """Everything one implicit-Euler step needs. Positions are AoS (n_cp, 3) float64 with
+    control point (i, j) at row j * n_u + i; ``rest`` is (n_cp, 2)."""
+    name: str
+    n_u: int
+    n_v: int
+    knots_u: np.ndarray
+    knots_v: np.ndarray
+    rest: np.ndarray
+    material: Material
+    x0: np.ndarray
+    v0: np.ndarray
+    pins: np.ndarray                     # int64 CP indices
+    pin_rest: np.ndarray                 # (n_pins, 3) pin positions at t = 0
+    dt: float = 0.01
+    gravity: np.ndarray = field(default_factory=lambda: np.array([0.0, 0.0, -9.81]))
+    drive_cp: int = -1                   # CP whose z is driven sinusoidally (-1: none)
+    drive_amp: float = 0.0
+    drive_hz: float = 0.0
+
+    @property
+    def n_cp(self) -> int:
+        return self.n_u * self.n_v
+
+    @property
+    def n_elem(self) -> int:
+        return (self.n_u - 2) * (self.n_v - 2)
+
+    def pin_targets(self, step: int) -> np.ndarray:
+        """Pin positions at the end of step ``step`` (0-based): the driven CP moves in z as
+        amp * sin(2 pi f t) with t = (step + 1) dt; every other pin holds its start position."""
+        tgt = self.pin_rest.copy()
+        if self.drive_cp >= 0:
+            t = (step + 1) * self.dt
+            k = int(np.nonzero(self.pins == self.drive_cp)[0][0])
+            tgt[k, 2] += self.drive_amp * np.sin(2.0 * np.pi * self.drive_hz * t)
+        return tgt
+
+
+def flat_sheet(n_u: int, n_v: int | None = None, L_u: float = 1.0, L_v: float | None = None,
+               spacing: int = 1, shear: float = 0.0):
+    """Knots and Greville rest CPs of a flat L_u x L_v sheet; ``shear`` skews it affinely."""
+    n_v = n_u if n_v is None else n_v
+    L_v = L_u if L_v is None else L_v
+    ku, kv = open_uniform_knots(n_u, spacing), open_uniform_knots(n_v, spacing)
+    gu = greville(ku, n_u) / ku[-1] * L_u
+    gv = greville(kv, n_v) / kv[-1] * L_v
+    X1, X2 = np.meshgrid(gu, gv)                     # [j, i]
+    rest = np.stack([X1.ravel() + shear * X2.ravel(), X2.ravel()], axis=1)
+    return ku, kv, rest
+
+
+def embed(rest: np.ndarray) -> np.ndarray:
+    return np.concatenate([rest, np.zeros((rest.shape[0], 1))], axis=1)
+
+
+def cp_index(n_u: int, i: int, j: int) -> int:
+    return j * n_u + i
+
+
+def hanging_sheet(n: int = 20, seed: int = 1, material: Material | None = None, noise: float = 1e-3) -> Scene:
+    """Upright hanging sheet: side 1 m, flat rest, x0 = rest + U(+-noise) in z, the two top
+    corners pinned, gravity along -y (in the sheet's plane), dt = 0.01 s."""
+    g = rng(seed)
+    ku, kv, rest = flat_sheet(n)
+    x0 = embed(rest)
+    x0[:, 2] += g.uniform(-noise, noise, size=x0.shape[0])
+    pins = np.array([cp_index(n, 0, n - 1), cp_index(n, n - 1, n - 1)], dtype=np.int64)
+    mat = material or stvk_material()
+    return Scene("hanging", n, n, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(),
+                 0.01, np.array([0.0, -9.81, 0.0]))
+
+
+def compressed_sheet(n: int = 100, seed: int = 2, material: Material | None = None,
+                     compression: float = 0.1, noise: float = 2e-3) -> Scene:
+    """Drape with in-plane compression: X1 -> (1 - compression) X1, z-noise U(+-noise), the
+    first and last CP columns held at their compressed positions, gravity along -z."""
+    g = rng(seed)
+    ku, kv, rest = flat_sheet(n)
+    x0 = embed(rest)
+    x0[:, 0] *= (1.0 - compression)
+    x0[:, 2] += g.uniform(-noise, noise, size=x0.shape[0])
+    j = np.arange(n)
+    pins = np.concatenate([j * n + 0, j * n + (n - 1)]).astype(np.int64)
+    mat = material or stvk_material()
+    return Scene("compressed", n, n, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(),
+                 0.01, np.array([0.0, 0.0, -9.81]))
+
+
+MATERIAL_GRID = [(E, t) for E in (1e3, 1e4, 1e5) for t in (0.5e-3, 1e-3, 2e-3)]
+
+
+def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: float = 1e-3) -> Scene:
+    """Large sheet with a material cell from the (E, t) grid, K ~ U{4..16} random held CPs plus
+    the corner CP (0,0) driven in z with amplitude 5 cm at 1 Hz; gravity along -z."""
+    g = rng(seed)
+    if cell is None:
+        cell = (seed - 300) % len(MATERIAL_GRID)
+    E, t = MATERIAL_GRID[cell]
+    ku, kv, rest = flat_sheet(n)
+    x0 = embed(rest)
+    x0[:, 2] += g.uniform(-noise, noise, size=x0.shape[0])
+    K = int(g.integers(4, 17))
+    others = g.choice(np.arange(1, n * n), size=K, replace=False)
+    pins = np.concatenate([[0], np.sort(others)]).astype(np.int64)
+    mat = stvk_material(young=E, thickness=t)
+    return Scene("driven", n, n, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(),
+                 0.01, np.array([0.0, 0.0, -9.81]), drive_cp=0, drive_amp=0.05, drive_hz=1.0)
+
+
+def smooth_field(n_u: int, n_v: int, seed: int, amp: float = 0.05, modes: int = 3) -> np.ndarray:
+    """A smooth random displacement field on the CP grid (sum of low sine modes), (n_cp, 3)."""
+    g = rng(seed)
+    s = np.linspace(0.0, 1.0, n_u)[None, :]
+    t = np.linspace(0.0, 1.0, n_v)[:, None]
+    out = np.zeros((n_v, n_u, 3))
+    for c in range(3):
+        for _ in range(modes):
+            a, b = g.integers(1, 4, size=2)
+            ph = g.uniform(0, 2 * np.pi, size=2)
+            out[:, :, c] += amp * g.uniform(-1, 1) * np.sin(a * np.pi * s + ph[0]) * np.sin(b * np.pi * t + ph[1])
+    return out.reshape(-1, 3)

@@ -1,0 +1,94 @@
+"""Pins for the oracle's implicit-Euler / projected-Newton step (CPU only).
+
+Pinned against: conservation of linear momentum without pins or gravity (the contact-free
+form of the paper's two-plate test, Sec. 6.2), the Kirchhoff simply-supported plate closed
+form of the paper's bending benchmark (Sec. 6.2, "Convergence under Refinement (Bending)"),
+and one-iteration exactness on a quadratic energy checked by an independent dense solve."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+
+
+def sheet_from_scene(sc):
+    m = sc.material
+    return oracle.Sheet(sc.n_u, sc.n_v, sc.knots_u, sc.knots_v, sc.rest, m.membrane, m.young, m.poisson,
+                        m.thickness, m.mu_st1, m.mu_st2, m.mu_sh, m.mu_bend, m.rho_area)
+
+
+def test_momentum_is_conserved_without_pins_or_gravity():
+    sc = syn.hanging_sheet(10, seed=3)
+    sh = sheet_from_scene(sc)
+    rng = np.random.default_rng(4)
+    x = sc.x0 + syn.smooth_field(10, 10, 6, amp=0.02)
+    v = 0.3 * rng.standard_normal(x.shape)
+    M = oracle.lumped_mass(sh)
+    p0 = (M[:, None] * v).sum(axis=0)
+    res = oracle.newton_step(sh, x, v, 0.01, np.zeros(3), rtol=1e-8)
+    p1 = (M[:, None] * res.v).sum(axis=0)
+    # internal forces sum to zero, so sum_a M_a (x_a - xhat_a) = dt^2 sum_a g_a at the end
+    bound = 0.01 * np.sqrt(x.size) * res.g_norm + 1e-14 * np.abs(M[:, None] * v).sum()
+    assert np.abs(p1 - p0).max() <= bound
+    assert res.g_norm <= 1e-8 * res.g0_norm
+
+
+def test_hanging_step_converges_and_is_a_stationary_point():
+    sc = syn.hanging_sheet(12, seed=1)
+    sh = sheet_from_scene(sc)
+    res = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), rtol=1e-9)
+    assert res.g_norm <= 1e-9 * res.g0_norm
+    assert np.allclose(res.x[sc.pins], sc.pin_targets(0))
+    mask = np.zeros(sh.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    E, g, _ = oracle.assemble(sh, res.x, sc.x0 + sc.dt * sc.v0, sc.dt, sc.gravity, mask, want_hessian=False)
+    assert np.linalg.norm(g) <= 1e-9 * res.g0_norm
+    # the sheet falls: free CPs move along gravity (-y)
+    assert res.v[~mask, 1].mean() < 0
+
+
+def test_quadratic_energy_needs_one_newton_iteration():
+    """Bending plus inertia only (zero membrane stiffness) is quadratic: one Newton iteration
+    lands on the minimiser, which equals a dense solve of the same linear system."""
+    n = 8
+    sc = syn.hanging_sheet(n, seed=2, material=syn.stvk_material(young=0.0, mu_bend=0.05))
+    sh = sheet_from_scene(sc)
+    x0 = sc.x0 + syn.smooth_field(n, n, 2, amp=0.05)
+    res = oracle.newton_step(sh, x0, sc.v0, sc.dt, sc.gravity, sc.pins, x0[sc.pins], fixed_iters=1)
+    mask = np.zeros(sh.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    E, g, H = oracle.assemble(sh, res.x, x0, sc.dt, sc.gravity, mask, want_hessian=True)
+    assert np.linalg.norm(g) < 1e-10 * res.g0_norm
+    E0, g0, H0 = oracle.assemble(sh, x0, x0, sc.dt, sc.gravity, mask)
+    dense = oracle.stencil_to_csr(sh, H0).toarray()
+    p = np.linalg.solve(dense, -g0.reshape(-1))
+    assert np.allclose(res.x.reshape(-1), x0.reshape(-1) + p, atol=1e-12 * np.abs(x0).max())
+
+
+def plate_deflection(N):
+    """Square plate, bending only, boundary CPs fixed (simply supported: the edge is held,
+    slopes are free), uniform load q = 9.81 per unit area; static solve (no inertia)."""
+    n = N + 2
+    E, nu, h, q = 2e6, 0.03, 0.01, 9.81
+    D = syn.plate_bending_stiffness(E, nu, h)
+    ku, kv, rest = syn.flat_sheet(n)
+    # rho_area = 1 turns "gravity" into a load of q per unit area through the lumped mass
+    sh = oracle.Sheet(n, n, ku, kv, rest, 0, 0.0, nu, h, 0, 0, 0, D, 1.0)
+    x = syn.embed(rest)
+    pins = np.array([a for a in range(n * n) if a % n in (0, n - 1) or a // n in (0, n - 1)])
+    mask = np.zeros(n * n, dtype=bool)
+    mask[pins] = True
+    _, g, H = oracle.assemble(sh, x, None, None, np.array([0.0, 0.0, -q]), mask)
+    A = oracle.stencil_to_csr(sh, H)
+    import scipy.sparse.linalg as spla
+    p = spla.spsolve(A.tocsc(), -g.reshape(-1)).reshape(-1, 3)
+    xs = x + p
+    return -oracle.surface_point(sh, xs, N / 2, N / 2)[2]
+
+
+def test_plate_benchmark_converges_to_kirchhoff_solution():
+    """Max deflection 0.048744 q a^4 (1 - nu^2) / (E h^3) (Sec. 6.2; 0.23887 m here)."""
+    exact = 0.048744 * 9.81 * (1 - 0.03 ** 2) / (2e6 * 0.01 ** 3)
+    errs = [abs(plate_deflection(N) - exact) / exact for N in (8, 16, 32)]
+    assert errs[2] < 0.01
+    assert errs[0] > errs[1] > errs[2]
