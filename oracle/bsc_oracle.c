@@ -491,13 +491,13 @@ static int rule_sizes(const or_sheet *S, int *Nu, int *Nv)
     return (*Nu > 0 && *Nv > 0) ? OR_OK : OR_EINVAL;
 }
 
-/* Parametric-to-physical weight: span units -> knot units -> rest area. */
+/* Parametric-to-physical weight. The rule weights are in span units (a span has unit size)
+ * and J = dX/d(u,v) is taken with respect to the same span-unit coordinates, so
+ * int f dX = sum wbar f |det J| (Sec. 3.2: integrals over the rest domain). */
 static double phys_weight(const or_sheet *S, double wbar, double detJ)
 {
-    double hu, hv;
-    or_check_knots(S->knots_u, S->n_u, &hu);
-    or_check_knots(S->knots_v, S->n_v, &hv);
-    return wbar * hu * hv * fabs(detJ);
+    (void)S;
+    return wbar * fabs(detJ);
 }
 
 /* One membrane quadrature point: adds w*Psi, w*dPsi/dC and w*d2Psi/dC2 (projected if asked)

@@ -199,9 +199,11 @@ def test_membrane_interior_stencil_is_2x3():
 
 # ---- lumped mass --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n_u,n_v,Lu,Lv,shear", [(8, 8, 1.0, 1.0, 0.0), (10, 7, 2.0, 0.5, 0.0), (6, 9, 1.0, 1.5, 0.3)])
-def test_lumped_mass_closed_form(n_u, n_v, Lu, Lv, shear):
-    ku, kv, rest = syn.flat_sheet(n_u, n_v, Lu, Lv, shear=shear)
+@pytest.mark.parametrize("n_u,n_v,Lu,Lv,shear,spacing", [(8, 8, 1.0, 1.0, 0.0, 1), (10, 7, 2.0, 0.5, 0.0, 2),
+                                                          (6, 9, 1.0, 1.5, 0.3, 3)])
+def test_lumped_mass_closed_form(n_u, n_v, Lu, Lv, shear, spacing):
+    """Knot spacing only reparametrises the sheet: mass and area must not depend on it."""
+    ku, kv, rest = syn.flat_sheet(n_u, n_v, Lu, Lv, shear=shear, spacing=spacing)
     rho = 0.37
     sh = oracle.Sheet(n_u, n_v, ku, kv, rest, rho_area=rho)
     M = oracle.lumped_mass(sh).reshape(n_v, n_u)

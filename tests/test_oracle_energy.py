@@ -97,11 +97,11 @@ def test_projection_matches_lapack():
 
 # ---- whole-sheet invariants ---------------------------------------------------------------
 
-@pytest.mark.parametrize("shear", [0.0, 0.35])
-def test_affine_deformation_is_exact(shear):
+@pytest.mark.parametrize("shear,spacing", [(0.0, 1), (0.35, 1), (0.2, 2)])
+def test_affine_deformation_is_exact(shear, spacing):
     """phi = A X + b is reproduced exactly (linear precision), so F = A at every point, the
-    membrane energy is area * Psi(A) and the bending energy vanishes."""
-    sh = make_sheet(9, 7, 1.0, 0.8, shear=shear)
+    membrane energy is area * Psi(A) and the bending energy vanishes, for any knot spacing."""
+    sh = make_sheet(9, 7, 1.0, 0.8, shear=shear, spacing=spacing)
     A = np.array([[1.1, 0.2], [-0.1, 0.95], [0.3, -0.2]])
     x = sh.rest @ A.T + np.array([0.5, -1.0, 2.0])
     E, g, _ = oracle.assemble(sh, x, want_hessian=False)
