@@ -1,0 +1,224 @@
+/*
+ * bsc.h -- C ABI of the MI355X (gfx950) hot path of quadratic B-spline cloth finite elements
+ * (arXiv 2506.18867, "Efficient B-Spline Finite Elements for Cloth Simulation").
+ *
+ * The library evaluates the membrane and bending energy, gradient and Hessian of a quadratic
+ * B-spline sheet at the paper's separately reduced quadrature points (Sec. 4.1 and 4.2), projects
+ * every membrane point's density Hessian onto the PSD cone (Sec. 5.1), assembles the global
+ * 3x3-block Hessian on its fixed control-point pattern by a per-block gather (Sec. 5.2), and runs
+ * the projected-Newton minimisation of the implicit-Euler incremental potential (Sec. 3.2,
+ * Eq. "incremental_potential"; Sec. 5.1) with a hand-written block-Jacobi PCG.
+ *
+ * General rules
+ *   - Every call returns a bsc_status (0 = OK, < 0 = error) and never throws or aborts.
+ *     bsc_last_error() gives a message for the last failing call on a context.
+ *   - Pointers named d_* are device pointers (HIP global memory of the context's device);
+ *     everything else is host memory. The caller owns every buffer it passes, including the
+ *     workspace; the context owns only host-side tables. Nothing is freed across the boundary.
+ *   - Calls are asynchronous on the context's HIP stream unless stated otherwise; the caller
+ *     synchronises before reading results on the host.
+ *   - One context per host thread. Calls that overlap on one context race.
+ *   - Layouts. Control point (CP) (i,j), 0 <= i < n_u, 0 <= j < n_v, has index a = j*n_u + i.
+ *     Vectors over CPs are structure-of-arrays: v[c*n_cp + a] for component c in {0,1,2}
+ *     (a (3, n_v, n_u) contiguous tensor). An element is a knot span (k,l), index
+ *     e = l*(n_u-2) + k; its CPs are (k+a', l+b'), a',b' in {0,1,2}, local CP 3*b'+a',
+ *     local DOF r = 3*(3*b'+a') + c.
+ *   - Precision: BSC_FP64 computes everything in double. BSC_FP32_MIXED computes element
+ *     quantities, assembly and SpMV in float (float outputs), keeps the PSD eigen-problems in
+ *     double, and the Newton step keeps the gradient, energy differences, PCG residual and
+ *     dot products in double.
+ */
+#ifndef BSC_H
+#define BSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsc_ctx bsc_ctx;
+
+typedef enum {
+    BSC_OK = 0,
+    BSC_E_INVAL = -1,           /* bad argument, size or unsupported input                       */
+    BSC_E_KNOTS = -2,           /* knot vector is not open, uniform, integer, starting at 0        */
+    BSC_E_NOMEM = -3,           /* host allocation failed or workspace too small                   */
+    BSC_E_HIP = -4,             /* a HIP runtime call failed                                       */
+    BSC_E_NOT_CONVERGED = -5,   /* Newton hit max_newton before the stopping test                  */
+    BSC_E_LINESEARCH = -6,      /* no energy decrease after 20 step halvings                       */
+    BSC_E_NONFINITE = -7,       /* NaN or Inf in the state, gradient or energy                     */
+    BSC_E_PCG_BREAKDOWN = -8,   /* p^T H p <= 0 inside PCG                                         */
+    BSC_E_STATE = -9            /* call order violated (e.g. no workspace bound)                   */
+} bsc_status;
+
+enum { BSC_MEMBRANE_STVK = 0, BSC_MEMBRANE_FBW = 1 };
+enum { BSC_FP64 = 0, BSC_FP32_MIXED = 1 };
+enum { BSC_STOP_GRAD = 0, BSC_STOP_STEP = 1 };
+
+/* Material (Sec. 4). StVK: membrane energy per rest area t [mu |E_G|^2 + lam/2 tr(E_G)^2],
+ * E_G = (F^T F - I)/2, mu = E/(2(1+nu)), lam = E nu/(1-nu^2). FBW (Eq. "FBW stretching and
+ * shearing energy"): mu_st1, mu_st2, mu_sh per rest area. Bending (Eq. "general bending
+ * energy"): mu_bend/2 |Laplacian(phi)|^2 per rest area. rho_area: rest mass per area R^0. */
+typedef struct {
+    int32_t membrane;
+    double young, poisson, thickness;
+    double mu_st1, mu_st2, mu_sh;
+    double mu_bend;
+    double rho_area;
+} bsc_material;
+
+/* Options of one implicit-Euler step (Sec. 3.2, Sec. 5.1).
+ *   stop_mode BSC_STOP_GRAD: stop when |g_free|_2 <= rtol |g0_free|_2 (g0 at the first iterate);
+ *   stop_mode BSC_STOP_STEP: stop when |p|_inf / dt <= atol (the paper's rule).
+ *   fixed_newton_iters > 0 runs exactly that many iterations instead (for comparisons).
+ *   pcg_rtol: PCG stops when |r|_2 <= pcg_rtol |g|_2. warm_start: 1 uses the loaded network as
+ *   the PCG initial guess (falls back to zero when it does not reduce the residual). */
+typedef struct {
+    double dt;
+    double gravity[3];
+    int32_t precision;
+    int32_t stop_mode;
+    double rtol, atol;
+    int32_t max_newton, max_pcg;
+    double pcg_rtol;
+    int32_t warm_start;
+    int32_t fixed_newton_iters;
+} bsc_step_opts;
+
+typedef struct {
+    int32_t newton_iters, pcg_iters_total, ls_halvings, warm_start_used, warm_start_fallbacks;
+    double g0_norm, g_norm, energy;
+    double ms_assemble, ms_pcg, ms_linesearch, ms_warmstart, ms_total;
+} bsc_step_stats;
+
+/* Sizes of a context: CPs, elements, membrane quadrature points, bending evaluations (four per
+ * interior knot, one per boundary span), stored Hessian entries per CP (BSC_HESS_ENTRIES). */
+#define BSC_HESS_ENTRIES 114
+
+/* Creates a context for an n_u x n_v control grid (Sec. 3.1.2, Eq. "general B-spline patch").
+ *   knots_u / knots_v: host, n_u+3 / n_v+3 doubles; must be open uniform quadratic knot vectors
+ *     starting at 0 with integer knots (Sec. 3.1.2); n_u, n_v >= 5 (at least 3 spans).
+ *   rest_xy: host, 2*n_u*n_v doubles, AoS (X1, X2) per CP (Sec. 3.2). The device path supports
+ *     rest maps that are affine in (u,v) (control points at the Greville abscissae of an affine
+ *     image of the parameter rectangle, det > 0); others return BSC_E_INVAL.
+ *   mat: host; E, thickness, rho_area > 0, nu in (-1, 0.5) for StVK; mu_* >= 0 for FBW.
+ *   hip_stream: hipStream_t on which all work is enqueued (NULL = default stream).
+ * On success *out owns the host tables; free it with bsc_destroy. Host-only, synchronous. */
+bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *knots_u,
+                      const double *knots_v, const double *rest_xy, const bsc_material *mat,
+                      void *hip_stream);
+
+bsc_status bsc_sizes(const bsc_ctx *ctx, int32_t *n_cp, int32_t *n_elem, int32_t *n_membrane_pts,
+                     int32_t *n_bending_evals);
+
+/* Bytes of device workspace the context needs (tables, per-point buffers, solver vectors,
+ * the Hessian and the warm-start network). */
+bsc_status bsc_workspace_size(const bsc_ctx *ctx, size_t *bytes);
+
+/* Binds caller-owned device memory (>= bsc_workspace_size bytes, 256-byte aligned) and uploads
+ * the precomputed tables into it. Synchronises the context's stream before returning. */
+bsc_status bsc_bind_workspace(bsc_ctx *ctx, void *d_ws, size_t bytes);
+
+/* Sets the pinned CPs (Dirichlet conditions, Sec. 5.1: eliminated DOFs). cp_idx: host list of
+ * n distinct CP indices (n = 0 clears). Needs a bound workspace. Synchronous. */
+bsc_status bsc_set_pins(bsc_ctx *ctx, const int32_t *cp_idx, int32_t n);
+
+/* Per-element elastic (membrane + bending) energy, gradient and 27x27 Hessian (Sec. 4.1, 4.2,
+ * Sec. 5.2 step 1) with every membrane point's density Hessian projected to PSD.
+ *   d_x: 3*n_cp doubles (SoA), world CP positions.
+ *   d_energy: 1 double, total elastic energy (required).
+ *   d_elem_energy: n_elem values or NULL; d_elem_grad: 27*n_elem values or NULL, layout
+ *     [r][e]; d_elem_hess: 378*n_elem values or NULL, upper triangle (r <= c) of the
+ *     symmetric 27x27 matrix in row-major order, layout [entry][e].
+ *   Output values are double for BSC_FP64 and float for BSC_FP32_MIXED (d_energy is always
+ *   double). No pins, inertia or gravity are applied. */
+bsc_status bsc_eval_egh(bsc_ctx *ctx, int32_t precision, const double *d_x, double *d_energy,
+                        void *d_elem_energy, void *d_elem_grad, void *d_elem_hess);
+
+/* Incremental potential of Eq. "incremental_potential" with lumped mass (Eq. "lumped mass
+ * matrix"), gravity and eliminated pinned DOFs, assembled by per-block gather (Sec. 5.2):
+ *   E = sum_a M_a |x_a - xhat_a|^2 / (2 dt^2) - sum_a M_a grav.x_a + E_elastic(x).
+ *   d_xhat: 3*n_cp doubles, or NULL to drop the inertia term (dt is then ignored).
+ *   gravity: host, 3 doubles, or NULL for none.
+ *   d_energy: 1 double. d_grad: 3*n_cp values (SoA), zero on pinned CPs.
+ *   d_hess: BSC_HESS_ENTRIES*n_cp values, or NULL: the symmetric Hessian in upper-stencil
+ *     form, layout [entry][a]. Entries 0..5 are the diagonal block (xx,xy,xz,yy,yz,zz);
+ *     entry 6 + 9*(s-1) + 3*r + c is row r, column c of the block coupling CP a to CP a+d_s
+ *     for the upper offsets d_1..d_12 = (1,0),(2,0),(-2,1),(-1,1),(0,1),(1,1),(2,1),
+ *     (-2,2),(-1,2),(0,2),(1,2),(2,2) in (di,dj). Blocks reaching outside the grid are 0;
+ *     pinned CPs have an identity diagonal block and zero coupling blocks.
+ *   Values are double for BSC_FP64 and float for BSC_FP32_MIXED. */
+bsc_status bsc_assemble(bsc_ctx *ctx, int32_t precision, const double *d_x, const double *d_xhat,
+                        double dt, const double *gravity, double *d_energy, void *d_grad,
+                        void *d_hess);
+
+/* y = H x for a Hessian in upper-stencil form (as written by bsc_assemble with the same
+ * precision). d_in, d_out: 3*n_cp doubles, SoA; must not alias. */
+bsc_status bsc_spmv(bsc_ctx *ctx, int32_t precision, const void *d_hess, const double *d_in,
+                    double *d_out);
+
+/* Standard 3x3-block CSR (BSR) pattern of the Hessian: every CP pair with |di| <= 2 and
+ * |dj| <= 2 (the 5x5 control-point neighbourhood). row_ptr: host, n_cp+1 ints; col_idx: host,
+ * nnzb ints (pass NULL to query *nnzb). Columns ascending within a row. Host-only. */
+bsc_status bsc_bsr_pattern(const bsc_ctx *ctx, int32_t *row_ptr, int32_t *col_idx, int32_t *nnzb);
+
+/* Expands an upper-stencil Hessian into BSR values on the device: d_bsr_vals holds 9*nnzb
+ * values (row-major 3x3 blocks in the order of bsc_bsr_pattern), same precision as d_hess. */
+bsc_status bsc_export_bsr(bsc_ctx *ctx, int32_t precision, const void *d_hess, void *d_bsr_vals);
+
+/* One implicit-Euler step by projected Newton (Sec. 5.1): x0 = x^n with pinned CPs at their
+ * targets, xhat = x^n + dt v^n; per iteration assemble, stop test, block-Jacobi PCG for the
+ * direction on the free DOFs, backtracking from alpha = 1 halving until the energy difference
+ * (computed in double) is <= 0, update; finally v = (x - x^n)/dt.
+ *   d_x: in x^n, out x^{n+1} (3*n_cp doubles); d_v: in v^n, out v^{n+1}.
+ *   d_pin_targets: 3*n_pins doubles, SoA [c][pin] in the order given to bsc_set_pins (may be
+ *     NULL when there are no pins). stats: host, may be NULL. Synchronous.
+ * Returns BSC_E_NOT_CONVERGED, BSC_E_LINESEARCH, BSC_E_NONFINITE or BSC_E_PCG_BREAKDOWN on
+ * failure; x and v then hold the last iterate. */
+bsc_status bsc_newton_step(bsc_ctx *ctx, const bsc_step_opts *opts, double *d_x, double *d_v,
+                           const double *d_pin_targets, bsc_step_stats *stats);
+
+/* Learned PCG warm start (a method extension; not in the paper). A bias-free 6-layer 3x3
+ * convolutional net over the CP grid (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 channels, zero
+ * padding, LeakyReLU(0.1) between layers) maps the normalised gradient g/rms(g) to a
+ * direction p_hat; the step uses alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat as the
+ * PCG initial guess when it lowers the residual, else zero.
+ * Weights: BSC_NET_PARAMS floats, layer by layer, each [c_out][c_in][3][3]. */
+#define BSC_NET_PARAMS 38592
+bsc_status bsc_warmstart_load(bsc_ctx *ctx, const float *d_weights, int32_t n_params);
+
+/* Network forward for a batch of B grids of the context's size (training and inference).
+ *   d_in: B*3*n_cp floats [b][c][a]; d_out: B*3*n_cp floats; d_acts: B*5*32*n_cp floats,
+ *   the outputs of layers 1..5 after LeakyReLU, layout [layer][b][channel][a], kept for the
+ *   backward pass (NULL for inference only). d_weights: BSC_NET_PARAMS floats. */
+bsc_status bsc_net_forward(bsc_ctx *ctx, int32_t batch, const float *d_weights, const float *d_in,
+                           float *d_out, float *d_acts);
+
+/* Network backward: given d_dout (dLoss/dOut, B*3*n_cp floats) and the d_acts saved by the
+ * forward, writes dLoss/dWeights (BSC_NET_PARAMS floats, overwritten, deterministic) and, if
+ * d_din is not NULL, dLoss/dIn. d_scratch: bsc_net_scratch_size() bytes. */
+bsc_status bsc_net_backward(bsc_ctx *ctx, int32_t batch, const float *d_weights, const float *d_in,
+                            const float *d_acts, const float *d_dout, float *d_dweights, float *d_din,
+                            void *d_scratch);
+bsc_status bsc_net_scratch_size(const bsc_ctx *ctx, int32_t batch, size_t *bytes);
+
+/* Adam update of n parameters in place (step counter t >= 1). */
+bsc_status bsc_adam_step(bsc_ctx *ctx, int32_t n, float *d_param, const float *d_grad, float *d_m,
+                         float *d_v, float lr, float beta1, float beta2, float eps, int32_t t);
+
+/* Training loss of the warm-start net for a batch: for each sample b,
+ * L_b = 1 - (p_hat.p)^2 / (|p_hat|^2 |p|^2) (the relative error of the best scalar multiple of
+ * p_hat against the solved step p); writes the mean loss (1 float) and dL/dp_hat. */
+bsc_status bsc_net_loss(bsc_ctx *ctx, int32_t batch, const float *d_pred, const float *d_target,
+                        float *d_loss, float *d_dpred);
+
+const char *bsc_status_string(bsc_status s);
+const char *bsc_last_error(const bsc_ctx *ctx);
+void bsc_destroy(bsc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSC_H */

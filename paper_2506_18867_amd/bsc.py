@@ -1,0 +1,348 @@
+"""Thin ctypes binding of ``include/bsc.h`` (libbsc.so, HIP for gfx950).
+
+Argument marshalling only: every step of the computation runs in the library's kernels.
+PyTorch provides device memory (CUDA/HIP tensors passed by ``data_ptr()``) and the stream.
+Importing works without a GPU; any call that needs the library raises ``BscError`` when
+``libbsc.so`` is missing instead of falling back to anything else.
+
+Tensors: CP vectors are float64 ``(3, n_cp)`` (structure of arrays; CP (i, j) at column
+``j * n_u + i``); the Hessian is ``(114, n_cp)`` in the upper-stencil layout of
+``bsc_assemble`` (float64 for ``BSC_FP64``, float32 for ``BSC_FP32_MIXED``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsc.so")
+
+BSC_OK = 0
+BSC_FP64 = 0
+BSC_FP32_MIXED = 1
+BSC_MEMBRANE_STVK = 0
+BSC_MEMBRANE_FBW = 1
+BSC_STOP_GRAD = 0
+BSC_STOP_STEP = 1
+BSC_HESS_ENTRIES = 114
+BSC_NET_PARAMS = 38592
+STATUS = {0: "BSC_OK", -1: "BSC_E_INVAL", -2: "BSC_E_KNOTS", -3: "BSC_E_NOMEM", -4: "BSC_E_HIP",
+          -5: "BSC_E_NOT_CONVERGED", -6: "BSC_E_LINESEARCH", -7: "BSC_E_NONFINITE",
+          -8: "BSC_E_PCG_BREAKDOWN", -9: "BSC_E_STATE"}
+# upper-stencil slot offsets (di, dj); slot 0 is the diagonal
+SLOT_OFFSETS = [(0, 0), (1, 0), (2, 0), (-2, 1), (-1, 1), (0, 1), (1, 1), (2, 1), (-2, 2), (-1, 2), (0, 2), (1, 2), (2, 2)]
+
+
+class BscError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("membrane", ctypes.c_int32), ("young", ctypes.c_double), ("poisson", ctypes.c_double),
+                ("thickness", ctypes.c_double), ("mu_st1", ctypes.c_double), ("mu_st2", ctypes.c_double),
+                ("mu_sh", ctypes.c_double), ("mu_bend", ctypes.c_double), ("rho_area", ctypes.c_double)]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("precision", ctypes.c_int32),
+                ("stop_mode", ctypes.c_int32), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("max_newton", ctypes.c_int32), ("max_pcg", ctypes.c_int32), ("pcg_rtol", ctypes.c_double),
+                ("warm_start", ctypes.c_int32), ("fixed_newton_iters", ctypes.c_int32)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
+                ("ls_halvings", ctypes.c_int32), ("warm_start_used", ctypes.c_int32),
+                ("warm_start_fallbacks", ctypes.c_int32), ("g0_norm", ctypes.c_double),
+                ("g_norm", ctypes.c_double), ("energy", ctypes.c_double), ("ms_assemble", ctypes.c_double),
+                ("ms_pcg", ctypes.c_double), ("ms_linesearch", ctypes.c_double),
+                ("ms_warmstart", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Loads libbsc.so (raises BscError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BscError(-9, f"{LIB_PATH} is missing: build it with `python -m paper_2506_18867_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, D, F, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_float, ctypes.c_size_t
+    sig = {
+        "bsc_create": [ctypes.POINTER(P), I32, I32, P, P, P, ctypes.POINTER(Material), P],
+        "bsc_sizes": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "bsc_workspace_size": [P, ctypes.POINTER(SZ)],
+        "bsc_bind_workspace": [P, P, SZ],
+        "bsc_set_pins": [P, P, I32],
+        "bsc_eval_egh": [P, I32, P, P, P, P, P],
+        "bsc_assemble": [P, I32, P, P, D, P, P, P, P],
+        "bsc_spmv": [P, I32, P, P, P],
+        "bsc_bsr_pattern": [P, P, P, ctypes.POINTER(I32)],
+        "bsc_export_bsr": [P, I32, P, P],
+        "bsc_newton_step": [P, ctypes.POINTER(StepOpts), P, P, P, ctypes.POINTER(StepStats)],
+        "bsc_warmstart_load": [P, P, I32],
+        "bsc_net_forward": [P, I32, P, P, P, P],
+        "bsc_net_backward": [P, I32, P, P, P, P, P, P, P],
+        "bsc_net_scratch_size": [P, I32, ctypes.POINTER(SZ)],
+        "bsc_adam_step": [P, I32, P, P, P, P, F, F, F, F, I32],
+        "bsc_net_loss": [P, I32, P, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.bsc_status_string.argtypes = [ctypes.c_int]
+    lib.bsc_status_string.restype = ctypes.c_char_p
+    lib.bsc_last_error.argtypes = [P]
+    lib.bsc_last_error.restype = ctypes.c_char_p
+    lib.bsc_destroy.argtypes = [P]
+    lib.bsc_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    return ["bsc_create", "bsc_sizes", "bsc_workspace_size", "bsc_bind_workspace", "bsc_set_pins", "bsc_eval_egh",
+            "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step",
+            "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size", "bsc_adam_step",
+            "bsc_net_loss", "bsc_status_string", "bsc_last_error", "bsc_destroy"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_material(membrane=0, young=0.0, poisson=0.0, thickness=0.0, mu_st1=0.0, mu_st2=0.0, mu_sh=0.0,
+                  mu_bend=0.0, rho_area=0.0) -> Material:
+    return Material(membrane, young, poisson, thickness, mu_st1, mu_st2, mu_sh, mu_bend, rho_area)
+
+
+def make_opts(dt=0.01, gravity=(0.0, 0.0, -9.81), precision=BSC_FP64, stop_mode=BSC_STOP_GRAD, rtol=1e-6,
+              atol=1e-2, max_newton=50, max_pcg=2000, pcg_rtol=1e-4, warm_start=0, fixed_newton_iters=0) -> StepOpts:
+    return StepOpts(dt, (ctypes.c_double * 3)(*gravity), precision, stop_mode, rtol, atol, max_newton, max_pcg,
+                    pcg_rtol, warm_start, fixed_newton_iters)
+
+
+@dataclass
+class Sizes:
+    n_cp: int
+    n_elem: int
+    n_membrane_pts: int
+    n_bending_evals: int
+
+
+class Context:
+    """One sheet: owns the bsc_ctx handle and its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, n_u, n_v, knots_u, knots_v, rest, material: Material, device="cuda"):
+        import torch
+        self.lib = load()
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        ku = np.ascontiguousarray(knots_u, dtype=np.float64)
+        kv = np.ascontiguousarray(knots_v, dtype=np.float64)
+        rest = np.ascontiguousarray(rest, dtype=np.float64).reshape(-1)
+        h = ctypes.c_void_p()
+        self._mat = material
+        st = self.lib.bsc_create(ctypes.byref(h), self.n_u, self.n_v, _np_ptr(ku), _np_ptr(kv), _np_ptr(rest),
+                                 ctypes.byref(material), _stream())
+        if st != BSC_OK:
+            raise BscError(st, "bsc_create")
+        self.h = h
+        sz = ctypes.c_size_t()
+        self._check(self.lib.bsc_workspace_size(self.h, ctypes.byref(sz)), "bsc_workspace_size")
+        self.ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(self.lib.bsc_bind_workspace(self.h, ctypes.c_void_p(aligned), ctypes.c_size_t(sz.value)),
+                    "bsc_bind_workspace")
+        s = [ctypes.c_int32() for _ in range(4)]
+        self._check(self.lib.bsc_sizes(self.h, *[ctypes.byref(v) for v in s]), "bsc_sizes")
+        self.sizes = Sizes(*[v.value for v in s])
+        self.pins = np.zeros(0, dtype=np.int32)
+        self.device = device
+
+    def _check(self, st, what):
+        if st != BSC_OK:
+            msg = self.lib.bsc_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise BscError(st, f"{what}: {msg}")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and self.lib is not None:
+            self.lib.bsc_destroy(h)
+            self.h = None
+
+    @property
+    def n_cp(self):
+        return self.sizes.n_cp
+
+    @property
+    def n_elem(self):
+        return self.sizes.n_elem
+
+    # ---- calls named after the C ABI -----------------------------------------------------
+    def bsc_set_pins(self, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        self._check(self.lib.bsc_set_pins(self.h, _np_ptr(idx) if idx.size else None, int(idx.size)), "bsc_set_pins")
+        self.pins = idx
+
+    def bsc_eval_egh(self, x, precision=BSC_FP64, want_energy=True, want_grad=True, want_hess=True):
+        import torch
+        dt = torch.float64 if precision == BSC_FP64 else torch.float32
+        E = torch.zeros(1, dtype=torch.float64, device=x.device)
+        eE = torch.empty(self.n_elem, dtype=dt, device=x.device) if want_energy else None
+        eg = torch.empty(27, self.n_elem, dtype=dt, device=x.device) if want_grad else None
+        eH = torch.empty(378, self.n_elem, dtype=dt, device=x.device) if want_hess else None
+        self._check(self.lib.bsc_eval_egh(self.h, precision, _ptr(x), _ptr(E), _ptr(eE), _ptr(eg), _ptr(eH)),
+                    "bsc_eval_egh")
+        return E, eE, eg, eH
+
+    def bsc_assemble(self, x, xhat=None, dt=0.0, gravity=None, precision=BSC_FP64, want_hess=True, out=None):
+        import torch
+        tdt = torch.float64 if precision == BSC_FP64 else torch.float32
+        if out is None:
+            E = torch.zeros(1, dtype=torch.float64, device=x.device)
+            g = torch.empty(3, self.n_cp, dtype=tdt, device=x.device)
+            H = torch.empty(BSC_HESS_ENTRIES, self.n_cp, dtype=tdt, device=x.device) if want_hess else None
+        else:
+            E, g, H = out
+        grav = (ctypes.c_double * 3)(*gravity) if gravity is not None else None
+        self._check(self.lib.bsc_assemble(self.h, precision, _ptr(x), _ptr(xhat), float(dt), grav, _ptr(E), _ptr(g),
+                                          _ptr(H)), "bsc_assemble")
+        return E, g, H
+
+    def bsc_spmv(self, H, v, precision=BSC_FP64, out=None):
+        import torch
+        y = torch.empty_like(v) if out is None else out
+        self._check(self.lib.bsc_spmv(self.h, precision, _ptr(H), _ptr(v), _ptr(y)), "bsc_spmv")
+        return y
+
+    def bsc_bsr_pattern(self):
+        nnzb = ctypes.c_int32()
+        self._check(self.lib.bsc_bsr_pattern(self.h, None, None, ctypes.byref(nnzb)), "bsc_bsr_pattern")
+        rp = np.zeros(self.n_cp + 1, dtype=np.int32)
+        ci = np.zeros(nnzb.value, dtype=np.int32)
+        self._check(self.lib.bsc_bsr_pattern(self.h, _np_ptr(rp), _np_ptr(ci), ctypes.byref(nnzb)), "bsc_bsr_pattern")
+        return rp, ci
+
+    def bsc_export_bsr(self, H, precision=BSC_FP64):
+        import torch
+        rp, ci = self.bsc_bsr_pattern()
+        vals = torch.empty(ci.size, 3, 3, dtype=H.dtype, device=H.device)
+        self._check(self.lib.bsc_export_bsr(self.h, precision, _ptr(H), _ptr(vals)), "bsc_export_bsr")
+        return rp, ci, vals
+
+    def bsc_newton_step(self, x, v, pin_targets=None, opts: StepOpts | None = None, raise_on_error=True):
+        opts = opts or make_opts()
+        stats = StepStats()
+        st = self.lib.bsc_newton_step(self.h, ctypes.byref(opts), _ptr(x), _ptr(v), _ptr(pin_targets),
+                                      ctypes.byref(stats))
+        if st != BSC_OK and raise_on_error:
+            self._check(st, "bsc_newton_step")
+        return st, stats
+
+    def bsc_warmstart_load(self, weights):
+        self._check(self.lib.bsc_warmstart_load(self.h, _ptr(weights), int(weights.numel())), "bsc_warmstart_load")
+
+    def bsc_net_forward(self, weights, inp, acts=None):
+        import torch
+        batch = inp.shape[0]
+        out = torch.empty_like(inp)
+        self._check(self.lib.bsc_net_forward(self.h, batch, _ptr(weights), _ptr(inp), _ptr(out), _ptr(acts)),
+                    "bsc_net_forward")
+        return out
+
+    def bsc_net_scratch_size(self, batch):
+        sz = ctypes.c_size_t()
+        self._check(self.lib.bsc_net_scratch_size(self.h, batch, ctypes.byref(sz)), "bsc_net_scratch_size")
+        return sz.value
+
+    def bsc_net_backward(self, weights, inp, acts, dout, want_din=False, scratch=None):
+        import torch
+        batch = inp.shape[0]
+        dw = torch.empty_like(weights)
+        din = torch.empty_like(inp) if want_din else None
+        if scratch is None:
+            scratch = torch.empty(max(1, self.bsc_net_scratch_size(batch)), dtype=torch.uint8, device=inp.device)
+        self._check(self.lib.bsc_net_backward(self.h, batch, _ptr(weights), _ptr(inp), _ptr(acts), _ptr(dout),
+                                              _ptr(dw), _ptr(din), _ptr(scratch)), "bsc_net_backward")
+        return dw, din
+
+    def bsc_adam_step(self, param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.bsc_adam_step(self.h, int(param.numel()), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
+                                           lr, beta1, beta2, eps, int(t)), "bsc_adam_step")
+
+    def bsc_net_loss(self, pred, target):
+        import torch
+        loss = torch.zeros(1, dtype=torch.float32, device=pred.device)
+        dpred = torch.empty_like(pred)
+        self._check(self.lib.bsc_net_loss(self.h, pred.shape[0], _ptr(pred), _ptr(target), _ptr(loss), _ptr(dpred)),
+                    "bsc_net_loss")
+        return loss, dpred
+
+
+def bsc_create(n_u, n_v, knots_u, knots_v, rest, material: Material, device="cuda") -> Context:
+    """bsc_create + bsc_workspace_size + bsc_bind_workspace in one call."""
+    return Context(n_u, n_v, knots_u, knots_v, rest, material, device)
+
+
+def context_for_scene(scene, device="cuda") -> Context:
+    """Context plus pins for a ``synthetic.Scene``."""
+    m = scene.material
+    mat = make_material(m.membrane, m.young, m.poisson, m.thickness, m.mu_st1, m.mu_st2, m.mu_sh, m.mu_bend,
+                        m.rho_area)
+    ctx = Context(scene.n_u, scene.n_v, scene.knots_u, scene.knots_v, scene.rest, mat, device)
+    if len(scene.pins):
+        ctx.bsc_set_pins(scene.pins)
+    return ctx
+
+
+def to_soa(x_aos, device="cuda"):
+    """(n_cp, 3) numpy -> (3, n_cp) float64 device tensor."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x_aos, dtype=np.float64).T)).to(device)
+
+
+def to_aos(x_soa) -> np.ndarray:
+    return x_soa.detach().cpu().double().numpy().T.copy()
+
+
+def stencil_to_blocks(H, n_u: int, n_v: int) -> dict:
+    """Host-side expansion of an upper-stencil Hessian (numpy (114, n_cp)) into a dict
+    (a, b) -> 3x3 block for every CP pair of the 5x5 pattern (both triangles)."""
+    Hn = np.asarray(H, dtype=np.float64)
+    n = n_u * n_v
+    out = {}
+    for a in range(n):
+        i, j = a % n_u, a // n_u
+        d = Hn[0:6, a]
+        out[(a, a)] = np.array([[d[0], d[1], d[2]], [d[1], d[3], d[4]], [d[2], d[4], d[5]]])
+        for s in range(1, 13):
+            di, dj = SLOT_OFFSETS[s]
+            ib, jb = i + di, j + dj
+            if 0 <= ib < n_u and 0 <= jb < n_v:
+                b = jb * n_u + ib
+                blk = Hn[6 + 9 * (s - 1): 6 + 9 * s, a].reshape(3, 3)
+                out[(a, b)] = blk
+                out[(b, a)] = blk.T
+    return out

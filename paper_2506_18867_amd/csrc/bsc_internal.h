@@ -1,0 +1,144 @@
+// bsc_internal.h -- shared declarations of the HIP library behind include/bsc.h.
+//
+// Device data layout (all in the caller-owned workspace):
+//   membrane points  mp_*  sorted by element, SoA: element index, local span coordinates
+//                          (t_u, t_v) in [0,1], physical weight w = wbar |det dX/d(u,v)|
+//   bending evals    be_*  same layout; weight w (the bending stiffness is applied in-kernel)
+//   per CP           mass (lumped), hbend[13][n_cp] (constant bending Hessian, scalar per
+//                          upper-stencil slot), pinmask
+//   per point        ptA[21][n_mp] w * projected density Hessian (upper triangle of 6x6),
+//                    ptP[6][n_mp] w * first Piola stress, ptE[n_mp] w * Psi
+//   per bending eval beD[3][n_be] w * mu_bend * Laplacian(phi), beE[n_be]
+//   Hessian          hess[114][n_cp] upper-stencil form (see bsc_assemble)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bsc.h"
+
+namespace bsc {
+
+constexpr int kBlock = 256;
+constexpr int kSlots = 13;            // diagonal + 12 upper offsets
+constexpr int kHessEntries = BSC_HESS_ENTRIES;
+
+// Upper-stencil slot offsets (di, dj); slot 0 is the diagonal.
+constexpr int kSlotDi[kSlots] = {0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
+constexpr int kSlotDj[kSlots] = {0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
+
+// First Hessian entry of a slot: 0 for the diagonal (6 entries), 6 + 9 (s - 1) otherwise.
+__host__ __device__ constexpr int slot_entry(int s) { return s == 0 ? 0 : 6 + 9 * (s - 1); }
+
+// Slot of an offset, or -1 for a lower offset / outside the 5x5 neighbourhood.
+__host__ __device__ inline int upper_slot(int di, int dj) {
+    if (di < -2 || di > 2 || dj < 0 || dj > 2) return -1;
+    if (dj == 0) return di < 0 ? -1 : di;      // 0, 1, 2
+    return 3 + (dj - 1) * 5 + (di + 2);
+}
+
+// Everything a kernel needs to know about the sheet (passed by value).
+struct DevSheet {
+    int n_u, n_v, Nu, Nv, n_cp, n_elem, n_mp, n_be;
+    double A00, A01, A10, A11, b0, b1;      // rest map X = A (u, v) + b, span units
+    double K00, K01, K10, K11;              // K = A^{-1}: K[m][b] = d u_m / d X_b
+    double c_uu, c_vv, c_uv;                // Laplacian coefficients (affine rest)
+    int membrane;                           // BSC_MEMBRANE_*
+    double mu, lam;                         // StVK per-area Lame parameters
+    double mu1, mu2, msh;                   // FBW stiffnesses
+    double mu_bend;
+    const int32_t *mp_elem, *mp_off;
+    const double *mp_tu, *mp_tv, *mp_w;
+    const int32_t *be_elem, *be_off;
+    const double *be_tu, *be_tv, *be_w;
+    const double *mass, *hbend;
+    const int32_t *pinmask;
+};
+
+// Device buffers carved out of the workspace.
+struct DevBufs {
+    // tables
+    int32_t *mp_elem, *mp_off, *be_elem, *be_off, *pinmask, *pin_idx;
+    double *mp_tu, *mp_tv, *mp_w, *be_tu, *be_tv, *be_w, *mass, *hbend;
+    // per-point intermediates (sized for double; float uses the front half)
+    void *ptA, *ptP;
+    double *ptE, *ptP64, *beD, *beE;
+    // reductions
+    double *partials;                        // 8 arrays of max_blocks
+    int32_t *bsr_rowptr;                     // n_cp + 1 (standard BSR export)
+    double *scalars;                         // solver scalars (see solve.hip)
+    int32_t *iscalars;
+    // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
+    double *g, *xn, *xhat, *dir, *r, *z, *p0, *p1, *q, *pinv, *tmp;
+    void *hess;                              // kHessEntries n_cp doubles
+    // warm-start network
+    float *net_w, *net_in, *net_out, *net_act0, *net_act1;
+    int max_blocks;
+};
+
+}  // namespace bsc
+
+struct bsc_ctx {
+    int n_u = 0, n_v = 0, Nu = 0, Nv = 0, n_cp = 0, n_elem = 0, n_mp = 0, n_be = 0;
+    bsc_material mat{};
+    bsc::DevSheet dev{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // host tables
+    std::vector<int32_t> mp_elem, mp_off, be_elem, be_off;
+    std::vector<double> mp_tu, mp_tv, mp_w, be_tu, be_tv, be_w, mass, hbend;
+    std::vector<int32_t> pins;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bsc::DevBufs buf{};
+    bool net_loaded = false;
+    std::string err;
+};
+
+namespace bsc {
+
+bsc_status fail(bsc_ctx *ctx, bsc_status st, const std::string &msg);
+bsc_status hip_check(bsc_ctx *ctx, hipError_t e, const char *what);
+size_t layout_workspace(const bsc_ctx *ctx, DevBufs *b, char *base);
+DevSheet dev_sheet(const bsc_ctx *ctx);
+
+// ---- launchers (eval.hip) ----
+// Membrane points (w Psi, w P and, with hess, w A+), bending evaluations; element gather;
+// per-CP gradient; per-block Hessian gather; energy reduction.
+hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
+                         const double *x, hipStream_t st);
+hipError_t launch_grad(const DevSheet &S, const DevBufs &B, int precision, const double *x,
+                       const double *xhat, double inv_dt2, const double *grav, void *g,
+                       bool from64, hipStream_t st);
+hipError_t launch_hess(const DevSheet &S, const DevBufs &B, int precision, double inv_dt2, void *hess,
+                       hipStream_t st);
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, bool with_cp, double *out,
+                                hipStream_t st);
+hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,
+                       hipStream_t st);
+
+// ---- launchers (solve.hip) ----
+hipError_t launch_spmv(const DevSheet &S, int precision, const void *hess, const double *in, double *out,
+                       hipStream_t st);
+hipError_t launch_export_bsr(const DevSheet &S, int precision, const void *hess, const int32_t *row_ptr,
+                             const int32_t *col_idx, void *vals, hipStream_t st);
+bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *v, const double *pin_tgt,
+                       bsc_step_stats *stats);
+
+// ---- launchers (net.hip) ----
+hipError_t net_forward(int n_u, int n_v, int batch, const float *w, const float *in, float *out,
+                       float *acts, float *tmp0, float *tmp1, hipStream_t st);
+hipError_t net_backward(int n_u, int n_v, int batch, const float *w, const float *in, const float *acts,
+                        const float *dout, float *dw, float *din, void *scratch, hipStream_t st);
+size_t net_scratch_bytes(int n_u, int n_v, int batch);
+hipError_t net_adam(int n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
+                    float eps, int t, hipStream_t st);
+hipError_t net_loss(int n_cp, int batch, const float *pred, const float *tgt, float *loss, float *dpred,
+                    float *scratch, hipStream_t st);
+
+}  // namespace bsc

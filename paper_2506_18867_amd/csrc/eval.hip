@@ -1,0 +1,674 @@
+// eval.hip -- element evaluation and spline-structured assembly for gfx950.
+//
+// Stage 1 (one thread per quadrature point, coalesced SoA tables):
+//   membrane point: deformation gradient from the 3x3 CP stencil of its span (Eq. "deformation
+//   gradient"), energy density, first Piola stress and the 6x6 density Hessian (Sec. 4.1),
+//   projected to PSD in double (Sec. 5.1); stored pre-multiplied by the point weight.
+//   bending evaluation: Laplacian of phi (Eq. "Laplacian in parametric space"), stored as
+//   w mu_bend Laplacian(phi) (Sec. 4.2).
+// Stage 2 (gathers, no atomics, deterministic): per CP gradient, per (CP, upper-stencil slot)
+//   3x3 Hessian block summing the weighted contributions of the quadrature points shared by
+//   the two CPs (Sec. 5.2, "Elasticity Hessian Assembly"), per element outputs.
+// Energies are reduced per block into partial sums and summed in a fixed order.
+#include "bsc_internal.h"
+
+namespace bsc {
+namespace {
+
+enum { kFirst = 0, kInner = 1, kLast = 2 };
+
+__device__ __forceinline__ int span_type(int k, int N) { return k == 0 ? kFirst : (k == N - 1 ? kLast : kInner); }
+
+// Values and first derivatives of the three quadratic pieces on a span (local t in [0,1]).
+template <typename T>
+__device__ __forceinline__ void pieces(int type, T t, T N[3], T D[3]) {
+    const T s = T(1) - t;
+    if (type == kInner) {
+        N[0] = T(0.5) * s * s; N[1] = T(0.5) + t * s; N[2] = T(0.5) * t * t;
+        D[0] = -s; D[1] = s - t; D[2] = t;
+    } else if (type == kFirst) {
+        N[0] = s * s; N[1] = t * (T(2) - T(1.5) * t); N[2] = T(0.5) * t * t;
+        D[0] = T(-2) * s; D[1] = T(2) - T(3) * t; D[2] = t;
+    } else {
+        N[0] = T(0.5) * s * s; N[1] = s * (T(2) - T(1.5) * s); N[2] = t * t;
+        D[0] = -s; D[1] = T(1) - T(3) * t; D[2] = T(2) * t;
+    }
+}
+
+__device__ __forceinline__ void second(int type, double D2[3]) {
+    if (type == kInner) { D2[0] = 1.0; D2[1] = -2.0; D2[2] = 1.0; }
+    else if (type == kFirst) { D2[0] = 2.0; D2[1] = -3.0; D2[2] = 1.0; }
+    else { D2[0] = 1.0; D2[1] = -3.0; D2[2] = 2.0; }
+}
+
+__device__ __forceinline__ double greville(int i, int n) {
+    return i == 0 ? 0.0 : (i == n - 1 ? double(n - 2) : double(i) - 0.5);
+}
+
+// Displacement of CP (i,j) from its rest position embedded in the plane z = 0.
+__device__ __forceinline__ void displacement(const DevSheet &S, const double *x, int i, int j, double d[3]) {
+    const int a = j * S.n_u + i;
+    const double gu = greville(i, S.n_u), gv = greville(j, S.n_v);
+    d[0] = x[a] - (S.A00 * gu + S.A01 * gv + S.b0);
+    d[1] = x[S.n_cp + a] - (S.A10 * gu + S.A11 * gv + S.b1);
+    d[2] = x[2 * S.n_cp + a];
+}
+
+// Index of (r, c), r <= c, in the row-major upper triangle of a 6x6 matrix.
+__host__ __device__ constexpr int u6(int r, int c) { return r <= c ? r * 6 - r * (r - 1) / 2 + (c - r) : c * 6 - c * (c - 1) / 2 + (r - c); }
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    const int nw = (blockDim.x + 63) >> 6;
+    v = (int(threadIdx.x) < nw) ? sh[threadIdx.x] : 0.0;
+    if (wid == 0) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    }
+    return v;
+}
+
+// ---- membrane densities (T precision) -------------------------------------------------------
+// G = dd/dX (3x2) is the displacement gradient; F = [I; 0] + G. Green strain is formed from G
+// (E = sym(G_top) + G^T G / 2) so that no O(1) cancellation against I occurs.
+
+template <typename T>
+__device__ void stvk(const T G[3][2], T mu, T lam, T &psi, T P[3][2], T A[6][6], bool hess) {
+    T F[3][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) F[i][g] = G[i][g] + ((i == g) ? T(1) : T(0));
+    T E[2][2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+            E[g][d] = T(0.5) * (G[g][d] + G[d][g] + G[0][g] * G[0][d] + G[1][g] * G[1][d] + G[2][g] * G[2][d]);
+    const T tr = E[0][0] + E[1][1];
+    psi = mu * (E[0][0] * E[0][0] + T(2) * E[0][1] * E[0][1] + E[1][1] * E[1][1]) + T(0.5) * lam * tr * tr;
+    T Sm[2][2] = {{T(2) * mu * E[0][0] + lam * tr, T(2) * mu * E[0][1]}, {T(2) * mu * E[1][0], T(2) * mu * E[1][1] + lam * tr}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) P[i][g] = F[i][0] * Sm[0][g] + F[i][1] * Sm[1][g];
+    if (!hess) return;
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const T ffij = F[i][0] * F[j][0] + F[i][1] * F[j][1];
+                    A[3 * g + i][3 * d + j] = (i == j ? Sm[g][d] : T(0)) + mu * F[i][d] * F[j][g] +
+                                              (g == d ? mu * ffij : T(0)) + lam * F[i][g] * F[j][d];
+                }
+}
+
+template <typename T>
+__device__ void fbw(const T G[3][2], T mu1, T mu2, T msh, T &psi, T P[3][2], T A[6][6], bool hess) {
+    T f[2][3];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[g][i] = G[i][g] + ((i == g) ? T(1) : T(0));
+    const T mus[2] = {mu1, mu2};
+    T len[2], lm1[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        // I5 - 1 = 2 G_gg + |G_:g|^2 without cancellation; sqrt(I5) - 1 = (I5 - 1)/(sqrt(I5) + 1)
+        const T i5m1 = T(2) * G[g][g] + G[0][g] * G[0][g] + G[1][g] * G[1][g] + G[2][g] * G[2][g];
+        len[g] = sqrt(T(1) + i5m1);
+        lm1[g] = i5m1 / (len[g] + T(1));
+    }
+    const T I6 = f[0][0] * f[1][0] + f[0][1] * f[1][1] + f[0][2] * f[1][2];
+    psi = msh * I6 * I6 + mu1 * lm1[0] * lm1[0] + mu2 * lm1[1] * lm1[1];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            P[i][g] = T(2) * msh * I6 * f[1 - g][i] + T(2) * mus[g] * (lm1[g] / len[g]) * f[g][i];
+    if (!hess) return;
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    T a;
+                    if (g == d) {
+                        a = T(2) * msh * f[1 - g][i] * f[1 - g][j] +
+                            T(2) * mus[g] * ((i == j ? lm1[g] / len[g] : T(0)) + f[g][i] * f[g][j] / (len[g] * len[g] * len[g]));
+                    } else {
+                        a = T(2) * msh * (f[d][i] * f[g][j] + (i == j ? I6 : T(0)));
+                    }
+                    A[3 * g + i][3 * d + j] = a;
+                }
+}
+
+// ---- PSD projection in double -------------------------------------------------------------
+// A positive-definite matrix (Cholesky succeeds) is its own projection; otherwise a cyclic
+// Jacobi eigen-decomposition (symmetric Schur rotations) is run to convergence and the
+// negative eigenvalues are clamped to zero.
+
+__device__ bool cholesky_pd(const double A[6][6]) {
+    double L[6][6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0.0)) return false;
+        const double ljj = sqrt(d), inv = 1.0 / ljj;
+        L[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double s = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = s * inv;
+        }
+    }
+    return true;
+}
+
+__device__ void project_psd(double A[6][6]) {
+    if (cholesky_pd(A)) return;
+    double V[6][6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) V[r][c] = (r == c) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double a2 = A[r][c] * A[r][c];
+                tot += a2;
+                if (r != c) off += a2;
+            }
+        if (off <= 1e-32 * tot) break;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < 6; ++q) {
+                const double apq = A[p][q];
+                if (apq != 0.0) {
+                    const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const double akp = A[k][p], akq = A[k][q];
+                        A[k][p] = c * akp - s * akq;
+                        A[k][q] = s * akp + c * akq;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const double apk = A[p][k], aqk = A[q][k];
+                        A[p][k] = c * apk - s * aqk;
+                        A[q][k] = s * apk + c * aqk;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const double vkp = V[k][p], vkq = V[k][q];
+                        V[k][p] = c * vkp - s * vkq;
+                        V[k][q] = s * vkp + c * vkq;
+                    }
+                }
+            }
+        }
+    }
+    double lam[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) lam[r] = A[r][r] > 0.0 ? A[r][r] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = r; c < 6; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) s += V[r][m] * lam[m] * V[c][m];
+            A[r][c] = s;
+            A[c][r] = s;
+        }
+}
+
+// Gradient w.r.t. X of the 9 local basis functions at span coordinates (tu, tv).
+template <typename T>
+__device__ __forceinline__ void local_grads(const DevSheet &S, int k, int l, T tu, T tv, T dN[9][2]) {
+    T Nu[3], Du[3], Nv[3], Dv[3];
+    pieces<T>(span_type(k, S.Nu), tu, Nu, Du);
+    pieces<T>(span_type(l, S.Nv), tv, Nv, Dv);
+    const T K00 = T(S.K00), K01 = T(S.K01), K10 = T(S.K10), K11 = T(S.K11);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T du = Du[a] * Nv[b], dv = Nu[a] * Dv[b];
+            dN[3 * b + a][0] = du * K00 + dv * K10;
+            dN[3 * b + a][1] = du * K01 + dv * K11;
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void one_grad(const DevSheet &S, int k, int l, int a, int b, T tu, T tv, T g[2]) {
+    T Nu[3], Du[3], Nv[3], Dv[3];
+    pieces<T>(span_type(k, S.Nu), tu, Nu, Du);
+    pieces<T>(span_type(l, S.Nv), tv, Nv, Dv);
+    const T du = Du[a] * Nv[b], dv = Nu[a] * Dv[b];
+    g[0] = du * T(S.K00) + dv * T(S.K10);
+    g[1] = du * T(S.K01) + dv * T(S.K11);
+}
+
+// Laplacian coefficients L of the 9 local CPs for a bending evaluation.
+__device__ __forceinline__ void bend_L(const DevSheet &S, int k, int l, double tu, double tv, double L[9]) {
+    double Nu[3], Du[3], D2u[3], Nv[3], Dv[3], D2v[3];
+    const int tyu = span_type(k, S.Nu), tyv = span_type(l, S.Nv);
+    pieces<double>(tyu, tu, Nu, Du);
+    pieces<double>(tyv, tv, Nv, Dv);
+    second(tyu, D2u);
+    second(tyv, D2v);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            L[3 * b + a] = S.c_uu * D2u[a] * Nv[b] + S.c_vv * Nu[a] * D2v[b] + S.c_uv * Du[a] * Dv[b];
+}
+
+// ---- stage 1 kernels ------------------------------------------------------------------------
+
+template <typename T, bool HESS>
+__global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *__restrict__ x, T *__restrict__ ptA,
+                                                     T *__restrict__ ptP, double *__restrict__ ptE,
+                                                     double *__restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    double e_loc = 0.0;
+    if (q < S.n_mp) {
+        const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
+        const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
+        const double w = S.mp_w[q];
+        T dN[9][2];
+        local_grads<T>(S, k, l, tu, tv, dN);
+        T G[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            double d[3];
+            displacement(S, x, k + m % 3, l + m / 3, d);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T dc = T(d[c]);
+                G[c][0] += dc * dN[m][0];
+                G[c][1] += dc * dN[m][1];
+            }
+        }
+        T psi, P[3][2], A[6][6];
+        if (S.membrane == BSC_MEMBRANE_STVK) stvk<T>(G, T(S.mu), T(S.lam), psi, P, A, HESS);
+        else fbw<T>(G, T(S.mu1), T(S.mu2), T(S.msh), psi, P, A, HESS);
+        e_loc = w * double(psi);
+        ptE[q] = e_loc;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ptP[(2 * i + g) * S.n_mp + q] = T(w * double(P[i][g]));
+        if (HESS) {
+            double Ad[6][6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) Ad[r][c] = 0.5 * (double(A[r][c]) + double(A[c][r]));
+            project_psd(Ad);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = r; c < 6; ++c) ptA[u6(r, c) * S.n_mp + q] = T(w * Ad[r][c]);
+        }
+    }
+    const double s = block_sum(e_loc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__restrict__ x, double *__restrict__ beD,
+                                                    double *__restrict__ beE, double *__restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    double e_loc = 0.0;
+    if (q < S.n_be) {
+        const int e = S.be_elem[q], k = e % S.Nu, l = e / S.Nu;
+        double L[9];
+        bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+        double lap[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            double d[3];
+            displacement(S, x, k + m % 3, l + m / 3, d);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lap[c] += L[m] * d[c];
+        }
+        const double wm = S.be_w[q] * S.mu_bend;
+        e_loc = 0.5 * wm * (lap[0] * lap[0] + lap[1] * lap[1] + lap[2] * lap[2]);
+        beE[q] = e_loc;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) beD[c * S.n_be + q] = wm * lap[c];
+    }
+    const double s = block_sum(e_loc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ---- stage 2: per-CP gradient ---------------------------------------------------------------
+
+template <typename T, typename TP>
+__global__ void __launch_bounds__(kBlock) k_grad(DevSheet S, const TP *__restrict__ ptP, const double *__restrict__ beD,
+                                                 const double *__restrict__ x, const double *__restrict__ xhat,
+                                                 double inv_dt2, double gx, double gy, double gz,
+                                                 T *__restrict__ gout, double *__restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    double e_loc = 0.0;
+    if (a < S.n_cp) {
+        const int i = a % S.n_u, j = a / S.n_u;
+        T acc[3] = {T(0), T(0), T(0)};
+        double accb[3] = {0.0, 0.0, 0.0};
+        for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
+            for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
+                const int e = l * S.Nu + k, la = i - k, lb = j - l;
+                for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+                    T dn[2];
+                    one_grad<T>(S, k, l, la, lb, T(S.mp_tu[q]), T(S.mp_tv[q]), dn);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += T(ptP[(2 * c) * S.n_mp + q]) * dn[0] + T(ptP[(2 * c + 1) * S.n_mp + q]) * dn[1];
+                }
+                for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
+                    double L[9];
+                    bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+                    const double Lm = L[3 * lb + la];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) accb[c] += beD[c * S.n_be + q] * Lm;
+                }
+            }
+        }
+        double gsum[3];
+        const double M = S.mass[a];
+        const double grav[3] = {gx, gy, gz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gsum[c] = double(acc[c]) + accb[c];
+            const double xc = x[c * S.n_cp + a];
+            if (xhat) {
+                const double dlt = xc - xhat[c * S.n_cp + a];
+                gsum[c] += M * inv_dt2 * dlt;
+                e_loc += 0.5 * M * inv_dt2 * dlt * dlt;
+            }
+            gsum[c] -= M * grav[c];
+            e_loc -= M * grav[c] * xc;
+        }
+        const bool pinned = S.pinmask[a] != 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gout[c * S.n_cp + a] = pinned ? T(0) : T(gsum[c]);
+    }
+    const double s = block_sum(e_loc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// ---- stage 2: per (CP, slot) Hessian block ---------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_hess(DevSheet S, const T *__restrict__ ptA, double inv_dt2,
+                                                 T *__restrict__ hess) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (a >= S.n_cp) return;
+    const int i = a % S.n_u, j = a / S.n_u;
+    const int ib = i + kSlotDi[s], jb = j + kSlotDj[s];
+    const int e0 = slot_entry(s);
+    const size_t ncp = S.n_cp;
+    T acc[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    const bool inside = ib >= 0 && ib < S.n_u && jb < S.n_v;
+    const bool pinned = inside && (S.pinmask[a] != 0 || S.pinmask[jb * S.n_u + ib] != 0);
+    if (inside && !pinned) {
+        for (int l = max(0, max(j, jb) - 2); l <= min(min(j, jb), S.Nv - 1); ++l) {
+            for (int k = max(0, max(i, ib) - 2); k <= min(min(i, ib), S.Nu - 1); ++k) {
+                const int e = l * S.Nu + k;
+                const int la = i - k, lb = j - l, ma = ib - k, mb = jb - l;
+                for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+                    T ga[2], gb[2];
+                    const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
+                    one_grad<T>(S, k, l, la, lb, tu, tv, ga);
+                    one_grad<T>(S, k, l, ma, mb, tu, tv, gb);
+                    const T c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const T a00 = ptA[u6(r, c) * S.n_mp + q];
+                            const T a01 = ptA[u6(r, 3 + c) * S.n_mp + q];
+                            const T a10 = ptA[u6(3 + r, c) * S.n_mp + q];
+                            const T a11 = ptA[u6(3 + r, 3 + c) * S.n_mp + q];
+                            acc[r][c] += c00 * a00 + c01 * a01 + c10 * a10 + c11 * a11;
+                        }
+                }
+            }
+        }
+        const T hb = T(S.hbend[s * ncp + a]) + ((s == 0) ? T(S.mass[a] * inv_dt2) : T(0));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r][r] += hb;
+    } else if (pinned && s == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r][r] = T(1);
+    }
+    if (s == 0) {
+        hess[(e0 + 0) * ncp + a] = acc[0][0];
+        hess[(e0 + 1) * ncp + a] = acc[0][1];
+        hess[(e0 + 2) * ncp + a] = acc[0][2];
+        hess[(e0 + 3) * ncp + a] = acc[1][1];
+        hess[(e0 + 4) * ncp + a] = acc[1][2];
+        hess[(e0 + 5) * ncp + a] = acc[2][2];
+    } else {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hess[(e0 + 3 * r + c) * ncp + a] = acc[r][c];
+    }
+}
+
+// ---- per-element outputs -------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_hess(DevSheet S, const T *__restrict__ ptA, T *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ent = blockIdx.y;                   // 0..377, upper triangle of 27x27, row-major
+    if (e >= S.n_elem) return;
+    int r = 0, rem = ent;
+    while (rem >= 27 - r) { rem -= 27 - r; ++r; }
+    const int c = r + rem;
+    const int m = r / 3, ci = r % 3, n = c / 3, cj = c % 3;
+    const int k = e % S.Nu, l = e / S.Nu;
+    double acc = 0.0;
+    for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+        T ga[2], gb[2];
+        const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
+        one_grad<T>(S, k, l, m % 3, m / 3, tu, tv, ga);
+        one_grad<T>(S, k, l, n % 3, n / 3, tu, tv, gb);
+        T v = T(0);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) v += ga[g] * gb[d] * ptA[u6(3 * g + ci, 3 * d + cj) * S.n_mp + q];
+        acc += double(v);
+    }
+    if (ci == cj) {
+        for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
+            double L[9];
+            bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+            acc += S.be_w[q] * S.mu_bend * L[m] * L[n];
+        }
+    }
+    out[size_t(ent) * S.n_elem + e] = T(acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_grad(DevSheet S, const T *__restrict__ ptP, const double *__restrict__ beD,
+                                                      const double *__restrict__ ptE, const double *__restrict__ beE,
+                                                      T *__restrict__ eE, T *__restrict__ eg) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S.n_elem) return;
+    const int k = e % S.Nu, l = e / S.Nu;
+    if (eg) {
+        for (int m = 0; m < 9; ++m) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+                T gm[2];
+                one_grad<T>(S, k, l, m % 3, m / 3, T(S.mp_tu[q]), T(S.mp_tv[q]), gm);
+                for (int c = 0; c < 3; ++c)
+                    acc[c] += double(ptP[(2 * c) * S.n_mp + q] * gm[0] + ptP[(2 * c + 1) * S.n_mp + q] * gm[1]);
+            }
+            for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
+                double L[9];
+                bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+                for (int c = 0; c < 3; ++c) acc[c] += beD[c * S.n_be + q] * L[m];
+            }
+            for (int c = 0; c < 3; ++c) eg[size_t(3 * m + c) * S.n_elem + e] = T(acc[c]);
+        }
+    }
+    if (eE) {
+        double s = 0.0;
+        for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) s += ptE[q];
+        for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) s += beE[q];
+        eE[e] = T(s);
+    }
+}
+
+// Sums up to four partial arrays (each of length n) in a fixed order into out[0].
+__global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ p0, int n0, const double *__restrict__ p1,
+                                                   int n1, const double *__restrict__ p2, int n2,
+                                                   double *__restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    double v = 0.0;
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) v += p0[t];
+    for (int t = threadIdx.x; t < n1; t += blockDim.x) v += p1[t];
+    for (int t = threadIdx.x; t < n2; t += blockDim.x) v += p2[t];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
+                         const double *x, hipStream_t st) {
+    // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch.
+    double *pm = B.partials, *pb = B.partials + B.max_blocks;
+    if (grad64 || precision == BSC_FP64) {
+        double *P = grad64 ? B.ptP64 : (double *)B.ptP;
+        if (hess && !grad64)
+            k_membrane<double, true><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+        else
+            k_membrane<double, false><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+    } else {
+        if (hess)
+            k_membrane<float, true><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+        else
+            k_membrane<float, false><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+    }
+    k_bending<<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const DevSheet &S, const DevBufs &B, int precision, const double *x, const double *xhat,
+                       double inv_dt2, const double *grav, void *g, bool from64, hipStream_t st) {
+    double *pc = B.partials + 2 * B.max_blocks;
+    const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
+    if (from64)
+        k_grad<double, double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, B.ptP64, B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)g, pc);
+    else if (precision == BSC_FP64)
+        k_grad<double, double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.ptP, B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)g, pc);
+    else
+        k_grad<float, float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.ptP, B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)g, pc);
+    return hipGetLastError();
+}
+
+hipError_t launch_hess(const DevSheet &S, const DevBufs &B, int precision, double inv_dt2, void *hess, hipStream_t st) {
+    dim3 grid(blocks(S.n_cp), kSlots);
+    if (precision == BSC_FP64)
+        k_hess<double><<<grid, kBlock, 0, st>>>(S, (const double *)B.ptA, inv_dt2, (double *)hess);
+    else
+        k_hess<float><<<grid, kBlock, 0, st>>>(S, (const float *)B.ptA, inv_dt2, (float *)hess);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, bool with_cp, double *out, hipStream_t st) {
+    k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
+                                   B.partials + 2 * B.max_blocks, with_cp ? blocks(S.n_cp) : 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH, hipStream_t st) {
+    if (precision == BSC_FP64) {
+        if (eH) k_elem_hess<double><<<dim3(blocks(S.n_elem), 378), kBlock, 0, st>>>(S, (const double *)B.ptA, (double *)eH);
+        if (eE || eg)
+            k_elem_grad<double><<<blocks(S.n_elem), kBlock, 0, st>>>(S, (const double *)B.ptP, B.beD, B.ptE, B.beE, (double *)eE, (double *)eg);
+    } else {
+        if (eH) k_elem_hess<float><<<dim3(blocks(S.n_elem), 378), kBlock, 0, st>>>(S, (const float *)B.ptA, (float *)eH);
+        if (eE || eg)
+            k_elem_grad<float><<<blocks(S.n_elem), kBlock, 0, st>>>(S, (const float *)B.ptP, B.beD, B.ptE, B.beE, (float *)eE, (float *)eg);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bsc
+
+using namespace bsc;
+
+extern "C" {
+
+bsc_status bsc_eval_egh(bsc_ctx *c, int32_t precision, const double *d_x, double *d_energy, void *d_elem_energy,
+                        void *d_elem_grad, void *d_elem_hess) {
+    if (!c) return BSC_E_INVAL;
+    if (!c->ws) return fail(c, BSC_E_STATE, "no workspace bound");
+    if (!d_x || !d_energy) return fail(c, BSC_E_INVAL, "null pointer");
+    if (precision != BSC_FP64 && precision != BSC_FP32_MIXED) return fail(c, BSC_E_INVAL, "bad precision");
+    const DevSheet &S = c->dev;
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_elem_hess != nullptr, false, d_x, c->stream), "eval points");
+    if (st != BSC_OK) return st;
+    st = hip_check(c, launch_energy_reduce(S, c->buf, false, d_energy, c->stream), "energy reduce");
+    if (st != BSC_OK) return st;
+    return hip_check(c, launch_elem(S, c->buf, precision, d_elem_energy, d_elem_grad, d_elem_hess, c->stream), "element gather");
+}
+
+bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const double *d_xhat, double dt,
+                        const double *gravity, double *d_energy, void *d_grad, void *d_hess) {
+    if (!c) return BSC_E_INVAL;
+    if (!c->ws) return fail(c, BSC_E_STATE, "no workspace bound");
+    if (!d_x || !d_energy || !d_grad) return fail(c, BSC_E_INVAL, "null pointer");
+    if (precision != BSC_FP64 && precision != BSC_FP32_MIXED) return fail(c, BSC_E_INVAL, "bad precision");
+    double inv_dt2 = 0.0;
+    if (d_xhat) {
+        if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, BSC_E_INVAL, "dt must be positive");
+        inv_dt2 = 1.0 / (dt * dt);
+    }
+    const DevSheet &S = c->dev;
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream), "eval points");
+    if (st != BSC_OK) return st;
+    st = hip_check(c, launch_grad(S, c->buf, precision, d_x, d_xhat, inv_dt2, gravity, d_grad, false, c->stream), "gradient");
+    if (st != BSC_OK) return st;
+    st = hip_check(c, launch_energy_reduce(S, c->buf, true, d_energy, c->stream), "energy reduce");
+    if (st != BSC_OK) return st;
+    if (d_hess) st = hip_check(c, launch_hess(S, c->buf, precision, inv_dt2, d_hess, c->stream), "hessian");
+    return st;
+}
+
+}  // extern "C"

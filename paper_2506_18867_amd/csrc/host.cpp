@@ -1,0 +1,453 @@
+// host.cpp -- context creation, validation and the one-time precompute of the device tables:
+// reduced quadrature lists (Sec. 4.1 and 4.2), lumped mass (Sec. 5.1), constant bending
+// Hessian stencil (the bending Hessian of a flat rest shape is constant, so it is precomputed;
+// Sec. 6.5 step "bending Hessian precomputation"), workspace layout and the C ABI entry points
+// that are not solver calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "bsc_internal.h"
+
+namespace bsc {
+
+bsc_status fail(bsc_ctx *ctx, bsc_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+bsc_status hip_check(bsc_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return BSC_OK;
+    return fail(ctx, BSC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+enum SpanType { kFirst = 0, kInner = 1, kLast = 2 };
+
+int span_type(int k, int N) { return k == 0 ? kFirst : (k == N - 1 ? kLast : kInner); }
+
+// Quadratic B-spline pieces on a span of an open uniform knot vector, local t in [0,1]:
+// values, first and second derivatives of the three functions supported on the span.
+void pieces(int type, double t, double N[3], double D[3], double D2[3]) {
+    const double s = 1.0 - t;
+    if (type == kInner) {
+        N[0] = 0.5 * s * s; N[1] = 0.5 * (-2.0 * t * t + 2.0 * t + 1.0); N[2] = 0.5 * t * t;
+        D[0] = -s; D[1] = 1.0 - 2.0 * t; D[2] = t;
+        D2[0] = 1.0; D2[1] = -2.0; D2[2] = 1.0;
+    } else if (type == kFirst) {
+        N[0] = s * s; N[1] = 2.0 * t - 1.5 * t * t; N[2] = 0.5 * t * t;
+        D[0] = -2.0 * s; D[1] = 2.0 - 3.0 * t; D[2] = t;
+        D2[0] = 2.0; D2[1] = -3.0; D2[2] = 1.0;
+    } else {
+        N[0] = 0.5 * s * s; N[1] = 2.0 * s - 1.5 * s * s; N[2] = t * t;
+        D[0] = -s; D[1] = 1.0 - 3.0 * t; D[2] = 2.0 * t;
+        D2[0] = 1.0; D2[1] = -3.0; D2[2] = 2.0;
+    }
+}
+
+// Greville abscissa of CP i in span units: 0, 1/2, 3/2, ..., N - 1/2, N.
+double greville(int i, int n) {
+    if (i == 0) return 0.0;
+    if (i == n - 1) return double(n - 2);
+    return i - 0.5;
+}
+
+struct Pt { double u, v, w; int k, l; };
+
+const double kG2 = 0.28867513459481288225;   // 1 / (2 sqrt 3)
+const double kG3 = 0.38729833462074168852;   // sqrt(3/5) / 2
+
+// Membrane rule (Sec. 4.1): 3x3 Gauss on corner spans, 3x2 / 2x3 on side spans, and in the
+// interior region alternating 1x2 / 2x1 Gauss on dual-grid cells centred at the knots,
+// clipped to the region (two points on the knot line for edge half cells, one at the knot
+// for corner quarter cells). Weights: Gauss weights times the clipped cell area.
+std::vector<Pt> membrane_points(int Nu, int Nv) {
+    std::vector<Pt> out;
+    const double o2[2] = {-kG2, kG2}, w2[2] = {0.5, 0.5};
+    const double o3[3] = {-kG3, 0.0, kG3}, w3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    for (int l = 0; l < Nv; ++l) {
+        for (int k = 0; k < Nu; ++k) {
+            const bool eu = (k == 0 || k == Nu - 1), ev = (l == 0 || l == Nv - 1);
+            if (!eu && !ev) continue;
+            const int nu = eu ? 3 : 2, nv = ev ? 3 : 2;
+            const double *ou = eu ? o3 : o2, *wu = eu ? w3 : w2;
+            const double *ov = ev ? o3 : o2, *wv = ev ? w3 : w2;
+            for (int b = 0; b < nv; ++b)
+                for (int a = 0; a < nu; ++a) out.push_back({k + 0.5 + ou[a], l + 0.5 + ov[b], wu[a] * wv[b], k, l});
+        }
+    }
+    for (int b = 1; b < Nv; ++b) {
+        for (int a = 1; a < Nu; ++a) {
+            const bool hu = (a == 1 || a == Nu - 1), hv = (b == 1 || b == Nv - 1);
+            double pu[2], pv[2], w;
+            int np = 2;
+            if (hu && hv) { np = 1; w = 0.25; pu[0] = a; pv[0] = b; }
+            else if (hu) { w = 0.25; pu[0] = pu[1] = a; pv[0] = b - kG2; pv[1] = b + kG2; }
+            else if (hv) { w = 0.25; pv[0] = pv[1] = b; pu[0] = a - kG2; pu[1] = a + kG2; }
+            else if (((a + b) & 1) == 0) { w = 0.5; pu[0] = pu[1] = a; pv[0] = b - kG2; pv[1] = b + kG2; }
+            else { w = 0.5; pv[0] = pv[1] = b; pu[0] = a - kG2; pu[1] = a + kG2; }
+            for (int q = 0; q < np; ++q) {
+                int k = std::min(int(std::floor(pu[q])), Nu - 1);
+                int l = std::min(int(std::floor(pv[q])), Nv - 1);
+                out.push_back({pu[q], pv[q], w, k, l});
+            }
+        }
+    }
+    return out;
+}
+
+// Bending rule (Sec. 4.2): one point per boundary span centre, one per interior knot weighted
+// by its clipped dual cell; each knot point is evaluated in its four adjacent spans with a
+// quarter of the weight (mean of the one-sided values).
+std::vector<Pt> bending_points(int Nu, int Nv) {
+    std::vector<Pt> out;
+    for (int l = 0; l < Nv; ++l)
+        for (int k = 0; k < Nu; ++k)
+            if (k == 0 || k == Nu - 1 || l == 0 || l == Nv - 1) out.push_back({k + 0.5, l + 0.5, 1.0, k, l});
+    for (int b = 1; b < Nv; ++b) {
+        for (int a = 1; a < Nu; ++a) {
+            const double cu = (a == 1 || a == Nu - 1) ? 0.5 : 1.0;
+            const double cv = (b == 1 || b == Nv - 1) ? 0.5 : 1.0;
+            const double w = 0.25 * cu * cv;
+            for (int dl = -1; dl <= 0; ++dl)
+                for (int dk = -1; dk <= 0; ++dk) out.push_back({double(a), double(b), w, a + dk, b + dl});
+        }
+    }
+    return out;
+}
+
+// Sorts points by element and fills the SoA tables plus per-element offsets.
+void fill_tables(const std::vector<Pt> &pts, int Nu, int n_elem, double wscale, std::vector<int32_t> &elem,
+                 std::vector<int32_t> &off, std::vector<double> &tu, std::vector<double> &tv,
+                 std::vector<double> &w) {
+    off.assign(n_elem + 1, 0);
+    for (const Pt &p : pts) off[p.l * Nu + p.k + 1]++;
+    for (int e = 0; e < n_elem; ++e) off[e + 1] += off[e];
+    std::vector<int32_t> cur(off.begin(), off.end() - 1);
+    const size_t n = pts.size();
+    elem.assign(n, 0); tu.assign(n, 0.0); tv.assign(n, 0.0); w.assign(n, 0.0);
+    for (const Pt &p : pts) {
+        const int e = p.l * Nu + p.k;
+        const int d = cur[e]++;
+        elem[d] = e; tu[d] = p.u - p.k; tv[d] = p.v - p.l; w[d] = p.w * wscale;
+    }
+}
+
+bool knots_ok(const double *kn, int n, double *spacing) {
+    const int nk = n + 3;
+    if (n < 5) return false;
+    if (kn[0] != 0.0 || kn[1] != 0.0 || kn[2] != 0.0) return false;
+    if (kn[nk - 1] != kn[nk - 2] || kn[nk - 2] != kn[nk - 3]) return false;
+    const double h = kn[3] - kn[2];
+    if (!(h > 0.0) || h != std::floor(h)) return false;
+    for (int s = 2; s < nk - 3; ++s)
+        if (kn[s + 1] - kn[s] != h) return false;
+    *spacing = h;
+    return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+DevSheet dev_sheet(const bsc_ctx *ctx) { return ctx->dev; }
+
+size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t ncp = c->n_cp, nmp = c->n_mp, nbe = c->n_be, ne = c->n_elem;
+    const int max_items = int(std::max(std::max(nmp, nbe), std::max(ncp, ne)));
+    // at least 256: the fixed-grid reductions (dot products, max-norm) launch 256 blocks
+    const int max_blocks = std::max(256, (max_items + kBlock - 1) / kBlock + 1);
+    DevBufs t{};
+    t.max_blocks = max_blocks;
+    t.mp_elem = (int32_t *)take(4 * nmp);
+    t.mp_off = (int32_t *)take(4 * (ne + 1));
+    t.mp_tu = (double *)take(8 * nmp);
+    t.mp_tv = (double *)take(8 * nmp);
+    t.mp_w = (double *)take(8 * nmp);
+    t.be_elem = (int32_t *)take(4 * nbe);
+    t.be_off = (int32_t *)take(4 * (ne + 1));
+    t.be_tu = (double *)take(8 * nbe);
+    t.be_tv = (double *)take(8 * nbe);
+    t.be_w = (double *)take(8 * nbe);
+    t.mass = (double *)take(8 * ncp);
+    t.hbend = (double *)take(8 * kSlots * ncp);
+    t.pinmask = (int32_t *)take(4 * ncp);
+    t.pin_idx = (int32_t *)take(4 * ncp);
+    t.ptA = take(8 * 21 * nmp);
+    t.ptP = take(8 * 6 * nmp);
+    t.ptE = (double *)take(8 * nmp);
+    t.ptP64 = (double *)take(8 * 6 * nmp);
+    t.beD = (double *)take(8 * 3 * nbe);
+    t.beE = (double *)take(8 * nbe);
+    t.partials = (double *)take(8 * 8 * size_t(max_blocks));
+    t.bsr_rowptr = (int32_t *)take(4 * (ncp + 1));
+    t.scalars = (double *)take(8 * 64);
+    t.iscalars = (int32_t *)take(4 * 64);
+    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.z, &t.p0, &t.p1, &t.q, &t.tmp};
+    for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
+    t.pinv = (double *)take(8 * 6 * ncp);
+    t.hess = take(8 * size_t(kHessEntries) * ncp);
+    t.net_w = (float *)take(4 * BSC_NET_PARAMS);
+    t.net_in = (float *)take(4 * 3 * ncp);
+    t.net_out = (float *)take(4 * 3 * ncp);
+    t.net_act0 = (float *)take(4 * 32 * ncp);
+    t.net_act1 = (float *)take(4 * 32 * ncp);
+    if (b) *b = t;
+    return off;
+}
+
+}  // namespace bsc
+
+using namespace bsc;
+
+extern "C" {
+
+const char *bsc_status_string(bsc_status s) {
+    switch (s) {
+        case BSC_OK: return "ok";
+        case BSC_E_INVAL: return "invalid argument";
+        case BSC_E_KNOTS: return "invalid knot vector";
+        case BSC_E_NOMEM: return "out of memory";
+        case BSC_E_HIP: return "HIP runtime error";
+        case BSC_E_NOT_CONVERGED: return "Newton did not converge";
+        case BSC_E_LINESEARCH: return "line search failed";
+        case BSC_E_NONFINITE: return "non-finite value";
+        case BSC_E_PCG_BREAKDOWN: return "PCG breakdown";
+        case BSC_E_STATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+const char *bsc_last_error(const bsc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void bsc_destroy(bsc_ctx *ctx) { delete ctx; }
+
+bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *knots_u, const double *knots_v,
+                      const double *rest_xy, const bsc_material *mat, void *hip_stream) {
+    if (!out) return BSC_E_INVAL;
+    *out = nullptr;
+    if (!knots_u || !knots_v || !rest_xy || !mat) return BSC_E_INVAL;
+    if (n_u < 5 || n_v < 5 || n_u > 32768 || n_v > 32768 || int64_t(n_u) * n_v > (int64_t(1) << 28))
+        return BSC_E_INVAL;
+    double hu = 0, hv = 0;
+    if (!knots_ok(knots_u, n_u, &hu) || !knots_ok(knots_v, n_v, &hv)) return BSC_E_KNOTS;
+    if (mat->membrane == BSC_MEMBRANE_STVK) {
+        if (!(mat->young >= 0.0) || !(mat->thickness > 0.0) || !(mat->poisson > -1.0 && mat->poisson < 0.5))
+            return BSC_E_INVAL;
+    } else if (mat->membrane == BSC_MEMBRANE_FBW) {
+        if (!(mat->mu_st1 >= 0.0 && mat->mu_st2 >= 0.0 && mat->mu_sh >= 0.0)) return BSC_E_INVAL;
+    } else {
+        return BSC_E_INVAL;
+    }
+    if (!(mat->mu_bend >= 0.0) || !(mat->rho_area > 0.0)) return BSC_E_INVAL;
+    for (int64_t a = 0; a < 2 * int64_t(n_u) * n_v; ++a)
+        if (!std::isfinite(rest_xy[a])) return BSC_E_INVAL;
+
+    bsc_ctx *c = new (std::nothrow) bsc_ctx;
+    if (!c) return BSC_E_NOMEM;
+    c->n_u = n_u; c->n_v = n_v; c->Nu = n_u - 2; c->Nv = n_v - 2;
+    c->n_cp = n_u * n_v; c->n_elem = c->Nu * c->Nv;
+    c->mat = *mat;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+
+    // The rest map X(u,v) = sum N_a X^a is affine iff the CPs are an affine image of the
+    // Greville abscissae (linear precision); read A and b off three corners and verify.
+    auto R = [&](int i, int j, int comp) { return rest_xy[2 * (int64_t(j) * n_u + i) + comp]; };
+    const int Nu = c->Nu, Nv = c->Nv;
+    double A[2][2], b[2];
+    for (int comp = 0; comp < 2; ++comp) {
+        b[comp] = R(0, 0, comp);
+        A[comp][0] = (R(n_u - 1, 0, comp) - b[comp]) / Nu;
+        A[comp][1] = (R(0, n_v - 1, comp) - b[comp]) / Nv;
+    }
+    double ext = std::fabs(A[0][0]) * Nu + std::fabs(A[0][1]) * Nv + std::fabs(A[1][0]) * Nu + std::fabs(A[1][1]) * Nv;
+    for (int j = 0; j < n_v; ++j)
+        for (int i = 0; i < n_u; ++i)
+            for (int comp = 0; comp < 2; ++comp) {
+                double want = A[comp][0] * greville(i, n_u) + A[comp][1] * greville(j, n_v) + b[comp];
+                if (std::fabs(R(i, j, comp) - want) > 1e-12 * ext) {
+                    c->err = "rest shape is not an affine image of the Greville grid (unsupported)";
+                    bsc_status st = BSC_E_INVAL;
+                    delete c;
+                    return st;
+                }
+            }
+    const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    if (!(det > 0.0)) { delete c; return BSC_E_INVAL; }
+    const double K[2][2] = {{A[1][1] / det, -A[0][1] / det}, {-A[1][0] / det, A[0][0] / det}};
+
+    // quadrature tables
+    fill_tables(membrane_points(Nu, Nv), Nu, c->n_elem, det, c->mp_elem, c->mp_off, c->mp_tu, c->mp_tv, c->mp_w);
+    fill_tables(bending_points(Nu, Nv), Nu, c->n_elem, det, c->be_elem, c->be_off, c->be_tu, c->be_tv, c->be_w);
+    c->n_mp = int(c->mp_elem.size());
+    c->n_be = int(c->be_elem.size());
+
+    // Laplacian in parametric space for an affine rest: only the second-derivative terms remain.
+    const double c_uu = K[0][0] * K[0][0] + K[0][1] * K[0][1];
+    const double c_vv = K[1][0] * K[1][0] + K[1][1] * K[1][1];
+    const double c_uv = 2.0 * (K[0][0] * K[1][0] + K[0][1] * K[1][1]);
+
+    // Lumped mass: row sums of the consistent mass = int rho N_a dX (partition of unity),
+    // factorised for the affine rest as rho |det A| (int N_i du)(int N_j dv), 3-point Gauss.
+    auto integrals = [&](int n, int N) {
+        std::vector<double> m(n, 0.0);
+        const double o3[3] = {-kG3, 0.0, kG3}, w3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+        for (int k = 0; k < N; ++k) {
+            double Nv3[3], D[3], D2[3];
+            for (int g = 0; g < 3; ++g) {
+                pieces(span_type(k, N), 0.5 + o3[g], Nv3, D, D2);
+                for (int a = 0; a < 3; ++a) m[k + a] += w3[g] * Nv3[a];
+            }
+        }
+        return m;
+    };
+    std::vector<double> mu1 = integrals(n_u, Nu), mv1 = integrals(n_v, Nv);
+    c->mass.assign(c->n_cp, 0.0);
+    for (int j = 0; j < n_v; ++j)
+        for (int i = 0; i < n_u; ++i) c->mass[j * n_u + i] = mat->rho_area * det * mu1[i] * mv1[j];
+
+    // Constant bending Hessian: scalar stencil h[s][a] = sum over evaluations of
+    // w mu L_a L_b for the upper-stencil slot s linking CP a to CP b (the 3x3 block is h I).
+    c->hbend.assign(size_t(kSlots) * c->n_cp, 0.0);
+    for (int q = 0; q < c->n_be; ++q) {
+        const int e = c->be_elem[q], k = e % Nu, l = e / Nu;
+        double Nu3[3], Du[3], D2u[3], Nv3[3], Dv[3], D2v[3];
+        pieces(span_type(k, Nu), c->be_tu[q], Nu3, Du, D2u);
+        pieces(span_type(l, Nv), c->be_tv[q], Nv3, Dv, D2v);
+        double L[9];
+        for (int bb = 0; bb < 3; ++bb)
+            for (int aa = 0; aa < 3; ++aa)
+                L[3 * bb + aa] = c_uu * D2u[aa] * Nv3[bb] + c_vv * Nu3[aa] * D2v[bb] + c_uv * Du[aa] * Dv[bb];
+        const double wm = c->be_w[q] * mat->mu_bend;
+        for (int m = 0; m < 9; ++m)
+            for (int n = 0; n < 9; ++n) {
+                const int di = n % 3 - m % 3, dj = n / 3 - m / 3;
+                const int s = upper_slot(di, dj);
+                if (s < 0) continue;
+                const int a = (l + m / 3) * n_u + (k + m % 3);
+                c->hbend[size_t(s) * c->n_cp + a] += wm * L[m] * L[n];
+            }
+    }
+
+    DevSheet &S = c->dev;
+    S.n_u = n_u; S.n_v = n_v; S.Nu = Nu; S.Nv = Nv; S.n_cp = c->n_cp; S.n_elem = c->n_elem;
+    S.n_mp = c->n_mp; S.n_be = c->n_be;
+    S.A00 = A[0][0]; S.A01 = A[0][1]; S.A10 = A[1][0]; S.A11 = A[1][1]; S.b0 = b[0]; S.b1 = b[1];
+    S.K00 = K[0][0]; S.K01 = K[0][1]; S.K10 = K[1][0]; S.K11 = K[1][1];
+    S.c_uu = c_uu; S.c_vv = c_vv; S.c_uv = c_uv;
+    S.membrane = mat->membrane;
+    S.mu = mat->young * mat->thickness / (2.0 * (1.0 + mat->poisson));
+    S.lam = mat->young * mat->thickness * mat->poisson / (1.0 - mat->poisson * mat->poisson);
+    S.mu1 = mat->mu_st1; S.mu2 = mat->mu_st2; S.msh = mat->mu_sh;
+    S.mu_bend = mat->mu_bend;
+    (void)hu; (void)hv;
+    *out = c;
+    return BSC_OK;
+}
+
+bsc_status bsc_sizes(const bsc_ctx *c, int32_t *n_cp, int32_t *n_elem, int32_t *n_mp, int32_t *n_be) {
+    if (!c) return BSC_E_INVAL;
+    if (n_cp) *n_cp = c->n_cp;
+    if (n_elem) *n_elem = c->n_elem;
+    if (n_mp) *n_mp = c->n_mp;
+    if (n_be) *n_be = c->n_be;
+    return BSC_OK;
+}
+
+bsc_status bsc_workspace_size(const bsc_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return BSC_E_INVAL;
+    *bytes = layout_workspace(c, nullptr, nullptr);
+    return BSC_OK;
+}
+
+bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
+    if (!c || !d_ws) return BSC_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(c, BSC_E_INVAL, "workspace must be 256-byte aligned");
+    const size_t need = layout_workspace(c, nullptr, nullptr);
+    if (bytes < need) return fail(c, BSC_E_NOMEM, "workspace too small");
+    c->ws = (char *)d_ws;
+    c->ws_bytes = bytes;
+    layout_workspace(c, &c->buf, c->ws);
+    DevBufs &B = c->buf;
+    struct Up { void *dst; const void *src; size_t n; } ups[] = {
+        {B.mp_elem, c->mp_elem.data(), 4 * c->mp_elem.size()}, {B.mp_off, c->mp_off.data(), 4 * c->mp_off.size()},
+        {B.mp_tu, c->mp_tu.data(), 8 * c->mp_tu.size()}, {B.mp_tv, c->mp_tv.data(), 8 * c->mp_tv.size()},
+        {B.mp_w, c->mp_w.data(), 8 * c->mp_w.size()},
+        {B.be_elem, c->be_elem.data(), 4 * c->be_elem.size()}, {B.be_off, c->be_off.data(), 4 * c->be_off.size()},
+        {B.be_tu, c->be_tu.data(), 8 * c->be_tu.size()}, {B.be_tv, c->be_tv.data(), 8 * c->be_tv.size()},
+        {B.be_w, c->be_w.data(), 8 * c->be_w.size()},
+        {B.mass, c->mass.data(), 8 * c->mass.size()}, {B.hbend, c->hbend.data(), 8 * c->hbend.size()},
+    };
+    for (const Up &u : ups) {
+        bsc_status st = hip_check(c, hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, c->stream), "upload tables");
+        if (st != BSC_OK) return st;
+    }
+    bsc_status st = hip_check(c, hipMemsetAsync(B.pinmask, 0, 4 * size_t(c->n_cp), c->stream), "clear pins");
+    if (st != BSC_OK) return st;
+    std::vector<int32_t> rowptr(c->n_cp + 1);
+    int32_t nnzb = 0;
+    bsc_bsr_pattern(c, rowptr.data(), nullptr, &nnzb);
+    st = hip_check(c, hipMemcpyAsync(B.bsr_rowptr, rowptr.data(), 4 * rowptr.size(), hipMemcpyHostToDevice, c->stream), "upload pattern");
+    if (st != BSC_OK) return st;
+    st = hip_check(c, hipMemsetAsync(B.iscalars, 0, 4 * 64, c->stream), "clear scalars");
+    if (st != BSC_OK) return st;
+    st = hip_check(c, hipStreamSynchronize(c->stream), "bind workspace");
+    if (st != BSC_OK) return st;
+    c->pins.clear();
+    c->net_loaded = false;
+    DevSheet &S = c->dev;
+    S.mp_elem = B.mp_elem; S.mp_off = B.mp_off; S.mp_tu = B.mp_tu; S.mp_tv = B.mp_tv; S.mp_w = B.mp_w;
+    S.be_elem = B.be_elem; S.be_off = B.be_off; S.be_tu = B.be_tu; S.be_tv = B.be_tv; S.be_w = B.be_w;
+    S.mass = B.mass; S.hbend = B.hbend; S.pinmask = B.pinmask;
+    return BSC_OK;
+}
+
+bsc_status bsc_set_pins(bsc_ctx *c, const int32_t *idx, int32_t n) {
+    if (!c) return BSC_E_INVAL;
+    if (!c->ws) return fail(c, BSC_E_STATE, "bind a workspace before setting pins");
+    if (n < 0 || n > c->n_cp || (n > 0 && !idx)) return fail(c, BSC_E_INVAL, "bad pin list");
+    std::vector<int32_t> mask(c->n_cp, 0);
+    for (int a = 0; a < n; ++a) {
+        if (idx[a] < 0 || idx[a] >= c->n_cp) return fail(c, BSC_E_INVAL, "pin index out of range");
+        if (mask[idx[a]]) return fail(c, BSC_E_INVAL, "duplicate pin index");
+        mask[idx[a]] = 1;
+    }
+    bsc_status st = hip_check(c, hipMemcpyAsync(c->buf.pinmask, mask.data(), 4 * size_t(c->n_cp), hipMemcpyHostToDevice, c->stream), "upload pins");
+    if (st != BSC_OK) return st;
+    if (n > 0) {
+        st = hip_check(c, hipMemcpyAsync(c->buf.pin_idx, idx, 4 * size_t(n), hipMemcpyHostToDevice, c->stream), "upload pins");
+        if (st != BSC_OK) return st;
+    }
+    st = hip_check(c, hipStreamSynchronize(c->stream), "set pins");
+    if (st != BSC_OK) return st;
+    c->pins.assign(idx, idx + n);
+    return BSC_OK;
+}
+
+bsc_status bsc_bsr_pattern(const bsc_ctx *c, int32_t *row_ptr, int32_t *col_idx, int32_t *nnzb) {
+    if (!c || !nnzb) return BSC_E_INVAL;
+    int32_t cnt = 0;
+    for (int j = 0; j < c->n_v; ++j)
+        for (int i = 0; i < c->n_u; ++i) {
+            if (row_ptr) row_ptr[j * c->n_u + i] = cnt;
+            for (int jb = std::max(0, j - 2); jb <= std::min(c->n_v - 1, j + 2); ++jb)
+                for (int ib = std::max(0, i - 2); ib <= std::min(c->n_u - 1, i + 2); ++ib) {
+                    if (col_idx) col_idx[cnt] = jb * c->n_u + ib;
+                    ++cnt;
+                }
+        }
+    if (row_ptr) row_ptr[c->n_cp] = cnt;
+    *nnzb = cnt;
+    return BSC_OK;
+}
+
+}  // extern "C"

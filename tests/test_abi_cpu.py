@@ -1,0 +1,129 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol include/bsc.h declares,
+and its host-only calls (create, validation, sizes, workspace, BSR pattern) behave as documented.
+No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from paper_2506_18867_amd import bsc
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bsc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    decl = r"^(?:bsc_status|const char \*|void)\s*\*?\s*(bsc_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bsc.load()
+    names = declared_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(bsc.exported_symbols()) == set(names)
+
+
+def _create(n_u, n_v, ku, kv, rest, mat=None):
+    lib = bsc.load()
+    mat = mat or bsc.make_material(0, 1e4, 0.3, 1e-3, mu_bend=1e-6, rho_area=0.2)
+    h = ctypes.c_void_p()
+    ku = np.ascontiguousarray(ku, dtype=np.float64)
+    kv = np.ascontiguousarray(kv, dtype=np.float64)
+    rest = np.ascontiguousarray(rest, dtype=np.float64).reshape(-1)
+    st = lib.bsc_create(ctypes.byref(h), n_u, n_v, bsc._np_ptr(ku), bsc._np_ptr(kv), bsc._np_ptr(rest),
+                        ctypes.byref(mat), None)
+    return st, h
+
+
+def test_create_sizes_match_quadrature_counts():
+    lib = bsc.load()
+    for n_u, n_v in [(5, 5), (7, 7), (20, 20), (9, 6)]:
+        ku, kv, rest = syn.flat_sheet(n_u, n_v)
+        st, h = _create(n_u, n_v, ku, kv, rest)
+        assert st == 0
+        s = [ctypes.c_int32() for _ in range(4)]
+        assert lib.bsc_sizes(h, *[ctypes.byref(v) for v in s]) == 0
+        n_cp, n_elem, n_mp, n_be = [v.value for v in s]
+        Nu, Nv = n_u - 2, n_v - 2
+        assert n_cp == n_u * n_v and n_elem == Nu * Nv
+        if Nu == Nv:
+            N = Nu
+            assert n_mp == 36 + 24 * (N - 2) + 2 * (N - 3) ** 2 + 8 * (N - 3) + 4
+        assert n_be == 4 * (Nu - 1) * (Nv - 1) + (Nu * Nv - (Nu - 2) * (Nv - 2))
+        sz = ctypes.c_size_t()
+        assert lib.bsc_workspace_size(h, ctypes.byref(sz)) == 0
+        assert sz.value > 114 * 8 * n_cp
+        lib.bsc_destroy(h)
+
+
+def test_create_rejects_bad_inputs():
+    lib = bsc.load()
+    ku, kv, rest = syn.flat_sheet(8)
+    bad = ku.copy()
+    bad[5] += 0.5
+    assert _create(8, 8, bad, kv, rest)[0] == -2                      # BSC_E_KNOTS
+    nonopen = np.arange(11, dtype=float)
+    assert _create(8, 8, nonopen, kv, rest)[0] == -2
+    ku4, kv4, rest4 = syn.flat_sheet(4)
+    assert _create(4, 4, ku4, kv4, rest4)[0] == -1                    # too few spans
+    curved = rest.copy()
+    curved[10] += 0.01
+    assert _create(8, 8, ku, kv, curved)[0] == -1                     # non-affine rest
+    flipped = rest.copy()
+    flipped[:, 0] *= -1
+    assert _create(8, 8, ku, kv, flipped)[0] == -1                    # det < 0
+    assert _create(8, 8, ku, kv, rest, bsc.make_material(0, 1e4, 0.6, 1e-3, rho_area=0.2))[0] == -1
+    assert _create(8, 8, ku, kv, rest, bsc.make_material(0, 1e4, 0.3, 1e-3, rho_area=0.0))[0] == -1
+    assert _create(8, 8, ku, kv, rest, bsc.make_material(7, 1e4, 0.3, 1e-3, rho_area=0.2))[0] == -1
+    nan_rest = rest.copy()
+    nan_rest[3, 1] = np.nan
+    assert _create(8, 8, ku, kv, nan_rest)[0] == -1
+
+
+def test_create_accepts_spacing_sheared_and_nonsquare():
+    ku, kv, rest = syn.flat_sheet(9, 6, 2.0, 0.7, spacing=3, shear=0.4)
+    st, h = _create(9, 6, ku, kv, rest)
+    assert st == 0
+    bsc.load().bsc_destroy(h)
+
+
+def test_calls_without_workspace_fail_cleanly():
+    lib = bsc.load()
+    ku, kv, rest = syn.flat_sheet(6)
+    st, h = _create(6, 6, ku, kv, rest)
+    assert st == 0
+    assert lib.bsc_set_pins(h, None, 0) == -9                          # BSC_E_STATE
+    assert lib.bsc_eval_egh(h, 0, None, None, None, None, None) == -9
+    assert lib.bsc_assemble(h, 0, None, None, 0.01, None, None, None, None) == -9
+    assert lib.bsc_spmv(h, 0, None, None, None) == -9
+    opts = bsc.make_opts()
+    assert lib.bsc_newton_step(h, ctypes.byref(opts), None, None, None, None) == -9
+    assert b"workspace" in lib.bsc_last_error(h)
+    lib.bsc_destroy(h)
+    assert lib.bsc_status_string(-6) == b"line search failed"
+
+
+def test_bsr_pattern_is_the_5x5_neighbourhood():
+    lib = bsc.load()
+    n_u, n_v = 7, 6
+    ku, kv, rest = syn.flat_sheet(n_u, n_v)
+    st, h = _create(n_u, n_v, ku, kv, rest)
+    nnzb = ctypes.c_int32()
+    assert lib.bsc_bsr_pattern(h, None, None, ctypes.byref(nnzb)) == 0
+    rp = np.zeros(n_u * n_v + 1, dtype=np.int32)
+    ci = np.zeros(nnzb.value, dtype=np.int32)
+    assert lib.bsc_bsr_pattern(h, bsc._np_ptr(rp), bsc._np_ptr(ci), ctypes.byref(nnzb)) == 0
+    want = []
+    for a in range(n_u * n_v):
+        i, j = a % n_u, a // n_u
+        row = sorted(jb * n_u + ib for jb in range(n_v) for ib in range(n_u) if abs(ib - i) <= 2 and abs(jb - j) <= 2)
+        assert list(ci[rp[a]:rp[a + 1]]) == row
+        want += row
+    assert nnzb.value == len(want) == (5 * n_u - 6) * (5 * n_v - 6)
+    lib.bsc_destroy(h)
