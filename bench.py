@@ -42,14 +42,23 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--noise", type=float, default=0.0, help="z-noise amplitude of the start state [m]")
+    p.add_argument("--stop", choices=["grad", "step"], default="step",
+                   help="grad: |g| <= rtol |g0|; step: |p|_inf / dt <= atol (the paper's rule)")
+    p.add_argument("--rtol", type=float, default=1e-6)
+    p.add_argument("--atol", type=float, default=1e-2)
+    p.add_argument("--max-newton", type=int, default=200)
+    p.add_argument("--pcg-rtol", type=float, default=1e-3)
+    p.add_argument("--grad-steps", type=int, default=2, help="steps of the |g|<=1e-6|g0| leg (0: skip)")
     return p.parse_args()
 
 
-def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch):
+def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
     """Runs `steps` implicit-Euler steps in place; returns (seconds, list of stats dicts)."""
     stats = []
-    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=1e-6,
-                         pcg_rtol=1e-3, max_newton=60, max_pcg=4000)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=args.rtol,
+                         atol=args.atol, stop_mode=bsc.BSC_STOP_GRAD if args.stop == "grad" else bsc.BSC_STOP_STEP,
+                         pcg_rtol=args.pcg_rtol, max_newton=args.max_newton, max_pcg=4000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -111,20 +120,35 @@ def main():
     from paper_2506_18867_amd import bsc
 
     torch.cuda.set_device(0)
-    sc = syn.driven_sheet(args.n, seed=args.seed)
+    sc = syn.driven_sheet(args.n, seed=args.seed, noise=args.noise)
     ctx = bsc.context_for_scene(sc)
     x0 = bsc.to_soa(sc.x0)
     v0 = bsc.to_soa(sc.v0)
 
     # warm-up + timed steps, FP32-mixed (headline)
     x, v = x0.clone(), v0.clone()
-    run_steps(ctx, sc, x, v, args.warmup, 0, bsc.BSC_FP32_MIXED, bsc, torch)
+    run_steps(ctx, sc, x, v, args.warmup, 0, bsc.BSC_FP32_MIXED, bsc, torch, args)
     xs, vs = x.clone(), v.clone()
-    sec32, st32 = run_steps(ctx, sc, x, v, args.steps, args.warmup, bsc.BSC_FP32_MIXED, bsc, torch)
+    sec32, st32 = run_steps(ctx, sc, x, v, args.steps, args.warmup, bsc.BSC_FP32_MIXED, bsc, torch, args)
     sec64, st64 = None, None
     if not args.no_fp64:
         x64, v64 = xs.clone(), vs.clone()
-        sec64, st64 = run_steps(ctx, sc, x64, v64, args.steps, args.warmup, bsc.BSC_FP64, bsc, torch)
+        sec64, st64 = run_steps(ctx, sc, x64, v64, args.steps, args.warmup, bsc.BSC_FP64, bsc, torch, args)
+
+    # the configs' gradient tolerance |g| <= 1e-6 |g0| on the first steps from the start state
+    grad_leg = None
+    if args.grad_steps > 0:
+        class _A:
+            pass
+        ga = _A()
+        ga.rtol, ga.atol, ga.stop, ga.pcg_rtol, ga.max_newton = 1e-6, args.atol, "grad", args.pcg_rtol, args.max_newton
+        grad_leg = {}
+        for name, prec in (("fp32_mixed", bsc.BSC_FP32_MIXED), ("fp64", bsc.BSC_FP64)):
+            xg, vg = x0.clone(), v0.clone()
+            secg, stg = run_steps(ctx, sc, xg, vg, args.grad_steps, 0, prec, bsc, torch, ga)
+            grad_leg[name] = {"ms_per_step": round(1e3 * secg / args.grad_steps, 3),
+                              "newton": [s["newton_iters"] for s in stg], "pcg": [s["pcg_iters_total"] for s in stg],
+                              "g_rel": [float("%.3g" % (s["g_norm"] / s["g0_norm"])) for s in stg]}
 
     # per-kernel timings at the current state (same stream as the library)
     n, ne = sc.n_cp, sc.n_elem
@@ -174,11 +198,17 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"driven sheet {args.n}x{args.n} CPs ({ne} elements), E=1e4 Pa, t=1 mm, dt=0.01 s, "
-                               f"|g|<=1e-6|g0|, FP32-mixed", "n_cp": n, "n_elem": ne, "seed": args.seed,
+                               + (f"|g|<={args.rtol:g}|g0|" if args.stop == "grad" else f"|p|inf/dt<={args.atol:g}")
+                               + ", FP32-mixed", "n_cp": n, "n_elem": ne, "seed": args.seed, "noise": args.noise,
                    "parallelism": "single GPU"},
         "newton_step_ms": {"fp32_mixed": round(ms_step32, 3),
                            "fp64": round(1e3 * sec64 / args.steps, 3) if sec64 else None},
         "speedup_vs_fp64": round(sec64 / sec32, 3) if sec64 else None,
+        "grad_tol_1e-6": grad_leg,
+        "per_step": {"newton_fp32": [s["newton_iters"] for s in st32], "pcg_fp32": [s["pcg_iters_total"] for s in st32],
+                     "halvings_fp32": [s["ls_halvings"] for s in st32],
+                     "g_rel_fp32": [float("%.3g" % (s["g_norm"] / s["g0_norm"])) for s in st32],
+                     "g_rel_fp64": [float("%.3g" % (s["g_norm"] / s["g0_norm"])) for s in st64] if st64 else None},
         "iters": {"newton_fp32": newton32, "pcg_fp32": pcg32,
                   "newton_fp64": sum(s["newton_iters"] for s in st64) if st64 else None,
                   "pcg_fp64": sum(s["pcg_iters_total"] for s in st64) if st64 else None},

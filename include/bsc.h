@@ -180,6 +180,14 @@ bsc_status bsc_export_bsr(bsc_ctx *ctx, int32_t precision, const void *d_hess, v
 bsc_status bsc_newton_step(bsc_ctx *ctx, const bsc_step_opts *opts, double *d_x, double *d_v,
                            const double *d_pin_targets, bsc_step_stats *stats);
 
+/* Sample log for training the warm start: while capacity > 0, every Newton iteration of
+ * bsc_newton_step appends its free-DOF gradient g and its PCG direction p (the solve of
+ * H p = -g at the step's pcg_rtol) as floats, SoA [c][a], at d_g + 3*n_cp*k and d_p + 3*n_cp*k
+ * for k = 0, 1, ... up to capacity samples. The caller owns both device buffers. capacity = 0
+ * disables logging. bsc_sample_log_count returns how many samples have been written. */
+bsc_status bsc_set_sample_log(bsc_ctx *ctx, float *d_g, float *d_p, int32_t capacity);
+bsc_status bsc_sample_log_count(const bsc_ctx *ctx, int32_t *count);
+
 /* Learned PCG warm start (a method extension; not in the paper). A bias-free 6-layer 3x3
  * convolutional net over the CP grid (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 channels, zero
  * padding, LeakyReLU(0.1) between layers) maps the normalised gradient g/rms(g) to a
@@ -208,11 +216,13 @@ bsc_status bsc_net_scratch_size(const bsc_ctx *ctx, int32_t batch, size_t *bytes
 bsc_status bsc_adam_step(bsc_ctx *ctx, int32_t n, float *d_param, const float *d_grad, float *d_m,
                          float *d_v, float lr, float beta1, float beta2, float eps, int32_t t);
 
-/* Training loss of the warm-start net for a batch: for each sample b,
- * L_b = 1 - (p_hat.p)^2 / (|p_hat|^2 |p|^2) (the relative error of the best scalar multiple of
- * p_hat against the solved step p); writes the mean loss (1 float) and dL/dp_hat. */
-bsc_status bsc_net_loss(bsc_ctx *ctx, int32_t batch, const float *d_pred, const float *d_target,
-                        float *d_loss, float *d_dpred);
+/* Training loss of the warm-start net for a batch: for each sample b, over the CPs where the
+ * network input d_in is not zero in all three components (pinned CPs have a zero gradient),
+ * L_b = 1 - (p_hat.p)^2 / (|p_hat|^2 |p|^2), the squared relative error of the best scalar
+ * multiple of p_hat against the solved step p. Writes the mean loss (1 float, device) and
+ * dL/dp_hat (B*3*n_cp floats, zero on masked CPs). */
+bsc_status bsc_net_loss(bsc_ctx *ctx, int32_t batch, const float *d_in, const float *d_pred,
+                        const float *d_target, float *d_loss, float *d_dpred);
 
 const char *bsc_status_string(bsc_status s);
 const char *bsc_last_error(const bsc_ctx *ctx);

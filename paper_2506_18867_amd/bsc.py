@@ -96,7 +96,9 @@ def load():
         "bsc_net_backward": [P, I32, P, P, P, P, P, P, P],
         "bsc_net_scratch_size": [P, I32, ctypes.POINTER(SZ)],
         "bsc_adam_step": [P, I32, P, P, P, P, F, F, F, F, I32],
-        "bsc_net_loss": [P, I32, P, P, P, P],
+        "bsc_net_loss": [P, I32, P, P, P, P, P],
+        "bsc_set_sample_log": [P, P, P, I32],
+        "bsc_sample_log_count": [P, ctypes.POINTER(I32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -116,7 +118,8 @@ def exported_symbols() -> list[str]:
     return ["bsc_create", "bsc_sizes", "bsc_workspace_size", "bsc_bind_workspace", "bsc_set_pins", "bsc_eval_egh",
             "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step",
             "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size", "bsc_adam_step",
-            "bsc_net_loss", "bsc_status_string", "bsc_last_error", "bsc_destroy"]
+            "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_status_string", "bsc_last_error",
+            "bsc_destroy"]
 
 
 def _ptr(t):
@@ -261,6 +264,14 @@ class Context:
             self._check(st, "bsc_newton_step")
         return st, stats
 
+    def bsc_set_sample_log(self, g_buf, p_buf, capacity):
+        self._check(self.lib.bsc_set_sample_log(self.h, _ptr(g_buf), _ptr(p_buf), int(capacity)), "bsc_set_sample_log")
+
+    def bsc_sample_log_count(self):
+        c = ctypes.c_int32()
+        self._check(self.lib.bsc_sample_log_count(self.h, ctypes.byref(c)), "bsc_sample_log_count")
+        return c.value
+
     def bsc_warmstart_load(self, weights):
         self._check(self.lib.bsc_warmstart_load(self.h, _ptr(weights), int(weights.numel())), "bsc_warmstart_load")
 
@@ -292,12 +303,12 @@ class Context:
         self._check(self.lib.bsc_adam_step(self.h, int(param.numel()), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
                                            lr, beta1, beta2, eps, int(t)), "bsc_adam_step")
 
-    def bsc_net_loss(self, pred, target):
+    def bsc_net_loss(self, inp, pred, target):
         import torch
         loss = torch.zeros(1, dtype=torch.float32, device=pred.device)
         dpred = torch.empty_like(pred)
-        self._check(self.lib.bsc_net_loss(self.h, pred.shape[0], _ptr(pred), _ptr(target), _ptr(loss), _ptr(dpred)),
-                    "bsc_net_loss")
+        self._check(self.lib.bsc_net_loss(self.h, pred.shape[0], _ptr(inp), _ptr(pred), _ptr(target), _ptr(loss),
+                                          _ptr(dpred)), "bsc_net_loss")
         return loss, dpred
 
 

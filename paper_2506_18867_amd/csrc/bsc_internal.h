@@ -73,10 +73,11 @@ struct DevBufs {
     double *scalars;                         // solver scalars (see solve.hip)
     int32_t *iscalars;
     // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
-    double *g, *xn, *xhat, *dir, *r, *z, *p0, *p1, *q, *pinv, *tmp;
+    double *g, *xn, *xhat, *dir, *r, *z, *p0, *p1, *q, *pinv, *tmp, *phat;
     void *hess;                              // kHessEntries n_cp doubles
     // warm-start network
-    float *net_w, *net_in, *net_out, *net_act0, *net_act1;
+    float *net_w, *net_w_fwd, *net_wr, *net_in, *net_out, *net_act0, *net_act1, *net_scale;
+    double *net_lpart;                        // loss partials: 1024 samples x 64 blocks x 3
     int max_blocks;
 };
 
@@ -98,6 +99,16 @@ struct bsc_ctx {
     bsc::DevBufs buf{};
     bool net_loaded = false;
     std::string err;
+    // replayable chunk of CG iterations (kernel arguments depend only on the workspace)
+    hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
+    bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
+    // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
+    float *log_g = nullptr, *log_p = nullptr;
+    int log_cap = 0, log_count = 0;
+    ~bsc_ctx() {
+        for (auto &g : cg_graph)
+            if (g) (void)hipGraphExecDestroy(g);
+    }
 };
 
 namespace bsc {
@@ -131,14 +142,14 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                        bsc_step_stats *stats);
 
 // ---- launchers (net.hip) ----
-hipError_t net_forward(int n_u, int n_v, int batch, const float *w, const float *in, float *out,
-                       float *acts, float *tmp0, float *tmp1, hipStream_t st);
+hipError_t net_forward_impl(int n_u, int n_v, int batch, const float *w, const float *in, float *out, float *acts,
+                            float *tmp0, float *tmp1, float *scale, float *wr, bool reordered, hipStream_t st);
 hipError_t net_backward(int n_u, int n_v, int batch, const float *w, const float *in, const float *acts,
                         const float *dout, float *dw, float *din, void *scratch, hipStream_t st);
 size_t net_scratch_bytes(int n_u, int n_v, int batch);
 hipError_t net_adam(int n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
                     float eps, int t, hipStream_t st);
-hipError_t net_loss(int n_cp, int batch, const float *pred, const float *tgt, float *loss, float *dpred,
-                    float *scratch, hipStream_t st);
+hipError_t net_loss(int n_cp, int batch, const float *in, const float *pred, const float *tgt, float *loss,
+                    float *dpred, double *part, hipStream_t st);
 
 }  // namespace bsc

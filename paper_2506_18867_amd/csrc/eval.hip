@@ -245,6 +245,213 @@ __device__ void project_psd(double A[6][6]) {
         }
 }
 
+// Structured projection. Both membrane models depend on F only through f1, f2, so in the
+// orthonormal frame (e1 = f1/|f1|, e3 = f1 x f2 / |f1 x f2|, e2 = e3 x e1) the 6x6 density
+// Hessian splits into a 4x4 in-plane block and a 2x2 block acting on the normal components
+// (for StVK the latter is exactly the second Piola stress S). Each block is projected on its
+// own (Cholesky test, then Jacobi for the 4x4, closed form for the 2x2) and rotated back. This
+// equals the projection of the full matrix; degenerate F (parallel columns) returns false.
+
+__device__ bool cholesky_pd4(const double A[4][4]) {
+    double L[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double d = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0.0)) return false;
+        const double ljj = sqrt(d), inv = 1.0 / ljj;
+        L[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < 4; ++i) {
+            double sm = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) sm -= L[i][k] * L[j][k];
+            L[i][j] = sm * inv;
+        }
+    }
+    return true;
+}
+
+__device__ void project_psd4(double A[4][4]) {
+    if (cholesky_pd4(A)) return;
+    double V[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) V[r][c] = (r == c) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, tot = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double a2 = A[r][c] * A[r][c];
+                tot += a2;
+                if (r != c) off += a2;
+            }
+        if (off <= 1e-32 * tot) break;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < 4; ++q) {
+                const double apq = A[p][q];
+                if (apq != 0.0) {
+                    const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double akp = A[k][p], akq = A[k][q];
+                        A[k][p] = c * akp - s * akq;
+                        A[k][q] = s * akp + c * akq;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double apk = A[p][k], aqk = A[q][k];
+                        A[p][k] = c * apk - s * aqk;
+                        A[q][k] = s * apk + c * aqk;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double vkp = V[k][p], vkq = V[k][q];
+                        V[k][p] = c * vkp - s * vkq;
+                        V[k][q] = s * vkp + c * vkq;
+                    }
+                }
+            }
+        }
+    }
+    double lam[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lam[r] = A[r][r] > 0.0 ? A[r][r] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = r; c < 4; ++c) {
+            double sm = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) sm += V[r][m] * lam[m] * V[c][m];
+            A[r][c] = sm;
+            A[c][r] = sm;
+        }
+}
+
+// Symmetric 2x2 [[a, b], [b, c]] projected to PSD in closed form.
+__device__ void project_psd2(double &a, double &b, double &c) {
+    const double h = 0.5 * (a - c), m = 0.5 * (a + c);
+    const double r = sqrt(h * h + b * b);
+    const double l1 = m + r, l2 = m - r;          // l1 >= l2
+    if (l2 >= 0.0) return;
+    if (l1 <= 0.0) { a = b = c = 0.0; return; }
+    // keep l1 v v^T, v the unit eigenvector of l1
+    double vx, vy;
+    if (h >= 0.0) { vx = h + r; vy = b; } else { vx = b; vy = r - h; }
+    const double nn = vx * vx + vy * vy;
+    if (nn == 0.0) { a = fmax(a, 0.0); c = fmax(c, 0.0); b = 0.0; return; }
+    const double k = l1 / nn;
+    a = k * vx * vx; b = k * vx * vy; c = k * vy * vy;
+}
+
+// Builds the projected 6x6 density Hessian of the membrane model at displacement gradient G
+// (double) into A. Returns false when f1 and f2 are (nearly) parallel.
+__device__ bool project_structured(const DevSheet &S, const double G[3][2], double A[6][6]) {
+    double f[2][3];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[g][i] = G[i][g] + ((i == g) ? 1.0 : 0.0);
+    const double l1 = sqrt(f[0][0] * f[0][0] + f[0][1] * f[0][1] + f[0][2] * f[0][2]);
+    double n[3] = {f[0][1] * f[1][2] - f[0][2] * f[1][1], f[0][2] * f[1][0] - f[0][0] * f[1][2], f[0][0] * f[1][1] - f[0][1] * f[1][0]};
+    const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double l2 = sqrt(f[1][0] * f[1][0] + f[1][1] * f[1][1] + f[1][2] * f[1][2]);
+    if (!(l1 > 0.0) || !(ln > 1e-8 * l1 * l2)) return false;
+    double e[3][3];                                 // e[0] = e1, e[1] = e2, e[2] = e3
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { e[0][i] = f[0][i] / l1; e[2][i] = n[i] / ln; }
+    e[1][0] = e[2][1] * e[0][2] - e[2][2] * e[0][1];
+    e[1][1] = e[2][2] * e[0][0] - e[2][0] * e[0][2];
+    e[1][2] = e[2][0] * e[0][1] - e[2][1] * e[0][0];
+    // in-plane components: F2[i][g] = f_g . e_i (i, g in {0,1}); f1 . e2 = 0
+    double F2[2][2];
+    F2[0][0] = l1; F2[1][0] = 0.0;
+    F2[0][1] = f[1][0] * e[0][0] + f[1][1] * e[0][1] + f[1][2] * e[0][2];
+    F2[1][1] = ln / l1;
+    double P4[4][4], Na, Nb, Nc;                    // P4 index 2*gamma + i
+    if (S.membrane == BSC_MEMBRANE_STVK) {
+        double E[2][2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                E[g][d] = 0.5 * (G[g][d] + G[d][g] + G[0][g] * G[0][d] + G[1][g] * G[1][d] + G[2][g] * G[2][d]);
+        const double tr = E[0][0] + E[1][1];
+        const double Sm[2][2] = {{2.0 * S.mu * E[0][0] + S.lam * tr, 2.0 * S.mu * E[0][1]},
+                                 {2.0 * S.mu * E[1][0], 2.0 * S.mu * E[1][1] + S.lam * tr}};
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const double ff = F2[i][0] * F2[j][0] + F2[i][1] * F2[j][1];
+                        P4[2 * g + i][2 * d + j] = (i == j ? Sm[g][d] : 0.0) + S.mu * F2[i][d] * F2[j][g] +
+                                                   (g == d ? S.mu * ff : 0.0) + S.lam * F2[i][g] * F2[j][d];
+                    }
+        Na = Sm[0][0]; Nb = Sm[0][1]; Nc = Sm[1][1];
+    } else {
+        const double mus[2] = {S.mu1, S.mu2};
+        double len[2], q[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const double i5m1 = 2.0 * G[g][g] + G[0][g] * G[0][g] + G[1][g] * G[1][g] + G[2][g] * G[2][g];
+            len[g] = sqrt(1.0 + i5m1);
+            q[g] = (i5m1 / (len[g] + 1.0)) / len[g];          // 1 - 1/|f_g|
+        }
+        const double I6 = F2[0][0] * F2[0][1] + F2[1][0] * F2[1][1];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        double a;
+                        if (g == d) {
+                            a = 2.0 * S.msh * F2[i][1 - g] * F2[j][1 - g] +
+                                2.0 * mus[g] * ((i == j ? q[g] : 0.0) + F2[i][g] * F2[j][g] / (len[g] * len[g] * len[g]));
+                        } else {
+                            a = 2.0 * S.msh * (F2[i][d] * F2[j][g] + (i == j ? I6 : 0.0));
+                        }
+                        P4[2 * g + i][2 * d + j] = a;
+                    }
+        Na = 2.0 * mus[0] * q[0]; Nb = 2.0 * S.msh * I6; Nc = 2.0 * mus[1] * q[1];
+    }
+    project_psd4(P4);
+    project_psd2(Na, Nb, Nc);
+    const double N2[2][2] = {{Na, Nb}, {Nb, Nc}};
+    // rotate back: A[(g,i),(d,j)] = sum_{a,b<2} e_a[i] P4[(g,a),(d,b)] e_b[j] + N[g][d] e3[i] e3[j]
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double v = N2[g][d] * e[2][i] * e[2][j];
+#pragma unroll
+                    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb) v += e[aa][i] * P4[2 * g + aa][2 * d + bb] * e[bb][j];
+                    A[3 * g + i][3 * d + j] = v;
+                }
+    return true;
+}
+
 // Gradient w.r.t. X of the 9 local basis functions at span coordinates (tu, tv).
 template <typename T>
 __device__ __forceinline__ void local_grads(const DevSheet &S, int k, int l, T tu, T tv, T dN[9][2]) {
@@ -329,7 +536,12 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
             for (int r = 0; r < 6; ++r)
 #pragma unroll
                 for (int c = 0; c < 6; ++c) Ad[r][c] = 0.5 * (double(A[r][c]) + double(A[c][r]));
-            project_psd(Ad);
+            if (!cholesky_pd(Ad)) {
+                double Gd[3][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { Gd[c][0] = double(G[c][0]); Gd[c][1] = double(G[c][1]); }
+                if (!project_structured(S, Gd, Ad)) project_psd(Ad);
+            }
 #pragma unroll
             for (int r = 0; r < 6; ++r)
 #pragma unroll

@@ -5,6 +5,7 @@
 // that are not solver calls.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -164,7 +165,8 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     const size_t ncp = c->n_cp, nmp = c->n_mp, nbe = c->n_be, ne = c->n_elem;
     const int max_items = int(std::max(std::max(nmp, nbe), std::max(ncp, ne)));
     // at least 256: the fixed-grid reductions (dot products, max-norm) launch 256 blocks
-    const int max_blocks = std::max(256, (max_items + kBlock - 1) / kBlock + 1);
+    // also >= the SpMV grid (64 rows per block)
+    const int max_blocks = std::max(256, std::max((max_items + kBlock - 1) / kBlock + 1, int(ncp / 64) + 2));
     DevBufs t{};
     t.max_blocks = max_blocks;
     t.mp_elem = (int32_t *)take(4 * nmp);
@@ -191,15 +193,19 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.bsr_rowptr = (int32_t *)take(4 * (ncp + 1));
     t.scalars = (double *)take(8 * 64);
     t.iscalars = (int32_t *)take(4 * 64);
-    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.z, &t.p0, &t.p1, &t.q, &t.tmp};
+    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.z, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat};
     for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
     t.pinv = (double *)take(8 * 6 * ncp);
     t.hess = take(8 * size_t(kHessEntries) * ncp);
     t.net_w = (float *)take(4 * BSC_NET_PARAMS);
+    t.net_w_fwd = (float *)take(4 * BSC_NET_PARAMS);
+    t.net_wr = (float *)take(4 * BSC_NET_PARAMS);
     t.net_in = (float *)take(4 * 3 * ncp);
     t.net_out = (float *)take(4 * 3 * ncp);
     t.net_act0 = (float *)take(4 * 32 * ncp);
     t.net_act1 = (float *)take(4 * 32 * ncp);
+    t.net_scale = (float *)take(4 * 1024);
+    t.net_lpart = (double *)take(8 * 1024 * 64 * 3);
     if (b) *b = t;
     return off;
 }
@@ -257,6 +263,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     c->n_cp = n_u * n_v; c->n_elem = c->Nu * c->Nv;
     c->mat = *mat;
     c->stream = (hipStream_t)hip_stream;
+    if (const char *ng = std::getenv("BSC_NO_GRAPHS")) c->use_graphs = !(ng[0] == '1');
     if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
 
     // The rest map X(u,v) = sum N_a X^a is affine iff the CPs are an affine image of the
@@ -404,6 +411,10 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     if (st != BSC_OK) return st;
     c->pins.clear();
     c->net_loaded = false;
+    c->log_g = c->log_p = nullptr;
+    c->log_cap = c->log_count = 0;
+    for (auto &g : c->cg_graph)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     DevSheet &S = c->dev;
     S.mp_elem = B.mp_elem; S.mp_off = B.mp_off; S.mp_tu = B.mp_tu; S.mp_tv = B.mp_tv; S.mp_w = B.mp_w;
     S.be_elem = B.be_elem; S.be_off = B.be_off; S.be_tu = B.be_tu; S.be_tv = B.be_tv; S.be_w = B.be_w;
@@ -430,6 +441,22 @@ bsc_status bsc_set_pins(bsc_ctx *c, const int32_t *idx, int32_t n) {
     st = hip_check(c, hipStreamSynchronize(c->stream), "set pins");
     if (st != BSC_OK) return st;
     c->pins.assign(idx, idx + n);
+    return BSC_OK;
+}
+
+bsc_status bsc_set_sample_log(bsc_ctx *c, float *d_g, float *d_p, int32_t capacity) {
+    if (!c) return BSC_E_INVAL;
+    if (capacity < 0 || (capacity > 0 && (!d_g || !d_p))) return fail(c, BSC_E_INVAL, "bad sample log");
+    c->log_g = d_g;
+    c->log_p = d_p;
+    c->log_cap = capacity;
+    c->log_count = 0;
+    return BSC_OK;
+}
+
+bsc_status bsc_sample_log_count(const bsc_ctx *c, int32_t *count) {
+    if (!c || !count) return BSC_E_INVAL;
+    *count = c->log_count;
     return BSC_OK;
 }
 

@@ -1,13 +1,14 @@
 // solve.hip -- projected-Newton minimisation of the incremental potential (Sec. 3.2, Sec. 5.1)
 // with a hand-written block-Jacobi PCG on the upper-stencil Hessian.
 //
-// SpMV: one thread per CP row; the 13 stored blocks of the row (diagonal + upper offsets) are
-// read at the row's own index in 114 coalesced planes, and the 12 lower blocks are the
-// transposes of the upper blocks stored at the neighbour rows a - d_s (also coalesced).
-// PCG: two kernels per iteration. Scalars (alpha, beta, r.z, ...) live in device memory; the
-// last block of each kernel (a device-scope counter) finishes the dot products from per-block
-// partial sums in a fixed order, so results are deterministic and the host only polls a
-// convergence flag every few iterations.
+// SpMV: tiles of 64 rows, 8 waves per tile, each wave one group of the row's 25 block
+// products; the 13 stored blocks of a row (diagonal + upper offsets) are read at the row's own
+// index in 114 coalesced planes, the 12 lower blocks are the transposes of the upper blocks
+// stored at the neighbour rows a - d_s (also coalesced, usually from the same XCD's L2).
+// PCG (Chronopoulos-Gear form): two kernels per iteration, an SpMV that also emits per-block
+// partial dot products and a vector update whose blocks all re-sum those partials in the same
+// fixed order. Scalars live in device memory, nothing uses atomics or in-kernel fences, results
+// are deterministic, and the host only polls a convergence flag every few iterations.
 // Line search: the energy difference E(x + alpha p) - E(x) is evaluated in double without
 // forming the two energies: the inertia, gravity and bending terms are exact quadratics in
 // alpha (coefficients computed once), and each membrane point evaluates Psi(F + alpha dF) -
@@ -22,8 +23,12 @@ namespace {
 
 inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_TOL2, S_BB, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_WS_NUM, S_WS_DEN, S_WS_RR };
-enum { I_DONE = 0, I_ITERS, I_BREAK, I_CNT_A, I_CNT_B, I_CNT_C, I_MAXIT };
+enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_WS0, S_WS1, S_WS2, S_WS3 };
+enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
+
+constexpr int kRowsPerTile = 64;     // one wave of rows per SpMV block
+constexpr int kGroups = 8;           // waves per SpMV block, one group of block products each
+constexpr int kReduceBlocks = 256;   // grid of the fixed-grid reductions
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -40,81 +45,144 @@ __device__ double block_sum(double v, double *sh) {
     const int nw = (blockDim.x + 63) >> 6;
     v = (int(threadIdx.x) < nw) ? sh[threadIdx.x] : 0.0;
     if (wid == 0) v = wave_sum(v);
-    return v;
+    return v;          // valid in thread 0
 }
 
-// Publishes this block's partial sums and reports whether it is the last block to finish.
-// The release/acquire pair at agent scope orders the partial stores before the counter.
-__device__ bool publish_last(double *partials, int stride, const double *vals, int nvals, int32_t *counter) {
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        for (int t = 0; t < nvals; ++t) partials[t * stride + blockIdx.x] = vals[t];
-        const int prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == int(gridDim.x) - 1);
+// Every block of a kernel re-sums the partials of the previous kernel in the same order, so
+// all blocks obtain bitwise-identical scalars without atomics or fences; the result is
+// broadcast to the whole block.
+__device__ double sum_partials(const double *p, int n, double *sh, double *bcast) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v += p[t];
+    v = block_sum(v, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) *bcast = v;
+    __syncthreads();
+    return *bcast;
+}
+
+// Block-wide sums of three values at once (one LDS round trip); valid in every thread.
+__device__ void block_sum3(double v[3], double *sh /* 3 * 16 */) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[16 * k + wid] = v[k];
     }
     __syncthreads();
-    return last;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += sh[16 * k + q];
+        v[k] = t;
+    }
 }
 
-// In the last block: ordered sum of one partial array (coherent loads).
-__device__ double gather_sum(const double *partials, int n, double *sh) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x)
-        v += __hip_atomic_load(partials + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum(v, sh);
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every
+// XCD a contiguous range of row tiles so that the neighbour rows a - d_s (whose stored upper
+// blocks the lower products read) are usually in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + k;
 }
 
 // ---- SpMV ------------------------------------------------------------------------------------
 
-// y_a = sum_b H_ab p_b with p given by a functor (so PCG can form p = z + beta p_old on the fly).
-template <typename T, typename PF>
-__device__ __forceinline__ void row_product(const DevSheet &S, const T *__restrict__ H, int a, PF pf, double y[3]) {
+// One of the 25 block products of row a: 0 = diagonal, 1..12 = upper slot s (block stored at
+// row a), 13..24 = lower slot s - 12 (transpose of the block stored at row a - d_s).
+template <typename T>
+__device__ __forceinline__ void block_product(const DevSheet &S, const T *__restrict__ H, const double *__restrict__ u,
+                                              int a, int i, int j, int pid, T acc[3]) {
     const size_t n = S.n_cp;
-    const int i = a % S.n_u, j = a / S.n_u;
-    T pa[3];
-    pf(a, pa);
-    const T d0 = H[0 * n + a], d1 = H[1 * n + a], d2 = H[2 * n + a], d3 = H[3 * n + a], d4 = H[4 * n + a], d5 = H[5 * n + a];
-    T acc0 = d0 * pa[0] + d1 * pa[1] + d2 * pa[2];
-    T acc1 = d1 * pa[0] + d3 * pa[1] + d4 * pa[2];
-    T acc2 = d2 * pa[0] + d4 * pa[1] + d5 * pa[2];
-#pragma unroll
-    for (int s = 1; s < kSlots; ++s) {
-        const int di = kSlotDi[s], dj = kSlotDj[s], e0 = slot_entry(s);
+    if (pid == 0) {
+        const T u0 = T(u[a]), u1 = T(u[n + a]), u2 = T(u[2 * n + a]);
+        const T d0 = H[a], d1 = H[n + a], d2 = H[2 * n + a], d3 = H[3 * n + a], d4 = H[4 * n + a], d5 = H[5 * n + a];
+        acc[0] += d0 * u0 + d1 * u1 + d2 * u2;
+        acc[1] += d1 * u0 + d3 * u1 + d4 * u2;
+        acc[2] += d2 * u0 + d4 * u1 + d5 * u2;
+        return;
+    }
+    const bool upper = pid <= 12;
+    const int s = upper ? pid : pid - 12;
+    const int di = kSlotDi[s], dj = kSlotDj[s], e0 = slot_entry(s);
+    if (upper) {
         const int ib = i + di, jb = j + dj;
-        if (ib >= 0 && ib < S.n_u && jb < S.n_v) {          // upper block (a, a + d)
-            const int b = jb * S.n_u + ib;
-            T pb[3];
-            pf(b, pb);
+        if (ib < 0 || ib >= S.n_u || jb >= S.n_v) return;
+        const int b = jb * S.n_u + ib;
+        const T u0 = T(u[b]), u1 = T(u[n + b]), u2 = T(u[2 * n + b]);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const T v = H[(e0 + 3 * r) * n + a] * pb[0] + H[(e0 + 3 * r + 1) * n + a] * pb[1] + H[(e0 + 3 * r + 2) * n + a] * pb[2];
-                if (r == 0) acc0 += v; else if (r == 1) acc1 += v; else acc2 += v;
-            }
-        }
+        for (int r = 0; r < 3; ++r)
+            acc[r] += H[(e0 + 3 * r) * n + a] * u0 + H[(e0 + 3 * r + 1) * n + a] * u1 + H[(e0 + 3 * r + 2) * n + a] * u2;
+    } else {
         const int ic = i - di, jc = j - dj;
-        if (ic >= 0 && ic < S.n_u && jc >= 0) {             // lower block = (block (a - d, a))^T
-            const int b = jc * S.n_u + ic;
-            T pb[3];
-            pf(b, pb);
+        if (ic < 0 || ic >= S.n_u || jc < 0) return;
+        const int b = jc * S.n_u + ic;
+        const T u0 = T(u[b]), u1 = T(u[n + b]), u2 = T(u[2 * n + b]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T v = H[(e0 + c) * n + b] * pb[0] + H[(e0 + 3 + c) * n + b] * pb[1] + H[(e0 + 6 + c) * n + b] * pb[2];
-                if (c == 0) acc0 += v; else if (c == 1) acc1 += v; else acc2 += v;
+        for (int c = 0; c < 3; ++c)
+            acc[c] += H[(e0 + c) * n + b] * u0 + H[(e0 + 3 + c) * n + b] * u1 + H[(e0 + 6 + c) * n + b] * u2;
+    }
+}
+
+// w = H u for a tile of 64 rows; wave g computes block products g, g+8, g+16, g+24 and the
+// eight partial results are summed through LDS. With DOTS the kernel is the first half of a
+// CG iteration: it exits when the solve is done and emits per-block partials of r.u, w.u, r.r.
+template <typename T, bool DOTS>
+__global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S, const T *__restrict__ H,
+                                                                     const double *__restrict__ u, double *__restrict__ w,
+                                                                     const double *__restrict__ r, double *partials,
+                                                                     int stride, int32_t *isc) {
+    __shared__ T ys[kGroups][3][kRowsPerTile];
+    __shared__ double sh[kGroups];
+    if (DOTS) {
+        if (isc[I_DONE]) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) isc[I_ITA] = isc[I_ITB];
+    }
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = tile * kRowsPerTile + lane;
+    T acc[3] = {T(0), T(0), T(0)};
+    if (a < S.n_cp) {
+        const int i = a % S.n_u, j = a / S.n_u;
+        for (int m = 0; m < 4; ++m) {
+            const int pid = g + kGroups * m;
+            if (pid < 25) block_product<T>(S, H, u, a, i, j, pid, acc);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
+    __syncthreads();
+    double gam = 0.0, del = 0.0, rho = 0.0;
+    if (g == 0 && a < S.n_cp) {
+        const size_t n = S.n_cp;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T y = ys[0][c][lane];
+#pragma unroll
+            for (int q = 1; q < kGroups; ++q) y += ys[q][c][lane];
+            const double wc = double(y);
+            w[c * n + a] = wc;
+            if (DOTS) {
+                const double uc = u[c * n + a], rc = r[c * n + a];
+                gam += rc * uc;
+                del += wc * uc;
+                rho += rc * rc;
             }
         }
     }
-    y[0] = double(acc0); y[1] = double(acc1); y[2] = double(acc2);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_spmv(DevSheet S, const T *__restrict__ H, const double *__restrict__ in,
-                                                 double *__restrict__ out) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= S.n_cp) return;
-    const size_t n = S.n_cp;
-    double y[3];
-    row_product<T>(S, H, a, [&](int b, T p[3]) { p[0] = T(in[b]); p[1] = T(in[n + b]); p[2] = T(in[2 * n + b]); }, y);
-    out[a] = y[0]; out[n + a] = y[1]; out[2 * n + a] = y[2];
+    if (DOTS) {
+        // only wave 0 holds values: a wave reduction suffices
+        gam = wave_sum(gam);
+        del = wave_sum(del);
+        rho = wave_sum(rho);
+        if (threadIdx.x == 0) {
+            partials[blockIdx.x] = gam;
+            partials[stride + blockIdx.x] = del;
+            partials[2 * stride + blockIdx.x] = rho;
+        }
+    }
 }
 
 template <typename T>
@@ -166,21 +234,17 @@ __global__ void k_apply_pins(int n_cp, int npins, const int32_t *__restrict__ id
     for (int c = 0; c < 3; ++c) x[c * n_cp + a] = tgt[c * npins + t];
 }
 
-// Dot product of two vectors of length n into scalars[slot] (single kernel, last-block finish).
-__global__ void __launch_bounds__(kBlock) k_dot(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                double *partials, double *scal, int slot, int32_t *cnt) {
+// Per-block partials of x.y (grid of kReduceBlocks); k_finish sums them into scal[slot].
+__global__ void __launch_bounds__(kBlock) k_dot_part(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                                     double *__restrict__ partials) {
     __shared__ double sh[kBlock / 64];
     double v = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) v += x[t] * y[t];
-    const double s = block_sum(v, sh);
-    if (publish_last(partials, 0, &s, 1, cnt)) {
-        const double tot = gather_sum(partials, gridDim.x, sh);
-        if (threadIdx.x == 0) { scal[slot] = tot; *cnt = 0; }
-    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_absmax(int n, const double *__restrict__ x, double *partials, double *scal,
-                                                   int slot, int32_t *cnt) {
+__global__ void __launch_bounds__(kBlock) k_absmax_part(int n, const double *__restrict__ x, double *__restrict__ partials) {
     __shared__ double sh[kBlock / 64];
     double v = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) v = fmax(v, fabs(x[t]));
@@ -189,21 +253,38 @@ __global__ void __launch_bounds__(kBlock) k_absmax(int n, const double *__restri
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, sh[w]);
-    if (publish_last(partials, 0, &v, 1, cnt)) {
-        if (threadIdx.x == 0) {
-            double m = 0.0;
-            for (int t = 0; t < int(gridDim.x); ++t)
-                m = fmax(m, __hip_atomic_load(partials + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            scal[slot] = m;
-            *cnt = 0;
-        }
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, sh[w]);
+        partials[blockIdx.x] = v;
     }
 }
 
-// ---- PCG -----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ partials, int n, int is_max, double *scal, int slot) {
+    __shared__ double sh[kBlock / 64];
+    if (is_max) {
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+            for (int t = 0; t < n; ++t) m = fmax(m, partials[t]);
+            scal[slot] = m;
+        }
+        return;
+    }
+    double v = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v += partials[t];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) scal[slot] = v;
+}
 
-// Block-Jacobi preconditioner: inverse of each CP's 3x3 diagonal block, in double.
+// ---- preconditioned CG (Chronopoulos-Gear form: one reduction phase per iteration) --------
+//
+//   r0 = b - A x0, u0 = M^-1 r0; per iteration i:
+//     w_i = A u_i;  gamma_i = r_i.u_i, delta_i = w_i.u_i          (k_spmv_tile<DOTS>)
+//     stop if |r_i| <= tol; beta_i = gamma_i / gamma_{i-1};
+//     alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})  (alpha_0 = gamma_0/delta_0)
+//     p_i = u_i + beta_i p_{i-1}, s_i = w_i + beta_i s_{i-1}          (k_cg_update)
+//     x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i, u_{i+1} = M^-1 r_{i+1}
+// M is the block-Jacobi preconditioner (inverse 3x3 diagonal blocks, in double).
+
 template <typename T>
 __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, double *__restrict__ pinv) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,125 +312,162 @@ __device__ __forceinline__ void apply_pinv(const double *__restrict__ P, size_t 
     z[2] = i2 * r[0] + i4 * r[1] + i5 * r[2];
 }
 
-// r = b - q (q = A x0, or zero), z = M^-1 r, p_old = 0; finishes r.z, r.r, b.b and the tolerance.
-__global__ void __launch_bounds__(kBlock) k_pcg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
-                                                     const double *__restrict__ pinv, double *__restrict__ r,
-                                                     double *__restrict__ z, double *__restrict__ p0, double *__restrict__ p1,
-                                                     double *partials, int stride, double *scal, int32_t *isc,
-                                                     double rtol, int maxit) {
+// r = b - q (q = A x0, or none), u = M^-1 r, p = s = 0; per-block partials of b.b.
+__global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
+                                                    const double *__restrict__ pinv, double *__restrict__ r,
+                                                    double *__restrict__ u, double *__restrict__ p, double *__restrict__ sv,
+                                                    double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
+                                                    double rtol) {
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
-    double rz = 0.0, rr = 0.0, bb = 0.0;
+    double bb = 0.0;
     if (a < S.n_cp) {
-        double rv[3], zv[3];
+        double rv[3], uv[3];
         for (int c = 0; c < 3; ++c) {
             const double bc = b[c * n + a];
             rv[c] = q ? bc - q[c * n + a] : bc;
             bb += bc * bc;
         }
-        apply_pinv(pinv, n, a, rv, zv);
+        apply_pinv(pinv, n, a, rv, uv);
         for (int c = 0; c < 3; ++c) {
-            r[c * n + a] = rv[c]; z[c * n + a] = zv[c];
-            p0[c * n + a] = 0.0; p1[c * n + a] = 0.0;
-            rz += rv[c] * zv[c]; rr += rv[c] * rv[c];
+            r[c * n + a] = rv[c]; u[c * n + a] = uv[c];
+            p[c * n + a] = 0.0; sv[c * n + a] = 0.0;
         }
     }
-    double v[3];
-    v[0] = block_sum(rz, sh); v[1] = block_sum(rr, sh); v[2] = block_sum(bb, sh);
-    if (publish_last(partials, stride, v, 3, isc + I_CNT_A)) {
-        const double trz = gather_sum(partials, gridDim.x, sh);
-        const double trr = gather_sum(partials + stride, gridDim.x, sh);
-        const double tbb = gather_sum(partials + 2 * stride, gridDim.x, sh);
-        if (threadIdx.x == 0) {
-            scal[S_RZ] = trz; scal[S_RR] = trr; scal[S_BB] = tbb; scal[S_BETA] = 0.0;
-            scal[S_TOL2] = rtol * rtol * tbb;
-            isc[I_ITERS] = 0; isc[I_BREAK] = 0; isc[I_MAXIT] = maxit;
-            isc[I_DONE] = (trr <= rtol * rtol * tbb || trr == 0.0) ? 1 : 0;
-            isc[I_CNT_A] = 0;
-        }
+    bb = block_sum(bb, sh);
+    if (threadIdx.x == 0) pbb[blockIdx.x] = bb;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        isc[I_DONE] = 0; isc[I_ITA] = 0; isc[I_ITB] = 0; isc[I_BREAK] = 0; isc[I_MAXIT] = maxit; isc[I_ITERS] = 0;
+        scal[S_RTOL] = rtol;
     }
 }
 
-// p_new = z + beta p_old (formed on the fly for neighbours), q = A p_new, alpha = r.z / p.q.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_a(DevSheet S, const T *__restrict__ H, const double *__restrict__ z,
-                                                  const double *__restrict__ pold, double *__restrict__ pnew,
-                                                  double *__restrict__ q, double *partials, double *scal, int32_t *isc) {
-    __shared__ double sh[kBlock / 64];
+// Second half of a CG iteration (see above). Reads the partials of k_spmv_tile<DOTS>. The
+// row's own vector entries are loaded first so their latency overlaps the partial sums.
+__global__ void __launch_bounds__(kBlock) k_cg_update(DevSheet S, double *__restrict__ x, double *__restrict__ r,
+                                                      double *__restrict__ u, const double *__restrict__ w,
+                                                      double *__restrict__ p, double *__restrict__ sv,
+                                                      const double *__restrict__ pinv, const double *partials, int stride,
+                                                      int nb_spmv, const double *pbb, int nb_init, double *scal,
+                                                      int32_t *isc) {
+    __shared__ double sh[48];
     if (isc[I_DONE]) return;
-    const double beta = scal[S_BETA];
+    const int it = isc[I_ITA];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = a < S.n_cp;
     const size_t n = S.n_cp;
-    double pq = 0.0;
-    if (a < S.n_cp) {
-        auto pf = [&](int b, T p[3]) {
-            p[0] = T(z[b] + beta * pold[b]);
-            p[1] = T(z[n + b] + beta * pold[n + b]);
-            p[2] = T(z[2 * n + b] + beta * pold[2 * n + b]);
-        };
-        double y[3];
-        row_product<T>(S, H, a, pf, y);
+    double uo[3], wo[3], po[3], so[3], ro[3], pi[6];
+    if (active) {
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double pc = z[c * n + a] + beta * pold[c * n + a];
-            pnew[c * n + a] = pc;
-            q[c * n + a] = y[c];
-            pq += pc * y[c];
+            const size_t k = c * n + a;
+            uo[c] = u[k]; wo[c] = w[k]; po[c] = p[k]; so[c] = sv[k]; ro[c] = r[k];
         }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) pi[t] = pinv[t * n + a];
     }
-    const double s = block_sum(pq, sh);
-    if (publish_last(partials, 0, &s, 1, isc + I_CNT_A)) {
-        const double tot = gather_sum(partials, gridDim.x, sh);
-        if (threadIdx.x == 0) {
-            scal[S_PQ] = tot;
-            if (!(tot > 0.0)) { isc[I_BREAK] = 1; isc[I_DONE] = 1; scal[S_ALPHA] = 0.0; }
-            else scal[S_ALPHA] = scal[S_RZ] / tot;
-            isc[I_CNT_A] = 0;
-        }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nb_spmv; t += blockDim.x) {
+        v[0] += partials[t];
+        v[1] += partials[stride + t];
+        v[2] += partials[2 * stride + t];
+    }
+    block_sum3(v, sh);
+    const double gam = v[0], del = v[1], rho = v[2];
+    double tol2;
+    if (it == 0) {
+        double b3[3] = {0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < nb_init; t += blockDim.x) b3[0] += pbb[t];
+        block_sum3(b3, sh);
+        const double rtol = scal[S_RTOL];
+        tol2 = rtol * rtol * b3[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_TOL2] = tol2;
+    } else {
+        tol2 = scal[S_TOL2];
+    }
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (rho <= tol2 || it >= isc[I_MAXIT] || !(rho == rho)) {
+        if (lead) { isc[I_ITERS] = it; isc[I_DONE] = 1; }
+        return;
+    }
+    double alpha, beta;
+    if (it == 0) {
+        beta = 0.0;
+        alpha = del > 0.0 ? gam / del : -1.0;
+    } else {
+        const double gprev = scal[S_GAMMA0 + ((it + 1) & 1)], aprev = scal[S_ALPHA0 + ((it + 1) & 1)];
+        beta = gam / gprev;
+        const double den = del - beta * gam / aprev;
+        alpha = den > 0.0 ? gam / den : -1.0;
+    }
+    if (!(alpha > 0.0)) {                       // p^T A p <= 0: breakdown
+        if (lead) { isc[I_ITERS] = it; isc[I_BREAK] = 1; isc[I_DONE] = 1; }
+        return;
+    }
+    if (lead) {
+        scal[S_GAMMA0 + (it & 1)] = gam;
+        scal[S_ALPHA0 + (it & 1)] = alpha;
+        isc[I_ITB] = it + 1;
+    }
+    if (!active) return;
+    double rv[3], uv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t k = c * n + a;
+        const double pc = uo[c] + beta * po[c];
+        const double sc = wo[c] + beta * so[c];
+        p[k] = pc;
+        sv[k] = sc;
+        x[k] += alpha * pc;
+        rv[c] = ro[c] - alpha * sc;
+        r[k] = rv[c];
+    }
+    uv[0] = pi[0] * rv[0] + pi[1] * rv[1] + pi[2] * rv[2];
+    uv[1] = pi[1] * rv[0] + pi[3] * rv[1] + pi[4] * rv[2];
+    uv[2] = pi[2] * rv[0] + pi[4] * rv[1] + pi[5] * rv[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c * n + a] = uv[c];
+}
+
+// ---- warm start and sample log ------------------------------------------------------------
+
+__global__ void k_to_float(int n, const double *__restrict__ x, float *__restrict__ y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = float(x[t]);
+}
+
+// p_hat (double) from the net output, zero on pinned CPs.
+__global__ void k_phat(int n_cp, const float *__restrict__ out, const int32_t *__restrict__ pinmask, double *__restrict__ ph) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_cp) return;
+    const bool pinned = pinmask[a] != 0;
+    for (int c = 0; c < 3; ++c) ph[c * n_cp + a] = pinned ? 0.0 : double(out[c * n_cp + a]);
+}
+
+// Partials of g.ph, ph.w, g.w, w.w (4 arrays of kReduceBlocks).
+__global__ void __launch_bounds__(kBlock) k_dots4_part(int n, const double *__restrict__ g, const double *__restrict__ ph,
+                                                       const double *__restrict__ w, double *__restrict__ part, int stride) {
+    __shared__ double sh[48];
+    double v[3] = {0.0, 0.0, 0.0}, ww = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        v[0] += g[t] * ph[t]; v[1] += ph[t] * w[t]; v[2] += g[t] * w[t]; ww += w[t] * w[t];
+    }
+    block_sum3(v, sh);
+    __syncthreads();
+    double u3[3] = {ww, 0.0, 0.0};
+    block_sum3(u3, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0]; part[stride + blockIdx.x] = v[1];
+        part[2 * stride + blockIdx.x] = v[2]; part[3 * stride + blockIdx.x] = u3[0];
     }
 }
 
-// x += alpha p, r -= alpha q, z = M^-1 r; beta = r.z_new / r.z; convergence on |r|.
-__global__ void __launch_bounds__(kBlock) k_pcg_b(DevSheet S, double *__restrict__ x, double *__restrict__ r,
-                                                  double *__restrict__ z, const double *__restrict__ pinv,
-                                                  const double *__restrict__ p, const double *__restrict__ q,
-                                                  double *partials, int stride, double *scal, int32_t *isc) {
-    __shared__ double sh[kBlock / 64];
-    if (isc[I_DONE]) return;
-    const double alpha = scal[S_ALPHA];
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t n = S.n_cp;
-    double rz = 0.0, rr = 0.0;
-    if (a < S.n_cp) {
-        double rv[3], zv[3];
-        for (int c = 0; c < 3; ++c) {
-            x[c * n + a] += alpha * p[c * n + a];
-            rv[c] = r[c * n + a] - alpha * q[c * n + a];
-            r[c * n + a] = rv[c];
-        }
-        apply_pinv(pinv, n, a, rv, zv);
-        for (int c = 0; c < 3; ++c) {
-            z[c * n + a] = zv[c];
-            rz += rv[c] * zv[c];
-            rr += rv[c] * rv[c];
-        }
-    }
-    double v[2];
-    v[0] = block_sum(rz, sh);
-    v[1] = block_sum(rr, sh);
-    if (publish_last(partials, stride, v, 2, isc + I_CNT_B)) {
-        const double trz = gather_sum(partials, gridDim.x, sh);
-        const double trr = gather_sum(partials + stride, gridDim.x, sh);
-        if (threadIdx.x == 0) {
-            scal[S_BETA] = trz / scal[S_RZ];
-            scal[S_RZ] = trz;
-            scal[S_RR] = trr;
-            const int it = isc[I_ITERS] + 1;
-            isc[I_ITERS] = it;
-            if (trr <= scal[S_TOL2] || it >= isc[I_MAXIT] || !(trr == trr)) isc[I_DONE] = 1;
-            isc[I_CNT_B] = 0;
-        }
-    }
+__global__ void k_finish4(const double *__restrict__ part, int stride, int n, double *__restrict__ out) {
+    if (threadIdx.x >= 4) return;
+    double s = 0.0;
+    for (int t = 0; t < n; ++t) s += part[threadIdx.x * stride + t];
+    out[threadIdx.x] = s;
 }
 
 // ---- line search -------------------------------------------------------------------------
@@ -519,9 +637,14 @@ __global__ void k_update(int n, double alpha, const double *__restrict__ p, doub
 
 }  // namespace
 
+inline int spmv_blocks(int n_cp) { return (n_cp + kRowsPerTile - 1) / kRowsPerTile; }
+
 hipError_t launch_spmv(const DevSheet &S, int precision, const void *hess, const double *in, double *out, hipStream_t st) {
-    if (precision == BSC_FP64) k_spmv<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)hess, in, out);
-    else k_spmv<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)hess, in, out);
+    const int nb = spmv_blocks(S.n_cp);
+    if (precision == BSC_FP64)
+        k_spmv_tile<double, false><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const double *)hess, in, out, nullptr, nullptr, 0, nullptr);
+    else
+        k_spmv_tile<float, false><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const float *)hess, in, out, nullptr, nullptr, 0, nullptr);
     return hipGetLastError();
 }
 
@@ -610,7 +733,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             Timer t(st);
             bsc_status as = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav);
             if (as != BSC_OK) return as;
-            k_dot<<<256, kBlock, 0, st>>>(n3, B.g, B.g, B.partials + 7 * stride, B.scalars, S_GG, B.iscalars + I_CNT_C);
+            k_dot_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.g, B.partials + 7 * stride);
+            k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
             HIPX(hipMemcpyAsync(host, B.scalars + S_E, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read norms");
             HIPX(hipStreamSynchronize(st), "sync");
             s.ms_assemble += t.stop();
@@ -636,35 +760,102 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, B.pinv);
             k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
             HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
-            k_pcg_init<<<blocks(S.n_cp), kBlock, 0, st>>>(S, B.tmp, nullptr, B.pinv, B.r, B.z, B.p0, B.p1,
-                                                           B.partials, stride, B.scalars, B.iscalars, o->pcg_rtol, o->max_pcg);
-            HIPX(hipGetLastError(), "pcg init");
-            int32_t flags[2] = {0, 0};
-            int k = 0;
-            const int chunk = 16;
-            while (true) {
-                for (int c = 0; c < chunk; ++c, ++k) {
-                    double *pold = (k & 1) ? B.p1 : B.p0, *pnew = (k & 1) ? B.p0 : B.p1;
-                    if (prec == BSC_FP64)
-                        k_pcg_a<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.hess, B.z, pold, pnew, B.q, B.partials, B.scalars, B.iscalars);
-                    else
-                        k_pcg_a<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, B.z, pold, pnew, B.q, B.partials, B.scalars, B.iscalars);
-                    k_pcg_b<<<blocks(S.n_cp), kBlock, 0, st>>>(S, B.dir, B.r, B.z, B.pinv, pnew, B.q, B.partials + 2 * stride, stride, B.scalars, B.iscalars);
+            // CG vectors: r, u (= M^-1 r), w (= A u), p, s
+            double *r = B.r, *u = B.z, *w = B.q, *p = B.p0, *sv = B.p1;
+            const int nbs = spmv_blocks(S.n_cp), nbi = blocks(S.n_cp);
+            double *ppart = B.partials, *pbb = B.partials + 3 * stride;
+            const double *q0 = nullptr;
+            if (o->warm_start) {
+                // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
+                // kept only when |b - H x0| < |b| (else zero start)
+                Timer tw(st);
+                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
+                HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
+                                      B.net_scale, B.net_w_fwd, true, st), "warm start forward");
+                k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
+                HIPX(launch_spmv(S, prec, B.hess, B.phat, w, st), "warm start spmv");
+                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, w, B.partials + 4 * stride, stride);
+                k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
+                HIPX(hipGetLastError(), "warm start");
+                double d4[4];
+                HIPX(hipMemcpyAsync(d4, B.scalars + S_WS0, 4 * sizeof(double), hipMemcpyDeviceToHost, st), "read ws");
+                HIPX(hipStreamSynchronize(st), "sync ws");
+                const double gp = d4[0], pw = d4[1], gw = d4[2], ww = d4[3], bb = host[1];
+                bool use = false;
+                if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
+                    const double as = -gp / pw;
+                    // |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
+                    const double rr = bb + 2.0 * as * gw + as * as * ww;
+                    if (as > 0.0 && rr < bb) {
+                        use = true;
+                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
+                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, w, 0.0, w, w);                  // q0 = H x0
+                    }
                 }
-                HIPX(hipGetLastError(), "pcg");
-                HIPX(hipMemcpyAsync(flags, B.iscalars + I_DONE, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read pcg flags");
-                HIPX(hipStreamSynchronize(st), "sync pcg");
-                if (flags[0]) break;
+                if (use) s.warm_start_used++;
+                else s.warm_start_fallbacks++;
+                s.ms_warmstart += tw.stop();
+                q0 = use ? w : nullptr;
             }
-            int32_t brk = 0;
-            HIPX(hipMemcpyAsync(&brk, B.iscalars + I_BREAK, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read pcg break");
-            HIPX(hipStreamSynchronize(st), "sync");
+            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, B.pinv, r, u, p, sv, pbb, B.iscalars, B.scalars,
+                                               o->max_pcg, o->pcg_rtol);
+            HIPX(hipGetLastError(), "cg init");
+            int32_t flags[6] = {0, 0, 0, 0, 0, 0};
+            const int chunk = 16;
+            auto enqueue_chunk = [&](hipStream_t cs) {
+                for (int c = 0; c < chunk; ++c) {
+                    if (prec == BSC_FP64)
+                        k_spmv_tile<double, true><<<nbs, kRowsPerTile * kGroups, 0, cs>>>(S, (const double *)B.hess, u, w, r, ppart, stride, B.iscalars);
+                    else
+                        k_spmv_tile<float, true><<<nbs, kRowsPerTile * kGroups, 0, cs>>>(S, (const float *)B.hess, u, w, r, ppart, stride, B.iscalars);
+                    k_cg_update<<<nbi, kBlock, 0, cs>>>(S, B.dir, r, u, w, p, sv, B.pinv, ppart, stride, nbs, pbb, nbi,
+                                                         B.scalars, B.iscalars);
+                }
+            };
+            // The chunk is captured once into a graph (on a private stream) and replayed on the
+            // context's stream; its kernel arguments depend only on the bound workspace.
+            hipGraphExec_t &gx = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1];
+            if (!gx && ctx->use_graphs) {
+                hipStream_t cs = nullptr;
+                hipGraph_t graph = nullptr;
+                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    enqueue_chunk(cs);
+                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+                }
+                ok = ok && hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+                if (cs) (void)hipStreamDestroy(cs);
+                if (!ok) {
+                    if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
+                    (void)hipGetLastError();
+                }
+            }
+            while (true) {
+                if (gx) HIPX(hipGraphLaunch(gx, st), "cg graph");
+                else enqueue_chunk(st);
+                HIPX(hipGetLastError(), "cg");
+                HIPX(hipMemcpyAsync(flags, B.iscalars, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read cg flags");
+                HIPX(hipStreamSynchronize(st), "sync cg");
+                if (flags[I_DONE]) break;
+            }
+            const int32_t brk = flags[I_BREAK];
+            flags[1] = flags[I_ITERS];
             s.pcg_iters_total += flags[1];
             s.ms_pcg += t.stop();
             if (brk) { result = BSC_E_PCG_BREAKDOWN; break; }
+            if (ctx->log_count < ctx->log_cap) {
+                const size_t off = size_t(ctx->log_count) * n3;
+                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, ctx->log_g + off);
+                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.dir, ctx->log_p + off);
+                HIPX(hipGetLastError(), "sample log");
+                ctx->log_count++;
+            }
         }
         if (o->fixed_newton_iters <= 0 && o->stop_mode == BSC_STOP_STEP) {
-            k_absmax<<<256, kBlock, 0, st>>>(n3, B.dir, B.partials + 7 * stride, B.scalars, S_PMAX, B.iscalars + I_CNT_C);
+            k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.dir, B.partials + 7 * stride);
+            k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
             double pmax = 0.0;
             HIPX(hipMemcpyAsync(&pmax, B.scalars + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, st), "read pmax");
             HIPX(hipStreamSynchronize(st), "sync");

@@ -154,9 +154,10 @@ def compressed_sheet(n: int = 100, seed: int = 2, material: Material | None = No
 MATERIAL_GRID = [(E, t) for E in (1e3, 1e4, 1e5) for t in (0.5e-3, 1e-3, 2e-3)]
 
 
-def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: float = 1e-3) -> Scene:
+def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: float = 0.0) -> Scene:
     """Large sheet with a material cell from the (E, t) grid, K ~ U{4..16} random held CPs plus
-    the corner CP (0,0) driven in z with amplitude 5 cm at 1 Hz; gravity along -z."""
+    the corner CP (0,0) driven in z with amplitude 5 cm at 1 Hz; gravity along -z. Starts flat
+    (optional z-noise U(+-noise))."""
     g = rng(seed)
     if cell is None:
         cell = (seed - 300) % len(MATERIAL_GRID)
