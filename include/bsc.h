@@ -191,8 +191,9 @@ bsc_status bsc_sample_log_count(const bsc_ctx *ctx, int32_t *count);
 /* Learned PCG warm start (a method extension; not in the paper). A bias-free 6-layer 3x3
  * convolutional net over the CP grid (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3 channels, zero
  * padding, LeakyReLU(0.1) between layers) maps the normalised gradient g/rms(g) to a
- * direction p_hat; the step uses alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat as the
- * PCG initial guess when it lowers the residual, else zero.
+ * direction p_hat; the step uses alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat (the
+ * energy-optimal multiple, of either sign) as the PCG initial guess when it lowers the 2-norm of
+ * the residual, else zero.
  * Weights: BSC_NET_PARAMS floats, layer by layer, each [c_out][c_in][3][3]. */
 #define BSC_NET_PARAMS 38592
 bsc_status bsc_warmstart_load(bsc_ctx *ctx, const float *d_weights, int32_t n_params);

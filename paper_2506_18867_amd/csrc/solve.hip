@@ -783,10 +783,11 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 const double gp = d4[0], pw = d4[1], gw = d4[2], ww = d4[3], bb = host[1];
                 bool use = false;
                 if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
+                    // energy-optimal multiple of p_hat (either sign: the training loss fixes the
+                    // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
                     const double as = -gp / pw;
-                    // |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
                     const double rr = bb + 2.0 * as * gw + as * as * ww;
-                    if (as > 0.0 && rr < bb) {
+                    if (as != 0.0 && rr < bb) {
                         use = true;
                         k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
                         k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, w, 0.0, w, w);                  // q0 = H x0
