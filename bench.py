@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--max-newton", type=int, default=200)
     p.add_argument("--pcg-rtol", type=float, default=1e-3)
     p.add_argument("--grad-steps", type=int, default=2, help="steps of the |g|<=1e-6|g0| leg (0: skip)")
+    p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
     return p.parse_args()
 
 
@@ -58,7 +59,8 @@ def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
     stats = []
     opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=args.rtol,
                          atol=args.atol, stop_mode=bsc.BSC_STOP_GRAD if args.stop == "grad" else bsc.BSC_STOP_STEP,
-                         pcg_rtol=args.pcg_rtol, max_newton=args.max_newton, max_pcg=4000)
+                         pcg_rtol=args.pcg_rtol, max_newton=args.max_newton, max_pcg=4000,
+                         pcg_adaptive=getattr(args, "adaptive", 0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -142,6 +144,7 @@ def main():
             pass
         ga = _A()
         ga.rtol, ga.atol, ga.stop, ga.pcg_rtol, ga.max_newton = 1e-6, args.atol, "grad", args.pcg_rtol, args.max_newton
+        ga.adaptive = args.adaptive
         grad_leg = {}
         for name, prec in (("fp32_mixed", bsc.BSC_FP32_MIXED), ("fp64", bsc.BSC_FP64)):
             xg, vg = x0.clone(), v0.clone()
@@ -200,6 +203,8 @@ def main():
         "config": {"workload": f"driven sheet {args.n}x{args.n} CPs ({ne} elements), E=1e4 Pa, t=1 mm, dt=0.01 s, "
                                + (f"|g|<={args.rtol:g}|g0|" if args.stop == "grad" else f"|p|inf/dt<={args.atol:g}")
                                + ", FP32-mixed", "n_cp": n, "n_elem": ne, "seed": args.seed, "noise": args.noise,
+                   "pcg": "block-Jacobi PCG, " + ("Eisenstat-Walker tolerance in [%g, 0.1]" % args.pcg_rtol if args.adaptive
+                                                  else "fixed tolerance %g" % args.pcg_rtol),
                    "parallelism": "single GPU"},
         "newton_step_ms": {"fp32_mixed": round(ms_step32, 3),
                            "fp64": round(1e3 * sec64 / args.steps, 3) if sec64 else None},

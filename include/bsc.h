@@ -74,7 +74,10 @@ typedef struct {
  *   stop_mode BSC_STOP_STEP: stop when |p|_inf / dt <= atol (the paper's rule).
  *   fixed_newton_iters > 0 runs exactly that many iterations instead (for comparisons).
  *   pcg_rtol: PCG stops when |r|_2 <= pcg_rtol |g|_2. warm_start: 1 uses the loaded network as
- *   the PCG initial guess (falls back to zero when it does not reduce the residual). */
+ *   the PCG initial guess (falls back to zero when it does not reduce the residual).
+ *   pcg_adaptive: 1 chooses the PCG tolerance per Newton iteration by the Eisenstat-Walker rule
+ *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2, clamped to [pcg_rtol, 0.1] (eta_0 = 0.1); with
+ *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
 typedef struct {
     double dt;
     double gravity[3];
@@ -85,6 +88,7 @@ typedef struct {
     double pcg_rtol;
     int32_t warm_start;
     int32_t fixed_newton_iters;
+    int32_t pcg_adaptive;
 } bsc_step_opts;
 
 typedef struct {

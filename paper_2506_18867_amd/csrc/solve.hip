@@ -13,6 +13,7 @@
 // forming the two energies: the inertia, gravity and bending terms are exact quadratics in
 // alpha (coefficients computed once), and each membrane point evaluates Psi(F + alpha dF) -
 // Psi(F) from the strain increment.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -725,7 +726,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     HIPX(hipGetLastError(), "step setup");
 
     bsc_status result = BSC_OK;
-    double g0 = -1.0;
+    double g0 = -1.0, g_prev = -1.0;
+    double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, 0.1) : o->pcg_rtol;   // PCG tolerance of this iteration
+    bool force_tight = false;
     double host[4];
     int it = 0;
     for (;; ++it) {
@@ -752,6 +755,18 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             break;
         }
         if (it >= o->max_newton) { result = BSC_E_NOT_CONVERGED; break; }
+        if (force_tight) {
+            eta = o->pcg_rtol;
+            force_tight = false;
+        } else if (o->pcg_adaptive && g_prev > 0.0) {
+            // Eisenstat-Walker forcing term (choice 2, gamma = 0.9, exponent 2) with safeguard
+            const double ratio = gn / g_prev;
+            double e = 0.9 * ratio * ratio;
+            const double guard = 0.9 * eta * eta;
+            if (guard > 0.1) e = std::max(e, guard);
+            eta = std::min(0.1, std::max(o->pcg_rtol, e));
+        }
+        g_prev = gn;
 
         // ---- direction: PCG on H p = -g -----------------------------------------------
         {
@@ -799,7 +814,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 q0 = use ? w : nullptr;
             }
             k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, B.pinv, r, u, p, sv, pbb, B.iscalars, B.scalars,
-                                               o->max_pcg, o->pcg_rtol);
+                                               o->max_pcg, eta);
             HIPX(hipGetLastError(), "cg init");
             int32_t flags[6] = {0, 0, 0, 0, 0, 0};
             const int chunk = 16;
@@ -860,7 +875,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             double pmax = 0.0;
             HIPX(hipMemcpyAsync(&pmax, B.scalars + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, st), "read pmax");
             HIPX(hipStreamSynchronize(st), "sync");
-            if (pmax / dt <= o->atol) break;
+            if (pmax / dt <= o->atol) {
+                if (eta <= o->pcg_rtol) break;
+                force_tight = true;        // confirm the stop on a direction solved to pcg_rtol
+            }
         }
 
         // ---- backtracking line search on the energy difference ---------------------------
