@@ -220,6 +220,7 @@ def main():
         "assembly": {"fp32_ms": round(ms_asm32, 4), "fp64_ms": round(ms_asm64, 4),
                      "fp32_melem_s": round(ne / ms_asm32 / 1e3, 2), "fp64_melem_s": round(ne / ms_asm64 / 1e3, 2),
                      "fp32_gb_s": round(asm_bytes32 / ms_asm32 / 1e6, 1), "fp64_gb_s": round(asm_bytes64 / ms_asm64 / 1e6, 1)},
+        "pcg_us_per_iter_fp32": round(1e3 * sum(s["ms_pcg"] for s in st32) / max(1, pcg32), 3),
         "spmv": {"fp32_ms": round(ms_spmv32, 5), "fp64_ms": round(ms_spmv64, 5),
                  "fp32_gb_s": round(spmv_bytes32 / ms_spmv32 / 1e6, 1), "fp64_gb_s": round(spmv_bytes64 / ms_spmv64 / 1e6, 1)},
         "roofline": roof,

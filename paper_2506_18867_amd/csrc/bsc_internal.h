@@ -26,6 +26,8 @@ namespace bsc {
 constexpr int kBlock = 256;
 constexpr int kSlots = 13;            // diagonal + 12 upper offsets
 constexpr int kHessEntries = BSC_HESS_ENTRIES;
+// CG iteration tile: kCgTileU x kCgTileV control points per workgroup (one wave of rows)
+constexpr int kCgTileU = 64, kCgTileV = 2;
 
 // Upper-stencil slot offsets (di, dj); slot 0 is the diagonal.
 constexpr int kSlotDi[kSlots] = {0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
@@ -73,7 +75,8 @@ struct DevBufs {
     double *scalars;                         // solver scalars (see solve.hip)
     int32_t *iscalars;
     // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
-    double *g, *xn, *xhat, *dir, *r, *z, *p0, *p1, *q, *pinv, *tmp, *phat;
+    double *g, *xn, *xhat, *dir, *r, *p0, *p1, *q, *pinv, *tmp, *phat;
+    double *r2, *q2, *p2;                    // second halves of the CG double buffers
     void *hess;                              // kHessEntries n_cp doubles
     // warm-start network
     float *net_w, *net_w_fwd, *net_wr, *net_in, *net_out, *net_act0, *net_act1, *net_scale;

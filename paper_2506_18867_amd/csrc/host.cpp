@@ -165,8 +165,10 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     const size_t ncp = c->n_cp, nmp = c->n_mp, nbe = c->n_be, ne = c->n_elem;
     const int max_items = int(std::max(std::max(nmp, nbe), std::max(ncp, ne)));
     // at least 256: the fixed-grid reductions (dot products, max-norm) launch 256 blocks
-    // also >= the SpMV grid (64 rows per block)
-    const int max_blocks = std::max(256, std::max((max_items + kBlock - 1) / kBlock + 1, int(ncp / 64) + 2));
+    // also >= the SpMV grid (64 rows per block) and the CG grid (kCgTileU x kCgTileV tiles)
+    const int cg_tiles = ((c->n_u + kCgTileU - 1) / kCgTileU) * ((c->n_v + kCgTileV - 1) / kCgTileV);
+    const int max_blocks = std::max(std::max(256, cg_tiles + 1),
+                                    std::max((max_items + kBlock - 1) / kBlock + 1, int(ncp / 64) + 2));
     DevBufs t{};
     t.max_blocks = max_blocks;
     t.mp_elem = (int32_t *)take(4 * nmp);
@@ -193,7 +195,7 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.bsr_rowptr = (int32_t *)take(4 * (ncp + 1));
     t.scalars = (double *)take(8 * 64);
     t.iscalars = (int32_t *)take(4 * 64);
-    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.z, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat};
+    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2};
     for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
     t.pinv = (double *)take(8 * 6 * ncp);
     t.hess = take(8 * size_t(kHessEntries) * ncp);

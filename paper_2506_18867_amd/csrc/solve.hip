@@ -128,19 +128,11 @@ __device__ __forceinline__ void block_product(const DevSheet &S, const T *__rest
 }
 
 // w = H u for a tile of 64 rows; wave g computes block products g, g+8, g+16, g+24 and the
-// eight partial results are summed through LDS. With DOTS the kernel is the first half of a
-// CG iteration: it exits when the solve is done and emits per-block partials of r.u, w.u, r.r.
-template <typename T, bool DOTS>
+// eight partial results are summed through LDS.
+template <typename T>
 __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S, const T *__restrict__ H,
-                                                                     const double *__restrict__ u, double *__restrict__ w,
-                                                                     const double *__restrict__ r, double *partials,
-                                                                     int stride, int32_t *isc) {
+                                                                     const double *__restrict__ u, double *__restrict__ w) {
     __shared__ T ys[kGroups][3][kRowsPerTile];
-    __shared__ double sh[kGroups];
-    if (DOTS) {
-        if (isc[I_DONE]) return;
-        if (blockIdx.x == 0 && threadIdx.x == 0) isc[I_ITA] = isc[I_ITB];
-    }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = tile * kRowsPerTile + lane;
@@ -155,7 +147,6 @@ __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S
 #pragma unroll
     for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
     __syncthreads();
-    double gam = 0.0, del = 0.0, rho = 0.0;
     if (g == 0 && a < S.n_cp) {
         const size_t n = S.n_cp;
 #pragma unroll
@@ -163,25 +154,7 @@ __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S
             T y = ys[0][c][lane];
 #pragma unroll
             for (int q = 1; q < kGroups; ++q) y += ys[q][c][lane];
-            const double wc = double(y);
-            w[c * n + a] = wc;
-            if (DOTS) {
-                const double uc = u[c * n + a], rc = r[c * n + a];
-                gam += rc * uc;
-                del += wc * uc;
-                rho += rc * rc;
-            }
-        }
-    }
-    if (DOTS) {
-        // only wave 0 holds values: a wave reduction suffices
-        gam = wave_sum(gam);
-        del = wave_sum(del);
-        rho = wave_sum(rho);
-        if (threadIdx.x == 0) {
-            partials[blockIdx.x] = gam;
-            partials[stride + blockIdx.x] = del;
-            partials[2 * stride + blockIdx.x] = rho;
+            w[c * n + a] = double(y);
         }
     }
 }
@@ -262,10 +235,16 @@ __global__ void __launch_bounds__(kBlock) k_absmax_part(int n, const double *__r
 
 __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ partials, int n, int is_max, double *scal, int slot) {
     __shared__ double sh[kBlock / 64];
-    if (is_max) {
+    if (is_max) {                       // max is exact in any order
+        double m = 0.0;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, partials[t]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) sh[wid] = m;
+        __syncthreads();
         if (threadIdx.x == 0) {
-            double m = 0.0;
-            for (int t = 0; t < n; ++t) m = fmax(m, partials[t]);
+            for (int q = 1; q < int(blockDim.x + 63) / 64; ++q) m = fmax(m, sh[q]);
             scal[slot] = m;
         }
         return;
@@ -279,12 +258,13 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // ---- preconditioned CG (Chronopoulos-Gear form: one reduction phase per iteration) --------
 //
 //   r0 = b - A x0, u0 = M^-1 r0; per iteration i:
-//     w_i = A u_i;  gamma_i = r_i.u_i, delta_i = w_i.u_i          (k_spmv_tile<DOTS>)
+//     w_i = A u_i;  gamma_i = r_i.u_i, delta_i = w_i.u_i
 //     stop if |r_i| <= tol; beta_i = gamma_i / gamma_{i-1};
 //     alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})  (alpha_0 = gamma_0/delta_0)
-//     p_i = u_i + beta_i p_{i-1}, s_i = w_i + beta_i s_{i-1}          (k_cg_update)
+//     p_i = u_i + beta_i p_{i-1}, s_i = w_i + beta_i s_{i-1}
 //     x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i, u_{i+1} = M^-1 r_{i+1}
-// M is the block-Jacobi preconditioner (inverse 3x3 diagonal blocks, in double).
+// M is the block-Jacobi preconditioner (inverse 3x3 diagonal blocks, in double). One launch of
+// k_cg_fused per iteration (below).
 
 template <typename T>
 __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, double *__restrict__ pinv) {
@@ -313,10 +293,9 @@ __device__ __forceinline__ void apply_pinv(const double *__restrict__ P, size_t 
     z[2] = i2 * r[0] + i4 * r[1] + i5 * r[2];
 }
 
-// r = b - q (q = A x0, or none), u = M^-1 r, p = s = 0; per-block partials of b.b.
+// r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b.
 __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
-                                                    const double *__restrict__ pinv, double *__restrict__ r,
-                                                    double *__restrict__ u, double *__restrict__ p, double *__restrict__ sv,
+                                                    double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
                                                     double rtol) {
     __shared__ double sh[kBlock / 64];
@@ -324,16 +303,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     const size_t n = S.n_cp;
     double bb = 0.0;
     if (a < S.n_cp) {
-        double rv[3], uv[3];
         for (int c = 0; c < 3; ++c) {
             const double bc = b[c * n + a];
-            rv[c] = q ? bc - q[c * n + a] : bc;
+            r[c * n + a] = q ? bc - q[c * n + a] : bc;
+            p[c * n + a] = 0.0;
+            sv[c * n + a] = 0.0;
             bb += bc * bc;
-        }
-        apply_pinv(pinv, n, a, rv, uv);
-        for (int c = 0; c < 3; ++c) {
-            r[c * n + a] = rv[c]; u[c * n + a] = uv[c];
-            p[c * n + a] = 0.0; sv[c * n + a] = 0.0;
         }
     }
     bb = block_sum(bb, sh);
@@ -344,91 +319,222 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     }
 }
 
-// Second half of a CG iteration (see above). Reads the partials of k_spmv_tile<DOTS>. The
-// row's own vector entries are loaded first so their latency overlaps the partial sums.
-__global__ void __launch_bounds__(kBlock) k_cg_update(DevSheet S, double *__restrict__ x, double *__restrict__ r,
-                                                      double *__restrict__ u, const double *__restrict__ w,
-                                                      double *__restrict__ p, double *__restrict__ sv,
-                                                      const double *__restrict__ pinv, const double *partials, int stride,
-                                                      int nb_spmv, const double *pbb, int nb_init, double *scal,
-                                                      int32_t *isc) {
+// ---- fused CG iteration ---------------------------------------------------------------------
+//
+// Launch K_j (j >= 1) finishes CG iteration j-1 and starts iteration j in one kernel, on a tile
+// of kCgTileU x kCgTileV control points:
+//   prologue  gamma, delta, rho of iteration j-1 re-summed from the partials of K_{j-1} in
+//             every block (fixed order); stop test; alpha_{j-1}, beta_{j-1}.
+//   footprint for every CP of the tile and its 2-CP stencil halo:
+//               s_{j-1} = w_{j-1} + beta s_{j-2},  r_j = r_{j-1} - alpha s_{j-1},  u_j = M^-1 r_j
+//             into LDS (one expression everywhere, so all blocks agree bitwise on u_j); on the
+//             tile's own CPs also p_{j-1} = M^-1 r_{j-1} + beta p_{j-2}, x += alpha p_{j-1}, and
+//             the stores of s_{j-1}, r_j, p_{j-1}, x.
+//   SpMV      w_j = A u_j with u from LDS (8 waves; each wave one group of block products of a
+//             64-row set).
+//   partials  r_j.u_j, w_j.u_j, r_j.r_j per block.
+// u is never stored: M^-1 r is recomputed from r. r, w, s and the partials are double-buffered by
+// the parity of j, so no block reads a value another block of the same launch writes. K_0
+// (FIRST) forms u_0, w_0 = A u_0, its partials and the threshold rtol^2 b.b.
+
+struct CgBufs {
+    double *x, *p;
+    const double *r_in, *w_in, *s_in;             // r_{j-1}, w_{j-1}, s_{j-2}
+    double *r_out, *w_out, *s_out;                // r_j, w_j, s_{j-1}
+    const double *pinv;
+    const double *part_in;                        // 3 arrays (stride) from K_{j-1}
+    double *part_out;                             // 3 arrays (stride) for K_{j+1}
+    const double *pbb;                            // b.b partials of the init kernel (FIRST)
+    int stride, nb_init;
+    int slot_in, slot_out;                        // iteration-counter slots (alternate)
+};
+
+template <typename T, bool FIRST>
+__global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restrict__ H, CgBufs B, double *scal,
+                                                  int32_t *isc) {
+    constexpr int TX = kCgTileU, TY = kCgTileV, HX = TX + 4, HY = TY + 4, R = TX * TY;
+    constexpr int RS = R / 64, PG = 8 / RS;      // 64-row sets, product groups per set
+    static_assert(R % 64 == 0 && 8 % RS == 0 && HX * HY <= 512, "tile shape");
+    __shared__ T us[3][HY][HX];
+    __shared__ double u64[3][R];
+    __shared__ T ys[8][3][64];
     __shared__ double sh[48];
     if (isc[I_DONE]) return;
-    const int it = isc[I_ITA];
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = a < S.n_cp;
+    const int nb = gridDim.x;
+    const int ntx = (S.n_u + TX - 1) / TX;
+    const int tile = xcd_tile(blockIdx.x, nb);
+    const int tx0 = (tile % ntx) * TX, ty0 = (tile / ntx) * TY;
     const size_t n = S.n_cp;
-    double uo[3], wo[3], po[3], so[3], ro[3], pi[6];
-    if (active) {
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    double alpha = 0.0, beta = 0.0;
+    if (!FIRST) {
+        const int it = isc[B.slot_in];            // CG updates done before this launch (j - 1)
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+            v[0] += B.part_in[t];
+            v[1] += B.part_in[B.stride + t];
+            v[2] += B.part_in[2 * B.stride + t];
+        }
+        block_sum3(v, sh);
+        const double gam = v[0], del = v[1], rho = v[2];
+        if (rho <= scal[S_TOL2] || it >= isc[I_MAXIT] || !(rho == rho)) {
+            if (lead) { isc[I_ITERS] = it; isc[I_DONE] = 1; }
+            return;
+        }
+        if (it == 0) {
+            alpha = del > 0.0 ? gam / del : -1.0;
+        } else {
+            const double gprev = scal[S_GAMMA0 + ((it + 1) & 1)], aprev = scal[S_ALPHA0 + ((it + 1) & 1)];
+            beta = gam / gprev;
+            const double den = del - beta * gam / aprev;
+            alpha = den > 0.0 ? gam / den : -1.0;
+        }
+        if (!(alpha > 0.0)) {                     // p^T A p <= 0: breakdown
+            if (lead) { isc[I_ITERS] = it; isc[I_BREAK] = 1; isc[I_DONE] = 1; }
+            return;
+        }
+        if (lead) {
+            scal[S_GAMMA0 + (it & 1)] = gam;
+            scal[S_ALPHA0 + (it & 1)] = alpha;
+            isc[B.slot_out] = it + 1;
+        }
+    } else if (blockIdx.x == 0) {                 // uniform per block
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < B.nb_init; t += blockDim.x) v[0] += B.pbb[t];
+        block_sum3(v, sh);
+        if (threadIdx.x == 0) {
+            scal[S_TOL2] = scal[S_RTOL] * scal[S_RTOL] * v[0];
+            isc[B.slot_out] = 0;
+        }
+    }
+    double gam = 0.0, rho = 0.0, del = 0.0;
+    {
+        const int t = threadIdx.x;
+        if (t < HX * HY) {
+            const int hx = t % HX, hy = t / HX;
+            const int gi = tx0 - 2 + hx, gj = ty0 - 2 + hy;
+            double uv[3] = {0.0, 0.0, 0.0};
+            if (gi >= 0 && gi < S.n_u && gj >= 0 && gj < S.n_v) {
+                const int a = gj * S.n_u + gi;
+                const bool own = hx >= 2 && hx < 2 + TX && hy >= 2 && hy < 2 + TY;
+                double ri[3], rv[3], sc[3], po[3], xo[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const size_t k = c * n + a;
-            uo[c] = u[k]; wo[c] = w[k]; po[c] = p[k]; so[c] = sv[k]; ro[c] = r[k];
+                for (int c = 0; c < 3; ++c) ri[c] = B.r_in[c * n + a];
+                if (!FIRST) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sc[c] = B.w_in[c * n + a] + beta * B.s_in[c * n + a];
+                    if (own) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) { po[c] = B.p[c * n + a]; xo[c] = B.x[c * n + a]; }
+                    }
+                }
+                if (FIRST) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rv[c] = ri[c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rv[c] = ri[c] - alpha * sc[c];
+                }
+                apply_pinv(B.pinv, n, a, rv, uv);
+                if (own) {
+                    if (!FIRST) {
+                        double uo[3];
+                        apply_pinv(B.pinv, n, a, ri, uo);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const size_t k = c * n + a;
+                            const double pc = uo[c] + beta * po[c];
+                            B.p[k] = pc;
+                            B.x[k] = xo[c] + alpha * pc;
+                            B.s_out[k] = sc[c];
+                            B.r_out[k] = rv[c];
+                        }
+                    }
+                    const int o = (hy - 2) * TX + (hx - 2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        u64[c][o] = uv[c];
+                        gam += rv[c] * uv[c];
+                        rho += rv[c] * rv[c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) us[c][hy][hx] = T(uv[c]);
+        }
+    }
+    __syncthreads();
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    {
+        const int rs = g / PG, pg = g % PG;
+        const int rr = rs * 64 + lane;
+        const int lx = rr % TX, ly = rr / TX;
+        const int gi = tx0 + lx, gj = ty0 + ly;
+        T acc[3] = {T(0), T(0), T(0)};
+        if (gi < S.n_u && gj < S.n_v) {
+            const int a = gj * S.n_u + gi;
+#pragma unroll
+            for (int m = 0; m < (25 + PG - 1) / PG; ++m) {
+                const int pid = pg + PG * m;
+                if (pid >= 25) break;
+                if (pid == 0) {
+                    const T u0 = us[0][ly + 2][lx + 2], u1 = us[1][ly + 2][lx + 2], u2 = us[2][ly + 2][lx + 2];
+                    const T d0 = H[a], d1 = H[n + a], d2 = H[2 * n + a], d3 = H[3 * n + a], d4 = H[4 * n + a], d5 = H[5 * n + a];
+                    acc[0] += d0 * u0 + d1 * u1 + d2 * u2;
+                    acc[1] += d1 * u0 + d3 * u1 + d4 * u2;
+                    acc[2] += d2 * u0 + d4 * u1 + d5 * u2;
+                    continue;
+                }
+                const bool upper = pid <= 12;
+                const int sl = upper ? pid : pid - 12;
+                const int di = kSlotDi[sl], dj = kSlotDj[sl], e0 = slot_entry(sl);
+                if (upper) {
+                    const int ib = gi + di, jb = gj + dj;
+                    if (ib < 0 || ib >= S.n_u || jb >= S.n_v) continue;
+                    const int hy = ly + 2 + dj, hx = lx + 2 + di;
+                    const T u0 = us[0][hy][hx], u1 = us[1][hy][hx], u2 = us[2][hy][hx];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        acc[q] += H[(e0 + 3 * q) * n + a] * u0 + H[(e0 + 3 * q + 1) * n + a] * u1 + H[(e0 + 3 * q + 2) * n + a] * u2;
+                } else {
+                    const int ic = gi - di, jc = gj - dj;
+                    if (ic < 0 || ic >= S.n_u || jc < 0) continue;
+                    const int b = jc * S.n_u + ic;
+                    const int hy = ly + 2 - dj, hx = lx + 2 - di;
+                    const T u0 = us[0][hy][hx], u1 = us[1][hy][hx], u2 = us[2][hy][hx];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += H[(e0 + c) * n + b] * u0 + H[(e0 + 3 + c) * n + b] * u1 + H[(e0 + 6 + c) * n + b] * u2;
+                }
+            }
         }
 #pragma unroll
-        for (int t = 0; t < 6; ++t) pi[t] = pinv[t * n + a];
+        for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
     }
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < nb_spmv; t += blockDim.x) {
-        v[0] += partials[t];
-        v[1] += partials[stride + t];
-        v[2] += partials[2 * stride + t];
+    __syncthreads();
+    if (threadIdx.x < R) {
+        const int rr = threadIdx.x, rs = rr >> 6, l = rr & 63;
+        const int gi = tx0 + rr % TX, gj = ty0 + rr / TX;
+        if (gi < S.n_u && gj < S.n_v) {
+            const int a = gj * S.n_u + gi;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T y = ys[rs * PG][c][l];
+#pragma unroll
+                for (int q = 1; q < PG; ++q) y += ys[rs * PG + q][c][l];
+                const double wc = double(y);
+                B.w_out[c * n + a] = wc;
+                del += wc * u64[c][rr];
+            }
+        }
     }
+    double v[3] = {gam, del, rho};
     block_sum3(v, sh);
-    const double gam = v[0], del = v[1], rho = v[2];
-    double tol2;
-    if (it == 0) {
-        double b3[3] = {0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < nb_init; t += blockDim.x) b3[0] += pbb[t];
-        block_sum3(b3, sh);
-        const double rtol = scal[S_RTOL];
-        tol2 = rtol * rtol * b3[0];
-        if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_TOL2] = tol2;
-    } else {
-        tol2 = scal[S_TOL2];
+    if (threadIdx.x == 0) {
+        B.part_out[blockIdx.x] = v[0];
+        B.part_out[B.stride + blockIdx.x] = v[1];
+        B.part_out[2 * B.stride + blockIdx.x] = v[2];
     }
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (rho <= tol2 || it >= isc[I_MAXIT] || !(rho == rho)) {
-        if (lead) { isc[I_ITERS] = it; isc[I_DONE] = 1; }
-        return;
-    }
-    double alpha, beta;
-    if (it == 0) {
-        beta = 0.0;
-        alpha = del > 0.0 ? gam / del : -1.0;
-    } else {
-        const double gprev = scal[S_GAMMA0 + ((it + 1) & 1)], aprev = scal[S_ALPHA0 + ((it + 1) & 1)];
-        beta = gam / gprev;
-        const double den = del - beta * gam / aprev;
-        alpha = den > 0.0 ? gam / den : -1.0;
-    }
-    if (!(alpha > 0.0)) {                       // p^T A p <= 0: breakdown
-        if (lead) { isc[I_ITERS] = it; isc[I_BREAK] = 1; isc[I_DONE] = 1; }
-        return;
-    }
-    if (lead) {
-        scal[S_GAMMA0 + (it & 1)] = gam;
-        scal[S_ALPHA0 + (it & 1)] = alpha;
-        isc[I_ITB] = it + 1;
-    }
-    if (!active) return;
-    double rv[3], uv[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const size_t k = c * n + a;
-        const double pc = uo[c] + beta * po[c];
-        const double sc = wo[c] + beta * so[c];
-        p[k] = pc;
-        sv[k] = sc;
-        x[k] += alpha * pc;
-        rv[c] = ro[c] - alpha * sc;
-        r[k] = rv[c];
-    }
-    uv[0] = pi[0] * rv[0] + pi[1] * rv[1] + pi[2] * rv[2];
-    uv[1] = pi[1] * rv[0] + pi[3] * rv[1] + pi[4] * rv[2];
-    uv[2] = pi[2] * rv[0] + pi[4] * rv[1] + pi[5] * rv[2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) u[c * n + a] = uv[c];
 }
 
 // ---- warm start and sample log ------------------------------------------------------------
@@ -639,13 +745,14 @@ __global__ void k_update(int n, double alpha, const double *__restrict__ p, doub
 }  // namespace
 
 inline int spmv_blocks(int n_cp) { return (n_cp + kRowsPerTile - 1) / kRowsPerTile; }
+inline int cg_blocks(int n_u, int n_v) { return ((n_u + kCgTileU - 1) / kCgTileU) * ((n_v + kCgTileV - 1) / kCgTileV); }
 
 hipError_t launch_spmv(const DevSheet &S, int precision, const void *hess, const double *in, double *out, hipStream_t st) {
     const int nb = spmv_blocks(S.n_cp);
     if (precision == BSC_FP64)
-        k_spmv_tile<double, false><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const double *)hess, in, out, nullptr, nullptr, 0, nullptr);
+        k_spmv_tile<double><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const double *)hess, in, out);
     else
-        k_spmv_tile<float, false><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const float *)hess, in, out, nullptr, nullptr, 0, nullptr);
+        k_spmv_tile<float><<<nb, kRowsPerTile * kGroups, 0, st>>>(S, (const float *)hess, in, out);
     return hipGetLastError();
 }
 
@@ -775,10 +882,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, B.pinv);
             k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
             HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
-            // CG vectors: r, u (= M^-1 r), w (= A u), p, s
-            double *r = B.r, *u = B.z, *w = B.q, *p = B.p0, *sv = B.p1;
-            const int nbs = spmv_blocks(S.n_cp), nbi = blocks(S.n_cp);
-            double *ppart = B.partials, *pbb = B.partials + 3 * stride;
+            // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
+            // is recomputed where it is needed)
+            double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
+            double *p = B.p0, *w = wb[0];
+            const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
+            double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
             const double *q0 = nullptr;
             if (o->warm_start) {
                 // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
@@ -813,19 +922,33 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 s.ms_warmstart += tw.stop();
                 q0 = use ? w : nullptr;
             }
-            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, B.pinv, r, u, p, sv, pbb, B.iscalars, B.scalars,
+            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
                                                o->max_pcg, eta);
+            auto bufs = [&](int j) {
+                CgBufs c{};
+                c.x = B.dir; c.p = p; c.pinv = B.pinv;
+                c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
+                const int cur = j & 1, prev = (j + 1) & 1;
+                c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
+                c.w_in = wb[prev]; c.w_out = wb[cur];
+                c.s_in = sb[prev]; c.s_out = sb[cur];
+                c.part_in = part[prev]; c.part_out = part[cur];
+                c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
+                return c;
+            };
+            if (prec == BSC_FP64)
+                k_cg_fused<double, true><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+            else
+                k_cg_fused<float, true><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
             HIPX(hipGetLastError(), "cg init");
             int32_t flags[6] = {0, 0, 0, 0, 0, 0};
-            const int chunk = 16;
+            const int chunk = 16;                   // even: every chunk starts on an odd launch
             auto enqueue_chunk = [&](hipStream_t cs) {
-                for (int c = 0; c < chunk; ++c) {
+                for (int c = 1; c <= chunk; ++c) {
                     if (prec == BSC_FP64)
-                        k_spmv_tile<double, true><<<nbs, kRowsPerTile * kGroups, 0, cs>>>(S, (const double *)B.hess, u, w, r, ppart, stride, B.iscalars);
+                        k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
                     else
-                        k_spmv_tile<float, true><<<nbs, kRowsPerTile * kGroups, 0, cs>>>(S, (const float *)B.hess, u, w, r, ppart, stride, B.iscalars);
-                    k_cg_update<<<nbi, kBlock, 0, cs>>>(S, B.dir, r, u, w, p, sv, B.pinv, ppart, stride, nbs, pbb, nbi,
-                                                         B.scalars, B.iscalars);
+                        k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
                 }
             };
             // The chunk is captured once into a graph (on a private stream) and replayed on the
