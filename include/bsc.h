@@ -91,10 +91,18 @@ typedef struct {
     int32_t pcg_adaptive;
 } bsc_step_opts;
 
+/* Statistics of one step. ms_* are wall-clock phase times on the host (each phase ends with a
+ * stream synchronisation). The PCG iterations run as launches of one fused kernel (one per
+ * iteration, replayed in fixed-size chunks; launches after convergence exit at once):
+ * cg_launches counts them, cg_active_launches those that performed an iteration, and
+ * ms_cg_kernels is their GPU time from HIP events recorded on the context's stream around
+ * each chunk. */
 typedef struct {
     int32_t newton_iters, pcg_iters_total, ls_halvings, warm_start_used, warm_start_fallbacks;
     double g0_norm, g_norm, energy;
     double ms_assemble, ms_pcg, ms_linesearch, ms_warmstart, ms_total;
+    int32_t cg_launches, cg_active_launches;
+    double ms_cg_kernels;
 } bsc_step_stats;
 
 /* Sizes of a context: CPs, elements, membrane quadrature points, bending evaluations (four per

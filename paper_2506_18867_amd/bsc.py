@@ -62,7 +62,9 @@ class StepStats(ctypes.Structure):
                 ("warm_start_fallbacks", ctypes.c_int32), ("g0_norm", ctypes.c_double),
                 ("g_norm", ctypes.c_double), ("energy", ctypes.c_double), ("ms_assemble", ctypes.c_double),
                 ("ms_pcg", ctypes.c_double), ("ms_linesearch", ctypes.c_double),
-                ("ms_warmstart", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_warmstart", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("cg_launches", ctypes.c_int32), ("cg_active_launches", ctypes.c_int32),
+                ("ms_cg_kernels", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

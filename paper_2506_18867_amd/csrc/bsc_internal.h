@@ -33,8 +33,20 @@ constexpr int kCgTileU = 64, kCgTileV = 2;
 constexpr int kSlotDi[kSlots] = {0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};
 constexpr int kSlotDj[kSlots] = {0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2};
 
+// The same offsets computed arithmetically: a runtime index into the tables above becomes a
+// memory load on the device, which stalls the loads whose addresses depend on it.
+__host__ __device__ constexpr int slot_di(int s) { return s <= 2 ? s : (s <= 7 ? s - 5 : s - 10); }
+__host__ __device__ constexpr int slot_dj(int s) { return s == 0 ? 0 : (s <= 2 ? 0 : (s <= 7 ? 1 : 2)); }
+
 // First Hessian entry of a slot: 0 for the diagonal (6 entries), 6 + 9 (s - 1) otherwise.
 __host__ __device__ constexpr int slot_entry(int s) { return s == 0 ? 0 : 6 + 9 * (s - 1); }
+
+constexpr bool slot_offsets_agree() {
+    for (int s = 0; s < kSlots; ++s)
+        if (slot_di(s) != kSlotDi[s] || slot_dj(s) != kSlotDj[s]) return false;
+    return true;
+}
+static_assert(slot_offsets_agree(), "slot offsets");
 
 // Slot of an offset, or -1 for a lower offset / outside the 5x5 neighbourhood.
 __host__ __device__ inline int upper_slot(int di, int dj) {
@@ -108,9 +120,14 @@ struct bsc_ctx {
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
     float *log_g = nullptr, *log_p = nullptr;
     int log_cap = 0, log_count = 0;
+    // events around the CG chunks (created at the first Newton step)
+    hipEvent_t cg_ev[2] = {nullptr, nullptr};
+    bool cg_ev_ok = false, cg_ev_tried = false;
     ~bsc_ctx() {
         for (auto &g : cg_graph)
             if (g) (void)hipGraphExecDestroy(g);
+        for (auto &e : cg_ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 

@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(kBlock) k_hess(DevSheet S, const T *__restrict
     const int s = blockIdx.y;
     if (a >= S.n_cp) return;
     const int i = a % S.n_u, j = a / S.n_u;
-    const int ib = i + kSlotDi[s], jb = j + kSlotDj[s];
+    const int ib = i + slot_di(s), jb = j + slot_dj(s);
     const int e0 = slot_entry(s);
     const size_t ncp = S.n_cp;
     T acc[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};

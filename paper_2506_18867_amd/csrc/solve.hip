@@ -81,6 +81,32 @@ __device__ void block_sum3(double v[3], double *sh /* 3 * 16 */) {
     }
 }
 
+// Butterfly sum over a wave: every lane ends with the same, bitwise identical total (each
+// step adds the same two numbers in both lanes of a pair).
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Block totals of three values whose per-wave totals are already in every lane (one LDS round
+// trip); valid in every thread, summed over the waves in a fixed order.
+__device__ void wave_totals3(double v[3], double *sh /* 3 * 16 */) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sh[16 * k + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += sh[16 * k + q];
+        v[k] = t;
+    }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every
 // XCD a contiguous range of row tiles so that the neighbour rows a - d_s (whose stored upper
 // blocks the lower products read) are usually in the same L2.
@@ -107,7 +133,7 @@ __device__ __forceinline__ void block_product(const DevSheet &S, const T *__rest
     }
     const bool upper = pid <= 12;
     const int s = upper ? pid : pid - 12;
-    const int di = kSlotDi[s], dj = kSlotDj[s], e0 = slot_entry(s);
+    const int di = slot_di(s), dj = slot_dj(s), e0 = slot_entry(s);
     if (upper) {
         const int ib = i + di, jb = j + dj;
         if (ib < 0 || ib >= S.n_u || jb >= S.n_v) return;
@@ -354,6 +380,7 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
                                                   int32_t *isc) {
     constexpr int TX = kCgTileU, TY = kCgTileV, HX = TX + 4, HY = TY + 4, R = TX * TY;
     constexpr int RS = R / 64, PG = 8 / RS;      // 64-row sets, product groups per set
+    constexpr int NP = (25 + PG - 1) / PG;       // block products per wave
     static_assert(R % 64 == 0 && 8 % RS == 0 && HX * HY <= 512, "tile shape");
     __shared__ T us[3][HY][HX];
     __shared__ double u64[3][R];
@@ -366,25 +393,80 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     const int tx0 = (tile % ntx) * TX, ty0 = (tile / ntx) * TY;
     const size_t n = S.n_cp;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    double alpha = 0.0, beta = 0.0;
+
+    // (1) loads that do not depend on this launch's scalars: first the partials and scalars of
+    //     the previous launch (waited for at once), then the footprint vectors (in flight during
+    //     the cross-wave half of the reduction)
+    double v[3] = {0.0, 0.0, 0.0};
+    int it = 0, maxit = 0;
+    double tol2 = 0.0, gam01[2] = {0.0, 0.0}, alp01[2] = {0.0, 0.0};
     if (!FIRST) {
-        const int it = isc[B.slot_in];            // CG updates done before this launch (j - 1)
-        double v[3] = {0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+        it = isc[B.slot_in];                      // CG updates done before this launch (j - 1)
+        maxit = isc[I_MAXIT];
+        tol2 = scal[S_TOL2];
+        gam01[0] = scal[S_GAMMA0]; gam01[1] = scal[S_GAMMA1];
+        alp01[0] = scal[S_ALPHA0]; alp01[1] = scal[S_ALPHA1];
+        if (int(threadIdx.x) < nb) {
+            v[0] = B.part_in[threadIdx.x];
+            v[1] = B.part_in[B.stride + threadIdx.x];
+            v[2] = B.part_in[2 * B.stride + threadIdx.x];
+        }
+        for (int t = threadIdx.x + blockDim.x; t < nb; t += blockDim.x) {
             v[0] += B.part_in[t];
             v[1] += B.part_in[B.stride + t];
             v[2] += B.part_in[2 * B.stride + t];
         }
-        block_sum3(v, sh);
+    } else if (blockIdx.x == 0) {
+        for (int t = threadIdx.x; t < B.nb_init; t += blockDim.x) v[0] += B.pbb[t];
+    }
+    // wave sums now, so that only the partials are waited for; the cross-wave half of the
+    // reduction runs after the loads below are issued (a barrier does not wait for loads)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_sum_all(v[k]);
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rs = g / PG, pg = g % PG;
+    const int rrow = rs * 64 + lane;
+    const int lx = rrow % TX, ly = rrow / TX;
+    const int ri_ = tx0 + lx, rj_ = ty0 + ly;
+    const bool row_ok = ri_ < S.n_u && rj_ < S.n_v;
+    const int ra = row_ok ? rj_ * S.n_u + ri_ : 0;
+    // the footprint CP of this thread (the tile and its 2-CP halo)
+    const int t = threadIdx.x;
+    const int hx = t % HX, hy = t / HX;
+    const int fi = tx0 - 2 + hx, fj = ty0 - 2 + hy;
+    const bool fp = t < HX * HY && fi >= 0 && fi < S.n_u && fj >= 0 && fj < S.n_v;
+    const bool own = fp && hx >= 2 && hx < 2 + TX && hy >= 2 && hy < 2 + TY;
+    const int fa = fp ? fj * S.n_u + fi : 0;
+    double rin[3] = {0.0, 0.0, 0.0}, win[3] = {0.0, 0.0, 0.0}, sin_[3] = {0.0, 0.0, 0.0};
+    double po[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0}, pv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (fp) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rin[c] = B.r_in[c * n + fa];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pv[k] = B.pinv[k * n + fa];
+        if (!FIRST) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { win[c] = B.w_in[c * n + fa]; sin_[c] = B.s_in[c * n + fa]; }
+            if (own) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { po[c] = B.p[c * n + fa]; xo[c] = B.x[c * n + fa]; }
+            }
+        }
+    }
+
+    // (2) prologue: the scalars of iteration j-1 (bitwise the same in every block)
+    double alpha = 0.0, beta = 0.0;
+    if (!FIRST) {
+        wave_totals3(v, sh);
         const double gam = v[0], del = v[1], rho = v[2];
-        if (rho <= scal[S_TOL2] || it >= isc[I_MAXIT] || !(rho == rho)) {
+        if (rho <= tol2 || it >= maxit || !(rho == rho)) {
             if (lead) { isc[I_ITERS] = it; isc[I_DONE] = 1; }
             return;
         }
         if (it == 0) {
             alpha = del > 0.0 ? gam / del : -1.0;
         } else {
-            const double gprev = scal[S_GAMMA0 + ((it + 1) & 1)], aprev = scal[S_ALPHA0 + ((it + 1) & 1)];
+            const double gprev = gam01[(it + 1) & 1], aprev = alp01[(it + 1) & 1];
             beta = gam / gprev;
             const double den = del - beta * gam / aprev;
             alpha = den > 0.0 ? gam / den : -1.0;
@@ -399,112 +481,98 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
             isc[B.slot_out] = it + 1;
         }
     } else if (blockIdx.x == 0) {                 // uniform per block
-        double v[3] = {0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < B.nb_init; t += blockDim.x) v[0] += B.pbb[t];
-        block_sum3(v, sh);
+        wave_totals3(v, sh);
         if (threadIdx.x == 0) {
             scal[S_TOL2] = scal[S_RTOL] * scal[S_RTOL] * v[0];
             isc[B.slot_out] = 0;
         }
     }
+
+    // (3) footprint: s, r, u = M^-1 r; own CPs also p, x and the stores
     double gam = 0.0, rho = 0.0, del = 0.0;
-    {
-        const int t = threadIdx.x;
-        if (t < HX * HY) {
-            const int hx = t % HX, hy = t / HX;
-            const int gi = tx0 - 2 + hx, gj = ty0 - 2 + hy;
-            double uv[3] = {0.0, 0.0, 0.0};
-            if (gi >= 0 && gi < S.n_u && gj >= 0 && gj < S.n_v) {
-                const int a = gj * S.n_u + gi;
-                const bool own = hx >= 2 && hx < 2 + TX && hy >= 2 && hy < 2 + TY;
-                double ri[3], rv[3], sc[3], po[3], xo[3];
+    if (t < HX * HY) {
+        double uv[3] = {0.0, 0.0, 0.0};
+        if (fp) {
+            double rv[3], sc[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ri[c] = B.r_in[c * n + a];
+            for (int c = 0; c < 3; ++c) {
+                sc[c] = win[c] + beta * sin_[c];
+                rv[c] = FIRST ? rin[c] : rin[c] - alpha * sc[c];
+            }
+            uv[0] = pv[0] * rv[0] + pv[1] * rv[1] + pv[2] * rv[2];
+            uv[1] = pv[1] * rv[0] + pv[3] * rv[1] + pv[4] * rv[2];
+            uv[2] = pv[2] * rv[0] + pv[4] * rv[1] + pv[5] * rv[2];
+            if (own) {
                 if (!FIRST) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) sc[c] = B.w_in[c * n + a] + beta * B.s_in[c * n + a];
-                    if (own) {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) { po[c] = B.p[c * n + a]; xo[c] = B.x[c * n + a]; }
-                    }
-                }
-                if (FIRST) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) rv[c] = ri[c];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) rv[c] = ri[c] - alpha * sc[c];
-                }
-                apply_pinv(B.pinv, n, a, rv, uv);
-                if (own) {
-                    if (!FIRST) {
-                        double uo[3];
-                        apply_pinv(B.pinv, n, a, ri, uo);
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const size_t k = c * n + a;
-                            const double pc = uo[c] + beta * po[c];
-                            B.p[k] = pc;
-                            B.x[k] = xo[c] + alpha * pc;
-                            B.s_out[k] = sc[c];
-                            B.r_out[k] = rv[c];
-                        }
-                    }
-                    const int o = (hy - 2) * TX + (hx - 2);
+                    double uo[3];
+                    uo[0] = pv[0] * rin[0] + pv[1] * rin[1] + pv[2] * rin[2];
+                    uo[1] = pv[1] * rin[0] + pv[3] * rin[1] + pv[4] * rin[2];
+                    uo[2] = pv[2] * rin[0] + pv[4] * rin[1] + pv[5] * rin[2];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        u64[c][o] = uv[c];
-                        gam += rv[c] * uv[c];
-                        rho += rv[c] * rv[c];
+                        const size_t k = c * n + fa;
+                        const double pc = uo[c] + beta * po[c];
+                        B.p[k] = pc;
+                        B.x[k] = xo[c] + alpha * pc;
+                        B.s_out[k] = sc[c];
+                        B.r_out[k] = rv[c];
                     }
                 }
-            }
+                const int o = (hy - 2) * TX + (hx - 2);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) us[c][hy][hx] = T(uv[c]);
+                for (int c = 0; c < 3; ++c) {
+                    u64[c][o] = uv[c];
+                    gam += rv[c] * uv[c];
+                    rho += rv[c] * rv[c];
+                }
+            }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) us[c][hy][hx] = T(uv[c]);
     }
     __syncthreads();
-    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    // (4) w = A u for the wave's block products, u from LDS
     {
-        const int rs = g / PG, pg = g % PG;
-        const int rr = rs * 64 + lane;
-        const int lx = rr % TX, ly = rr / TX;
-        const int gi = tx0 + lx, gj = ty0 + ly;
         T acc[3] = {T(0), T(0), T(0)};
-        if (gi < S.n_u && gj < S.n_v) {
-            const int a = gj * S.n_u + gi;
+        if (row_ok) {
 #pragma unroll
-            for (int m = 0; m < (25 + PG - 1) / PG; ++m) {
+            for (int m = 0; m < NP; ++m) {
                 const int pid = pg + PG * m;
                 if (pid >= 25) break;
                 if (pid == 0) {
+                    T h[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) h[k] = H[k * n + ra];
                     const T u0 = us[0][ly + 2][lx + 2], u1 = us[1][ly + 2][lx + 2], u2 = us[2][ly + 2][lx + 2];
-                    const T d0 = H[a], d1 = H[n + a], d2 = H[2 * n + a], d3 = H[3 * n + a], d4 = H[4 * n + a], d5 = H[5 * n + a];
-                    acc[0] += d0 * u0 + d1 * u1 + d2 * u2;
-                    acc[1] += d1 * u0 + d3 * u1 + d4 * u2;
-                    acc[2] += d2 * u0 + d4 * u1 + d5 * u2;
+                    acc[0] += h[0] * u0 + h[1] * u1 + h[2] * u2;
+                    acc[1] += h[1] * u0 + h[3] * u1 + h[4] * u2;
+                    acc[2] += h[2] * u0 + h[4] * u1 + h[5] * u2;
                     continue;
                 }
                 const bool upper = pid <= 12;
                 const int sl = upper ? pid : pid - 12;
-                const int di = kSlotDi[sl], dj = kSlotDj[sl], e0 = slot_entry(sl);
+                const int di = slot_di(sl), dj = slot_dj(sl), e0 = slot_entry(sl);
+                T h[9];
                 if (upper) {
-                    const int ib = gi + di, jb = gj + dj;
+                    const int ib = ri_ + di, jb = rj_ + dj;
                     if (ib < 0 || ib >= S.n_u || jb >= S.n_v) continue;
-                    const int hy = ly + 2 + dj, hx = lx + 2 + di;
-                    const T u0 = us[0][hy][hx], u1 = us[1][hy][hx], u2 = us[2][hy][hx];
 #pragma unroll
-                    for (int q = 0; q < 3; ++q)
-                        acc[q] += H[(e0 + 3 * q) * n + a] * u0 + H[(e0 + 3 * q + 1) * n + a] * u1 + H[(e0 + 3 * q + 2) * n + a] * u2;
+                    for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + ra];
+                    const int yy = ly + 2 + dj, xx = lx + 2 + di;
+                    const T u0 = us[0][yy][xx], u1 = us[1][yy][xx], u2 = us[2][yy][xx];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) acc[q] += h[3 * q] * u0 + h[3 * q + 1] * u1 + h[3 * q + 2] * u2;
                 } else {
-                    const int ic = gi - di, jc = gj - dj;
+                    const int ic = ri_ - di, jc = rj_ - dj;
                     if (ic < 0 || ic >= S.n_u || jc < 0) continue;
-                    const int b = jc * S.n_u + ic;
-                    const int hy = ly + 2 - dj, hx = lx + 2 - di;
-                    const T u0 = us[0][hy][hx], u1 = us[1][hy][hx], u2 = us[2][hy][hx];
+                    const int src = jc * S.n_u + ic;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        acc[c] += H[(e0 + c) * n + b] * u0 + H[(e0 + 3 + c) * n + b] * u1 + H[(e0 + 6 + c) * n + b] * u2;
+                    for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + src];
+                    const int yy = ly + 2 - dj, xx = lx + 2 - di;
+                    const T u0 = us[0][yy][xx], u1 = us[1][yy][xx], u2 = us[2][yy][xx];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += h[c] * u0 + h[3 + c] * u1 + h[6 + c] * u2;
                 }
             }
         }
@@ -512,28 +580,30 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
         for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
     }
     __syncthreads();
+
+    // (5) w_j, the partials r.u, w.u, r.r
     if (threadIdx.x < R) {
-        const int rr = threadIdx.x, rs = rr >> 6, l = rr & 63;
+        const int rr = threadIdx.x, rset = rr >> 6, l = rr & 63;
         const int gi = tx0 + rr % TX, gj = ty0 + rr / TX;
         if (gi < S.n_u && gj < S.n_v) {
             const int a = gj * S.n_u + gi;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                T y = ys[rs * PG][c][l];
+                T y = ys[rset * PG][c][l];
 #pragma unroll
-                for (int q = 1; q < PG; ++q) y += ys[rs * PG + q][c][l];
+                for (int q = 1; q < PG; ++q) y += ys[rset * PG + q][c][l];
                 const double wc = double(y);
                 B.w_out[c * n + a] = wc;
                 del += wc * u64[c][rr];
             }
         }
     }
-    double v[3] = {gam, del, rho};
-    block_sum3(v, sh);
+    double w3[3] = {gam, del, rho};
+    block_sum3(w3, sh);
     if (threadIdx.x == 0) {
-        B.part_out[blockIdx.x] = v[0];
-        B.part_out[B.stride + blockIdx.x] = v[1];
-        B.part_out[2 * B.stride + blockIdx.x] = v[2];
+        B.part_out[blockIdx.x] = w3[0];
+        B.part_out[B.stride + blockIdx.x] = w3[1];
+        B.part_out[2 * B.stride + blockIdx.x] = w3[2];
     }
 }
 
@@ -826,6 +896,11 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const int stride = B.max_blocks;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
+    if (!ctx->cg_ev_tried) {
+        ctx->cg_ev_tried = true;
+        ctx->cg_ev_ok = hipEventCreate(&ctx->cg_ev[0]) == hipSuccess && hipEventCreate(&ctx->cg_ev[1]) == hipSuccess;
+        if (!ctx->cg_ev_ok) (void)hipGetLastError();
+    }
 
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
@@ -972,13 +1047,22 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 }
             }
             while (true) {
+                if (ctx->cg_ev_ok) HIPX(hipEventRecord(ctx->cg_ev[0], st), "cg event");
                 if (gx) HIPX(hipGraphLaunch(gx, st), "cg graph");
                 else enqueue_chunk(st);
                 HIPX(hipGetLastError(), "cg");
+                if (ctx->cg_ev_ok) HIPX(hipEventRecord(ctx->cg_ev[1], st), "cg event");
                 HIPX(hipMemcpyAsync(flags, B.iscalars, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read cg flags");
                 HIPX(hipStreamSynchronize(st), "sync cg");
+                if (ctx->cg_ev_ok) {
+                    float ms = 0.f;
+                    HIPX(hipEventElapsedTime(&ms, ctx->cg_ev[0], ctx->cg_ev[1]), "cg event time");
+                    s.ms_cg_kernels += ms;
+                }
+                s.cg_launches += chunk;
                 if (flags[I_DONE]) break;
             }
+            s.cg_active_launches += flags[I_ITERS];
             const int32_t brk = flags[I_BREAK];
             flags[1] = flags[I_ITERS];
             s.pcg_iters_total += flags[1];
