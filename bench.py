@@ -171,13 +171,14 @@ def main():
 
     # Algorithmic bytes. Assembly: reads x (24 B/CP), writes g and the 114-entry upper-stencil
     # Hessian. SpMV: reads the Hessian and x, writes y. Fused CG iteration (k_cg_fused, FP32
-    # Hessian): reads the Hessian (456 B/CP), r, w, s, p, x (5 x 24 B) and the block-Jacobi
-    # inverse (48 B); writes p, x, s, r, w (5 x 24 B): 744 B per CP per iteration.
+    # Hessian): reads the Hessian (456 B/CP), r, s, p, x (4 x 24 B, double), w (12 B, float: the
+    # FP32 SpMV's output) and the block-Jacobi inverse (6 floats, 24 B); writes p, x, s, r
+    # (4 x 24 B) and w (12 B): 696 B per CP per iteration.
     asm_bytes32 = n * (24 + 3 * 4 + 114 * 4)
     asm_bytes64 = n * (24 + 3 * 8 + 114 * 8)
     spmv_bytes32 = n * (114 * 4 + 24 + 24)
     spmv_bytes64 = n * (114 * 8 + 24 + 24)
-    cg_bytes32 = n * (114 * 4 + 5 * 24 + 48 + 5 * 24)
+    cg_bytes32 = n * (114 * 4 + 4 * 24 + 12 + 24 + 4 * 24 + 12)
     newton32 = sum(s["newton_iters"] for s in st32)
     pcg32 = sum(s["pcg_iters_total"] for s in st32)
     ms_step32 = 1e3 * sec32 / args.steps

@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // k_cg_fused per iteration (below).
 
 template <typename T>
-__global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, double *__restrict__ pinv) {
+__global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.n_cp) return;
     const size_t n = S.n_cp;
@@ -309,14 +309,7 @@ __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, double *__re
         inv[0] = a00 > 0.0 ? 1.0 / a00 : 1.0; inv[1] = inv[2] = 0.0;
         inv[3] = a11 > 0.0 ? 1.0 / a11 : 1.0; inv[4] = 0.0; inv[5] = a22 > 0.0 ? 1.0 / a22 : 1.0;
     }
-    for (int t = 0; t < 6; ++t) pinv[t * n + a] = inv[t];
-}
-
-__device__ __forceinline__ void apply_pinv(const double *__restrict__ P, size_t n, int a, const double r[3], double z[3]) {
-    const double i0 = P[a], i1 = P[n + a], i2 = P[2 * n + a], i3 = P[3 * n + a], i4 = P[4 * n + a], i5 = P[5 * n + a];
-    z[0] = i0 * r[0] + i1 * r[1] + i2 * r[2];
-    z[1] = i1 * r[0] + i3 * r[1] + i4 * r[2];
-    z[2] = i2 * r[0] + i4 * r[1] + i5 * r[2];
+    for (int t = 0; t < 6; ++t) pinv[t * n + a] = T(inv[t]);
 }
 
 // r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b.
@@ -365,9 +358,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
 
 struct CgBufs {
     double *x, *p;
-    const double *r_in, *w_in, *s_in;             // r_{j-1}, w_{j-1}, s_{j-2}
-    double *r_out, *w_out, *s_out;                // r_j, w_j, s_{j-1}
-    const double *pinv;
+    const double *r_in, *s_in;                    // r_{j-1}, s_{j-2}
+    double *r_out, *s_out;                        // r_j, s_{j-1}
+    const void *w_in;                             // w_{j-1}, working precision (SpMV output)
+    void *w_out;                                  // w_j
+    const void *pinv;                             // block-Jacobi inverse, working precision
     const double *part_in;                        // 3 arrays (stride) from K_{j-1}
     double *part_out;                             // 3 arrays (stride) for K_{j+1}
     const double *pbb;                            // b.b partials of the init kernel (FIRST)
@@ -387,6 +382,9 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     __shared__ T ys[8][3][64];
     __shared__ double sh[48];
     if (isc[I_DONE]) return;
+    const T *__restrict__ w_in = (const T *)B.w_in;
+    const T *__restrict__ pinv = (const T *)B.pinv;
+    T *__restrict__ w_out = (T *)B.w_out;
     const int nb = gridDim.x;
     const int ntx = (S.n_u + TX - 1) / TX;
     const int tile = xcd_tile(blockIdx.x, nb);
@@ -443,10 +441,10 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
 #pragma unroll
         for (int c = 0; c < 3; ++c) rin[c] = B.r_in[c * n + fa];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) pv[k] = B.pinv[k * n + fa];
+        for (int k = 0; k < 6; ++k) pv[k] = double(pinv[k * n + fa]);
         if (!FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { win[c] = B.w_in[c * n + fa]; sin_[c] = B.s_in[c * n + fa]; }
+            for (int c = 0; c < 3; ++c) { win[c] = double(w_in[c * n + fa]); sin_[c] = B.s_in[c * n + fa]; }
             if (own) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { po[c] = B.p[c * n + fa]; xo[c] = B.x[c * n + fa]; }
@@ -532,48 +530,48 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     }
     __syncthreads();
 
-    // (4) w = A u for the wave's block products, u from LDS
+    // (4) w = A u for the wave's block products, u from LDS. In FP32, out-of-grid neighbours read
+    //     a valid row and take u = 0, so the body has no data-dependent branch and the compiler
+    //     keeps several products' loads in flight; FP64 blocks take twice the registers, so there
+    //     they are skipped by a branch (higher occupancy).
+    constexpr bool BRANCH_FREE = sizeof(T) == 4;
     {
         T acc[3] = {T(0), T(0), T(0)};
-        if (row_ok) {
 #pragma unroll
-            for (int m = 0; m < NP; ++m) {
-                const int pid = pg + PG * m;
-                if (pid >= 25) break;
-                if (pid == 0) {
-                    T h[6];
+        for (int m = 0; m < NP; ++m) {
+            const int pid = pg + PG * m;                 // wave-uniform
+            if (pid >= 25) break;
+            if (pid == 0) {
+                T h[6];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) h[k] = H[k * n + ra];
-                    const T u0 = us[0][ly + 2][lx + 2], u1 = us[1][ly + 2][lx + 2], u2 = us[2][ly + 2][lx + 2];
-                    acc[0] += h[0] * u0 + h[1] * u1 + h[2] * u2;
-                    acc[1] += h[1] * u0 + h[3] * u1 + h[4] * u2;
-                    acc[2] += h[2] * u0 + h[4] * u1 + h[5] * u2;
-                    continue;
-                }
-                const bool upper = pid <= 12;
-                const int sl = upper ? pid : pid - 12;
-                const int di = slot_di(sl), dj = slot_dj(sl), e0 = slot_entry(sl);
-                T h[9];
-                if (upper) {
-                    const int ib = ri_ + di, jb = rj_ + dj;
-                    if (ib < 0 || ib >= S.n_u || jb >= S.n_v) continue;
+                for (int k = 0; k < 6; ++k) h[k] = H[k * n + ra];
+                const T u0 = us[0][ly + 2][lx + 2], u1 = us[1][ly + 2][lx + 2], u2 = us[2][ly + 2][lx + 2];
+                acc[0] += h[0] * u0 + h[1] * u1 + h[2] * u2;
+                acc[1] += h[1] * u0 + h[3] * u1 + h[4] * u2;
+                acc[2] += h[2] * u0 + h[4] * u1 + h[5] * u2;
+                continue;
+            }
+            const bool upper = pid <= 12;
+            const int sl = upper ? pid : pid - 12;
+            const int di = slot_di(sl), dj = slot_dj(sl), e0 = slot_entry(sl);
+            const int sgn = upper ? 1 : -1;
+            const int ib = ri_ + sgn * di, jb = rj_ + sgn * dj;
+            const bool ok = row_ok && ib >= 0 && ib < S.n_u && jb >= 0 && jb < S.n_v;
+            if constexpr (!BRANCH_FREE) {
+                if (!ok) continue;
+            }
+            const int src = (upper || !ok) ? ra : jb * S.n_u + ib;
+            T h[9];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + ra];
-                    const int yy = ly + 2 + dj, xx = lx + 2 + di;
-                    const T u0 = us[0][yy][xx], u1 = us[1][yy][xx], u2 = us[2][yy][xx];
+            for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + src];
+            const int yy = ly + 2 + sgn * dj, xx = lx + 2 + sgn * di;
+            const T u0 = ok ? us[0][yy][xx] : T(0), u1 = ok ? us[1][yy][xx] : T(0), u2 = ok ? us[2][yy][xx] : T(0);
+            if (upper) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) acc[q] += h[3 * q] * u0 + h[3 * q + 1] * u1 + h[3 * q + 2] * u2;
-                } else {
-                    const int ic = ri_ - di, jc = rj_ - dj;
-                    if (ic < 0 || ic >= S.n_u || jc < 0) continue;
-                    const int src = jc * S.n_u + ic;
+                for (int q = 0; q < 3; ++q) acc[q] += h[3 * q] * u0 + h[3 * q + 1] * u1 + h[3 * q + 2] * u2;
+            } else {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + src];
-                    const int yy = ly + 2 - dj, xx = lx + 2 - di;
-                    const T u0 = us[0][yy][xx], u1 = us[1][yy][xx], u2 = us[2][yy][xx];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] += h[c] * u0 + h[3 + c] * u1 + h[6 + c] * u2;
-                }
+                for (int c = 0; c < 3; ++c) acc[c] += h[c] * u0 + h[3 + c] * u1 + h[6 + c] * u2;
             }
         }
 #pragma unroll
@@ -592,9 +590,8 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
                 T y = ys[rset * PG][c][l];
 #pragma unroll
                 for (int q = 1; q < PG; ++q) y += ys[rset * PG + q][c][l];
-                const double wc = double(y);
-                B.w_out[c * n + a] = wc;
-                del += wc * u64[c][rr];
+                w_out[c * n + a] = y;
+                del += double(y) * u64[c][rr];
             }
         }
     }
@@ -954,13 +951,14 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         {
             Timer t(st);
             if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.hess, B.pinv);
-            else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, B.pinv);
+            else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv);
             k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
             HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
             // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
             // is recomputed where it is needed)
             double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
-            double *p = B.p0, *w = wb[0];
+            double *p = B.p0;
+            double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
             const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
             double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
             const double *q0 = nullptr;
@@ -972,8 +970,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
                                       B.net_scale, B.net_w_fwd, true, st), "warm start forward");
                 k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
-                HIPX(launch_spmv(S, prec, B.hess, B.phat, w, st), "warm start spmv");
-                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, w, B.partials + 4 * stride, stride);
+                HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
+                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
                 k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
                 HIPX(hipGetLastError(), "warm start");
                 double d4[4];
@@ -989,13 +987,13 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                     if (as != 0.0 && rr < bb) {
                         use = true;
                         k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
-                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, w, 0.0, w, w);                  // q0 = H x0
+                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
                     }
                 }
                 if (use) s.warm_start_used++;
                 else s.warm_start_fallbacks++;
                 s.ms_warmstart += tw.stop();
-                q0 = use ? w : nullptr;
+                q0 = use ? hq : nullptr;
             }
             k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
                                                o->max_pcg, eta);
