@@ -71,7 +71,62 @@ struct DevSheet {
     const double *be_tu, *be_tv, *be_w;
     const double *mass, *hbend;
     const int32_t *pinmask;
+    // tiled assembly (k_assemble_tile): tile height and the per-tile maximum of the membrane
+    // points of the elements a tile touches, per precision combination (AsmKind)
+    int asm_ty[3], asm_maxp[3];
 };
+
+// Tiled assembly: tiles of kAsmTileU x ty CPs; the precision combinations of the per-point
+// Hessian (A), stress (P) and outputs.
+#ifndef BSC_ASM_TILE_U
+#define BSC_ASM_TILE_U 16
+#endif
+#ifndef BSC_ASM_THREADS
+#define BSC_ASM_THREADS 512
+#endif
+#ifndef BSC_ASM_LDS_KB
+#define BSC_ASM_LDS_KB 64
+#endif
+constexpr int kAsmTileU = BSC_ASM_TILE_U;
+constexpr int kAsmThreads = BSC_ASM_THREADS;
+enum AsmKind { kAsmF32 = 0, kAsmF64 = 1, kAsmMixed = 2 };   // (A, P, g) = (f, f, f), (d, d, d), (f, d, d)
+constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
+
+// LDS layout of one assembly tile (offsets in bytes): local membrane point offsets of the
+// (tx + 2) x (ty + 2) elements, the work counter, and per membrane point the weighted density
+// Hessian A (21 entries) plus either the gradients of its 9 local basis functions (18, when A
+// is FP32) or its span coordinates tu, tv (FP64: the gradients are recomputed).
+struct AsmLds {
+    size_t el_off, counter, A, dN, tu, tv, total;
+};
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+__host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int sizeA) {
+    AsmLds L;
+    const size_t ne = size_t(tx + 2) * (ty + 2);
+    L.el_off = 0;
+    L.counter = align16(L.el_off + 4 * (ne + 1));
+    L.A = align16(L.counter + 4);
+    const size_t after_a = align16(L.A + size_t(21) * sizeA * maxp);
+    if (sizeA == 4) {
+        L.dN = after_a;
+        L.tu = L.tv = 0;
+        L.total = align16(L.dN + size_t(18) * 4 * maxp);
+    } else {
+        L.dN = 0;
+        L.tu = after_a;
+        L.tv = L.tu + 8 * size_t(maxp);
+        L.total = align16(L.tv + 8 * size_t(maxp));
+    }
+    return L;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every
+// XCD a contiguous range of tiles so that neighbouring tiles, which read each other's halo
+// (stencil neighbours, shared elements), are usually in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + k;
+}
 
 // Device buffers carved out of the workspace.
 struct DevBufs {
@@ -140,15 +195,14 @@ DevSheet dev_sheet(const bsc_ctx *ctx);
 
 // ---- launchers (eval.hip) ----
 // Membrane points (w Psi, w P and, with hess, w A+), bending evaluations; element gather;
-// per-CP gradient; per-block Hessian gather; energy reduction.
+// tiled assembly of the per-CP gradient and (hess != NULL) the upper-stencil Hessian blocks
+// (kind: AsmKind); energy reduction (n_cp_partials: the assembly's tile count, or 0).
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
                          const double *x, hipStream_t st);
-hipError_t launch_grad(const DevSheet &S, const DevBufs &B, int precision, const double *x,
-                       const double *xhat, double inv_dt2, const double *grav, void *g,
-                       bool from64, hipStream_t st);
-hipError_t launch_hess(const DevSheet &S, const DevBufs &B, int precision, double inv_dt2, void *hess,
-                       hipStream_t st);
-hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, bool with_cp, double *out,
+int assemble_tiles(const DevSheet &S, int kind);
+hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
+                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st);
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out,
                                 hipStream_t st);
 hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,
                        hipStream_t st);

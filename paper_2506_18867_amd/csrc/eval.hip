@@ -6,9 +6,10 @@
 //   projected to PSD in double (Sec. 5.1); stored pre-multiplied by the point weight.
 //   bending evaluation: Laplacian of phi (Eq. "Laplacian in parametric space"), stored as
 //   w mu_bend Laplacian(phi) (Sec. 4.2).
-// Stage 2 (gathers, no atomics, deterministic): per CP gradient, per (CP, upper-stencil slot)
-//   3x3 Hessian block summing the weighted contributions of the quadrature points shared by
-//   the two CPs (Sec. 5.2, "Elasticity Hessian Assembly"), per element outputs.
+// Stage 2 (gathers, no atomics, deterministic): per CP gradient and per (CP, upper-stencil
+//   slot) 3x3 Hessian block summing the weighted contributions of the quadrature points shared
+//   by the two CPs (Sec. 5.2, "Elasticity Hessian Assembly"), one workgroup per tile of CPs with
+//   the tile's points staged in LDS; per element outputs.
 // Energies are reduced per block into partial sums and summed in a fixed order.
 #include "bsc_internal.h"
 
@@ -33,6 +34,49 @@ __device__ __forceinline__ void pieces(int type, T t, T N[3], T D[3]) {
         N[0] = T(0.5) * s * s; N[1] = s * (T(2) - T(1.5) * s); N[2] = t * t;
         D[0] = -s; D[1] = T(1) - T(3) * t; D[2] = T(2) * t;
     }
+}
+
+// Value, first and second derivative of local piece a (0..2) alone, selected without indexing
+// a local array (a runtime index into one would place it in scratch memory).
+template <typename T>
+__device__ __forceinline__ void piece_at(int type, int a, T t, T &n, T &d, T &d2) {
+    const T s = T(1) - t;
+    T n0, n1, n2, e0, e1, e2, f0, f1, f2;
+    if (type == kInner) {
+        n0 = T(0.5) * s * s; n1 = T(0.5) + t * s; n2 = T(0.5) * t * t;
+        e0 = -s; e1 = s - t; e2 = t;
+        f0 = T(1); f1 = T(-2); f2 = T(1);
+    } else if (type == kFirst) {
+        n0 = s * s; n1 = t * (T(2) - T(1.5) * t); n2 = T(0.5) * t * t;
+        e0 = T(-2) * s; e1 = T(2) - T(3) * t; e2 = t;
+        f0 = T(2); f1 = T(-3); f2 = T(1);
+    } else {
+        n0 = T(0.5) * s * s; n1 = s * (T(2) - T(1.5) * s); n2 = t * t;
+        e0 = -s; e1 = T(1) - T(3) * t; e2 = T(2) * t;
+        f0 = T(1); f1 = T(-3); f2 = T(2);
+    }
+    n = a == 0 ? n0 : (a == 1 ? n1 : n2);
+    d = a == 0 ? e0 : (a == 1 ? e1 : e2);
+    d2 = a == 0 ? f0 : (a == 1 ? f1 : f2);
+}
+
+// Gradient w.r.t. X of local basis function (a, b) of span (k, l) at (tu, tv).
+template <typename T>
+__device__ __forceinline__ void grad_at(const DevSheet &S, int k, int l, int a, int b, T tu, T tv, T g[2]) {
+    T nu, du, d2u, nv, dv, d2v;
+    piece_at<T>(span_type(k, S.Nu), a, tu, nu, du, d2u);
+    piece_at<T>(span_type(l, S.Nv), b, tv, nv, dv, d2v);
+    const T xu = du * nv, xv = nu * dv;
+    g[0] = xu * T(S.K00) + xv * T(S.K10);
+    g[1] = xu * T(S.K01) + xv * T(S.K11);
+}
+
+// Laplacian coefficient of local CP (a, b) for a bending evaluation of span (k, l).
+__device__ __forceinline__ double lap_at(const DevSheet &S, int k, int l, int a, int b, double tu, double tv) {
+    double nu, du, d2u, nv, dv, d2v;
+    piece_at<double>(span_type(k, S.Nu), a, tu, nu, du, d2u);
+    piece_at<double>(span_type(l, S.Nv), b, tv, nv, dv, d2v);
+    return S.c_uu * d2u * nv + S.c_vv * nu * d2v + S.c_uv * du * dv;
 }
 
 __device__ __forceinline__ void second(int type, double D2[3]) {
@@ -579,121 +623,207 @@ __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// ---- stage 2: per-CP gradient ---------------------------------------------------------------
+// ---- stage 2, tiled: Hessian blocks from LDS, gradient ------------------------------------------
+//
+// One workgroup per tile of kAsmTileU x ty CPs. The membrane points of the elements that the
+// tile's CPs touch (at most (kAsmTileU + 2) x (ty + 2) elements) are staged in LDS once: the
+// weighted density Hessian A (21 entries) and the gradients of the 9 local basis functions
+// (FP32) or the span coordinates (FP64, gradients recomputed). Work items (CP, slot): slots
+// 0..12 are the upper-stencil Hessian blocks, slot 13 is the gradient with the per-CP energy
+// terms (stresses and bending terms gathered from global memory). Items are numbered slot-major
+// with the slots by decreasing cost, and handed to waves in chunks of 64 from an LDS counter.
+// Each item sums over elements and points in a fixed order, so the result does not depend on
+// which wave takes it.
+template <typename TA, typename TP, typename TG>
+__global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int kind, const TA *__restrict__ ptA,
+                                                               const TP *__restrict__ ptP, const double *__restrict__ beD,
+                                                               const double *__restrict__ x, const double *__restrict__ xhat,
+                                                               double inv_dt2, double gx, double gy, double gz,
+                                                               TA *__restrict__ hess, TG *__restrict__ gout,
+                                                               double *__restrict__ partials) {
+    constexpr bool STAGE_DN = sizeof(TA) == 4;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ double sh[kAsmThreads / 64];
+    const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
+    const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, int(sizeof(TA)));
+    int *el_off = (int *)(lds + L.el_off);
+    int *counter = (int *)(lds + L.counter);
+    TA *pA = (TA *)(lds + L.A);
+    TA *pdN = (TA *)(lds + L.dN);
+    double *ptu = (double *)(lds + L.tu), *ptv = (double *)(lds + L.tv);
 
-template <typename T, typename TP>
-__global__ void __launch_bounds__(kBlock) k_grad(DevSheet S, const TP *__restrict__ ptP, const double *__restrict__ beD,
-                                                 const double *__restrict__ x, const double *__restrict__ xhat,
-                                                 double inv_dt2, double gx, double gy, double gz,
-                                                 T *__restrict__ gout, double *__restrict__ partials) {
-    __shared__ double sh[kBlock / 64];
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    double e_loc = 0.0;
-    if (a < S.n_cp) {
-        const int i = a % S.n_u, j = a / S.n_u;
-        T acc[3] = {T(0), T(0), T(0)};
-        double accb[3] = {0.0, 0.0, 0.0};
-        for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
-            for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
-                const int e = l * S.Nu + k, la = i - k, lb = j - l;
-                for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
-                    T dn[2];
-                    one_grad<T>(S, k, l, la, lb, T(S.mp_tu[q]), T(S.mp_tv[q]), dn);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        acc[c] += T(ptP[(2 * c) * S.n_mp + q]) * dn[0] + T(ptP[(2 * c + 1) * S.n_mp + q]) * dn[1];
-                }
-                for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
-                    double L[9];
-                    bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
-                    const double Lm = L[3 * lb + la];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) accb[c] += beD[c * S.n_be + q] * Lm;
-                }
+    const int ntx = (S.n_u + kAsmTileU - 1) / kAsmTileU;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx0 = (tile % ntx) * kAsmTileU, ty0 = (tile / ntx) * ty;
+    const int k0 = max(0, tx0 - 2), k1 = min(S.Nu - 1, tx0 + kAsmTileU - 1);
+    const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + ty - 1);
+    const int nk = k1 - k0 + 1, nl = l1 - l0 + 1, ne = nk * nl;
+
+    if (hess) {
+        // local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0));
+        // the points of one element row are contiguous in the global tables
+        for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
+            const int r = t / nk, kk = t % nk;
+            int mb = 0;
+            for (int q = 0; q < r; ++q) {
+                const int e0 = (l0 + q) * S.Nu;
+                mb += S.mp_off[e0 + k1 + 1] - S.mp_off[e0 + k0];
             }
-        }
-        double gsum[3];
-        const double M = S.mass[a];
-        const double grav[3] = {gx, gy, gz};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            gsum[c] = double(acc[c]) + accb[c];
-            const double xc = x[c * S.n_cp + a];
-            if (xhat) {
-                const double dlt = xc - xhat[c * S.n_cp + a];
-                gsum[c] += M * inv_dt2 * dlt;
-                e_loc += 0.5 * M * inv_dt2 * dlt * dlt;
+            if (r < nl) {
+                const int e0 = (l0 + r) * S.Nu + k0;
+                mb += S.mp_off[e0 + kk] - S.mp_off[e0];
             }
-            gsum[c] -= M * grav[c];
-            e_loc -= M * grav[c] * xc;
+            el_off[t] = mb;
         }
-        const bool pinned = S.pinmask[a] != 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gout[c * S.n_cp + a] = pinned ? T(0) : T(gsum[c]);
     }
-    const double s = block_sum(e_loc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
+    if (threadIdx.x == 0) *counter = 0;
+    __syncthreads();
+    if (hess) {
+        const int np = el_off[ne];
+        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+            int r = 0;
+            while (r + 1 < nl && el_off[(r + 1) * nk] <= t) ++r;
+            const int q = S.mp_off[(l0 + r) * S.Nu + k0] + (t - el_off[r * nk]);
+#pragma unroll
+            for (int c = 0; c < 21; ++c) pA[c * maxp + t] = ptA[c * S.n_mp + q];
+            if constexpr (STAGE_DN) {
+                const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
+                TA dN[9][2];
+                local_grads<TA>(S, k, l, TA(S.mp_tu[q]), TA(S.mp_tv[q]), dN);
+#pragma unroll
+                for (int m = 0; m < 9; ++m) {
+                    pdN[(2 * m) * maxp + t] = dN[m][0];
+                    pdN[(2 * m + 1) * maxp + t] = dN[m][1];
+                }
+            } else {
+                ptu[t] = S.mp_tu[q];
+                ptv[t] = S.mp_tv[q];
+            }
+        }
+    }
+    __syncthreads();
 
-// ---- stage 2: per (CP, slot) Hessian block ---------------------------------------------------
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_hess(DevSheet S, const T *__restrict__ ptA, double inv_dt2,
-                                                 T *__restrict__ hess) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (a >= S.n_cp) return;
-    const int i = a % S.n_u, j = a / S.n_u;
-    const int ib = i + slot_di(s), jb = j + slot_dj(s);
-    const int e0 = slot_entry(s);
+    // slots by decreasing number of shared elements (13 = gradient), 4 bits each
+    constexpr unsigned long long kO[14] = {0, 1, 5, 13, 4, 6, 2, 10, 3, 7, 9, 11, 8, 12};
+    constexpr unsigned long long kPacked = kO[0] | kO[1] << 4 | kO[2] << 8 | kO[3] << 12 | kO[4] << 16 | kO[5] << 20 |
+                                           kO[6] << 24 | kO[7] << 28 | kO[8] << 32 | kO[9] << 36 | kO[10] << 40 |
+                                           kO[11] << 44 | kO[12] << 48 | kO[13] << 52;
+    const int R = kAsmTileU * ty;
+    const int nitems = (hess ? kSlots + 1 : 1) * R;
+    const int nchunks = (nitems + 63) / 64;
     const size_t ncp = S.n_cp;
-    T acc[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
-    const bool inside = ib >= 0 && ib < S.n_u && jb < S.n_v;
-    const bool pinned = inside && (S.pinmask[a] != 0 || S.pinmask[jb * S.n_u + ib] != 0);
-    if (inside && !pinned) {
-        for (int l = max(0, max(j, jb) - 2); l <= min(min(j, jb), S.Nv - 1); ++l) {
-            for (int k = max(0, max(i, ib) - 2); k <= min(min(i, ib), S.Nu - 1); ++k) {
-                const int e = l * S.Nu + k;
-                const int la = i - k, lb = j - l, ma = ib - k, mb = jb - l;
-                for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
-                    T ga[2], gb[2];
-                    const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
-                    one_grad<T>(S, k, l, la, lb, tu, tv, ga);
-                    one_grad<T>(S, k, l, ma, mb, tu, tv, gb);
-                    const T c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
+    const int lane = threadIdx.x & 63;
+    double e_loc = 0.0;
+    for (;;) {
+        int ch = 0;
+        if (lane == 0) ch = atomicAdd(counter, 1);
+        ch = __shfl(ch, 0);
+        if (ch >= nchunks) break;
+        const int item = ch * 64 + lane;
+        if (item >= nitems) continue;
+        const int pos = item / R, c = item % R;
+        const int s = hess ? int((kPacked >> (4 * pos)) & 15ull) : kSlots;
+        const int i = tx0 + c % kAsmTileU, j = ty0 + c / kAsmTileU;
+        if (i >= S.n_u || j >= S.n_v) continue;
+        const int a = j * S.n_u + i;
+        if (s < kSlots) {
+            // Hessian block (a, b) of upper slot s
+            const int ib = i + slot_di(s), jb = j + slot_dj(s);
+            const int e0 = slot_entry(s);
+            TA acc[3][3] = {{TA(0), TA(0), TA(0)}, {TA(0), TA(0), TA(0)}, {TA(0), TA(0), TA(0)}};
+            const bool inside = ib >= 0 && ib < S.n_u && jb < S.n_v;
+            const bool pinned = inside && (S.pinmask[a] != 0 || S.pinmask[jb * S.n_u + ib] != 0);
+            if (inside && !pinned) {
+                for (int l = max(0, max(j, jb) - 2); l <= min(min(j, jb), S.Nv - 1); ++l) {
+                    for (int k = max(0, max(i, ib) - 2); k <= min(min(i, ib), S.Nu - 1); ++k) {
+                        const int el = (l - l0) * nk + (k - k0);
+                        const int la = i - k, lb = j - l, ma = ib - k, mb = jb - l;
+                        for (int q = el_off[el]; q < el_off[el + 1]; ++q) {
+                            TA ga[2], gb[2];
+                            if constexpr (STAGE_DN) {
+                                const int oa = 2 * (3 * lb + la), ob = 2 * (3 * mb + ma);
+                                ga[0] = pdN[oa * maxp + q]; ga[1] = pdN[(oa + 1) * maxp + q];
+                                gb[0] = pdN[ob * maxp + q]; gb[1] = pdN[(ob + 1) * maxp + q];
+                            } else {
+                                const TA tu = TA(ptu[q]), tv = TA(ptv[q]);
+                                grad_at<TA>(S, k, l, la, lb, tu, tv, ga);
+                                grad_at<TA>(S, k, l, ma, mb, tu, tv, gb);
+                            }
+                            const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
 #pragma unroll
-                    for (int r = 0; r < 3; ++r)
+                            for (int r = 0; r < 3; ++r)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const T a00 = ptA[u6(r, c) * S.n_mp + q];
-                            const T a01 = ptA[u6(r, 3 + c) * S.n_mp + q];
-                            const T a10 = ptA[u6(3 + r, c) * S.n_mp + q];
-                            const T a11 = ptA[u6(3 + r, 3 + c) * S.n_mp + q];
-                            acc[r][c] += c00 * a00 + c01 * a01 + c10 * a10 + c11 * a11;
+                                for (int cc = 0; cc < 3; ++cc) {
+                                    const TA a00 = pA[u6(r, cc) * maxp + q];
+                                    const TA a01 = pA[u6(r, 3 + cc) * maxp + q];
+                                    const TA a10 = pA[u6(3 + r, cc) * maxp + q];
+                                    const TA a11 = pA[u6(3 + r, 3 + cc) * maxp + q];
+                                    acc[r][cc] += c00 * a00 + c01 * a01 + c10 * a10 + c11 * a11;
+                                }
                         }
+                    }
+                }
+                const TA hb = TA(S.hbend[s * ncp + a]) + ((s == 0) ? TA(S.mass[a] * inv_dt2) : TA(0));
+#pragma unroll
+                for (int r = 0; r < 3; ++r) acc[r][r] += hb;
+            } else if (pinned && s == 0) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) acc[r][r] = TA(1);
+            }
+            if (s == 0) {
+                hess[(e0 + 0) * ncp + a] = acc[0][0];
+                hess[(e0 + 1) * ncp + a] = acc[0][1];
+                hess[(e0 + 2) * ncp + a] = acc[0][2];
+                hess[(e0 + 3) * ncp + a] = acc[1][1];
+                hess[(e0 + 4) * ncp + a] = acc[1][2];
+                hess[(e0 + 5) * ncp + a] = acc[2][2];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) hess[(e0 + 3 * r + cc) * ncp + a] = acc[r][cc];
+            }
+        } else {
+            // gradient: membrane stresses and bending terms of the CP's elements, inertia, gravity
+            TG acc[3] = {TG(0), TG(0), TG(0)};
+            double accb[3] = {0.0, 0.0, 0.0};
+            for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
+                for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
+                    const int e = l * S.Nu + k, la = i - k, lb = j - l;
+                    for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+                        TG dn[2];
+                        grad_at<TG>(S, k, l, la, lb, TG(S.mp_tu[q]), TG(S.mp_tv[q]), dn);
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc)
+                            acc[cc] += TG(ptP[(2 * cc) * S.n_mp + q]) * dn[0] + TG(ptP[(2 * cc + 1) * S.n_mp + q]) * dn[1];
+                    }
+                    for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
+                        const double Lm = lap_at(S, k, l, la, lb, S.be_tu[q], S.be_tv[q]);
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) accb[cc] += beD[cc * S.n_be + q] * Lm;
+                    }
                 }
             }
+            const double M = S.mass[a];
+            const double grav[3] = {gx, gy, gz};
+            const bool pin = S.pinmask[a] != 0;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                double gs = double(acc[cc]) + accb[cc];
+                const double xc = x[cc * ncp + a];
+                if (xhat) {
+                    const double dlt = xc - xhat[cc * ncp + a];
+                    gs += M * inv_dt2 * dlt;
+                    e_loc += 0.5 * M * inv_dt2 * dlt * dlt;
+                }
+                gs -= M * grav[cc];
+                e_loc -= M * grav[cc] * xc;
+                gout[cc * ncp + a] = pin ? TG(0) : TG(gs);
+            }
         }
-        const T hb = T(S.hbend[s * ncp + a]) + ((s == 0) ? T(S.mass[a] * inv_dt2) : T(0));
-#pragma unroll
-        for (int r = 0; r < 3; ++r) acc[r][r] += hb;
-    } else if (pinned && s == 0) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) acc[r][r] = T(1);
     }
-    if (s == 0) {
-        hess[(e0 + 0) * ncp + a] = acc[0][0];
-        hess[(e0 + 1) * ncp + a] = acc[0][1];
-        hess[(e0 + 2) * ncp + a] = acc[0][2];
-        hess[(e0 + 3) * ncp + a] = acc[1][1];
-        hess[(e0 + 4) * ncp + a] = acc[1][2];
-        hess[(e0 + 5) * ncp + a] = acc[2][2];
-    } else {
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hess[(e0 + 3 * r + c) * ncp + a] = acc[r][c];
-    }
+    const double tot = block_sum(e_loc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
 // ---- per-element outputs -------------------------------------------------------------------
@@ -800,31 +930,32 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
     return hipGetLastError();
 }
 
-hipError_t launch_grad(const DevSheet &S, const DevBufs &B, int precision, const double *x, const double *xhat,
-                       double inv_dt2, const double *grav, void *g, bool from64, hipStream_t st) {
+int assemble_tiles(const DevSheet &S, int kind) {
+    return ((S.n_u + kAsmTileU - 1) / kAsmTileU) * ((S.n_v + S.asm_ty[kind] - 1) / S.asm_ty[kind]);
+}
+
+hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
+                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st) {
     double *pc = B.partials + 2 * B.max_blocks;
     const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
-    if (from64)
-        k_grad<double, double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, B.ptP64, B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)g, pc);
-    else if (precision == BSC_FP64)
-        k_grad<double, double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.ptP, B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)g, pc);
+    const int sa = kind == kAsmF64 ? 8 : 4;
+    const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], sa).total;
+    const int nt = assemble_tiles(S, kind);
+    if (kind == kAsmF32)
+        k_assemble_tile<float, float, float><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, (const float *)B.ptP,
+                                                                          B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
+    else if (kind == kAsmF64)
+        k_assemble_tile<double, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const double *)B.ptA, (const double *)B.ptP,
+                                                                             B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
     else
-        k_grad<float, float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.ptP, B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)g, pc);
+        k_assemble_tile<float, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, B.ptP64,
+                                                                            B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
     return hipGetLastError();
 }
 
-hipError_t launch_hess(const DevSheet &S, const DevBufs &B, int precision, double inv_dt2, void *hess, hipStream_t st) {
-    dim3 grid(blocks(S.n_cp), kSlots);
-    if (precision == BSC_FP64)
-        k_hess<double><<<grid, kBlock, 0, st>>>(S, (const double *)B.ptA, inv_dt2, (double *)hess);
-    else
-        k_hess<float><<<grid, kBlock, 0, st>>>(S, (const float *)B.ptA, inv_dt2, (float *)hess);
-    return hipGetLastError();
-}
-
-hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, bool with_cp, double *out, hipStream_t st) {
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out, hipStream_t st) {
     k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
-                                   B.partials + 2 * B.max_blocks, with_cp ? blocks(S.n_cp) : 0, out);
+                                   B.partials + 2 * B.max_blocks, n_cp_partials, out);
     return hipGetLastError();
 }
 
@@ -856,7 +987,7 @@ bsc_status bsc_eval_egh(bsc_ctx *c, int32_t precision, const double *d_x, double
     const DevSheet &S = c->dev;
     bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_elem_hess != nullptr, false, d_x, c->stream), "eval points");
     if (st != BSC_OK) return st;
-    st = hip_check(c, launch_energy_reduce(S, c->buf, false, d_energy, c->stream), "energy reduce");
+    st = hip_check(c, launch_energy_reduce(S, c->buf, 0, d_energy, c->stream), "energy reduce");
     if (st != BSC_OK) return st;
     return hip_check(c, launch_elem(S, c->buf, precision, d_elem_energy, d_elem_grad, d_elem_hess, c->stream), "element gather");
 }
@@ -875,12 +1006,10 @@ bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const 
     const DevSheet &S = c->dev;
     bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream), "eval points");
     if (st != BSC_OK) return st;
-    st = hip_check(c, launch_grad(S, c->buf, precision, d_x, d_xhat, inv_dt2, gravity, d_grad, false, c->stream), "gradient");
+    const int kind = precision == BSC_FP64 ? kAsmF64 : kAsmF32;
+    st = hip_check(c, launch_assemble(S, c->buf, kind, d_x, d_xhat, inv_dt2, gravity, d_grad, d_hess, c->stream), "assemble");
     if (st != BSC_OK) return st;
-    st = hip_check(c, launch_energy_reduce(S, c->buf, true, d_energy, c->stream), "energy reduce");
-    if (st != BSC_OK) return st;
-    if (d_hess) st = hip_check(c, launch_hess(S, c->buf, precision, inv_dt2, d_hess, c->stream), "hessian");
-    return st;
+    return hip_check(c, launch_energy_reduce(S, c->buf, assemble_tiles(S, kind), d_energy, c->stream), "energy reduce");
 }
 
 }  // extern "C"

@@ -107,14 +107,6 @@ __device__ void wave_totals3(double v[3], double *sh /* 3 * 16 */) {
     }
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every
-// XCD a contiguous range of row tiles so that the neighbour rows a - d_s (whose stored upper
-// blocks the lower products read) are usually in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + k;
-}
-
 // ---- SpMV ------------------------------------------------------------------------------------
 
 // One of the 25 block products of row a: 0 = diagonal, 1..12 = upper slot s (block stored at
@@ -864,17 +856,16 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     const DevSheet &S = ctx->dev;
     const DevBufs &B = ctx->buf;
     hipStream_t st = ctx->stream;
+    // FP32-mixed: the Hessian from FP32 points; the gradient (and energy) from FP64 points
     if (prec == BSC_FP64) {
         HIPX(launch_points(S, B, BSC_FP64, true, false, x, st), "points");
-        HIPX(launch_grad(S, B, BSC_FP64, x, xhat, inv_dt2, grav, B.g, false, st), "gradient");
-        HIPX(launch_hess(S, B, BSC_FP64, inv_dt2, B.hess, st), "hessian");
     } else {
         HIPX(launch_points(S, B, BSC_FP32_MIXED, true, false, x, st), "points32");
-        HIPX(launch_hess(S, B, BSC_FP32_MIXED, inv_dt2, B.hess, st), "hessian32");
         HIPX(launch_points(S, B, BSC_FP64, false, true, x, st), "points64");
-        HIPX(launch_grad(S, B, BSC_FP64, x, xhat, inv_dt2, grav, B.g, true, st), "gradient64");
     }
-    HIPX(launch_energy_reduce(S, B, true, B.scalars + S_E, st), "energy");
+    const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
+    HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st), "assemble");
+    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st), "energy");
     return BSC_OK;
 }
 
