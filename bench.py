@@ -30,6 +30,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one active k_cg_fused<float> launch on this workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches that ran an
+# iteration), each divided by what the same counter reads for a 1 GiB device copy whose source
+# was evicted first (`bench.py --copy-probe 1024`: FETCH_SIZE 0.500, WRITE_SIZE 1.000 of the
+# bytes). Summary and commands: profiles/k_cg_fused_226_traffic.md. Valid only for the kernel
+# source it was measured on (hash of its text in solve.hip); otherwise reported as null.
+CG_TRAFFIC = {"kernel_sha256_16": "ddf5192d0223d00a", "fetch_kib": 15641.1, "write_kib": 5469.7,
+              "fetch_factor": 0.500, "write_factor": 1.000}
+
+
+def cg_kernel_sha():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2506_18867_amd", "csrc", "solve.hip")).read()
+    a = src.index("template <typename T, bool FIRST>\n__global__ void __launch_bounds__(512) k_cg_fused")
+    b = src.index("\n}\n", a) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def cg_traffic_bytes():
+    """Calibrated HBM bytes per active fused-CG launch, or None if the kernel changed since."""
+    t = CG_TRAFFIC
+    try:
+        if cg_kernel_sha() != t["kernel_sha256_16"]:
+            return None
+    except (OSError, ValueError):
+        return None
+    return int(1024 * (t["fetch_kib"] / t["fetch_factor"] + t["write_kib"] / t["write_factor"]))
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -53,7 +81,26 @@ def parse():
     p.add_argument("--pcg-rtol", type=float, default=1e-3)
     p.add_argument("--grad-steps", type=int, default=2, help="steps of the |g|<=1e-6|g0| leg (0: skip)")
     p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run the traffic-counter calibration: one device-to-device copy of MIB MiB whose "
+                        "source has been evicted from the caches, then exit")
     return p.parse_args()
+
+
+def copy_probe(mib, torch):
+    """Calibration for the FETCH_SIZE / WRITE_SIZE counters: a plain copy of known size. The source
+    is written first, then a second buffer of the same size is written to evict it from the L2s
+    and the Infinity Cache, so the copy reads every byte from HBM."""
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    evict = torch.empty(n, dtype=torch.uint8, device="cuda")
+    evict.fill_(2)
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n}), flush=True)
 
 
 def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
@@ -119,6 +166,9 @@ def main():
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe, torch)
+        return
 
     import synthetic as syn
     from paper_2506_18867_amd import bsc
@@ -206,6 +256,8 @@ def main():
     for k in ("launches", "active_launches", "bytes_per_active_launch"):
         if k in dom:
             roof[k] = dom[k]
+    if "active_launches" in dom:
+        roof["traffic"] = cg_traffic_bytes()          # HBM bytes per active launch (calibrated counters)
 
     result = {
         "metric": "element E/g/H+assembly Melem/s, HBM GB/s; Newton-step ms at fixed residual vs FP64",
