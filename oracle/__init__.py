@@ -57,6 +57,10 @@ def _load():
     lib.or_membrane_rule.argtypes = [i, i, p, i]
     lib.or_bending_rule.restype = i
     lib.or_bending_rule.argtypes = [i, i, p, i]
+    lib.or_membrane_rule_q.restype = i
+    lib.or_membrane_rule_q.argtypes = [i, i, i, p, i]
+    lib.or_bending_rule_q.restype = i
+    lib.or_bending_rule_q.argtypes = [i, i, i, p, i]
     lib.or_membrane_density.restype = None
     lib.or_membrane_density.argtypes = [i, p, d, d, d, d, d, d, p, p, p]
     lib.or_project_psd6.restype = None
@@ -86,6 +90,7 @@ class _CSheet(ctypes.Structure):
         ("young", ctypes.c_double), ("poisson", ctypes.c_double), ("thickness", ctypes.c_double),
         ("mu_st1", ctypes.c_double), ("mu_st2", ctypes.c_double), ("mu_sh", ctypes.c_double),
         ("mu_bend", ctypes.c_double), ("rho_area", ctypes.c_double),
+        ("quadrature", ctypes.c_int),
     ]
 
 
@@ -118,6 +123,7 @@ class Sheet:
     mu_sh: float = 0.0
     mu_bend: float = 0.0
     rho_area: float = 0.0
+    quadrature: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _CSheet:
@@ -126,7 +132,8 @@ class Sheet:
         self._keep = [ku, kv, rest]
         return _CSheet(self.n_u, self.n_v, ku.ctypes.data, kv.ctypes.data, rest.ctypes.data,
                        int(self.membrane), self.young, self.poisson, self.thickness,
-                       self.mu_st1, self.mu_st2, self.mu_sh, self.mu_bend, self.rho_area)
+                       self.mu_st1, self.mu_st2, self.mu_sh, self.mu_bend, self.rho_area,
+                       _quad(self.quadrature))
 
     @property
     def n_cp(self) -> int:
@@ -158,21 +165,37 @@ def check_knots(knots, n: int):
     return (N, h.value) if N > 0 else (None, None)
 
 
-def membrane_rule(Nu: int, Nv: int) -> np.ndarray:
-    """(M, 5) array of (u, v, wbar, k, l) in span units (Sec. 4.1, Reduced Integration)."""
+QUAD_REDUCED, QUAD_GAUSS2, QUAD_INTERIOR1, QUAD_CORNER2 = 0, 1, 2, 3
+QUADRATURES = {"reduced": QUAD_REDUCED, "gauss2": QUAD_GAUSS2, "interior1": QUAD_INTERIOR1, "corner2": QUAD_CORNER2}
+
+
+def _quad(q) -> int:
+    q = QUADRATURES.get(q, q) if isinstance(q, str) else int(q)
+    if q not in (0, 1, 2, 3):
+        raise ValueError(f"unknown quadrature {q}")
+    return q
+
+
+def membrane_rule(Nu: int, Nv: int, quadrature=QUAD_REDUCED) -> np.ndarray:
+    """(M, 5) array of (u, v, wbar, k, l) in span units. QUAD_REDUCED is the paper's rule
+    (Sec. 4.1, Reduced Integration); the others are the comparison rules of Sec. 6.4 (standard
+    2x2 Gauss on interior spans, 1x1 interior, 2x2 corners)."""
     lib = _load()
-    n = lib.or_membrane_rule(Nu, Nv, None, 0)
+    q = _quad(quadrature)
+    n = lib.or_membrane_rule_q(Nu, Nv, q, None, 0)
     out = np.zeros((n, 5))
-    lib.or_membrane_rule(Nu, Nv, _ptr(out), n)
+    lib.or_membrane_rule_q(Nu, Nv, q, _ptr(out), n)
     return out
 
 
-def bending_rule(Nu: int, Nv: int) -> np.ndarray:
-    """(B', 5) array of bending evaluations (u, v, wbar, k, l) (Sec. 4.2; reading R2)."""
+def bending_rule(Nu: int, Nv: int, quadrature=QUAD_REDUCED) -> np.ndarray:
+    """(B', 5) array of bending evaluations (u, v, wbar, k, l) (Sec. 4.2; reading R2). With
+    QUAD_GAUSS2 the interior spans take 2x2 Gauss points (Sec. 6.4, configuration (A))."""
     lib = _load()
-    n = lib.or_bending_rule(Nu, Nv, None, 0)
+    q = _quad(quadrature)
+    n = lib.or_bending_rule_q(Nu, Nv, q, None, 0)
     out = np.zeros((n, 5))
-    lib.or_bending_rule(Nu, Nv, _ptr(out), n)
+    lib.or_bending_rule_q(Nu, Nv, q, _ptr(out), n)
     return out
 
 

@@ -134,20 +134,38 @@ static int push(double *out, int cap, int cnt, double u, double v, double w, int
 
 static int imin(int a, int b) { return a < b ? a : b; }
 
+/* Quadrature variants. OR_QUAD_REDUCED is the paper's scheme (Sec. 4.1, 4.2). The others are
+ * the comparison rules of its ablation study (Sec. 6.4): the standard 2x2 Gauss rule on every
+ * interior knot span for membrane and bending (boundary spans unchanged), a single midpoint
+ * per interior span for the membrane ("1x1", which admits hourglass modes), and 2x2 instead of
+ * 3x3 Gauss on the four corner spans for the membrane. */
+enum { OR_QUAD_REDUCED = 0, OR_QUAD_GAUSS2 = 1, OR_QUAD_INTERIOR1 = 2, OR_QUAD_CORNER2 = 3 };
+
 /* Membrane rule. Boundary knot spans: 3x3 Gauss at the four corners, 3 (across) x 2 (along)
  * on the sides. Interior region [1,Nu-1]x[1,Nv-1]: cells of the dual grid (lines through the
  * control points, i.e. at half-integers) centred at knot (a,b), clipped to the region.
  * Full cells alternate 1x2 / 2x1 Gauss by the parity of a+b; edge half cells carry two
  * points on the knot line, corner quarter cells one point at the knot. Returns the count. */
-int or_membrane_rule(int Nu, int Nv, double *out, int cap)
+int or_membrane_rule_q(int Nu, int Nv, int quad, double *out, int cap)
 {
     int cnt = 0;
     double ou[3], wu[3], ov[3], wv[3];
     for (int l = 0; l < Nv; ++l) {
         for (int k = 0; k < Nu; ++k) {
             int bu = (k == 0 || k == Nu - 1), bv = (l == 0 || l == Nv - 1);
-            if (!bu && !bv) continue;
-            int nu = bu ? 3 : 2, nv = bv ? 3 : 2;
+            int nu, nv;
+            if (bu && bv) {
+                nu = nv = (quad == OR_QUAD_CORNER2) ? 2 : 3;      /* corner spans */
+            } else if (bu || bv) {
+                nu = bu ? 3 : 2; nv = bv ? 3 : 2;                  /* side spans   */
+            } else if (quad == OR_QUAD_GAUSS2) {
+                nu = nv = 2;                                       /* interior, standard rule */
+            } else if (quad == OR_QUAD_INTERIOR1) {
+                cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 1.0, k, l);   /* span midpoint */
+                continue;
+            } else {
+                continue;                                          /* dual-grid cells below */
+            }
             gauss_1d(nu, ou, wu);
             gauss_1d(nv, ov, wv);
             for (int b = 0; b < nv; ++b)
@@ -155,6 +173,7 @@ int or_membrane_rule(int Nu, int Nv, double *out, int cap)
                     cnt = push(out, cap, cnt, k + 0.5 + ou[a], l + 0.5 + ov[b], wu[a] * wv[b], k, l);
         }
     }
+    if (quad == OR_QUAD_GAUSS2 || quad == OR_QUAD_INTERIOR1) return cnt;
     for (int b = 1; b <= Nv - 1; ++b) {
         for (int a = 1; a <= Nu - 1; ++a) {
             int edge_u = (a == 1 || a == Nu - 1), edge_v = (b == 1 || b == Nv - 1);
@@ -191,17 +210,33 @@ int or_membrane_rule(int Nu, int Nv, double *out, int cap)
     return cnt;
 }
 
+int or_membrane_rule(int Nu, int Nv, double *out, int cap)
+{
+    return or_membrane_rule_q(Nu, Nv, OR_QUAD_REDUCED, out, cap);
+}
+
 /* Bending rule: one point at the centre of every boundary knot span (weight 1) and one at
  * every interior knot (a,b), the centre of its dual cell, weighted by the clipped cell area.
  * Reading R2: the knot point is evaluated four times, once with the polynomials of each
- * adjacent span, each carrying a quarter of the weight. Returns the number of evaluations. */
-int or_bending_rule(int Nu, int Nv, double *out, int cap)
+ * adjacent span, each carrying a quarter of the weight. With OR_QUAD_GAUSS2 the interior spans
+ * take 2x2 Gauss points instead of the knot points. Returns the number of evaluations. */
+int or_bending_rule_q(int Nu, int Nv, int quad, double *out, int cap)
 {
     int cnt = 0;
     for (int l = 0; l < Nv; ++l)
         for (int k = 0; k < Nu; ++k)
             if (k == 0 || k == Nu - 1 || l == 0 || l == Nv - 1)
                 cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 1.0, k, l);
+    if (quad == OR_QUAD_GAUSS2) {              /* standard 2x2 Gauss on the interior spans */
+        double o[3], w[3];
+        gauss_1d(2, o, w);
+        for (int l = 1; l < Nv - 1; ++l)
+            for (int k = 1; k < Nu - 1; ++k)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a)
+                        cnt = push(out, cap, cnt, k + 0.5 + o[a], l + 0.5 + o[b], w[a] * w[b], k, l);
+        return cnt;
+    }
     for (int b = 1; b <= Nv - 1; ++b) {
         for (int a = 1; a <= Nu - 1; ++a) {
             double lu = (a == 1 || a == Nu - 1) ? 0.5 : 1.0;
@@ -216,6 +251,11 @@ int or_bending_rule(int Nu, int Nv, double *out, int cap)
         }
     }
     return cnt;
+}
+
+int or_bending_rule(int Nu, int Nv, double *out, int cap)
+{
+    return or_bending_rule_q(Nu, Nv, OR_QUAD_REDUCED, out, cap);
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -233,6 +273,7 @@ typedef struct {
     double mu_st1, mu_st2, mu_sh;
     double mu_bend;
     double rho_area;
+    int quadrature;             /* OR_QUAD_*                                                  */
 } or_sheet;
 
 typedef struct {
@@ -584,18 +625,18 @@ int or_element_egh(const or_sheet *S, const double *x, int project, double *E_e,
     memset(g_e, 0, sizeof(double) * 27 * ne);
     if (H_e) memset(H_e, 0, sizeof(double) * 729 * ne);
     double *Hscratch = H_e ? NULL : (double *)calloc(729, sizeof(double));
-    int nm = or_membrane_rule(Nu, Nv, NULL, 0);
+    int nm = or_membrane_rule_q(Nu, Nv, S->quadrature, NULL, 0);
     double *rm = (double *)malloc(sizeof(double) * 5 * nm);
-    or_membrane_rule(Nu, Nv, rm, nm);
+    or_membrane_rule_q(Nu, Nv, S->quadrature, rm, nm);
     for (int q = 0; q < nm; ++q) {
         const double *rec = rm + 5 * q;
         int e = (int)rec[4] * Nu + (int)rec[3];
         membrane_point(S, x, rec, project, E_e + e, g_e + 27 * e, H_e ? H_e + 729 * e : Hscratch);
     }
     free(rm);
-    int nb = or_bending_rule(Nu, Nv, NULL, 0);
+    int nb = or_bending_rule_q(Nu, Nv, S->quadrature, NULL, 0);
     double *rb = (double *)malloc(sizeof(double) * 5 * nb);
-    or_bending_rule(Nu, Nv, rb, nb);
+    or_bending_rule_q(Nu, Nv, S->quadrature, rb, nb);
     for (int q = 0; q < nb; ++q) {
         const double *rec = rb + 5 * q;
         int e = (int)rec[4] * Nu + (int)rec[3];

@@ -88,10 +88,13 @@ class Tiny:
         return out
 
     # quadrature, rebuilt from the wording of the paper (span units)
-    def membrane_points(self, full_gauss=False):
+    def membrane_points(self, full_gauss=False, rule="reduced"):
+        """rule: "reduced" (Sec. 4.1), or the comparison rules of Sec. 6.4: "gauss2" (2x2 on the
+        interior spans), "interior1" (one midpoint per interior span), "corner2" (2x2 on the
+        corner spans instead of 3x3)."""
         g2 = 0.5 / math.sqrt(3.0)
         g3 = 0.5 * math.sqrt(0.6)
-        G = {2: [(-g2, 0.5), (g2, 0.5)], 3: [(-g3, 5 / 18), (0.0, 8 / 18), (g3, 5 / 18)]}
+        G = {1: [(0.0, 1.0)], 2: [(-g2, 0.5), (g2, 0.5)], 3: [(-g3, 5 / 18), (0.0, 8 / 18), (g3, 5 / 18)]}
         pts = []
         Nu, Nv = self.Nu, self.Nv
         for l in range(Nv):
@@ -100,14 +103,20 @@ class Tiny:
                 on_v = l in (0, Nv - 1)
                 if full_gauss:
                     nu_, nv_ = 3, 3
+                elif on_u and on_v and rule == "corner2":
+                    nu_, nv_ = 2, 2
                 elif on_u or on_v:
                     nu_, nv_ = (3 if on_u else 2), (3 if on_v else 2)
+                elif rule == "gauss2":
+                    nu_, nv_ = 2, 2
+                elif rule == "interior1":
+                    nu_, nv_ = 1, 1
                 else:
                     continue
                 for ou, wu in G[nu_]:
                     for ov, wv in G[nv_]:
                         pts.append((k + 0.5 + ou, l + 0.5 + ov, wu * wv, k, l))
-        if full_gauss:
+        if full_gauss or rule in ("gauss2", "interior1"):
             return pts
         for b in range(1, Nv):
             for a in range(1, Nu):
@@ -127,9 +136,20 @@ class Tiny:
                     pts.append((u, v, w, min(int(math.floor(u)), Nu - 1), min(int(math.floor(v)), Nv - 1)))
         return pts
 
-    def bending_points(self, full_gauss=False):
+    def bending_points(self, full_gauss=False, rule="reduced"):
         pts = []
         Nu, Nv = self.Nu, self.Nv
+        if rule == "gauss2":                   # span centres on the boundary ring, 2x2 inside
+            g2 = 0.5 / math.sqrt(3.0)
+            for l in range(Nv):
+                for k in range(Nu):
+                    if k in (0, Nu - 1) or l in (0, Nv - 1):
+                        pts.append((k + 0.5, l + 0.5, 1.0, k, l))
+                    else:
+                        for ou in (-g2, g2):
+                            for ov in (-g2, g2):
+                                pts.append((k + 0.5 + ou, l + 0.5 + ov, 0.25, k, l))
+            return pts
         if full_gauss:
             g3 = 0.5 * math.sqrt(0.6)
             G = [(-g3, 5 / 18), (0.0, 8 / 18), (g3, 5 / 18)]
@@ -156,18 +176,18 @@ class Tiny:
         Eg = 0.5 * (F.T @ F - np.eye(2))
         return mu * np.sum(Eg * Eg) + 0.5 * lam * np.trace(Eg) ** 2
 
-    def elastic_energy(self, x, full_gauss=False):
+    def elastic_energy(self, x, full_gauss=False, rule="reduced"):
         x = np.asarray(x, dtype=float)
         K = self.K
         total = 0.0
-        for u, v, w, k, l in self.membrane_points(full_gauss):
+        for u, v, w, k, l in self.membrane_points(full_gauss, rule):
             d = self.derivs(x, k, l, u, v)
             F = np.stack([d["u"] * K[0, 0] + d["v"] * K[1, 0], d["u"] * K[0, 1] + d["v"] * K[1, 1]], axis=1)
             total += w * self.detJ * self.stvk(F)
         c_uu = K[0, 0] ** 2 + K[0, 1] ** 2
         c_vv = K[1, 0] ** 2 + K[1, 1] ** 2
         c_uv = 2 * (K[0, 0] * K[1, 0] + K[0, 1] * K[1, 1])
-        for u, v, w, k, l in self.bending_points(full_gauss):
+        for u, v, w, k, l in self.bending_points(full_gauss, rule):
             d = self.derivs(x, k, l, u, v)
             lap = c_uu * d["uu"] + c_vv * d["vv"] + c_uv * d["uv"]
             total += w * self.detJ * 0.5 * self.mu_bend * float(np.dot(lap, lap))
