@@ -81,6 +81,8 @@ def parse():
     p.add_argument("--pcg-rtol", type=float, default=1e-3)
     p.add_argument("--grad-steps", type=int, default=2, help="steps of the |g|<=1e-6|g0| leg (0: skip)")
     p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
+    p.add_argument("--quad-steps", type=int, default=3,
+                   help="steps of the quadrature-ablation leg (reduced vs 2x2 interior rule; 0: skip)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run the traffic-counter calibration: one device-to-device copy of MIB MiB whose "
                         "source has been evicted from the caches, then exit")
@@ -205,6 +207,31 @@ def main():
                               "newton": [s["newton_iters"] for s in stg], "pcg": [s["pcg_iters_total"] for s in stg],
                               "g_rel": [float("%.3g" % (s["g_norm"] / s["g0_norm"])) for s in stg]}
 
+    # Quadrature ablation (Sec. 6.4, timing breakdown (A) vs (B)): the standard 2x2 Gauss rule on
+    # the interior spans against the reduced rule, a few FP32-mixed steps from the same start state.
+    quad_leg = None
+    if args.quad_steps > 0:
+        quad_leg = {}
+        for name, rule in (("reduced", bsc.BSC_QUAD_REDUCED), ("gauss2_interior", bsc.BSC_QUAD_GAUSS2)):
+            qctx = bsc.context_for_scene(sc, quadrature=rule)
+            xq, vq = x0.clone(), v0.clone()
+            run_steps(qctx, sc, xq, vq, 1, 0, bsc.BSC_FP32_MIXED, bsc, torch, args)        # warm-up
+            xq, vq = x0.clone(), v0.clone()
+            secq, stq = run_steps(qctx, sc, xq, vq, args.quad_steps, 0, bsc.BSC_FP32_MIXED, bsc, torch, args)
+            nq = sum(s_["newton_iters"] for s_ in stq)
+            outq = (torch.zeros(1, dtype=torch.float64, device="cuda"),
+                    torch.empty(3, sc.n_cp, dtype=torch.float32, device="cuda"),
+                    torch.empty(114, sc.n_cp, dtype=torch.float32, device="cuda"))
+            ms_a = time_kernel(lambda: qctx.bsc_assemble(xq, xq, sc.dt, tuple(sc.gravity), bsc.BSC_FP32_MIXED,
+                                                         out=outq), 20, torch)
+            quad_leg[name] = {"membrane_points": qctx.sizes.n_membrane_pts, "bending_evals": qctx.sizes.n_bending_evals,
+                              "ms_per_step": round(1e3 * secq / args.quad_steps, 3),
+                              "newton": [s_["newton_iters"] for s_ in stq],
+                              "pcg": [s_["pcg_iters_total"] for s_ in stq],
+                              "ms_per_newton_iter": round(1e3 * secq / max(1, nq), 4),
+                              "assembly_fp32_ms": round(ms_a, 4)}
+            del qctx
+
     # per-kernel timings at the current state (same stream as the library)
     n, ne = sc.n_cp, sc.n_elem
     xhat = x.clone()
@@ -293,6 +320,7 @@ def main():
                       "active_launches": cg_active, "gb_s": round(cg_bytes32 * cg_active / max(cg_ms, 1e-9) / 1e6, 1)},
         "spmv": {"fp32_ms": round(ms_spmv32, 5), "fp64_ms": round(ms_spmv64, 5),
                  "fp32_gb_s": round(spmv_bytes32 / ms_spmv32 / 1e6, 1), "fp64_gb_s": round(spmv_bytes64 / ms_spmv64 / 1e6, 1)},
+        "quadrature_ablation": quad_leg,
         "roofline": roof,
         "cpu_baseline": None,
     }

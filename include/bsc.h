@@ -57,16 +57,29 @@ enum { BSC_MEMBRANE_STVK = 0, BSC_MEMBRANE_FBW = 1 };
 enum { BSC_FP64 = 0, BSC_FP32_MIXED = 1 };
 enum { BSC_STOP_GRAD = 0, BSC_STOP_STEP = 1 };
 
-/* Material (Sec. 4). StVK: membrane energy per rest area t [mu |E_G|^2 + lam/2 tr(E_G)^2],
- * E_G = (F^T F - I)/2, mu = E/(2(1+nu)), lam = E nu/(1-nu^2). FBW (Eq. "FBW stretching and
- * shearing energy"): mu_st1, mu_st2, mu_sh per rest area. Bending (Eq. "general bending
- * energy"): mu_bend/2 |Laplacian(phi)|^2 per rest area. rho_area: rest mass per area R^0. */
+/* Quadrature rule of the membrane and bending energies. BSC_QUAD_REDUCED is the paper's
+ * reduced integration (Sec. 4.1 and 4.2, Fig. "quadrature"): 3x3 Gauss on corner spans, 3x2 on
+ * side spans, alternating 1x2 / 2x1 Gauss on the dual-grid cells of the interior for the
+ * membrane; span centres on the boundary and the interior knots for bending. The others are the
+ * comparison rules of the ablation (Sec. 6.4), all with the same boundary placement except as
+ * stated: BSC_QUAD_GAUSS2 the standard 2x2 Gauss rule on every interior span for membrane and
+ * bending; BSC_QUAD_INTERIOR1 one midpoint per interior span for the membrane (admits hourglass
+ * modes); BSC_QUAD_CORNER2 2x2 instead of 3x3 Gauss on the four corner spans for the membrane. */
+enum { BSC_QUAD_REDUCED = 0, BSC_QUAD_GAUSS2 = 1, BSC_QUAD_INTERIOR1 = 2, BSC_QUAD_CORNER2 = 3 };
+
+/* Material and discretisation (Sec. 4). StVK: membrane energy per rest area
+ * t [mu |E_G|^2 + lam/2 tr(E_G)^2], E_G = (F^T F - I)/2, mu = E/(2(1+nu)), lam = E nu/(1-nu^2).
+ * FBW (Eq. "FBW stretching and shearing energy"): mu_st1, mu_st2, mu_sh per rest area. Bending
+ * (Eq. "general bending energy"): mu_bend/2 |Laplacian(phi)|^2 per rest area. rho_area: rest
+ * mass per area R^0. quadrature: BSC_QUAD_* (0 is the paper's rule); others return
+ * BSC_E_INVAL from bsc_create. */
 typedef struct {
     int32_t membrane;
     double young, poisson, thickness;
     double mu_st1, mu_st2, mu_sh;
     double mu_bend;
     double rho_area;
+    int32_t quadrature;
 } bsc_material;
 
 /* Options of one implicit-Euler step (Sec. 3.2, Sec. 5.1).

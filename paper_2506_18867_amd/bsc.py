@@ -45,7 +45,8 @@ class BscError(RuntimeError):
 class Material(ctypes.Structure):
     _fields_ = [("membrane", ctypes.c_int32), ("young", ctypes.c_double), ("poisson", ctypes.c_double),
                 ("thickness", ctypes.c_double), ("mu_st1", ctypes.c_double), ("mu_st2", ctypes.c_double),
-                ("mu_sh", ctypes.c_double), ("mu_bend", ctypes.c_double), ("rho_area", ctypes.c_double)]
+                ("mu_sh", ctypes.c_double), ("mu_bend", ctypes.c_double), ("rho_area", ctypes.c_double),
+                ("quadrature", ctypes.c_int32)]
 
 
 class StepOpts(ctypes.Structure):
@@ -138,9 +139,12 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+BSC_QUAD_REDUCED, BSC_QUAD_GAUSS2, BSC_QUAD_INTERIOR1, BSC_QUAD_CORNER2 = 0, 1, 2, 3
+
+
 def make_material(membrane=0, young=0.0, poisson=0.0, thickness=0.0, mu_st1=0.0, mu_st2=0.0, mu_sh=0.0,
-                  mu_bend=0.0, rho_area=0.0) -> Material:
-    return Material(membrane, young, poisson, thickness, mu_st1, mu_st2, mu_sh, mu_bend, rho_area)
+                  mu_bend=0.0, rho_area=0.0, quadrature=BSC_QUAD_REDUCED) -> Material:
+    return Material(membrane, young, poisson, thickness, mu_st1, mu_st2, mu_sh, mu_bend, rho_area, quadrature)
 
 
 def make_opts(dt=0.01, gravity=(0.0, 0.0, -9.81), precision=BSC_FP64, stop_mode=BSC_STOP_GRAD, rtol=1e-6,
@@ -321,11 +325,11 @@ def bsc_create(n_u, n_v, knots_u, knots_v, rest, material: Material, device="cud
     return Context(n_u, n_v, knots_u, knots_v, rest, material, device)
 
 
-def context_for_scene(scene, device="cuda") -> Context:
+def context_for_scene(scene, device="cuda", quadrature=BSC_QUAD_REDUCED) -> Context:
     """Context plus pins for a ``synthetic.Scene``."""
     m = scene.material
     mat = make_material(m.membrane, m.young, m.poisson, m.thickness, m.mu_st1, m.mu_st2, m.mu_sh, m.mu_bend,
-                        m.rho_area)
+                        m.rho_area, quadrature)
     ctx = Context(scene.n_u, scene.n_v, scene.knots_u, scene.knots_v, scene.rest, mat, device)
     if len(scene.pins):
         ctx.bsc_set_pins(scene.pins)

@@ -64,21 +64,37 @@ const double kG3 = 0.38729833462074168852;   // sqrt(3/5) / 2
 // interior region alternating 1x2 / 2x1 Gauss on dual-grid cells centred at the knots,
 // clipped to the region (two points on the knot line for edge half cells, one at the knot
 // for corner quarter cells). Weights: Gauss weights times the clipped cell area.
-std::vector<Pt> membrane_points(int Nu, int Nv) {
+//
+// Comparison rules (Sec. 6.4, selected by bsc_material.quadrature): BSC_QUAD_GAUSS2 puts 2x2
+// Gauss on every interior span instead of the dual-grid cells, BSC_QUAD_INTERIOR1 one point at
+// the centre of every interior span, BSC_QUAD_CORNER2 2x2 instead of 3x3 Gauss on the corner
+// spans.
+std::vector<Pt> membrane_points(int Nu, int Nv, int quad) {
     std::vector<Pt> out;
+    const double o1[1] = {0.0}, w1[1] = {1.0};
     const double o2[2] = {-kG2, kG2}, w2[2] = {0.5, 0.5};
     const double o3[3] = {-kG3, 0.0, kG3}, w3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    auto order = [&](int npt, const double **o, const double **w) {
+        *o = npt == 1 ? o1 : (npt == 2 ? o2 : o3);
+        *w = npt == 1 ? w1 : (npt == 2 ? w2 : w3);
+    };
     for (int l = 0; l < Nv; ++l) {
         for (int k = 0; k < Nu; ++k) {
             const bool eu = (k == 0 || k == Nu - 1), ev = (l == 0 || l == Nv - 1);
-            if (!eu && !ev) continue;
-            const int nu = eu ? 3 : 2, nv = ev ? 3 : 2;
-            const double *ou = eu ? o3 : o2, *wu = eu ? w3 : w2;
-            const double *ov = ev ? o3 : o2, *wv = ev ? w3 : w2;
+            int nu, nv;
+            if (eu && ev) nu = nv = (quad == BSC_QUAD_CORNER2) ? 2 : 3;
+            else if (eu || ev) { nu = eu ? 3 : 2; nv = ev ? 3 : 2; }
+            else if (quad == BSC_QUAD_GAUSS2) nu = nv = 2;
+            else if (quad == BSC_QUAD_INTERIOR1) nu = nv = 1;
+            else continue;
+            const double *ou, *wu, *ov, *wv;
+            order(nu, &ou, &wu);
+            order(nv, &ov, &wv);
             for (int b = 0; b < nv; ++b)
                 for (int a = 0; a < nu; ++a) out.push_back({k + 0.5 + ou[a], l + 0.5 + ov[b], wu[a] * wv[b], k, l});
         }
     }
+    if (quad == BSC_QUAD_GAUSS2 || quad == BSC_QUAD_INTERIOR1) return out;
     for (int b = 1; b < Nv; ++b) {
         for (int a = 1; a < Nu; ++a) {
             const bool hu = (a == 1 || a == Nu - 1), hv = (b == 1 || b == Nv - 1);
@@ -102,11 +118,20 @@ std::vector<Pt> membrane_points(int Nu, int Nv) {
 // Bending rule (Sec. 4.2): one point per boundary span centre, one per interior knot weighted
 // by its clipped dual cell; each knot point is evaluated in its four adjacent spans with a
 // quarter of the weight (mean of the one-sided values).
-std::vector<Pt> bending_points(int Nu, int Nv) {
+// With BSC_QUAD_GAUSS2 the interior spans take 2x2 Gauss points instead of the knot points.
+std::vector<Pt> bending_points(int Nu, int Nv, int quad) {
     std::vector<Pt> out;
     for (int l = 0; l < Nv; ++l)
         for (int k = 0; k < Nu; ++k)
             if (k == 0 || k == Nu - 1 || l == 0 || l == Nv - 1) out.push_back({k + 0.5, l + 0.5, 1.0, k, l});
+    if (quad == BSC_QUAD_GAUSS2) {
+        for (int l = 1; l < Nv - 1; ++l)
+            for (int k = 1; k < Nu - 1; ++k)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a)
+                        out.push_back({k + 0.5 + (a ? kG2 : -kG2), l + 0.5 + (b ? kG2 : -kG2), 0.25, k, l});
+        return out;
+    }
     for (int b = 1; b < Nv; ++b) {
         for (int a = 1; a < Nu; ++a) {
             const double cu = (a == 1 || a == Nu - 1) ? 0.5 : 1.0;
@@ -260,6 +285,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
         return BSC_E_INVAL;
     }
     if (!(mat->mu_bend >= 0.0) || !(mat->rho_area > 0.0)) return BSC_E_INVAL;
+    if (mat->quadrature < BSC_QUAD_REDUCED || mat->quadrature > BSC_QUAD_CORNER2) return BSC_E_INVAL;
     for (int64_t a = 0; a < 2 * int64_t(n_u) * n_v; ++a)
         if (!std::isfinite(rest_xy[a])) return BSC_E_INVAL;
 
@@ -299,8 +325,8 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     const double K[2][2] = {{A[1][1] / det, -A[0][1] / det}, {-A[1][0] / det, A[0][0] / det}};
 
     // quadrature tables
-    fill_tables(membrane_points(Nu, Nv), Nu, c->n_elem, det, c->mp_elem, c->mp_off, c->mp_tu, c->mp_tv, c->mp_w);
-    fill_tables(bending_points(Nu, Nv), Nu, c->n_elem, det, c->be_elem, c->be_off, c->be_tu, c->be_tv, c->be_w);
+    fill_tables(membrane_points(Nu, Nv, mat->quadrature), Nu, c->n_elem, det, c->mp_elem, c->mp_off, c->mp_tu, c->mp_tv, c->mp_w);
+    fill_tables(bending_points(Nu, Nv, mat->quadrature), Nu, c->n_elem, det, c->be_elem, c->be_off, c->be_tu, c->be_tv, c->be_w);
     c->n_mp = int(c->mp_elem.size());
     c->n_be = int(c->be_elem.size());
 

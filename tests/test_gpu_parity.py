@@ -265,3 +265,59 @@ def test_cg_graph_replays_match_eager_launches(monkeypatch):
         results.append((x.cpu().numpy(), v.cpu().numpy()))
     assert np.array_equal(results[0][0], results[1][0])
     assert np.array_equal(results[0][1], results[1][1])
+
+
+# ---- quadrature variants (the comparison rules of the reduced-integration ablation) -----------
+
+@pytest.mark.parametrize("rule", [bsc.BSC_QUAD_GAUSS2, bsc.BSC_QUAD_INTERIOR1, bsc.BSC_QUAD_CORNER2])
+def test_quadrature_variants_match_oracle(rule):
+    """The same kernels on the comparison tables: point counts, element E/g/H and the assembled
+    incremental potential against the oracle's rule, FP64, on a sheared 9 x 7 sheet with pins."""
+    n_u, n_v = 9, 7
+    print(f"[quadrature variant] rule={rule} {n_u}x{n_v}", flush=True)
+    ku, kv, rest = syn.flat_sheet(n_u, n_v, 1.0, 0.8, shear=0.2)
+    mat = syn.stvk_material(young=1e4, thickness=1e-3, mu_bend=2e-3)
+    sh = oracle_sheet((n_u, n_v, ku, kv, rest), mat)
+    sh.quadrature = rule
+    ctx = bsc.Context(n_u, n_v, ku, kv, rest, bsc.make_material(0, mat.young, mat.poisson, mat.thickness,
+                                                               mu_bend=mat.mu_bend, rho_area=mat.rho_area,
+                                                               quadrature=rule))
+    assert ctx.sizes.n_membrane_pts == len(oracle.membrane_rule(n_u - 2, n_v - 2, rule))
+    x = syn.embed(rest) + syn.smooth_field(n_u, n_v, 5, amp=0.05)
+    x[:, 0] *= 0.94
+    E, eE, eg, eH = ctx.bsc_eval_egh(bsc.to_soa(x), bsc.BSC_FP64)
+    rE, rg, rH = oracle.element_egh(sh, x, project=True)
+    assert relerr(eE.cpu().numpy(), rE) < TOL64
+    assert relerr(eg.cpu().numpy(), rg.T) < TOL64
+    assert relerr(eH.cpu().numpy(), upper27(rH)) < TOL64
+    pins = np.array([0, n_u - 1, n_u * n_v - 1])
+    ctx.bsc_set_pins(pins)
+    mask = np.zeros(n_u * n_v, dtype=bool)
+    mask[pins] = True
+    xhat = syn.embed(rest) + 0.01 * syn.smooth_field(n_u, n_v, 6, amp=0.5)
+    Ea, ga, Ha = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(xhat), 0.01, (0.0, 0.0, -9.81), bsc.BSC_FP64)
+    rEa, rga, rHa = oracle.assemble(sh, x, xhat, 0.01, np.array([0.0, 0.0, -9.81]), mask)
+    assert relerr(Ea.item(), rEa) < TOL64
+    assert relerr(bsc.to_aos(ga), rga) < TOL64
+    assert relerr(Ha.cpu().numpy(), oracle_stencil_to_upper(rHa, n_u, n_v)) < TOL64
+
+
+def test_standard_2x2_rule_needs_as_many_newton_iterations():
+    """Sec. 6.4: reduced integration converges in about as many Newton iterations as the
+    standard 2x2 rule on the interior spans (paper's stopping rule, dt = 0.01 s). Driven sheet,
+    60 x 60 CPs, 8 steps, FP64, same start state."""
+    sc = syn.driven_sheet(60, seed=12, cell=7)
+    iters = {}
+    for rule in (bsc.BSC_QUAD_REDUCED, bsc.BSC_QUAD_GAUSS2):
+        ctx = bsc.context_for_scene(sc, quadrature=rule)
+        x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+        opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=bsc.BSC_FP64, stop_mode=bsc.BSC_STOP_STEP,
+                             max_newton=60, pcg_rtol=1e-6, max_pcg=4000)
+        per = []
+        for step in range(8):
+            st, s = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(step)), opts)
+            assert st == 0
+            per.append(s.newton_iters)
+        iters[rule] = per
+    print(f"[quadrature] Newton iterations per step: reduced {iters[0]} | 2x2 interior {iters[1]}")
+    assert abs(sum(iters[0]) - sum(iters[1])) <= max(4, 0.25 * sum(iters[1]))
