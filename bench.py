@@ -315,6 +315,8 @@ def main():
         "assembly": {"fp32_ms": round(ms_asm32, 4), "fp64_ms": round(ms_asm64, 4),
                      "fp32_melem_s": round(ne / ms_asm32 / 1e3, 2), "fp64_melem_s": round(ne / ms_asm64 / 1e3, 2),
                      "fp32_gb_s": round(asm_bytes32 / ms_asm32 / 1e6, 1), "fp64_gb_s": round(asm_bytes64 / ms_asm64 / 1e6, 1)},
+        "phases_ms_per_step_fp32": {k: round(sum(s[k] for s in st32) / args.steps, 3)
+                                    for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_warmstart", "ms_total")},
         "pcg_us_per_iter_fp32": round(1e3 * sum(s["ms_pcg"] for s in st32) / max(1, pcg32), 3),
         "cg_kernel": {"active_us": round(1e3 * cg_ms / max(1, cg_active), 3), "launches": cg_launches,
                       "active_launches": cg_active, "gb_s": round(cg_bytes32 * cg_active / max(cg_ms, 1e-9) / 1e6, 1)},

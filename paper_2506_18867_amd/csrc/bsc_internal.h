@@ -24,6 +24,7 @@
 namespace bsc {
 
 constexpr int kBlock = 256;
+constexpr int kScalars = 64;           // solver scalars (doubles); the int flags follow them
 constexpr int kSlots = 13;            // diagonal + 12 upper offsets
 constexpr int kHessEntries = BSC_HESS_ENTRIES;
 // CG iteration tile: kCgTileU x kCgTileV control points per workgroup (one wave of rows)
@@ -175,14 +176,20 @@ struct bsc_ctx {
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
     float *log_g = nullptr, *log_p = nullptr;
     int log_cap = 0, log_count = 0;
-    // events around the CG chunks (created at the first Newton step)
+    // events around the CG chunks and the step's phases (created at the first Newton step)
     hipEvent_t cg_ev[2] = {nullptr, nullptr};
+    hipEvent_t ph_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool cg_ev_ok = false, cg_ev_tried = false;
+    // pinned host buffer for the step's small read-backs (solver scalars followed by the flags)
+    char *pinned = nullptr;
     ~bsc_ctx() {
         for (auto &g : cg_graph)
             if (g) (void)hipGraphExecDestroy(g);
         for (auto &e : cg_ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto &e : ph_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 

@@ -24,7 +24,8 @@ namespace {
 
 inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 
-enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_WS0, S_WS1, S_WS2, S_WS3 };
+enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
+       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO };
 enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
 
 constexpr int kRowsPerTile = 64;     // one wave of rows per SpMV block
@@ -304,11 +305,30 @@ __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, T *__restric
     for (int t = 0; t < 6; ++t) pinv[t * n + a] = T(inv[t]);
 }
 
-// r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b.
+// PCG tolerance of a Newton iteration. EXPLICIT: given by the host. FIXED / TIGHT: pcg_rtol.
+// ADAPTIVE: Eisenstat-Walker forcing term (choice 2, gamma = 0.9, exponent 2) with the
+// safeguard, clamped to [pcg_rtol, 0.1], from |g| of this and the previous Newton iteration
+// (0.1 at the first); computed on the device so that no host round trip separates the
+// assembly from the solve.
+enum { ETA_EXPLICIT = 0, ETA_FIXED = 1, ETA_ADAPTIVE = 2, ETA_TIGHT = 3 };
+
+__device__ double forcing_term(int mode, int first, double eta_host, double rtol_min, double gn, double g_prev,
+                               double eta_prev) {
+    if (mode == ETA_EXPLICIT) return eta_host;
+    if (mode != ETA_ADAPTIVE) return rtol_min;
+    if (first) return fmax(rtol_min, 0.1);
+    const double ratio = gn / g_prev;
+    double e = 0.9 * ratio * ratio;
+    const double guard = 0.9 * eta_prev * eta_prev;
+    if (guard > 0.1) e = fmax(e, guard);
+    return fmin(0.1, fmax(rtol_min, e));
+}
+
+// r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b; the solve's tolerance.
 __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
                                                     double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
-                                                    double rtol) {
+                                                    int eta_mode, int first, double eta_host, double rtol_min) {
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
@@ -326,7 +346,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     if (threadIdx.x == 0) pbb[blockIdx.x] = bb;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         isc[I_DONE] = 0; isc[I_ITA] = 0; isc[I_ITB] = 0; isc[I_BREAK] = 0; isc[I_MAXIT] = maxit; isc[I_ITERS] = 0;
-        scal[S_RTOL] = rtol;
+        const double gn = sqrt(scal[S_GG]);
+        const double eta = forcing_term(eta_mode, first, eta_host, rtol_min, gn, scal[S_GPREV], scal[S_ETA]);
+        scal[S_RTOL] = eta;
+        scal[S_ETA] = eta;
+        scal[S_GPREV] = gn;
     }
 }
 
@@ -468,6 +492,7 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
         if (lead) {
             scal[S_GAMMA0 + (it & 1)] = gam;
             scal[S_ALPHA0 + (it & 1)] = alpha;
+            scal[S_RHO] = rho;                    // |r|^2 of iteration j-1: read by the host between bursts
             isc[B.slot_out] = it + 1;
         }
     } else if (blockIdx.x == 0) {                 // uniform per block
@@ -881,14 +906,43 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const int prec = o->precision;
     const double dt = o->dt, inv_dt2 = 1.0 / (dt * dt);
     const double *grav = o->gravity;
+    const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
     const int stride = B.max_blocks;
+    const bool step_rule = o->fixed_newton_iters <= 0 && o->stop_mode == BSC_STOP_STEP;
+    // With the step rule (and no warm start) nothing the host decides before the solve depends on
+    // the assembly: the PCG tolerance is formed on the device and E, |g| are read back with |p|
+    // and the line search's first trial after the solve, in one synchronisation.
+    const bool deferred = step_rule && !o->warm_start;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
     if (!ctx->cg_ev_tried) {
         ctx->cg_ev_tried = true;
-        ctx->cg_ev_ok = hipEventCreate(&ctx->cg_ev[0]) == hipSuccess && hipEventCreate(&ctx->cg_ev[1]) == hipSuccess;
-        if (!ctx->cg_ev_ok) (void)hipGetLastError();
+        bool ok = true;
+        for (auto &e : ctx->cg_ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+        for (auto &e : ctx->ph_ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+        ctx->cg_ev_ok = ok;
+        if (!ok) (void)hipGetLastError();
     }
+    const bool evok = ctx->cg_ev_ok;
+    // read-backs: the scalars and, right after them in the workspace, the int flags, in one copy
+    // into pinned host memory
+    if (!ctx->pinned) HIPX(hipHostMalloc((void **)&ctx->pinned, 1024, hipHostMallocDefault), "pinned host buffer");
+    if ((const char *)B.iscalars != (const char *)B.scalars + 8 * kScalars) return fail(ctx, BSC_E_STATE, "workspace layout");
+    const double *hs = (const double *)ctx->pinned;
+    const int32_t *hf = (const int32_t *)(ctx->pinned + 8 * kScalars);
+    auto pull = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(ctx->pinned, B.scalars, 8 * kScalars + 4 * 8, hipMemcpyDeviceToHost, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    };
+    auto mark = [&](int i) -> hipError_t { return evok ? hipEventRecord(ctx->ph_ev[i], st) : hipSuccess; };
+    auto span_ms = [&](int i, int j) -> double {      // both events complete (after a synchronisation)
+        float ms = 0.f;
+        if (evok && hipEventElapsedTime(&ms, ctx->ph_ev[i], ctx->ph_ev[j]) != hipSuccess) {
+            (void)hipGetLastError();
+            ms = 0.f;
+        }
+        return ms;
+    };
 
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
@@ -897,213 +951,275 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
     bsc_status result = BSC_OK;
     double g0 = -1.0, g_prev = -1.0;
-    double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, 0.1) : o->pcg_rtol;   // PCG tolerance of this iteration
+    double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, 0.1) : o->pcg_rtol;   // PCG tolerance (host-side modes)
     bool force_tight = false;
-    double host[4];
+    double host[2];
     int it = 0;
     for (;; ++it) {
+        // ---- assembly: E, g, H at x ---------------------------------------------------------
+        HIPX(mark(0), "event");
         {
-            Timer t(st);
             bsc_status as = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav);
             if (as != BSC_OK) return as;
-            k_dot_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.g, B.partials + 7 * stride);
-            k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
-            HIPX(hipMemcpyAsync(host, B.scalars + S_E, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read norms");
-            HIPX(hipStreamSynchronize(st), "sync");
-            s.ms_assemble += t.stop();
         }
-        const double E = host[0], gn = std::sqrt(host[1]);
-        if (!std::isfinite(E) || !std::isfinite(gn)) { result = BSC_E_NONFINITE; break; }
-        if (g0 < 0.0) g0 = gn;
-        s.energy = E;
-        s.g_norm = gn;
-        if (o->fixed_newton_iters > 0) {
-            if (it >= o->fixed_newton_iters) break;
-        } else if (o->stop_mode == BSC_STOP_GRAD && gn <= o->rtol * g0) {
-            break;
-        } else if (gn == 0.0) {
-            break;
-        }
-        if (it >= o->max_newton) { result = BSC_E_NOT_CONVERGED; break; }
-        if (force_tight) {
-            eta = o->pcg_rtol;
+        k_dot_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.g, B.partials + 7 * stride);
+        k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
+        HIPX(mark(1), "event");
+        int eta_mode = ETA_EXPLICIT;
+        if (!deferred) {
+            HIPX(pull(), "read norms");
+            host[0] = hs[S_E];
+            host[1] = hs[S_GG];
+            s.ms_assemble += span_ms(0, 1);
+            const double E = host[0], gn = std::sqrt(host[1]);
+            if (!std::isfinite(E) || !std::isfinite(gn)) { result = BSC_E_NONFINITE; break; }
+            if (g0 < 0.0) g0 = gn;
+            s.energy = E;
+            s.g_norm = gn;
+            if (o->fixed_newton_iters > 0) {
+                if (it >= o->fixed_newton_iters) break;
+            } else if (o->stop_mode == BSC_STOP_GRAD && gn <= o->rtol * g0) {
+                break;
+            } else if (gn == 0.0) {
+                break;
+            }
+            if (it >= o->max_newton) { result = BSC_E_NOT_CONVERGED; break; }
+            if (force_tight) {
+                eta = o->pcg_rtol;
+                force_tight = false;
+            } else if (o->pcg_adaptive && g_prev > 0.0) {
+                // Eisenstat-Walker forcing term (choice 2, gamma = 0.9, exponent 2) with safeguard
+                const double ratio = gn / g_prev;
+                double e = 0.9 * ratio * ratio;
+                const double guard = 0.9 * eta * eta;
+                if (guard > 0.1) e = std::max(e, guard);
+                eta = std::min(0.1, std::max(o->pcg_rtol, e));
+            }
+            g_prev = gn;
+        } else {
+            if (it >= o->max_newton) {
+                HIPX(pull(), "read norms");
+                host[0] = hs[S_E];
+                host[1] = hs[S_GG];
+                s.energy = host[0];
+                s.g_norm = std::sqrt(host[1]);
+                s.ms_assemble += span_ms(0, 1);
+                result = std::isfinite(host[0]) && std::isfinite(host[1]) ? BSC_E_NOT_CONVERGED : BSC_E_NONFINITE;
+                break;
+            }
+            eta_mode = force_tight ? ETA_TIGHT : (o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED);
             force_tight = false;
-        } else if (o->pcg_adaptive && g_prev > 0.0) {
-            // Eisenstat-Walker forcing term (choice 2, gamma = 0.9, exponent 2) with safeguard
-            const double ratio = gn / g_prev;
-            double e = 0.9 * ratio * ratio;
-            const double guard = 0.9 * eta * eta;
-            if (guard > 0.1) e = std::max(e, guard);
-            eta = std::min(0.1, std::max(o->pcg_rtol, e));
         }
-        g_prev = gn;
 
-        // ---- direction: PCG on H p = -g -----------------------------------------------
-        {
-            Timer t(st);
-            if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.hess, B.pinv);
-            else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv);
-            k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
-            HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
-            // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
-            // is recomputed where it is needed)
-            double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
-            double *p = B.p0;
-            double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
-            const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
-            double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
-            const double *q0 = nullptr;
-            if (o->warm_start) {
-                // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
-                // kept only when |b - H x0| < |b| (else zero start)
-                Timer tw(st);
-                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
-                HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
-                                      B.net_scale, B.net_w_fwd, true, st), "warm start forward");
-                k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
-                HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
-                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
-                k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
-                HIPX(hipGetLastError(), "warm start");
-                double d4[4];
-                HIPX(hipMemcpyAsync(d4, B.scalars + S_WS0, 4 * sizeof(double), hipMemcpyDeviceToHost, st), "read ws");
-                HIPX(hipStreamSynchronize(st), "sync ws");
-                const double gp = d4[0], pw = d4[1], gw = d4[2], ww = d4[3], bb = host[1];
-                bool use = false;
-                if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
-                    // energy-optimal multiple of p_hat (either sign: the training loss fixes the
-                    // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
-                    const double as = -gp / pw;
-                    const double rr = bb + 2.0 * as * gw + as * as * ww;
-                    if (as != 0.0 && rr < bb) {
-                        use = true;
-                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
-                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
-                    }
-                }
-                if (use) s.warm_start_used++;
-                else s.warm_start_fallbacks++;
-                s.ms_warmstart += tw.stop();
-                q0 = use ? hq : nullptr;
-            }
-            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
-                                               o->max_pcg, eta);
-            auto bufs = [&](int j) {
-                CgBufs c{};
-                c.x = B.dir; c.p = p; c.pinv = B.pinv;
-                c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
-                const int cur = j & 1, prev = (j + 1) & 1;
-                c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
-                c.w_in = wb[prev]; c.w_out = wb[cur];
-                c.s_in = sb[prev]; c.s_out = sb[cur];
-                c.part_in = part[prev]; c.part_out = part[cur];
-                c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
-                return c;
-            };
-            if (prec == BSC_FP64)
-                k_cg_fused<double, true><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
-            else
-                k_cg_fused<float, true><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
-            HIPX(hipGetLastError(), "cg init");
-            int32_t flags[6] = {0, 0, 0, 0, 0, 0};
-            const int chunk = 16;                   // even: every chunk starts on an odd launch
-            auto enqueue_chunk = [&](hipStream_t cs) {
-                for (int c = 1; c <= chunk; ++c) {
-                    if (prec == BSC_FP64)
-                        k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
-                    else
-                        k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
-                }
-            };
-            // The chunk is captured once into a graph (on a private stream) and replayed on the
-            // context's stream; its kernel arguments depend only on the bound workspace.
-            hipGraphExec_t &gx = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1];
-            if (!gx && ctx->use_graphs) {
-                hipStream_t cs = nullptr;
-                hipGraph_t graph = nullptr;
-                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                if (ok) {
-                    enqueue_chunk(cs);
-                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
-                }
-                ok = ok && hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0) == hipSuccess;
-                if (graph) (void)hipGraphDestroy(graph);
-                if (cs) (void)hipStreamDestroy(cs);
-                if (!ok) {
-                    if (gx) { (void)hipGraphExecDestroy(gx); gx = nullptr; }
-                    (void)hipGetLastError();
+        // ---- direction: PCG on H p = -g -----------------------------------------------------
+        HIPX(mark(2), "event");
+        if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.hess, B.pinv);
+        else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv);
+        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
+        HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
+        // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
+        // is recomputed where it is needed)
+        double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
+        double *p = B.p0;
+        double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
+        const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
+        double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
+        const double *q0 = nullptr;
+        if (o->warm_start) {
+            // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
+            // kept only when |b - H x0| < |b| (else zero start)
+            Timer tw(st);
+            k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
+            HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
+                                  B.net_scale, B.net_w_fwd, true, st), "warm start forward");
+            k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
+            HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
+            k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
+            k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
+            HIPX(hipGetLastError(), "warm start");
+            HIPX(pull(), "read ws");
+            const double gp = hs[S_WS0], pw = hs[S_WS1], gw = hs[S_WS2], ww = hs[S_WS3], bb = host[1];
+            bool use = false;
+            if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
+                // energy-optimal multiple of p_hat (either sign: the training loss fixes the
+                // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
+                const double as = -gp / pw;
+                const double rr = bb + 2.0 * as * gw + as * as * ww;
+                if (as != 0.0 && rr < bb) {
+                    use = true;
+                    k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
+                    k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
                 }
             }
-            while (true) {
-                if (ctx->cg_ev_ok) HIPX(hipEventRecord(ctx->cg_ev[0], st), "cg event");
-                if (gx) HIPX(hipGraphLaunch(gx, st), "cg graph");
-                else enqueue_chunk(st);
-                HIPX(hipGetLastError(), "cg");
-                if (ctx->cg_ev_ok) HIPX(hipEventRecord(ctx->cg_ev[1], st), "cg event");
-                HIPX(hipMemcpyAsync(flags, B.iscalars, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read cg flags");
-                HIPX(hipStreamSynchronize(st), "sync cg");
-                if (ctx->cg_ev_ok) {
-                    float ms = 0.f;
-                    HIPX(hipEventElapsedTime(&ms, ctx->cg_ev[0], ctx->cg_ev[1]), "cg event time");
-                    s.ms_cg_kernels += ms;
-                }
-                s.cg_launches += chunk;
-                if (flags[I_DONE]) break;
+            if (use) s.warm_start_used++;
+            else s.warm_start_fallbacks++;
+            s.ms_warmstart += tw.stop();
+            q0 = use ? hq : nullptr;
+        }
+        k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
+                                           eta_mode, it == 0 ? 1 : 0, eta, o->pcg_rtol);
+        auto bufs = [&](int j) {
+            CgBufs c{};
+            c.x = B.dir; c.p = p; c.pinv = B.pinv;
+            c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
+            const int cur = j & 1, prev = (j + 1) & 1;
+            c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
+            c.w_in = wb[prev]; c.w_out = wb[cur];
+            c.s_in = sb[prev]; c.s_out = sb[cur];
+            c.part_in = part[prev]; c.part_out = part[cur];
+            c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
+            return c;
+        };
+        if (prec == BSC_FP64)
+            k_cg_fused<double, true><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+        else
+            k_cg_fused<float, true><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+        HIPX(hipGetLastError(), "cg init");
+        int32_t flags[6] = {0, 0, 0, 0, 0, 0};
+        const int chunk = 8;                    // even: every chunk starts on an odd launch
+        auto enqueue_chunk = [&](hipStream_t cs) {
+            for (int c = 1; c <= chunk; ++c) {
+                if (prec == BSC_FP64)
+                    k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
+                else
+                    k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
             }
-            s.cg_active_launches += flags[I_ITERS];
-            const int32_t brk = flags[I_BREAK];
-            flags[1] = flags[I_ITERS];
-            s.pcg_iters_total += flags[1];
-            s.ms_pcg += t.stop();
-            if (brk) { result = BSC_E_PCG_BREAKDOWN; break; }
-            if (ctx->log_count < ctx->log_cap) {
-                const size_t off = size_t(ctx->log_count) * n3;
-                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, ctx->log_g + off);
-                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.dir, ctx->log_p + off);
-                HIPX(hipGetLastError(), "sample log");
-                ctx->log_count++;
+        };
+        // The chunk is captured once into a graph (on a private stream) and replayed on the
+        // context's stream; its kernel arguments depend only on the bound workspace.
+        hipGraphExec_t &gxe = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1];
+        if (!gxe && ctx->use_graphs) {
+            hipStream_t cs = nullptr;
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                enqueue_chunk(cs);
+                ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+            }
+            ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (cs) (void)hipStreamDestroy(cs);
+            if (!ok) {
+                if (gxe) { (void)hipGraphExecDestroy(gxe); gxe = nullptr; }
+                (void)hipGetLastError();
             }
         }
-        if (o->fixed_newton_iters <= 0 && o->stop_mode == BSC_STOP_STEP) {
+        // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
+        // exit at once). The first burst is two chunks; after each burst the host extrapolates the
+        // residual's geometric decay to the stopping threshold and sizes the next burst to about
+        // nine tenths of the iterations that remain.
+        int burst = 2, done_prev = 0;
+        double lrho_prev = 0.0;
+        bool have_prev = false;
+        while (true) {
+            if (evok) HIPX(hipEventRecord(ctx->cg_ev[0], st), "cg event");
+            for (int bi = 0; bi < burst; ++bi) {
+                if (gxe) HIPX(hipGraphLaunch(gxe, st), "cg graph");
+                else enqueue_chunk(st);
+            }
+            HIPX(hipGetLastError(), "cg");
+            if (evok) HIPX(hipEventRecord(ctx->cg_ev[1], st), "cg event");
+            HIPX(pull(), "read cg state");
+            for (int k = 0; k < 6; ++k) flags[k] = hf[k];
+            const double *cgs = hs;
+            if (evok) {
+                float ms = 0.f;
+                HIPX(hipEventElapsedTime(&ms, ctx->cg_ev[0], ctx->cg_ev[1]), "cg event time");
+                s.ms_cg_kernels += ms;
+            }
+            s.cg_launches += chunk * burst;
+            if (flags[I_DONE]) break;
+            // iterations done so far: the launches of the bursts minus the first (which forms w_0)
+            const int done = std::max(1, (flags[I_ITA] > flags[I_ITB] ? flags[I_ITA] : flags[I_ITB]) - 1);
+            const double tol2 = cgs[S_TOL2], rho = cgs[S_RHO];
+            if (!have_prev) {
+                const double eta_now = cgs[S_RTOL];
+                lrho_prev = eta_now > 0.0 ? std::log(tol2 / (eta_now * eta_now)) : std::log(rho);   // |b|^2
+                done_prev = 0;
+                have_prev = true;
+            }
+            burst = 1;
+            if (rho > 0.0 && tol2 > 0.0 && done > done_prev) {
+                const double rate = (std::log(rho) - lrho_prev) / double(done - done_prev);
+                if (rate < 0.0) {
+                    const double remaining = (std::log(tol2) - std::log(rho)) / rate;
+                    burst = std::max(1, std::min(8, int(0.9 * remaining) / chunk));
+                }
+                lrho_prev = std::log(rho);
+                done_prev = done;
+            }
+        }
+        HIPX(mark(3), "event");
+        s.cg_active_launches += flags[I_ITERS];
+        s.pcg_iters_total += flags[I_ITERS];
+        if (flags[I_BREAK]) { result = BSC_E_PCG_BREAKDOWN; break; }
+        if (ctx->log_count < ctx->log_cap) {
+            const size_t off = size_t(ctx->log_count) * n3;
+            k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, ctx->log_g + off);
+            k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.dir, ctx->log_p + off);
+            HIPX(hipGetLastError(), "sample log");
+            ctx->log_count++;
+        }
+
+        // ---- |p|_inf for the step rule, line-search coefficients and the trial at alpha = 1 ---
+        // The energy difference along p: the inertia, gravity and bending terms are quadratics in
+        // alpha (coefficients c1, c2), the membrane term is summed point by point.
+        HIPX(mark(4), "event");
+        if (step_rule) {
             k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.dir, B.partials + 7 * stride);
             k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
-            double pmax = 0.0;
-            HIPX(hipMemcpyAsync(&pmax, B.scalars + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, st), "read pmax");
-            HIPX(hipStreamSynchronize(st), "sync");
-            if (pmax / dt <= o->atol) {
-                if (eta <= o->pcg_rtol) break;
-                force_tight = true;        // confirm the stop on a direction solved to pcg_rtol
-            }
+        }
+        double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
+        k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
+        k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, B.dir, pb, stride);
+        k_sum2_into<<<1, kBlock, 0, st>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
+        k_sum2_into<<<1, kBlock, 0, st>>>(pa + stride, blocks(S.n_cp), pb + stride, blocks(S.n_be), B.scalars, S_C2);
+        k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, 1.0, B.partials + 6 * stride);
+        k_sum_into<<<1, kBlock, 0, st>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
+        HIPX(hipGetLastError(), "line search setup");
+        HIPX(mark(5), "event");
+        HIPX(pull(), "read scalars");
+        double sc[S_GPREV - S_E + 1];
+        for (int k = S_E; k <= S_GPREV; ++k) sc[k - S_E] = hs[k];
+        if (deferred) s.ms_assemble += span_ms(0, 1);
+        s.ms_pcg += span_ms(2, 3);
+        s.ms_linesearch += span_ms(4, 5);
+        auto scal = [&](int i) { return sc[i - S_E]; };
+        if (deferred) {
+            const double E = scal(S_E), gn = std::sqrt(scal(S_GG));
+            if (!std::isfinite(E) || !std::isfinite(gn)) { result = BSC_E_NONFINITE; break; }
+            if (g0 < 0.0) g0 = gn;
+            s.energy = E;
+            s.g_norm = gn;
+            eta = scal(S_ETA);
+        }
+        if (step_rule && scal(S_PMAX) / dt <= o->atol) {
+            if (eta <= o->pcg_rtol) break;
+            force_tight = true;        // confirm the stop on a direction solved to pcg_rtol
         }
 
-        // ---- backtracking line search on the energy difference ---------------------------
+        // ---- backtracking line search on the energy difference ------------------------------
         {
             Timer t(st);
-            const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
-            double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
-            k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
-            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, B.dir, pb, stride);
-            k_sum2_into<<<1, kBlock, 0, st>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
-            k_sum2_into<<<1, kBlock, 0, st>>>(pa + stride, blocks(S.n_cp), pb + stride, blocks(S.n_be), B.scalars, S_C2);
-            HIPX(hipGetLastError(), "line search setup");
-            double c12[2];
-            HIPX(hipMemcpyAsync(c12, B.scalars + S_C1, 2 * sizeof(double), hipMemcpyDeviceToHost, st), "read c1 c2");
+            const double c1 = scal(S_C1), c2 = scal(S_C2);
+            double dem = scal(S_DEM);
             double alpha = 1.0;
             bool ok = false;
-            for (int h = 0; h <= 20; ++h) {
-                k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, alpha, B.partials + 6 * stride);
-                k_sum_into<<<1, kBlock, 0, st>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
-                double dem = 0.0;
-                HIPX(hipMemcpyAsync(&dem, B.scalars + S_DEM, sizeof(double), hipMemcpyDeviceToHost, st), "read dE");
-                HIPX(hipStreamSynchronize(st), "sync ls");
-                const double dE = alpha * c12[0] + 0.5 * alpha * alpha * c12[1] + dem;
-                if (!std::isfinite(dE)) { alpha *= 0.5; s.ls_halvings++; continue; }
-                if (dE <= 0.0) { ok = true; break; }
+            int h = 0;
+            for (; h <= 20; ++h) {
+                if (h > 0) {
+                    k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, alpha, B.partials + 6 * stride);
+                    k_sum_into<<<1, kBlock, 0, st>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
+                    HIPX(pull(), "read dE");
+                    dem = hs[S_DEM];
+                }
+                const double dE = alpha * c1 + 0.5 * alpha * alpha * c2 + dem;
+                if (std::isfinite(dE) && dE <= 0.0) { ok = true; break; }
                 alpha *= 0.5;
                 s.ls_halvings++;
             }
-            s.ms_linesearch += t.stop();
+            if (h > 0) s.ms_linesearch += t.stop();
             if (!ok) { result = BSC_E_LINESEARCH; break; }
             k_update<<<blocks(n3), kBlock, 0, st>>>(n3, alpha, B.dir, x);
             HIPX(hipGetLastError(), "update");

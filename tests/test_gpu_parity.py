@@ -321,3 +321,47 @@ def test_standard_2x2_rule_needs_as_many_newton_iterations():
         iters[rule] = per
     print(f"[quadrature] Newton iterations per step: reduced {iters[0]} | 2x2 interior {iters[1]}")
     assert abs(sum(iters[0]) - sum(iters[1])) <= max(4, 0.25 * sum(iters[1]))
+
+
+def test_step_rule_device_tolerance_equals_host_tolerance():
+    """With the paper's step rule the Eisenstat-Walker tolerance is formed on the device and the
+    solve follows the assembly without a host round trip; with a warm start the same tolerance
+    is formed on the host. All-zero warm-start weights always fall back to a zero start, so both
+    paths must give bitwise the same steps."""
+    from oracle import net_ref
+    sc = syn.driven_sheet(40, seed=21)
+    res = []
+    for ws in (0, 1):
+        ctx = _ctx(sc)
+        if ws:
+            ctx.bsc_warmstart_load(torch.zeros(net_ref.N_PARAMS, dtype=torch.float32, device="cuda"))
+        x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+        opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=bsc.BSC_FP32_MIXED, warm_start=ws,
+                             stop_mode=bsc.BSC_STOP_STEP, atol=1e-2, pcg_rtol=1e-3, pcg_adaptive=1, max_pcg=4000)
+        iters = []
+        for step in range(3):
+            st, stt = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(step)), opts)
+            assert st == 0
+            iters.append((stt.newton_iters, stt.pcg_iters_total))
+        res.append((x.cpu().numpy(), iters))
+    print(f"[step rule] device tolerance {res[0][1]} | host tolerance {res[1][1]}")
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][0], res[1][0])
+
+
+def test_step_rule_stops_within_its_tolerance():
+    """The step rule |p|_inf / dt <= atol leaves the state within about atol dt of the converged
+    implicit-Euler step (Newton converges quadratically near the solution)."""
+    sc = syn.hanging_sheet(24, seed=5)
+    out = {}
+    for mode, extra in (("step", dict(stop_mode=bsc.BSC_STOP_STEP, atol=1e-2, pcg_adaptive=1)),
+                        ("grad", dict(stop_mode=bsc.BSC_STOP_GRAD, rtol=1e-10))):
+        ctx = _ctx(sc)
+        x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+        opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=bsc.BSC_FP64, pcg_rtol=1e-8,
+                             max_newton=60, max_pcg=4000, **extra)
+        for step in range(3):
+            st, _ = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(step)), opts)
+            assert st == 0
+        out[mode] = x.cpu().numpy()
+    assert np.abs(out["step"] - out["grad"]).max() <= 1e-2 * sc.dt
