@@ -397,6 +397,51 @@ __device__ void project_psd2(double &a, double &b, double &c) {
     a = k * vx * vx; b = k * vx * vy; c = k * vy * vy;
 }
 
+// PSD projection of the in-plane StVK block d^2 Psi / dF^2 (4x4, index 2 gamma + i) at the
+// in-plane deformation gradient F = [[a, b], [0, d]] (a, d > 0), in closed form. Psi depends on
+// F only through its singular values s1 >= s2 > 0; with F = U diag(s1, s2) V^T (U, V rotations)
+// the block's eigenvectors are the scaling directions u1 v1^T, u2 v2^T (mixed by the 2x2
+// Hessian of psi(s1, s2)), the twist (u2 v1^T - u1 v2^T)/sqrt2 and the flip
+// (u1 v2^T + u2 v1^T)/sqrt2, with eigenvalues (psi_1 + psi_2)/(s1 + s2) and
+// (psi_1 - psi_2)/(s1 - s2) (Smith, de Goes and Kim 2019, analytic eigensystems of isotropic
+// energies). For StVK, psi = mu/4 sum (s_i^2 - 1)^2 + lam/8 (s1^2 + s2^2 - 2)^2, both
+// quotients are polynomials, so equal singular values need no special case.
+__device__ void stvk_inplane_projected(double a, double b, double d, double mu, double lam, double P[4][4]) {
+    const double p = a * a, q = a * b, r = b * b + d * d;          // C = F^T F
+    const double h = 0.5 * (p - r), m = 0.5 * (p + r), rad = sqrt(h * h + q * q);
+    const double s1 = sqrt(m + rad), s2 = a * d / s1;
+    double vx, vy;                                                  // eigenvector of C for s1^2
+    if (h >= 0.0) { vx = h + rad; vy = q; } else { vx = q; vy = rad - h; }
+    const double nn = sqrt(vx * vx + vy * vy);
+    if (nn > 0.0) { vx /= nn; vy /= nn; } else { vx = 1.0; vy = 0.0; }
+    const double v1[2] = {vx, vy}, v2[2] = {-vy, vx};
+    const double u1[2] = {(a * vx + b * vy) / s1, (d * vy) / s1}, u2[2] = {-u1[1], u1[0]};
+    const double I = s1 * s1 + s2 * s2;
+    double b11 = mu * (3.0 * s1 * s1 - 1.0) + 0.5 * lam * (I - 2.0) + lam * s1 * s1;
+    double b22 = mu * (3.0 * s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0) + lam * s2 * s2;
+    double b12 = lam * s1 * s2;
+    project_psd2(b11, b12, b22);
+    const double lt = fmax(mu * (s1 * s1 - s1 * s2 + s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0), 0.0);
+    const double ll = fmax(mu * (s1 * s1 + s1 * s2 + s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0), 0.0);
+    double D1[4], D2[4], T[4], L[4];                                // vec index 2 gamma + i
+    const double k = 0.70710678118654752440;
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            D1[2 * g + i] = u1[i] * v1[g];
+            D2[2 * g + i] = u2[i] * v2[g];
+            T[2 * g + i] = k * (u2[i] * v1[g] - u1[i] * v2[g]);
+            L[2 * g + i] = k * (u1[i] * v2[g] + u2[i] * v1[g]);
+        }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            P[x][y] = b11 * D1[x] * D1[y] + b22 * D2[x] * D2[y] + b12 * (D1[x] * D2[y] + D2[x] * D1[y]) +
+                      lt * T[x] * T[y] + ll * L[x] * L[y];
+}
+
 // Builds the projected 6x6 density Hessian of the membrane model at displacement gradient G
 // (double) into A. Returns false when f1 and f2 are (nearly) parallel.
 __device__ bool project_structured(const DevSheet &S, const double G[3][2], double A[6][6]) {
@@ -430,21 +475,10 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
             for (int d = 0; d < 2; ++d)
                 E[g][d] = 0.5 * (G[g][d] + G[d][g] + G[0][g] * G[0][d] + G[1][g] * G[1][d] + G[2][g] * G[2][d]);
         const double tr = E[0][0] + E[1][1];
-        const double Sm[2][2] = {{2.0 * S.mu * E[0][0] + S.lam * tr, 2.0 * S.mu * E[0][1]},
-                                 {2.0 * S.mu * E[1][0], 2.0 * S.mu * E[1][1] + S.lam * tr}};
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int d = 0; d < 2; ++d)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const double ff = F2[i][0] * F2[j][0] + F2[i][1] * F2[j][1];
-                        P4[2 * g + i][2 * d + j] = (i == j ? Sm[g][d] : 0.0) + S.mu * F2[i][d] * F2[j][g] +
-                                                   (g == d ? S.mu * ff : 0.0) + S.lam * F2[i][g] * F2[j][d];
-                    }
-        Na = Sm[0][0]; Nb = Sm[0][1]; Nc = Sm[1][1];
+        Na = 2.0 * S.mu * E[0][0] + S.lam * tr;     // normal block: the second Piola-Kirchhoff stress
+        Nb = 2.0 * S.mu * E[0][1];
+        Nc = 2.0 * S.mu * E[1][1] + S.lam * tr;
+        stvk_inplane_projected(F2[0][0], F2[0][1], F2[1][1], S.mu, S.lam, P4);
     } else {
         const double mus[2] = {S.mu1, S.mu2};
         double len[2], q[2];
@@ -474,7 +508,7 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
                     }
         Na = 2.0 * mus[0] * q[0]; Nb = 2.0 * S.msh * I6; Nc = 2.0 * mus[1] * q[1];
     }
-    project_psd4(P4);
+    if (S.membrane != BSC_MEMBRANE_STVK) project_psd4(P4);
     project_psd2(Na, Nb, Nc);
     const double N2[2][2] = {{Na, Nb}, {Nb, Nc}};
     // rotate back: A[(g,i),(d,j)] = sum_{a,b<2} e_a[i] P4[(g,a),(d,b)] e_b[j] + N[g][d] e3[i] e3[j]
