@@ -94,30 +94,25 @@ enum AsmKind { kAsmF32 = 0, kAsmF64 = 1, kAsmMixed = 2 };   // (A, P, g) = (f, f
 constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
 
 // LDS layout of one assembly tile (offsets in bytes): local membrane point offsets of the
-// (tx + 2) x (ty + 2) elements, the work counter, and per membrane point the weighted density
-// Hessian A (21 entries) plus either the gradients of its 9 local basis functions (18, when A
-// is FP32) or its span coordinates tu, tv (FP64: the gradients are recomputed).
+// (tx + 2) x (ty + 2) elements, the first global point of each element row, the work counter,
+// then one record per membrane point. FP32
+// record (kAsmRecF floats, 16-byte aligned): the weighted density Hessian A (21 entries, padded
+// to 24), then the gradients of the 9 local basis functions (18). FP64 record (kAsmRecD
+// doubles): A (21), then the span coordinates tu, tv (the gradients are recomputed).
+constexpr int kAsmRecF = 44, kAsmRecD = 23;
 struct AsmLds {
-    size_t el_off, counter, A, dN, tu, tv, total;
+    size_t el_off, rows, counter, rec, rec_bytes, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 __host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int sizeA) {
     AsmLds L;
     const size_t ne = size_t(tx + 2) * (ty + 2);
-    L.el_off = 0;
-    L.counter = align16(L.el_off + 4 * (ne + 1));
-    L.A = align16(L.counter + 4);
-    const size_t after_a = align16(L.A + size_t(21) * sizeA * maxp);
-    if (sizeA == 4) {
-        L.dN = after_a;
-        L.tu = L.tv = 0;
-        L.total = align16(L.dN + size_t(18) * 4 * maxp);
-    } else {
-        L.dN = 0;
-        L.tu = after_a;
-        L.tv = L.tu + 8 * size_t(maxp);
-        L.total = align16(L.tv + 8 * size_t(maxp));
-    }
+    L.el_off = 0;                                   // local membrane point offsets (ne + 1)
+    L.rows = align16(L.el_off + 4 * (ne + 1));      // global first point of each element row (ty + 2)
+    L.counter = align16(L.rows + 4 * size_t(ty + 2));
+    L.rec = align16(L.counter + 4);
+    L.rec_bytes = sizeA == 4 ? 4 * kAsmRecF : 8 * kAsmRecD;
+    L.total = align16(L.rec + L.rec_bytes * size_t(maxp));
     return L;
 }
 

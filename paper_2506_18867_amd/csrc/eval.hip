@@ -664,13 +664,14 @@ __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__
 // weighted density Hessian A (21 entries) and the gradients of the 9 local basis functions
 // (FP32) or the span coordinates (FP64, gradients recomputed). Work items (CP, slot): slots
 // 0..12 are the upper-stencil Hessian blocks, slot 13 is the gradient with the per-CP energy
-// terms (stresses and bending terms gathered from global memory). Items are numbered slot-major
+// terms (membrane stresses gathered from global memory, bending as K_b d from the constant
+// bending stencil). Items are numbered slot-major
 // with the slots by decreasing cost, and handed to waves in chunks of 64 from an LDS counter.
 // Each item sums over elements and points in a fixed order, so the result does not depend on
 // which wave takes it.
 template <typename TA, typename TP, typename TG>
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int kind, const TA *__restrict__ ptA,
-                                                               const TP *__restrict__ ptP, const double *__restrict__ beD,
+                                                               const TP *__restrict__ ptP,
                                                                const double *__restrict__ x, const double *__restrict__ xhat,
                                                                double inv_dt2, double gx, double gy, double gz,
                                                                TA *__restrict__ hess, TG *__restrict__ gout,
@@ -681,10 +682,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
     const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, int(sizeof(TA)));
     int *el_off = (int *)(lds + L.el_off);
+    int *mrow = (int *)(lds + L.rows);
     int *counter = (int *)(lds + L.counter);
-    TA *pA = (TA *)(lds + L.A);
-    TA *pdN = (TA *)(lds + L.dN);
-    double *ptu = (double *)(lds + L.tu), *ptv = (double *)(lds + L.tv);
+    constexpr int REC = STAGE_DN ? kAsmRecF : kAsmRecD;      // record length in TA units
+    TA *prec = (TA *)(lds + L.rec);
 
     const int ntx = (S.n_u + kAsmTileU - 1) / kAsmTileU;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -693,23 +694,23 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + ty - 1);
     const int nk = k1 - k0 + 1, nl = l1 - l0 + 1, ne = nk * nl;
 
-    if (hess) {
-        // local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0));
-        // the points of one element row are contiguous in the global tables
-        for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
-            const int r = t / nk, kk = t % nk;
-            int mb = 0;
-            for (int q = 0; q < r; ++q) {
-                const int e0 = (l0 + q) * S.Nu;
-                mb += S.mp_off[e0 + k1 + 1] - S.mp_off[e0 + k0];
-            }
-            if (r < nl) {
-                const int e0 = (l0 + r) * S.Nu + k0;
-                mb += S.mp_off[e0 + kk] - S.mp_off[e0];
-            }
-            el_off[t] = mb;
+    // local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0)) and
+    // the global first point of each element row: the points of one element row are contiguous
+    // in the global tables
+    for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
+        const int r = t / nk, kk = t % nk;
+        int mb = 0;
+        for (int q = 0; q < r; ++q) {
+            const int e0 = (l0 + q) * S.Nu;
+            mb += S.mp_off[e0 + k1 + 1] - S.mp_off[e0 + k0];
         }
+        if (r < nl) {
+            const int e0 = (l0 + r) * S.Nu + k0;
+            mb += S.mp_off[e0 + kk] - S.mp_off[e0];
+        }
+        el_off[t] = mb;
     }
+    for (int r = threadIdx.x; r < nl; r += blockDim.x) mrow[r] = S.mp_off[(l0 + r) * S.Nu + k0];
     if (threadIdx.x == 0) *counter = 0;
     __syncthreads();
     if (hess) {
@@ -717,21 +718,22 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
         for (int t = threadIdx.x; t < np; t += blockDim.x) {
             int r = 0;
             while (r + 1 < nl && el_off[(r + 1) * nk] <= t) ++r;
-            const int q = S.mp_off[(l0 + r) * S.Nu + k0] + (t - el_off[r * nk]);
+            const int q = mrow[r] + (t - el_off[r * nk]);
+            TA *rec = prec + size_t(t) * REC;
 #pragma unroll
-            for (int c = 0; c < 21; ++c) pA[c * maxp + t] = ptA[c * S.n_mp + q];
+            for (int c = 0; c < 21; ++c) rec[c] = ptA[c * S.n_mp + q];
             if constexpr (STAGE_DN) {
                 const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
                 TA dN[9][2];
                 local_grads<TA>(S, k, l, TA(S.mp_tu[q]), TA(S.mp_tv[q]), dN);
 #pragma unroll
                 for (int m = 0; m < 9; ++m) {
-                    pdN[(2 * m) * maxp + t] = dN[m][0];
-                    pdN[(2 * m + 1) * maxp + t] = dN[m][1];
+                    rec[24 + 2 * m] = dN[m][0];
+                    rec[24 + 2 * m + 1] = dN[m][1];
                 }
             } else {
-                ptu[t] = S.mp_tu[q];
-                ptv[t] = S.mp_tv[q];
+                rec[21] = TA(S.mp_tu[q]);
+                rec[22] = TA(S.mp_tv[q]);
             }
         }
     }
@@ -772,28 +774,41 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                     for (int k = max(0, max(i, ib) - 2); k <= min(min(i, ib), S.Nu - 1); ++k) {
                         const int el = (l - l0) * nk + (k - k0);
                         const int la = i - k, lb = j - l, ma = ib - k, mb = jb - l;
+                        const int oa = 24 + 2 * (3 * lb + la), ob = 24 + 2 * (3 * mb + ma);
                         for (int q = el_off[el]; q < el_off[el + 1]; ++q) {
+                            const TA *rec = prec + size_t(q) * REC;
                             TA ga[2], gb[2];
                             if constexpr (STAGE_DN) {
-                                const int oa = 2 * (3 * lb + la), ob = 2 * (3 * mb + ma);
-                                ga[0] = pdN[oa * maxp + q]; ga[1] = pdN[(oa + 1) * maxp + q];
-                                gb[0] = pdN[ob * maxp + q]; gb[1] = pdN[(ob + 1) * maxp + q];
+                                TA Aq[21];
+                                // 16-byte reads of the record: A in entries 0..20, gradients from 24
+                                const float4 *r4 = (const float4 *)rec;
+#pragma unroll
+                                for (int v = 0; v < 5; ++v) {
+                                    const float4 t4 = r4[v];
+                                    Aq[4 * v] = t4.x; Aq[4 * v + 1] = t4.y; Aq[4 * v + 2] = t4.z; Aq[4 * v + 3] = t4.w;
+                                }
+                                Aq[20] = rec[20];
+                                const float2 a2 = *(const float2 *)(rec + oa), b2 = *(const float2 *)(rec + ob);
+                                ga[0] = a2.x; ga[1] = a2.y; gb[0] = b2.x; gb[1] = b2.y;
+                                const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
+#pragma unroll
+                                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                                    for (int cc = 0; cc < 3; ++cc)
+                                        acc[r][cc] += c00 * Aq[u6(r, cc)] + c01 * Aq[u6(r, 3 + cc)] +
+                                                      c10 * Aq[u6(3 + r, cc)] + c11 * Aq[u6(3 + r, 3 + cc)];
                             } else {
-                                const TA tu = TA(ptu[q]), tv = TA(ptv[q]);
+                                const TA tu = rec[21], tv = rec[22];
                                 grad_at<TA>(S, k, l, la, lb, tu, tv, ga);
                                 grad_at<TA>(S, k, l, ma, mb, tu, tv, gb);
+                                const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
+#pragma unroll
+                                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                                    for (int cc = 0; cc < 3; ++cc)
+                                        acc[r][cc] += c00 * rec[u6(r, cc)] + c01 * rec[u6(r, 3 + cc)] +
+                                                      c10 * rec[u6(3 + r, cc)] + c11 * rec[u6(3 + r, 3 + cc)];
                             }
-                            const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
-#pragma unroll
-                            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                                for (int cc = 0; cc < 3; ++cc) {
-                                    const TA a00 = pA[u6(r, cc) * maxp + q];
-                                    const TA a01 = pA[u6(r, 3 + cc) * maxp + q];
-                                    const TA a10 = pA[u6(3 + r, cc) * maxp + q];
-                                    const TA a11 = pA[u6(3 + r, 3 + cc) * maxp + q];
-                                    acc[r][cc] += c00 * a00 + c01 * a01 + c10 * a10 + c11 * a11;
-                                }
                         }
                     }
                 }
@@ -821,21 +836,43 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
             // gradient: membrane stresses and bending terms of the CP's elements, inertia, gravity
             TG acc[3] = {TG(0), TG(0), TG(0)};
             double accb[3] = {0.0, 0.0, 0.0};
+            // point ranges come from the LDS offsets, so every global load below is independent
             for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
+                const int r = l - l0, mbase = mrow[r] - el_off[r * nk];
                 for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
-                    const int e = l * S.Nu + k, la = i - k, lb = j - l;
-                    for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
+                    const int el = r * nk + (k - k0), la = i - k, lb = j - l;
+                    for (int t = el_off[el]; t < el_off[el + 1]; ++t) {
+                        const int q = mbase + t;
                         TG dn[2];
                         grad_at<TG>(S, k, l, la, lb, TG(S.mp_tu[q]), TG(S.mp_tv[q]), dn);
 #pragma unroll
                         for (int cc = 0; cc < 3; ++cc)
                             acc[cc] += TG(ptP[(2 * cc) * S.n_mp + q]) * dn[0] + TG(ptP[(2 * cc + 1) * S.n_mp + q]) * dn[1];
                     }
-                    for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
-                        const double Lm = lap_at(S, k, l, la, lb, S.be_tu[q], S.be_tv[q]);
+                }
+            }
+            // bending: the energy is quadratic with the constant stencil K_b (a scalar times I3 per
+            // block, built at create from the same bending evaluations), so its gradient is K_b d
+            // over the 25 stencil neighbours (d: displacement from the rest position)
 #pragma unroll
-                        for (int cc = 0; cc < 3; ++cc) accb[cc] += beD[cc * S.n_be + q] * Lm;
-                    }
+            for (int s2 = 0; s2 < kSlots; ++s2) {
+                const int di = slot_di(s2), dj = slot_dj(s2);
+                const int ib = i + di, jb = j + dj;
+                if (ib >= 0 && ib < S.n_u && jb < S.n_v) {
+                    const double w = S.hbend[s2 * ncp + a];
+                    double d[3];
+                    displacement(S, x, ib, jb, d);
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
+                }
+                if (s2 == 0) continue;
+                const int ic = i - di, jc = j - dj;
+                if (ic >= 0 && ic < S.n_u && jc >= 0) {
+                    const double w = S.hbend[s2 * ncp + jc * S.n_u + ic];
+                    double d[3];
+                    displacement(S, x, ic, jc, d);
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
                 }
             }
             const double M = S.mass[a];
@@ -977,13 +1014,13 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const 
     const int nt = assemble_tiles(S, kind);
     if (kind == kAsmF32)
         k_assemble_tile<float, float, float><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, (const float *)B.ptP,
-                                                                          B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
+                                                                          x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
     else if (kind == kAsmF64)
         k_assemble_tile<double, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const double *)B.ptA, (const double *)B.ptP,
-                                                                             B.beD, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
+                                                                             x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
     else
         k_assemble_tile<float, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, B.ptP64,
-                                                                            B.beD, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
+                                                                            x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
     return hipGetLastError();
 }
 
