@@ -12,6 +12,11 @@ figure. Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
 
 These sheets stand in for the paper's square-sheet benchmarks (upright hanging, drape,
 compression); no benchmark assets are used.
+
+``mapped_sheet`` builds the non-rectangular domains of the paper's robustness study of its
+reduced quadrature on distorted patches (varying aspect ratio, skewed corners, sharp turns
+within an edge) plus a curved quarter annulus: the Greville grid of the unit square pushed
+through a closed-form map. The rest map is then no longer affine.
 """
 from __future__ import annotations
 
@@ -114,6 +119,68 @@ def flat_sheet(n_u: int, n_v: int | None = None, L_u: float = 1.0, L_v: float | 
     return ku, kv, rest
 
 
+MAPPED_KINDS = ("aspect", "skew", "bend", "annulus")
+
+
+def mapped_sheet(n_u: int, n_v: int | None = None, kind: str = "skew", param: float | None = None,
+                 L_u: float = 1.0, L_v: float | None = None):
+    """Knots and rest CPs (n_cp, 2) of a non-rectangular sheet: CP (i, j) sits at the image of
+    its Greville point (s, t) in [0, 1]^2 under
+
+    - "aspect": the rectangle L_u x (L_u / param), param the aspect ratio (affine map);
+    - "skew": the bilinear map onto the quadrilateral (0, 0), (L_u, 0), P01 + (1.25 L_u, 0),
+      P01 = L_v (cos param, sin param): its corner at the origin has the angle param (degrees),
+      and its top edge is 25% longer than its bottom edge;
+    - "bend": X = (L_u s, L_v t + (1 - t) k L_u (1/2 - |s - 1/2|)) with k = tan((180 - param)/2):
+      the edge t = 0 turns at its midpoint with the interior angle param (degrees);
+    - "annulus": the quarter annulus r = r_in + (r_out - r_in) s, angle (pi / 2) t, with
+      r_out = L_u and r_in = param L_u.
+    """
+    n_v = n_u if n_v is None else n_v
+    L_v = L_u if L_v is None else L_v
+    ku, kv = open_uniform_knots(n_u), open_uniform_knots(n_v)
+    su = greville(ku, n_u) / ku[-1]
+    tv = greville(kv, n_v) / kv[-1]
+    S, T = np.meshgrid(su, tv)                       # [j, i]
+    if kind == "aspect":
+        ratio = 4.0 if param is None else param
+        X, Y = L_u * S, (L_u / ratio) * T
+    elif kind == "skew":
+        ang = np.deg2rad(60.0 if param is None else param)
+        P01 = np.array([L_v * np.cos(ang), L_v * np.sin(ang)])
+        P = np.array([[0.0, 0.0], [L_u, 0.0], P01, [L_u + 0.25 * L_u + P01[0], P01[1]]])
+        w = [(1 - S) * (1 - T), S * (1 - T), (1 - S) * T, S * T]
+        X = sum(wk * P[k, 0] for k, wk in enumerate(w))
+        Y = sum(wk * P[k, 1] for k, wk in enumerate(w))
+    elif kind == "bend":
+        k = np.tan(np.deg2rad(180.0 - (150.0 if param is None else param)) / 2.0)
+        X = L_u * S
+        Y = L_v * T + (1.0 - T) * k * L_u * (0.5 - np.abs(S - 0.5))
+    elif kind == "annulus":
+        r_in = (0.5 if param is None else param) * L_u
+        r = r_in + (L_u - r_in) * S
+        th = 0.5 * np.pi * T
+        X, Y = r * np.cos(th), r * np.sin(th)
+    else:
+        raise ValueError(f"unknown mapped sheet kind {kind!r}")
+    rest = np.stack([X.ravel(), Y.ravel()], axis=1)
+    return ku, kv, rest
+
+
+def mapped_hanging_sheet(n: int, kind: str, param: float | None = None, seed: int = 1,
+                         material: Material | None = None, noise: float = 1e-3) -> Scene:
+    """A mapped sheet hanging from the two corner CPs of its last row (j = n - 1), z-noise
+    U(+-noise), gravity along -y, dt = 0.01 s."""
+    g = rng(seed)
+    ku, kv, rest = mapped_sheet(n, n, kind, param)
+    x0 = embed(rest)
+    x0[:, 2] += g.uniform(-noise, noise, size=x0.shape[0])
+    pins = np.array([cp_index(n, 0, n - 1), cp_index(n, n - 1, n - 1)], dtype=np.int64)
+    mat = material or stvk_material()
+    return Scene(f"hanging-{kind}", n, n, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(),
+                 0.01, np.array([0.0, -9.81, 0.0]))
+
+
 def embed(rest: np.ndarray) -> np.ndarray:
     return np.concatenate([rest, np.zeros((rest.shape[0], 1))], axis=1)
 
@@ -154,15 +221,17 @@ def compressed_sheet(n: int = 100, seed: int = 2, material: Material | None = No
 MATERIAL_GRID = [(E, t) for E in (1e3, 1e4, 1e5) for t in (0.5e-3, 1e-3, 2e-3)]
 
 
-def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: float = 0.0) -> Scene:
+def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: float = 0.0,
+                 domain: tuple | None = None) -> Scene:
     """Large sheet with a material cell from the (E, t) grid, K ~ U{4..16} random held CPs plus
     the corner CP (0,0) driven in z with amplitude 5 cm at 1 Hz; gravity along -z. Starts flat
-    (optional z-noise U(+-noise))."""
+    (optional z-noise U(+-noise)). ``domain`` = (kind, param) places the rest CPs with
+    ``mapped_sheet`` instead of on the unit square (same pins and drive)."""
     g = rng(seed)
     if cell is None:
         cell = (seed - 300) % len(MATERIAL_GRID)
     E, t = MATERIAL_GRID[cell]
-    ku, kv, rest = flat_sheet(n)
+    ku, kv, rest = flat_sheet(n) if domain is None else mapped_sheet(n, n, domain[0], domain[1])
     x0 = embed(rest)
     x0[:, 2] += g.uniform(-noise, noise, size=x0.shape[0])
     K = int(g.integers(4, 17))
