@@ -83,6 +83,8 @@ def parse():
     p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
     p.add_argument("--quad-steps", type=int, default=3,
                    help="steps of the quadrature-ablation leg (reduced vs 2x2 interior rule; 0: skip)")
+    p.add_argument("--general-steps", type=int, default=3,
+                   help="steps of the general-rest leg (the same driven sheet on a curved domain; 0: skip)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run the traffic-counter calibration: one device-to-device copy of MIB MiB whose "
                         "source has been evicted from the caches, then exit")
@@ -232,6 +234,35 @@ def main():
                               "assembly_fp32_ms": round(ms_a, 4)}
             del qctx
 
+    # General rest shapes (Sec. 6.5, non-rectangular domains): the same driven sheet with its rest
+    # CPs on a domain whose rest map is not affine, so the library takes per-point rest geometry.
+    # FP32-mixed steps from the flat start state, the flat square timed the same way beside it.
+    general_leg = None
+    if args.general_steps > 0:
+        general_leg = {}
+        for name, dom in (("square", None), ("bend_150deg", ("bend", 150.0)), ("annulus_0.5", ("annulus", 0.5))):
+            gsc = syn.driven_sheet(args.n, seed=args.seed, noise=args.noise, domain=dom)
+            gctx = bsc.context_for_scene(gsc)
+            xq, vq = bsc.to_soa(gsc.x0), bsc.to_soa(gsc.v0)
+            run_steps(gctx, gsc, xq, vq, 1, 0, bsc.BSC_FP32_MIXED, bsc, torch, args)          # warm-up
+            xq, vq = bsc.to_soa(gsc.x0), bsc.to_soa(gsc.v0)
+            secq, stq = run_steps(gctx, gsc, xq, vq, args.general_steps, 0, bsc.BSC_FP32_MIXED, bsc, torch, args)
+            outq = (torch.zeros(1, dtype=torch.float64, device="cuda"),
+                    torch.empty(3, gsc.n_cp, dtype=torch.float32, device="cuda"),
+                    torch.empty(114, gsc.n_cp, dtype=torch.float32, device="cuda"))
+            outd = (torch.zeros(1, dtype=torch.float64, device="cuda"),
+                    torch.empty(3, gsc.n_cp, dtype=torch.float64, device="cuda"),
+                    torch.empty(114, gsc.n_cp, dtype=torch.float64, device="cuda"))
+            ms_a32 = time_kernel(lambda: gctx.bsc_assemble(xq, xq, gsc.dt, tuple(gsc.gravity), bsc.BSC_FP32_MIXED,
+                                                           out=outq), 20, torch)
+            ms_a64 = time_kernel(lambda: gctx.bsc_assemble(xq, xq, gsc.dt, tuple(gsc.gravity), bsc.BSC_FP64,
+                                                           out=outd), 20, torch)
+            general_leg[name] = {"ms_per_step": round(1e3 * secq / args.general_steps, 3),
+                                 "newton": [s_["newton_iters"] for s_ in stq],
+                                 "pcg": [s_["pcg_iters_total"] for s_ in stq],
+                                 "assembly_fp32_ms": round(ms_a32, 4), "assembly_fp64_ms": round(ms_a64, 4)}
+            del gctx
+
     # per-kernel timings at the current state (same stream as the library)
     n, ne = sc.n_cp, sc.n_elem
     xhat = x.clone()
@@ -323,6 +354,7 @@ def main():
         "spmv": {"fp32_ms": round(ms_spmv32, 5), "fp64_ms": round(ms_spmv64, 5),
                  "fp32_gb_s": round(spmv_bytes32 / ms_spmv32 / 1e6, 1), "fp64_gb_s": round(spmv_bytes64 / ms_spmv64 / 1e6, 1)},
         "quadrature_ablation": quad_leg,
+        "general_rest": general_leg,
         "roofline": roof,
         "cpu_baseline": None,
     }

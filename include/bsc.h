@@ -125,9 +125,14 @@ typedef struct {
 /* Creates a context for an n_u x n_v control grid (Sec. 3.1.2, Eq. "general B-spline patch").
  *   knots_u / knots_v: host, n_u+3 / n_v+3 doubles; must be open uniform quadratic knot vectors
  *     starting at 0 with integer knots (Sec. 3.1.2); n_u, n_v >= 5 (at least 3 spans).
- *   rest_xy: host, 2*n_u*n_v doubles, AoS (X1, X2) per CP (Sec. 3.2). The device path supports
- *     rest maps that are affine in (u,v) (control points at the Greville abscissae of an affine
- *     image of the parameter rectangle, det > 0); others return BSC_E_INVAL.
+ *   rest_xy: host, 2*n_u*n_v doubles, AoS (X1, X2) per CP (Sec. 3.2). Any rest map whose
+ *     Jacobian determinant is positive at every quadrature point (membrane, bending and the
+ *     3x3 Gauss mass points) is accepted; otherwise BSC_E_INVAL. An affine rest (control points
+ *     at the Greville abscissae of an affine image of the parameter rectangle) keeps the
+ *     inverse Jacobian and the Laplacian coefficients as sheet constants; any other rest map
+ *     gets them per quadrature point (Sec. 4.1 inverse function theorem; Sec. 4.2 Laplacian in
+ *     parametric space, with its first-derivative terms): 32 more workspace bytes per membrane
+ *     point, 40 per bending evaluation and 16 per CP.
  *   mat: host; E, thickness, rho_area > 0, nu in (-1, 0.5) for StVK; mu_* >= 0 for FBW.
  *   hip_stream: hipStream_t on which all work is enqueued (NULL = default stream).
  * On success *out owns the host tables; free it with bsc_destroy. Host-only, synchronous. */

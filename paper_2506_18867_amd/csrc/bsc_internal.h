@@ -16,6 +16,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,12 @@ struct DevSheet {
     double A00, A01, A10, A11, b0, b1;      // rest map X = A (u, v) + b, span units
     double K00, K01, K10, K11;              // K = A^{-1}: K[m][b] = d u_m / d X_b
     double c_uu, c_vv, c_uv;                // Laplacian coefficients (affine rest)
+    // General rest map (curved != 0): per-point tables replace the constants above. mp_K
+    // [4][n_mp] holds K = J^{-1} (k00, k01, k10, k11) at each membrane point, be_L [5][n_be]
+    // the Laplacian coefficients (c_uu, c_vv, c_uv, l_u, l_v) at each bending evaluation,
+    // rest [2][n_cp] the rest CPs. The weights mp_w, be_w include |det J| per point.
+    int curved;
+    const double *mp_K, *be_L, *rest;
     int membrane;                           // BSC_MEMBRANE_*
     double mu, lam;                         // StVK per-area Lame parameters
     double mu1, mu2, msh;                   // FBW stiffnesses
@@ -98,20 +105,21 @@ constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
 // then one record per membrane point. FP32
 // record (kAsmRecF floats, 16-byte aligned): the weighted density Hessian A (21 entries, padded
 // to 24), then the gradients of the 9 local basis functions (18). FP64 record (kAsmRecD
-// doubles): A (21), then the span coordinates tu, tv (the gradients are recomputed).
-constexpr int kAsmRecF = 44, kAsmRecD = 23;
+// doubles): A (21), then the span coordinates tu, tv (the gradients are recomputed), then for a
+// general (non-affine) rest map the point's inverse Jacobian K (4; kAsmRecDC doubles in all).
+constexpr int kAsmRecF = 44, kAsmRecD = 23, kAsmRecDC = 27;
 struct AsmLds {
     size_t el_off, rows, counter, rec, rec_bytes, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
-__host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int sizeA) {
+__host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int sizeA, bool curved) {
     AsmLds L;
     const size_t ne = size_t(tx + 2) * (ty + 2);
     L.el_off = 0;                                   // local membrane point offsets (ne + 1)
     L.rows = align16(L.el_off + 4 * (ne + 1));      // global first point of each element row (ty + 2)
     L.counter = align16(L.rows + 4 * size_t(ty + 2));
     L.rec = align16(L.counter + 4);
-    L.rec_bytes = sizeA == 4 ? 4 * kAsmRecF : 8 * kAsmRecD;
+    L.rec_bytes = sizeA == 4 ? 4 * kAsmRecF : 8 * (curved ? kAsmRecDC : kAsmRecD);
     L.total = align16(L.rec + L.rec_bytes * size_t(maxp));
     return L;
 }
@@ -129,6 +137,7 @@ struct DevBufs {
     // tables
     int32_t *mp_elem, *mp_off, *be_elem, *be_off, *pinmask, *pin_idx;
     double *mp_tu, *mp_tv, *mp_w, *be_tu, *be_tv, *be_w, *mass, *hbend;
+    double *mp_K, *be_L, *rest;              // general rest map only (zero bytes when affine)
     // per-point intermediates (sized for double; float uses the front half)
     void *ptA, *ptP;
     double *ptE, *ptP64, *beD, *beE;
@@ -158,6 +167,7 @@ struct bsc_ctx {
     // host tables
     std::vector<int32_t> mp_elem, mp_off, be_elem, be_off;
     std::vector<double> mp_tu, mp_tv, mp_w, be_tu, be_tv, be_w, mass, hbend;
+    std::vector<double> mp_K, be_L, rest;    // general rest map: SoA per-point geometry, rest CPs
     std::vector<int32_t> pins;
     // workspace
     char *ws = nullptr;

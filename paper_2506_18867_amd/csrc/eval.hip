@@ -16,87 +16,7 @@
 namespace bsc {
 namespace {
 
-enum { kFirst = 0, kInner = 1, kLast = 2 };
-
-__device__ __forceinline__ int span_type(int k, int N) { return k == 0 ? kFirst : (k == N - 1 ? kLast : kInner); }
-
-// Values and first derivatives of the three quadratic pieces on a span (local t in [0,1]).
-template <typename T>
-__device__ __forceinline__ void pieces(int type, T t, T N[3], T D[3]) {
-    const T s = T(1) - t;
-    if (type == kInner) {
-        N[0] = T(0.5) * s * s; N[1] = T(0.5) + t * s; N[2] = T(0.5) * t * t;
-        D[0] = -s; D[1] = s - t; D[2] = t;
-    } else if (type == kFirst) {
-        N[0] = s * s; N[1] = t * (T(2) - T(1.5) * t); N[2] = T(0.5) * t * t;
-        D[0] = T(-2) * s; D[1] = T(2) - T(3) * t; D[2] = t;
-    } else {
-        N[0] = T(0.5) * s * s; N[1] = s * (T(2) - T(1.5) * s); N[2] = t * t;
-        D[0] = -s; D[1] = T(1) - T(3) * t; D[2] = T(2) * t;
-    }
-}
-
-// Value, first and second derivative of local piece a (0..2) alone, selected without indexing
-// a local array (a runtime index into one would place it in scratch memory).
-template <typename T>
-__device__ __forceinline__ void piece_at(int type, int a, T t, T &n, T &d, T &d2) {
-    const T s = T(1) - t;
-    T n0, n1, n2, e0, e1, e2, f0, f1, f2;
-    if (type == kInner) {
-        n0 = T(0.5) * s * s; n1 = T(0.5) + t * s; n2 = T(0.5) * t * t;
-        e0 = -s; e1 = s - t; e2 = t;
-        f0 = T(1); f1 = T(-2); f2 = T(1);
-    } else if (type == kFirst) {
-        n0 = s * s; n1 = t * (T(2) - T(1.5) * t); n2 = T(0.5) * t * t;
-        e0 = T(-2) * s; e1 = T(2) - T(3) * t; e2 = t;
-        f0 = T(2); f1 = T(-3); f2 = T(1);
-    } else {
-        n0 = T(0.5) * s * s; n1 = s * (T(2) - T(1.5) * s); n2 = t * t;
-        e0 = -s; e1 = T(1) - T(3) * t; e2 = T(2) * t;
-        f0 = T(1); f1 = T(-3); f2 = T(2);
-    }
-    n = a == 0 ? n0 : (a == 1 ? n1 : n2);
-    d = a == 0 ? e0 : (a == 1 ? e1 : e2);
-    d2 = a == 0 ? f0 : (a == 1 ? f1 : f2);
-}
-
-// Gradient w.r.t. X of local basis function (a, b) of span (k, l) at (tu, tv).
-template <typename T>
-__device__ __forceinline__ void grad_at(const DevSheet &S, int k, int l, int a, int b, T tu, T tv, T g[2]) {
-    T nu, du, d2u, nv, dv, d2v;
-    piece_at<T>(span_type(k, S.Nu), a, tu, nu, du, d2u);
-    piece_at<T>(span_type(l, S.Nv), b, tv, nv, dv, d2v);
-    const T xu = du * nv, xv = nu * dv;
-    g[0] = xu * T(S.K00) + xv * T(S.K10);
-    g[1] = xu * T(S.K01) + xv * T(S.K11);
-}
-
-// Laplacian coefficient of local CP (a, b) for a bending evaluation of span (k, l).
-__device__ __forceinline__ double lap_at(const DevSheet &S, int k, int l, int a, int b, double tu, double tv) {
-    double nu, du, d2u, nv, dv, d2v;
-    piece_at<double>(span_type(k, S.Nu), a, tu, nu, du, d2u);
-    piece_at<double>(span_type(l, S.Nv), b, tv, nv, dv, d2v);
-    return S.c_uu * d2u * nv + S.c_vv * nu * d2v + S.c_uv * du * dv;
-}
-
-__device__ __forceinline__ void second(int type, double D2[3]) {
-    if (type == kInner) { D2[0] = 1.0; D2[1] = -2.0; D2[2] = 1.0; }
-    else if (type == kFirst) { D2[0] = 2.0; D2[1] = -3.0; D2[2] = 1.0; }
-    else { D2[0] = 1.0; D2[1] = -3.0; D2[2] = 2.0; }
-}
-
-__device__ __forceinline__ double greville(int i, int n) {
-    return i == 0 ? 0.0 : (i == n - 1 ? double(n - 2) : double(i) - 0.5);
-}
-
-// Displacement of CP (i,j) from its rest position embedded in the plane z = 0.
-__device__ __forceinline__ void displacement(const DevSheet &S, const double *x, int i, int j, double d[3]) {
-    const int a = j * S.n_u + i;
-    const double gu = greville(i, S.n_u), gv = greville(j, S.n_v);
-    d[0] = x[a] - (S.A00 * gu + S.A01 * gv + S.b0);
-    d[1] = x[S.n_cp + a] - (S.A10 * gu + S.A11 * gv + S.b1);
-    d[2] = x[2 * S.n_cp + a];
-}
+#include "geom.h"
 
 // Index of (r, c), r <= c, in the row-major upper triangle of a 6x6 matrix.
 __host__ __device__ constexpr int u6(int r, int c) { return r <= c ? r * 6 - r * (r - 1) / 2 + (c - r) : c * 6 - c * (c - 1) / 2 + (r - c); }
@@ -530,51 +450,9 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
     return true;
 }
 
-// Gradient w.r.t. X of the 9 local basis functions at span coordinates (tu, tv).
-template <typename T>
-__device__ __forceinline__ void local_grads(const DevSheet &S, int k, int l, T tu, T tv, T dN[9][2]) {
-    T Nu[3], Du[3], Nv[3], Dv[3];
-    pieces<T>(span_type(k, S.Nu), tu, Nu, Du);
-    pieces<T>(span_type(l, S.Nv), tv, Nv, Dv);
-    const T K00 = T(S.K00), K01 = T(S.K01), K10 = T(S.K10), K11 = T(S.K11);
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const T du = Du[a] * Nv[b], dv = Nu[a] * Dv[b];
-            dN[3 * b + a][0] = du * K00 + dv * K10;
-            dN[3 * b + a][1] = du * K01 + dv * K11;
-        }
-}
-
-template <typename T>
-__device__ __forceinline__ void one_grad(const DevSheet &S, int k, int l, int a, int b, T tu, T tv, T g[2]) {
-    T Nu[3], Du[3], Nv[3], Dv[3];
-    pieces<T>(span_type(k, S.Nu), tu, Nu, Du);
-    pieces<T>(span_type(l, S.Nv), tv, Nv, Dv);
-    const T du = Du[a] * Nv[b], dv = Nu[a] * Dv[b];
-    g[0] = du * T(S.K00) + dv * T(S.K10);
-    g[1] = du * T(S.K01) + dv * T(S.K11);
-}
-
-// Laplacian coefficients L of the 9 local CPs for a bending evaluation.
-__device__ __forceinline__ void bend_L(const DevSheet &S, int k, int l, double tu, double tv, double L[9]) {
-    double Nu[3], Du[3], D2u[3], Nv[3], Dv[3], D2v[3];
-    const int tyu = span_type(k, S.Nu), tyv = span_type(l, S.Nv);
-    pieces<double>(tyu, tu, Nu, Du);
-    pieces<double>(tyv, tv, Nv, Dv);
-    second(tyu, D2u);
-    second(tyv, D2v);
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            L[3 * b + a] = S.c_uu * D2u[a] * Nv[b] + S.c_vv * Nu[a] * D2v[b] + S.c_uv * Du[a] * Dv[b];
-}
-
 // ---- stage 1 kernels ------------------------------------------------------------------------
 
-template <typename T, bool HESS>
+template <typename T, bool HESS, bool CURVED>
 __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *__restrict__ x, T *__restrict__ ptA,
                                                      T *__restrict__ ptP, double *__restrict__ ptE,
                                                      double *__restrict__ partials) {
@@ -586,12 +464,12 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
         const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
         const double w = S.mp_w[q];
         T dN[9][2];
-        local_grads<T>(S, k, l, tu, tv, dN);
+        local_grads<T>(S, mp_geo_t<CURVED>(S, q), k, l, tu, tv, dN);
         T G[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
 #pragma unroll
         for (int m = 0; m < 9; ++m) {
             double d[3];
-            displacement(S, x, k + m % 3, l + m / 3, d);
+            displacement_t<CURVED>(S, x, k + m % 3, l + m / 3, d);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T dc = T(d[c]);
@@ -630,6 +508,7 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+template <bool CURVED>
 __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__restrict__ x, double *__restrict__ beD,
                                                     double *__restrict__ beE, double *__restrict__ partials) {
     __shared__ double sh[kBlock / 64];
@@ -638,12 +517,12 @@ __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__
     if (q < S.n_be) {
         const int e = S.be_elem[q], k = e % S.Nu, l = e / S.Nu;
         double L[9];
-        bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+        bend_L_t<CURVED>(S, be_geo_t<CURVED>(S, q), k, l, S.be_tu[q], S.be_tv[q], L);
         double lap[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int m = 0; m < 9; ++m) {
             double d[3];
-            displacement(S, x, k + m % 3, l + m / 3, d);
+            displacement_t<CURVED>(S, x, k + m % 3, l + m / 3, d);
 #pragma unroll
             for (int c = 0; c < 3; ++c) lap[c] += L[m] * d[c];
         }
@@ -669,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__
 // with the slots by decreasing cost, and handed to waves in chunks of 64 from an LDS counter.
 // Each item sums over elements and points in a fixed order, so the result does not depend on
 // which wave takes it.
-template <typename TA, typename TP, typename TG>
+template <typename TA, typename TP, typename TG, bool CURVED>
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int kind, const TA *__restrict__ ptA,
                                                                const TP *__restrict__ ptP,
                                                                const double *__restrict__ x, const double *__restrict__ xhat,
@@ -680,11 +559,11 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
     const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
-    const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, int(sizeof(TA)));
+    const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, int(sizeof(TA)), CURVED);
     int *el_off = (int *)(lds + L.el_off);
     int *mrow = (int *)(lds + L.rows);
     int *counter = (int *)(lds + L.counter);
-    constexpr int REC = STAGE_DN ? kAsmRecF : kAsmRecD;      // record length in TA units
+    constexpr int REC = STAGE_DN ? kAsmRecF : (CURVED ? kAsmRecDC : kAsmRecD);   // record length in TA units
     TA *prec = (TA *)(lds + L.rec);
 
     const int ntx = (S.n_u + kAsmTileU - 1) / kAsmTileU;
@@ -725,7 +604,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
             if constexpr (STAGE_DN) {
                 const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
                 TA dN[9][2];
-                local_grads<TA>(S, k, l, TA(S.mp_tu[q]), TA(S.mp_tv[q]), dN);
+                local_grads<TA>(S, mp_geo_t<CURVED>(S, q), k, l, TA(S.mp_tu[q]), TA(S.mp_tv[q]), dN);
 #pragma unroll
                 for (int m = 0; m < 9; ++m) {
                     rec[24 + 2 * m] = dN[m][0];
@@ -734,6 +613,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
             } else {
                 rec[21] = TA(S.mp_tu[q]);
                 rec[22] = TA(S.mp_tv[q]);
+                if constexpr (CURVED) {
+                    const PtK K = mp_geo_t<true>(S, q);
+                    rec[23] = K.k00; rec[24] = K.k01; rec[25] = K.k10; rec[26] = K.k11;
+                }
             }
         }
     }
@@ -799,8 +682,11 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                                                       c10 * Aq[u6(3 + r, cc)] + c11 * Aq[u6(3 + r, 3 + cc)];
                             } else {
                                 const TA tu = rec[21], tv = rec[22];
-                                grad_at<TA>(S, k, l, la, lb, tu, tv, ga);
-                                grad_at<TA>(S, k, l, ma, mb, tu, tv, gb);
+                                PtK K;
+                                if constexpr (CURVED) K = PtK{rec[23], rec[24], rec[25], rec[26]};
+                                else K = mp_geo_t<false>(S, 0);
+                                grad_at<TA>(S, K, k, l, la, lb, tu, tv, ga);
+                                grad_at<TA>(S, K, k, l, ma, mb, tu, tv, gb);
                                 const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
 #pragma unroll
                                 for (int r = 0; r < 3; ++r)
@@ -844,7 +730,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                     for (int t = el_off[el]; t < el_off[el + 1]; ++t) {
                         const int q = mbase + t;
                         TG dn[2];
-                        grad_at<TG>(S, k, l, la, lb, TG(S.mp_tu[q]), TG(S.mp_tv[q]), dn);
+                        grad_at<TG>(S, mp_geo_t<CURVED>(S, q), k, l, la, lb, TG(S.mp_tu[q]), TG(S.mp_tv[q]), dn);
 #pragma unroll
                         for (int cc = 0; cc < 3; ++cc)
                             acc[cc] += TG(ptP[(2 * cc) * S.n_mp + q]) * dn[0] + TG(ptP[(2 * cc + 1) * S.n_mp + q]) * dn[1];
@@ -861,7 +747,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 if (ib >= 0 && ib < S.n_u && jb < S.n_v) {
                     const double w = S.hbend[s2 * ncp + a];
                     double d[3];
-                    displacement(S, x, ib, jb, d);
+                    displacement_t<CURVED>(S, x, ib, jb, d);
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
                 }
@@ -870,7 +756,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 if (ic >= 0 && ic < S.n_u && jc >= 0) {
                     const double w = S.hbend[s2 * ncp + jc * S.n_u + ic];
                     double d[3];
-                    displacement(S, x, ic, jc, d);
+                    displacement_t<CURVED>(S, x, ic, jc, d);
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
                 }
@@ -913,8 +799,9 @@ __global__ void __launch_bounds__(kBlock) k_elem_hess(DevSheet S, const T *__res
     for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
         T ga[2], gb[2];
         const T tu = T(S.mp_tu[q]), tv = T(S.mp_tv[q]);
-        one_grad<T>(S, k, l, m % 3, m / 3, tu, tv, ga);
-        one_grad<T>(S, k, l, n % 3, n / 3, tu, tv, gb);
+        const PtK K = mp_geo(S, q);
+        one_grad<T>(S, K, k, l, m % 3, m / 3, tu, tv, ga);
+        one_grad<T>(S, K, k, l, n % 3, n / 3, tu, tv, gb);
         T v = T(0);
 #pragma unroll
         for (int g = 0; g < 2; ++g)
@@ -925,7 +812,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_hess(DevSheet S, const T *__res
     if (ci == cj) {
         for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
             double L[9];
-            bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+            bend_L(S, be_geo(S, q), k, l, S.be_tu[q], S.be_tv[q], L);
             acc += S.be_w[q] * S.mu_bend * L[m] * L[n];
         }
     }
@@ -944,13 +831,13 @@ __global__ void __launch_bounds__(kBlock) k_elem_grad(DevSheet S, const T *__res
             double acc[3] = {0.0, 0.0, 0.0};
             for (int q = S.mp_off[e]; q < S.mp_off[e + 1]; ++q) {
                 T gm[2];
-                one_grad<T>(S, k, l, m % 3, m / 3, T(S.mp_tu[q]), T(S.mp_tv[q]), gm);
+                one_grad<T>(S, mp_geo(S, q), k, l, m % 3, m / 3, T(S.mp_tu[q]), T(S.mp_tv[q]), gm);
                 for (int c = 0; c < 3; ++c)
                     acc[c] += double(ptP[(2 * c) * S.n_mp + q] * gm[0] + ptP[(2 * c + 1) * S.n_mp + q] * gm[1]);
             }
             for (int q = S.be_off[e]; q < S.be_off[e + 1]; ++q) {
                 double L[9];
-                bend_L(S, k, l, S.be_tu[q], S.be_tv[q], L);
+                bend_L(S, be_geo(S, q), k, l, S.be_tu[q], S.be_tv[q], L);
                 for (int c = 0; c < 3; ++c) acc[c] += beD[c * S.n_be + q] * L[m];
             }
             for (int c = 0; c < 3; ++c) eg[size_t(3 * m + c) * S.n_elem + e] = T(acc[c]);
@@ -985,19 +872,24 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
                          const double *x, hipStream_t st) {
     // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch.
     double *pm = B.partials, *pb = B.partials + B.max_blocks;
-    if (grad64 || precision == BSC_FP64) {
-        double *P = grad64 ? B.ptP64 : (double *)B.ptP;
-        if (hess && !grad64)
-            k_membrane<double, true><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
-        else
-            k_membrane<double, false><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
-    } else {
-        if (hess)
-            k_membrane<float, true><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
-        else
-            k_membrane<float, false><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
-    }
-    k_bending<<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+    auto go = [&](auto curved) {
+        constexpr bool C = decltype(curved)::value;
+        if (grad64 || precision == BSC_FP64) {
+            double *P = grad64 ? B.ptP64 : (double *)B.ptP;
+            if (hess && !grad64)
+                k_membrane<double, true, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+            else
+                k_membrane<double, false, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+        } else {
+            if (hess)
+                k_membrane<float, true, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+            else
+                k_membrane<float, false, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+        }
+        k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+    };
+    if (S.curved) go(std::true_type{});
+    else go(std::false_type{});
     return hipGetLastError();
 }
 
@@ -1010,17 +902,22 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const 
     double *pc = B.partials + 2 * B.max_blocks;
     const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
     const int sa = kind == kAsmF64 ? 8 : 4;
-    const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], sa).total;
+    const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], sa, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
-    if (kind == kAsmF32)
-        k_assemble_tile<float, float, float><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, (const float *)B.ptP,
-                                                                          x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
-    else if (kind == kAsmF64)
-        k_assemble_tile<double, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const double *)B.ptA, (const double *)B.ptP,
-                                                                             x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
-    else
-        k_assemble_tile<float, double, double><<<nt, kAsmThreads, lds, st>>>(S, kind, (const float *)B.ptA, B.ptP64,
-                                                                            x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
+    auto go = [&](auto curved) {
+        constexpr bool C = decltype(curved)::value;
+        if (kind == kAsmF32)
+            k_assemble_tile<float, float, float, C><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const float *)B.ptA, (const float *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
+        else if (kind == kAsmF64)
+            k_assemble_tile<double, double, double, C><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const double *)B.ptA, (const double *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
+        else
+            k_assemble_tile<float, double, double, C><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const float *)B.ptA, B.ptP64, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
+    };
+    if (S.curved) go(std::true_type{});
+    else go(std::false_type{});
     return hipGetLastError();
 }
 

@@ -55,6 +55,45 @@ double greville(int i, int n) {
     return i - 0.5;
 }
 
+// Rest-map geometry at span coordinates (tu, tv) of span (k, l), span units. J = dX/d(u,v)
+// and the second derivatives of X come from the 9 rest CPs of the span; K = J^{-1} (Sec. 4.1,
+// inverse function theorem). The Laplacian over X in parametric form (Sec. 4.2) is
+//   Lap f = G_uu f_uu + G_vv f_vv + 2 G_uv f_uv + (Lap u) f_u + (Lap v) f_v,
+// G_mn = grad xi_m . grad xi_n (rows of K). Lap xi follows from Lap X_c = 0 for the two
+// coordinate functions: J Lap(xi) = -(G_uu X_uu + G_vv X_vv + 2 G_uv X_uv).
+struct RestGeo { double K[2][2], det, cuu, cvv, cuv, lu, lv; };
+
+RestGeo rest_geometry(const double *rest_xy, int n_u, int Nu, int Nv, int k, int l, double tu, double tv) {
+    double Nu3[3], Du[3], D2u[3], Nv3[3], Dv[3], D2v[3];
+    pieces(span_type(k, Nu), tu, Nu3, Du, D2u);
+    pieces(span_type(l, Nv), tv, Nv3, Dv, D2v);
+    double J[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, Xuu[2] = {0.0, 0.0}, Xvv[2] = {0.0, 0.0}, Xuv[2] = {0.0, 0.0};
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const double *X = rest_xy + 2 * (size_t(l + b) * n_u + (k + a));
+            for (int c = 0; c < 2; ++c) {
+                J[c][0] += X[c] * Du[a] * Nv3[b];
+                J[c][1] += X[c] * Nu3[a] * Dv[b];
+                Xuu[c] += X[c] * D2u[a] * Nv3[b];
+                Xvv[c] += X[c] * Nu3[a] * D2v[b];
+                Xuv[c] += X[c] * Du[a] * Dv[b];
+            }
+        }
+    RestGeo g;
+    g.det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    g.K[0][0] = J[1][1] / g.det; g.K[0][1] = -J[0][1] / g.det;
+    g.K[1][0] = -J[1][0] / g.det; g.K[1][1] = J[0][0] / g.det;
+    const double Guu = g.K[0][0] * g.K[0][0] + g.K[0][1] * g.K[0][1];
+    const double Gvv = g.K[1][0] * g.K[1][0] + g.K[1][1] * g.K[1][1];
+    const double Guv = g.K[0][0] * g.K[1][0] + g.K[0][1] * g.K[1][1];
+    g.cuu = Guu; g.cvv = Gvv; g.cuv = 2.0 * Guv;
+    double h[2];
+    for (int c = 0; c < 2; ++c) h[c] = Guu * Xuu[c] + Gvv * Xvv[c] + 2.0 * Guv * Xuv[c];
+    g.lu = -(g.K[0][0] * h[0] + g.K[0][1] * h[1]);
+    g.lv = -(g.K[1][0] * h[0] + g.K[1][1] * h[1]);
+    return g;
+}
+
 struct Pt { double u, v, w; int k, l; };
 
 const double kG2 = 0.28867513459481288225;   // 1 / (2 sqrt 3)
@@ -212,6 +251,9 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.be_w = (double *)take(8 * nbe);
     t.mass = (double *)take(8 * ncp);
     t.hbend = (double *)take(8 * kSlots * ncp);
+    t.mp_K = (double *)take(8 * c->mp_K.size());
+    t.be_L = (double *)take(8 * c->be_L.size());
+    t.rest = (double *)take(8 * c->rest.size());
     t.pinmask = (int32_t *)take(4 * ncp);
     t.pin_idx = (int32_t *)take(4 * ncp);
     t.ptA = take(8 * 21 * nmp);
@@ -299,7 +341,9 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
 
     // The rest map X(u,v) = sum N_a X^a is affine iff the CPs are an affine image of the
-    // Greville abscissae (linear precision); read A and b off three corners and verify.
+    // Greville abscissae (linear precision); read A and b off three corners and test. An affine
+    // rest keeps K and the Laplacian coefficients as sheet constants; any other rest map gets
+    // per-point tables (the general path).
     auto R = [&](int i, int j, int comp) { return rest_xy[2 * (int64_t(j) * n_u + i) + comp]; };
     const int Nu = c->Nu, Nv = c->Nv;
     double A[2][2], b[2];
@@ -309,22 +353,28 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
         A[comp][1] = (R(0, n_v - 1, comp) - b[comp]) / Nv;
     }
     double ext = std::fabs(A[0][0]) * Nu + std::fabs(A[0][1]) * Nv + std::fabs(A[1][0]) * Nu + std::fabs(A[1][1]) * Nv;
-    for (int j = 0; j < n_v; ++j)
-        for (int i = 0; i < n_u; ++i)
+    bool affine = ext > 0.0;
+    for (int j = 0; j < n_v && affine; ++j)
+        for (int i = 0; i < n_u && affine; ++i)
             for (int comp = 0; comp < 2; ++comp) {
                 double want = A[comp][0] * greville(i, n_u) + A[comp][1] * greville(j, n_v) + b[comp];
-                if (std::fabs(R(i, j, comp) - want) > 1e-12 * ext) {
-                    c->err = "rest shape is not an affine image of the Greville grid (unsupported)";
-                    bsc_status st = BSC_E_INVAL;
-                    delete c;
-                    return st;
-                }
+                if (std::fabs(R(i, j, comp) - want) > 1e-12 * ext) affine = false;
             }
-    const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
-    if (!(det > 0.0)) { delete c; return BSC_E_INVAL; }
-    const double K[2][2] = {{A[1][1] / det, -A[0][1] / det}, {-A[1][0] / det, A[0][0] / det}};
+    const bool curved = !affine;
+    auto reject = [&](const char *why) {   // the context is not returned, so no error text
+        (void)why;
+        delete c;
+        return BSC_E_INVAL;
+    };
+    double det = 1.0, K[2][2] = {{1.0, 0.0}, {0.0, 1.0}};
+    if (affine) {
+        det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        if (!(det > 0.0)) return reject("rest map is not orientation preserving");
+        K[0][0] = A[1][1] / det; K[0][1] = -A[0][1] / det;
+        K[1][0] = -A[1][0] / det; K[1][1] = A[0][0] / det;
+    }
 
-    // quadrature tables
+    // quadrature tables (weights times |det J|: the constant here, per point below)
     fill_tables(membrane_points(Nu, Nv, mat->quadrature), Nu, c->n_elem, det, c->mp_elem, c->mp_off, c->mp_tu, c->mp_tv, c->mp_w);
     fill_tables(bending_points(Nu, Nv, mat->quadrature), Nu, c->n_elem, det, c->be_elem, c->be_off, c->be_tu, c->be_tv, c->be_w);
     c->n_mp = int(c->mp_elem.size());
@@ -335,24 +385,67 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     const double c_vv = K[1][0] * K[1][0] + K[1][1] * K[1][1];
     const double c_uv = 2.0 * (K[0][0] * K[1][0] + K[0][1] * K[1][1]);
 
-    // Lumped mass: row sums of the consistent mass = int rho N_a dX (partition of unity),
-    // factorised for the affine rest as rho |det A| (int N_i du)(int N_j dv), 3-point Gauss.
-    auto integrals = [&](int n, int N) {
-        std::vector<double> m(n, 0.0);
-        const double o3[3] = {-kG3, 0.0, kG3}, w3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
-        for (int k = 0; k < N; ++k) {
-            double Nv3[3], D[3], D2[3];
-            for (int g = 0; g < 3; ++g) {
-                pieces(span_type(k, N), 0.5 + o3[g], Nv3, D, D2);
-                for (int a = 0; a < 3; ++a) m[k + a] += w3[g] * Nv3[a];
-            }
+    if (curved) {
+        // per-point geometry; det J > 0 is required at every point (an orientation-preserving,
+        // locally invertible rest map)
+        const size_t nmp = c->n_mp, nbe = c->n_be, ncp = c->n_cp;
+        c->mp_K.assign(4 * nmp, 0.0);
+        c->be_L.assign(5 * nbe, 0.0);
+        c->rest.assign(2 * ncp, 0.0);
+        for (size_t a = 0; a < ncp; ++a) { c->rest[a] = rest_xy[2 * a]; c->rest[ncp + a] = rest_xy[2 * a + 1]; }
+        for (size_t q = 0; q < nmp; ++q) {
+            const int e = c->mp_elem[q];
+            const RestGeo g = rest_geometry(rest_xy, n_u, Nu, Nv, e % Nu, e / Nu, c->mp_tu[q], c->mp_tv[q]);
+            if (!(g.det > 0.0)) return reject("det J <= 0 at a membrane quadrature point");
+            c->mp_w[q] *= g.det;
+            c->mp_K[q] = g.K[0][0]; c->mp_K[nmp + q] = g.K[0][1];
+            c->mp_K[2 * nmp + q] = g.K[1][0]; c->mp_K[3 * nmp + q] = g.K[1][1];
         }
-        return m;
-    };
-    std::vector<double> mu1 = integrals(n_u, Nu), mv1 = integrals(n_v, Nv);
+        for (size_t q = 0; q < nbe; ++q) {
+            const int e = c->be_elem[q];
+            const RestGeo g = rest_geometry(rest_xy, n_u, Nu, Nv, e % Nu, e / Nu, c->be_tu[q], c->be_tv[q]);
+            if (!(g.det > 0.0)) return reject("det J <= 0 at a bending evaluation point");
+            c->be_w[q] *= g.det;
+            c->be_L[q] = g.cuu; c->be_L[nbe + q] = g.cvv; c->be_L[2 * nbe + q] = g.cuv;
+            c->be_L[3 * nbe + q] = g.lu; c->be_L[4 * nbe + q] = g.lv;
+        }
+    }
+
+    // Lumped mass: row sums of the consistent mass = int rho N_a dX (partition of unity), 3x3
+    // Gauss per span. For an affine rest it factorises as rho |det A| (int N_i du)(int N_j dv).
+    const double o3[3] = {-kG3, 0.0, kG3}, w3[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
     c->mass.assign(c->n_cp, 0.0);
-    for (int j = 0; j < n_v; ++j)
-        for (int i = 0; i < n_u; ++i) c->mass[j * n_u + i] = mat->rho_area * det * mu1[i] * mv1[j];
+    if (affine) {
+        auto integrals = [&](int n, int N) {
+            std::vector<double> m(n, 0.0);
+            for (int k = 0; k < N; ++k) {
+                double Nv3[3], D[3], D2[3];
+                for (int g = 0; g < 3; ++g) {
+                    pieces(span_type(k, N), 0.5 + o3[g], Nv3, D, D2);
+                    for (int a = 0; a < 3; ++a) m[k + a] += w3[g] * Nv3[a];
+                }
+            }
+            return m;
+        };
+        std::vector<double> mu1 = integrals(n_u, Nu), mv1 = integrals(n_v, Nv);
+        for (int j = 0; j < n_v; ++j)
+            for (int i = 0; i < n_u; ++i) c->mass[j * n_u + i] = mat->rho_area * det * mu1[i] * mv1[j];
+    } else {
+        for (int l = 0; l < Nv; ++l)
+            for (int k = 0; k < Nu; ++k)
+                for (int gb = 0; gb < 3; ++gb)
+                    for (int ga = 0; ga < 3; ++ga) {
+                        const double tu = 0.5 + o3[ga], tv = 0.5 + o3[gb];
+                        const RestGeo g = rest_geometry(rest_xy, n_u, Nu, Nv, k, l, tu, tv);
+                        if (!(g.det > 0.0)) return reject("det J <= 0 at a mass quadrature point");
+                        double Nu3[3], Nv3[3], D[3], D2[3];
+                        pieces(span_type(k, Nu), tu, Nu3, D, D2);
+                        pieces(span_type(l, Nv), tv, Nv3, D, D2);
+                        const double wq = mat->rho_area * w3[ga] * w3[gb] * g.det;
+                        for (int bb = 0; bb < 3; ++bb)
+                            for (int aa = 0; aa < 3; ++aa) c->mass[(l + bb) * n_u + (k + aa)] += wq * Nu3[aa] * Nv3[bb];
+                    }
+    }
 
     // Constant bending Hessian: scalar stencil h[s][a] = sum over evaluations of
     // w mu L_a L_b for the upper-stencil slot s linking CP a to CP b (the 3x3 block is h I).
@@ -362,10 +455,17 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
         double Nu3[3], Du[3], D2u[3], Nv3[3], Dv[3], D2v[3];
         pieces(span_type(k, Nu), c->be_tu[q], Nu3, Du, D2u);
         pieces(span_type(l, Nv), c->be_tv[q], Nv3, Dv, D2v);
+        double cu = c_uu, cv = c_vv, cuv = c_uv, lu = 0.0, lv = 0.0;
+        if (curved) {
+            const size_t nbe = c->n_be;
+            cu = c->be_L[q]; cv = c->be_L[nbe + q]; cuv = c->be_L[2 * nbe + q];
+            lu = c->be_L[3 * nbe + q]; lv = c->be_L[4 * nbe + q];
+        }
         double L[9];
         for (int bb = 0; bb < 3; ++bb)
             for (int aa = 0; aa < 3; ++aa)
-                L[3 * bb + aa] = c_uu * D2u[aa] * Nv3[bb] + c_vv * Nu3[aa] * D2v[bb] + c_uv * Du[aa] * Dv[bb];
+                L[3 * bb + aa] = cu * D2u[aa] * Nv3[bb] + cv * Nu3[aa] * D2v[bb] + cuv * Du[aa] * Dv[bb] +
+                                 lu * Du[aa] * Nv3[bb] + lv * Nu3[aa] * Dv[bb];
         const double wm = c->be_w[q] * mat->mu_bend;
         for (int m = 0; m < 9; ++m)
             for (int n = 0; n < 9; ++n) {
@@ -383,6 +483,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     S.A00 = A[0][0]; S.A01 = A[0][1]; S.A10 = A[1][0]; S.A11 = A[1][1]; S.b0 = b[0]; S.b1 = b[1];
     S.K00 = K[0][0]; S.K01 = K[0][1]; S.K10 = K[1][0]; S.K11 = K[1][1];
     S.c_uu = c_uu; S.c_vv = c_vv; S.c_uv = c_uv;
+    S.curved = curved ? 1 : 0;
     S.membrane = mat->membrane;
     S.mu = mat->young * mat->thickness / (2.0 * (1.0 + mat->poisson));
     S.lam = mat->young * mat->thickness * mat->poisson / (1.0 - mat->poisson * mat->poisson);
@@ -404,7 +505,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
                     for (int l = l0; l <= l1; ++l) np += c->mp_off[l * Nu + k1 + 1] - c->mp_off[l * Nu + k0];
                     maxp = std::max(maxp, np);
                 }
-            if (asm_lds_layout(kAsmTileU, ty, maxp, size_a[kind]).total <= kAsmLdsMax) {
+            if (asm_lds_layout(kAsmTileU, ty, maxp, size_a[kind], curved).total <= kAsmLdsMax) {
                 S.asm_ty[kind] = ty;
                 S.asm_maxp[kind] = maxp;
             }
@@ -448,8 +549,11 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
         {B.be_tu, c->be_tu.data(), 8 * c->be_tu.size()}, {B.be_tv, c->be_tv.data(), 8 * c->be_tv.size()},
         {B.be_w, c->be_w.data(), 8 * c->be_w.size()},
         {B.mass, c->mass.data(), 8 * c->mass.size()}, {B.hbend, c->hbend.data(), 8 * c->hbend.size()},
+        {B.mp_K, c->mp_K.data(), 8 * c->mp_K.size()}, {B.be_L, c->be_L.data(), 8 * c->be_L.size()},
+        {B.rest, c->rest.data(), 8 * c->rest.size()},
     };
     for (const Up &u : ups) {
+        if (u.n == 0) continue;
         bsc_status st = hip_check(c, hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, c->stream), "upload tables");
         if (st != BSC_OK) return st;
     }
@@ -474,6 +578,9 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     S.mp_elem = B.mp_elem; S.mp_off = B.mp_off; S.mp_tu = B.mp_tu; S.mp_tv = B.mp_tv; S.mp_w = B.mp_w;
     S.be_elem = B.be_elem; S.be_off = B.be_off; S.be_tu = B.be_tu; S.be_tv = B.be_tv; S.be_w = B.be_w;
     S.mass = B.mass; S.hbend = B.hbend; S.pinmask = B.pinmask;
+    S.mp_K = S.curved ? B.mp_K : nullptr;
+    S.be_L = S.curved ? B.be_L : nullptr;
+    S.rest = S.curved ? B.rest : nullptr;
     return BSC_OK;
 }
 

@@ -22,6 +22,8 @@
 namespace bsc {
 namespace {
 
+#include "geom.h"
+
 inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
@@ -693,25 +695,14 @@ __global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const doubl
     double c1 = 0.0, c2 = 0.0;
     if (q < S.n_be) {
         const int e = S.be_elem[q], k = e % S.Nu, l = e / S.Nu;
-        // Laplacian weights of the 9 local CPs (same pieces as the bending kernel)
-        const double tu = S.be_tu[q], tv = S.be_tv[q];
-        const int tyu = k == 0 ? 0 : (k == S.Nu - 1 ? 2 : 1), tyv = l == 0 ? 0 : (l == S.Nv - 1 ? 2 : 1);
-        double Nu[3], Du[3], D2u[3], Nv[3], Dv[3], D2v[3];
-        auto pc = [](int ty, double t, double N[3], double D[3], double D2[3]) {
-            const double s = 1.0 - t;
-            if (ty == 1) { N[0] = 0.5 * s * s; N[1] = 0.5 + t * s; N[2] = 0.5 * t * t; D[0] = -s; D[1] = s - t; D[2] = t; D2[0] = 1; D2[1] = -2; D2[2] = 1; }
-            else if (ty == 0) { N[0] = s * s; N[1] = t * (2.0 - 1.5 * t); N[2] = 0.5 * t * t; D[0] = -2 * s; D[1] = 2 - 3 * t; D[2] = t; D2[0] = 2; D2[1] = -3; D2[2] = 1; }
-            else { N[0] = 0.5 * s * s; N[1] = s * (2.0 - 1.5 * s); N[2] = t * t; D[0] = -s; D[1] = 1 - 3 * t; D[2] = 2 * t; D2[0] = 1; D2[1] = -3; D2[2] = 2; }
-        };
-        pc(tyu, tu, Nu, Du, D2u);
-        pc(tyv, tv, Nv, Dv, D2v);
+        // Laplacian weights of the 9 local CPs (the same as the bending kernel's)
+        double L[9];
+        bend_L(S, be_geo(S, q), k, l, S.be_tu[q], S.be_tv[q], L);
         double lp[3] = {0.0, 0.0, 0.0};
-        for (int b = 0; b < 3; ++b)
-            for (int a = 0; a < 3; ++a) {
-                const double L = S.c_uu * D2u[a] * Nv[b] + S.c_vv * Nu[a] * D2v[b] + S.c_uv * Du[a] * Dv[b];
-                const int cp = (l + b) * S.n_u + (k + a);
-                for (int c = 0; c < 3; ++c) lp[c] += L * p[c * n + cp];
-            }
+        for (int m = 0; m < 9; ++m) {
+            const int cp = (l + m / 3) * S.n_u + (k + m % 3);
+            for (int c = 0; c < 3; ++c) lp[c] += L[m] * p[c * n + cp];
+        }
         const double wm = S.be_w[q] * S.mu_bend;
         for (int c = 0; c < 3; ++c) {
             c1 += beD[c * S.n_be + q] * lp[c];     // beD = w mu Laplacian(phi(x))
@@ -732,32 +723,19 @@ __global__ void __launch_bounds__(kBlock) k_ls_membrane(DevSheet S, const double
     double de = 0.0;
     if (q < S.n_mp) {
         const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
-        const double tu = S.mp_tu[q], tv = S.mp_tv[q];
-        const int tyu = k == 0 ? 0 : (k == S.Nu - 1 ? 2 : 1), tyv = l == 0 ? 0 : (l == S.Nv - 1 ? 2 : 1);
-        double Nu[3], Du[3], Nv[3], Dv[3];
-        auto pc = [](int ty, double t, double N[3], double D[3]) {
-            const double s = 1.0 - t;
-            if (ty == 1) { N[0] = 0.5 * s * s; N[1] = 0.5 + t * s; N[2] = 0.5 * t * t; D[0] = -s; D[1] = s - t; D[2] = t; }
-            else if (ty == 0) { N[0] = s * s; N[1] = t * (2.0 - 1.5 * t); N[2] = 0.5 * t * t; D[0] = -2 * s; D[1] = 2 - 3 * t; D[2] = t; }
-            else { N[0] = 0.5 * s * s; N[1] = s * (2.0 - 1.5 * s); N[2] = t * t; D[0] = -s; D[1] = 1 - 3 * t; D[2] = 2 * t; }
-        };
-        pc(tyu, tu, Nu, Du);
-        pc(tyv, tv, Nv, Dv);
+        double dN[9][2];
+        local_grads<double>(S, mp_geo(S, q), k, l, S.mp_tu[q], S.mp_tv[q], dN);
         double G[3][2] = {{0, 0}, {0, 0}, {0, 0}}, dG[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int b = 0; b < 3; ++b)
-            for (int a = 0; a < 3; ++a) {
-                const double du = Du[a] * Nv[b], dv = Nu[a] * Dv[b];
-                const double g0 = du * S.K00 + dv * S.K10, g1 = du * S.K01 + dv * S.K11;
-                const int i = k + a, j = l + b, cp = j * S.n_u + i;
-                const double gu = i == 0 ? 0.0 : (i == S.n_u - 1 ? double(S.n_u - 2) : i - 0.5);
-                const double gv = j == 0 ? 0.0 : (j == S.n_v - 1 ? double(S.n_v - 2) : j - 0.5);
-                const double d[3] = {x[cp] - (S.A00 * gu + S.A01 * gv + S.b0), x[n + cp] - (S.A10 * gu + S.A11 * gv + S.b1), x[2 * n + cp]};
-                for (int c = 0; c < 3; ++c) {
-                    G[c][0] += d[c] * g0; G[c][1] += d[c] * g1;
-                    const double pcv = p[c * n + cp];
-                    dG[c][0] += pcv * g0; dG[c][1] += pcv * g1;
-                }
+        for (int m = 0; m < 9; ++m) {
+            const int cp = (l + m / 3) * S.n_u + (k + m % 3);
+            double d[3];
+            displacement(S, x, k + m % 3, l + m / 3, d);
+            for (int c = 0; c < 3; ++c) {
+                G[c][0] += d[c] * dN[m][0]; G[c][1] += d[c] * dN[m][1];
+                const double pcv = p[c * n + cp];
+                dG[c][0] += pcv * dN[m][0]; dG[c][1] += pcv * dN[m][1];
             }
+        }
         double F[3][2];
         for (int c = 0; c < 3; ++c)
             for (int g = 0; g < 2; ++g) F[c][g] = G[c][g] + (c == g ? 1.0 : 0.0);
@@ -855,18 +833,18 @@ struct Timer {
     bool ok;
     explicit Timer(hipStream_t s) : st(s) {
         ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
-        if (ok) hipEventRecord(a, st);
+        if (ok) (void)hipEventRecord(a, st);
     }
     double stop() {
         if (!ok) return 0.0;
         float ms = 0.f;
-        hipEventRecord(b, st);
-        hipEventSynchronize(b);
-        hipEventElapsedTime(&ms, a, b);
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
         return ms;
     }
     ~Timer() {
-        if (ok) { hipEventDestroy(a); hipEventDestroy(b); }
+        if (ok) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     }
 };
 

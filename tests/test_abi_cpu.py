@@ -72,9 +72,9 @@ def test_create_rejects_bad_inputs():
     assert _create(8, 8, nonopen, kv, rest)[0] == -2
     ku4, kv4, rest4 = syn.flat_sheet(4)
     assert _create(4, 4, ku4, kv4, rest4)[0] == -1                    # too few spans
-    curved = rest.copy()
-    curved[10] += 0.01
-    assert _create(8, 8, ku, kv, curved)[0] == -1                     # non-affine rest
+    folded = rest.copy()
+    folded[3 * 8 + 3, 0] += 0.4                                      # crosses two neighbours
+    assert _create(8, 8, ku, kv, folded)[0] == -1                     # det J < 0 inside
     flipped = rest.copy()
     flipped[:, 0] *= -1
     assert _create(8, 8, ku, kv, flipped)[0] == -1                    # det < 0
@@ -84,6 +84,19 @@ def test_create_rejects_bad_inputs():
     nan_rest = rest.copy()
     nan_rest[3, 1] = np.nan
     assert _create(8, 8, ku, kv, nan_rest)[0] == -1
+
+
+@pytest.mark.parametrize("kind", syn.MAPPED_KINDS)
+def test_create_accepts_general_rest_shapes(kind):
+    ku, kv, rest = syn.mapped_sheet(9, 7, kind)
+    st, h = _create(9, 7, ku, kv, rest)
+    assert st == 0
+    bsc.load().bsc_destroy(h)
+    nudged = syn.flat_sheet(8)[2].copy()
+    nudged[10] += 0.01                                                # a slightly curved rest
+    st, h = _create(8, 8, *syn.flat_sheet(8)[:2], nudged)
+    assert st == 0
+    bsc.load().bsc_destroy(h)
 
 
 def test_create_accepts_spacing_sheared_and_nonsquare():

@@ -1,0 +1,159 @@
+"""GPU parity on general (non-affine) rest shapes, through the C ABI: the distorted patches of
+the paper's robustness study (Sec. 6.5, "Support of Non-Rectangular Domains": aspect ratio,
+skewed corners, sharp turns within an edge) and a curved quarter annulus. The library switches
+to per-point rest geometry (inverse Jacobian per membrane point, Laplacian coefficients with
+their first-derivative terms per bending evaluation, rest CPs for the displacement) when the
+rest CPs are not an affine image of the Greville grid.
+
+Bars as for the affine sheets: FP64 within 1e-10 (element E/g/H, assembled E/g/H with pins,
+inertia and gravity, Newton iterates); FP32-mixed gradient within 1e-4 and Hessian within 1e-5;
+Newton steps reach the FP64 tolerance. Sizes span several assembly tiles with ragged tails and
+the full 226 x 226 sheet."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as syn
+from tests.helpers import oracle_sheet, oracle_stencil_to_upper, relerr, upper27
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2506_18867_amd import bsc  # noqa: E402
+
+TOL64 = 1e-10
+CASES = [("skew", 45.0, 9, 7), ("bend", 120.0, 11, 9), ("annulus", 0.5, 10, 10), ("aspect", 10.0, 23, 9),
+         ("bend", 150.0, 37, 21)]
+
+
+def _material():
+    return syn.stvk_material(young=1e4, thickness=1e-3, mu_bend=2e-3)
+
+
+def _ctx(n_u, n_v, ku, kv, rest, mat):
+    return bsc.Context(n_u, n_v, ku, kv, rest, bsc.make_material(0, mat.young, mat.poisson, mat.thickness,
+                                                                mu_bend=mat.mu_bend, rho_area=mat.rho_area))
+
+
+@pytest.mark.parametrize("kind,param,n_u,n_v", CASES)
+def test_eval_egh_fp64_on_mapped_rest(kind, param, n_u, n_v):
+    print(f"[general rest eval_egh] {kind} {param} {n_u}x{n_v}", flush=True)
+    ku, kv, rest = syn.mapped_sheet(n_u, n_v, kind, param)
+    mat = _material()
+    sh = oracle_sheet((n_u, n_v, ku, kv, rest), mat)
+    x = syn.embed(rest) + syn.smooth_field(n_u, n_v, 7, amp=0.05)
+    x[:, 0] *= 0.93                                            # some compression: indefinite points
+    ctx = _ctx(n_u, n_v, ku, kv, rest, mat)
+    E, eE, eg, eH = ctx.bsc_eval_egh(bsc.to_soa(x), bsc.BSC_FP64)
+    torch.cuda.synchronize()
+    rE, rg, rH = oracle.element_egh(sh, x, project=True)
+    assert relerr(E.item(), rE.sum()) < TOL64
+    assert relerr(eE.cpu().numpy(), rE) < TOL64
+    assert relerr(eg.cpu().numpy(), rg.T) < TOL64
+    assert relerr(eH.cpu().numpy(), upper27(rH)) < TOL64
+
+
+@pytest.mark.parametrize("kind,param,n_u,n_v", CASES)
+def test_assemble_on_mapped_rest(kind, param, n_u, n_v):
+    print(f"[general rest assemble] {kind} {param} {n_u}x{n_v}", flush=True)
+    ku, kv, rest = syn.mapped_sheet(n_u, n_v, kind, param)
+    mat = _material()
+    sh = oracle_sheet((n_u, n_v, ku, kv, rest), mat)
+    x = syn.embed(rest) + syn.smooth_field(n_u, n_v, 4, amp=0.03)
+    xhat = syn.embed(rest) + 0.01 * syn.smooth_field(n_u, n_v, 9, amp=0.5)
+    pins = np.array([0, n_u - 1, n_u * n_v - 1, n_u * (n_v // 2) + n_u // 2])
+    x[pins] = syn.embed(rest)[pins]
+    mask = np.zeros(n_u * n_v, dtype=bool)
+    mask[pins] = True
+    ctx = _ctx(n_u, n_v, ku, kv, rest, mat)
+    ctx.bsc_set_pins(pins)
+    grav = (0.0, -9.81, 0.0)
+    rE, rg, rH = oracle.assemble(sh, x, xhat, 0.01, np.array(grav), mask)
+    rHu = oracle_stencil_to_upper(rH, n_u, n_v)
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(xhat), 0.01, grav, bsc.BSC_FP64)
+    torch.cuda.synchronize()
+    assert relerr(E.item(), rE) < TOL64
+    assert relerr(bsc.to_aos(g), rg) < TOL64
+    assert relerr(H.cpu().numpy(), rHu) < TOL64
+    E32, g32, H32 = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(xhat), 0.01, grav, bsc.BSC_FP32_MIXED)
+    eg, eh = relerr(bsc.to_aos(g32), rg), relerr(H32.cpu().numpy(), rHu)
+    print(f"[general rest fp32] {kind}: grad rel err {eg:.2e}, hessian rel err {eh:.2e}")
+    assert eg < 1e-4 and eh < 1e-5 and relerr(E32.item(), rE) < 1e-5
+
+
+def test_full_size_226_annulus_matches_oracle():
+    """A 226 x 226 quarter annulus (the full workload size; the FP64 assembly tiles hold the
+    per-point inverse Jacobian in their LDS records), compared entry by entry."""
+    n = 226
+    print(f"[general rest assemble fp64] annulus n={n}", flush=True)
+    ku, kv, rest = syn.mapped_sheet(n, n, "annulus", 0.5)
+    mat = _material()
+    sh = oracle_sheet((n, n, ku, kv, rest), mat)
+    x = syn.embed(rest) + syn.smooth_field(n, n, 11, amp=0.02)
+    ctx = _ctx(n, n, ku, kv, rest, mat)
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(syn.embed(rest)), 0.01, (0.0, 0.0, -9.81), bsc.BSC_FP64)
+    torch.cuda.synchronize()
+    rE, rg, rH = oracle.assemble(sh, x, syn.embed(rest), 0.01, np.array([0.0, 0.0, -9.81]))
+    assert relerr(E.item(), rE) < TOL64
+    assert relerr(bsc.to_aos(g), rg) < TOL64
+    assert relerr(H.cpu().numpy(), oracle_stencil_to_upper(rH, n, n)) < TOL64
+
+
+@pytest.mark.parametrize("kind,param", [("bend", 120.0), ("annulus", 0.5)])
+def test_newton_fp64_iterates_on_mapped_rest(kind, param):
+    """Two Newton iterations on both sides (GPU PCG to 1e-14 against the oracle's sparse LU)."""
+    sc = syn.mapped_hanging_sheet(16, kind, param, seed=3)
+    sh = oracle_sheet(sc)
+    ctx = bsc.context_for_scene(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), fixed_newton_iters=2, pcg_rtol=1e-14, max_pcg=20000)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=2)
+    err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
+    print(f"[general rest newton fp64] {kind}: pcg={stats.pcg_iters_total} rel err of x - x0: {err:.2e}")
+    assert err < TOL64
+    assert relerr(bsc.to_aos(v), ref.v) < TOL64
+
+
+@pytest.mark.parametrize("precision", [bsc.BSC_FP64, bsc.BSC_FP32_MIXED])
+def test_newton_converges_on_mapped_rest(precision):
+    sc = syn.mapped_hanging_sheet(40, "annulus", 0.5, seed=5)
+    sh = oracle_sheet(sc)
+    ctx = bsc.context_for_scene(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=1e-6, pcg_rtol=1e-3)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    mask = np.zeros(sc.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    _, g, _ = oracle.assemble(sh, bsc.to_aos(x), sc.x0 + sc.dt * sc.v0, sc.dt, sc.gravity, mask, want_hessian=False)
+    print(f"[general rest newton] precision={precision} iters={stats.newton_iters} |g|/|g0| = "
+          f"{np.linalg.norm(g) / stats.g0_norm:.2e}")
+    assert np.linalg.norm(g) <= 1.01e-6 * stats.g0_norm
+
+
+def test_newton_iterations_on_distorted_patches():
+    """Sec. 6.5 reports solver iteration counts within a small constant factor of the
+    rectangular baseline for its three distortion categories (aspect ratio, skewed corners,
+    sharp turns within an edge). Hanging 40 x 40 sheets, 6 steps each with the paper's stopping
+    rule, FP64: Newton iterations of each distorted patch against the square. The quarter
+    annulus (not one of the paper's categories) is reported only."""
+    counts = {}
+    for kind, param in [("aspect", 1.0), ("aspect", 4.0), ("skew", 45.0), ("bend", 120.0), ("annulus", 0.5)]:
+        sc = syn.mapped_hanging_sheet(40, kind, param, seed=8)
+        ctx = bsc.context_for_scene(sc)
+        x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+        opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=bsc.BSC_FP64,
+                             stop_mode=bsc.BSC_STOP_STEP, max_newton=80, pcg_rtol=1e-6, max_pcg=8000)
+        newton = pcg = 0
+        for step in range(6):
+            st, s = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(step)), opts)
+            assert st == 0, (kind, step, st)
+            newton += s.newton_iters
+            pcg += s.pcg_iters_total
+        counts[f"{kind} {param:g}"] = (newton, pcg)
+    print(f"[distorted patches] (Newton, PCG) iterations over 6 steps: {counts}")
+    base = counts["aspect 1"][0]
+    for key in ("aspect 4", "skew 45", "bend 120"):
+        assert counts[key][0] <= 3 * base + 6, key
