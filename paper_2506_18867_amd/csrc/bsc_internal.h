@@ -92,8 +92,10 @@ struct DevSheet {
 #ifndef BSC_ASM_THREADS
 #define BSC_ASM_THREADS 512
 #endif
+// Dynamic LDS per assembly workgroup: two workgroups (plus their small static arrays) share
+// a CU's 160 KB.
 #ifndef BSC_ASM_LDS_KB
-#define BSC_ASM_LDS_KB 64
+#define BSC_ASM_LDS_KB 78
 #endif
 constexpr int kAsmTileU = BSC_ASM_TILE_U;
 constexpr int kAsmThreads = BSC_ASM_THREADS;
