@@ -254,3 +254,79 @@ def smooth_field(n_u: int, n_v: int, seed: int, amp: float = 0.05, modes: int = 
             ph = g.uniform(0, 2 * np.pi, size=2)
             out[:, :, c] += amp * g.uniform(-1, 1) * np.sin(a * np.pi * s + ph[0]) * np.sin(b * np.pi * t + ph[1])
     return out.reshape(-1, 3)
+
+
+# ---- contact mesh and contact pairs (input data for the contact-Hessian conversion) ----------
+
+def contact_mesh(n_u: int, n_v: int | None = None, dof_ratio: float = 2.0, spacing: int = 1):
+    """A triangle contact mesh embedded in the surface: an m_u x m_v grid of vertices at uniform
+    parametric coordinates covering the whole parameter rectangle (knot units), with about
+    dof_ratio times the control points' count (the paper uses twice the surface's DOFs), and the
+    two triangles of every grid cell. Returns (uv (n_vert, 2), triangles (n_tri, 3), (m_u, m_v))."""
+    n_v = n_u if n_v is None else n_v
+    m_u = max(2, int(round(np.sqrt(dof_ratio) * (n_u - 1))) + 1)
+    m_v = max(2, int(round(np.sqrt(dof_ratio) * (n_v - 1))) + 1)
+    U = np.linspace(0.0, spacing * (n_u - 2), m_u)
+    V = np.linspace(0.0, spacing * (n_v - 2), m_v)
+    uu, vv = np.meshgrid(U, V)                     # vertex (p, q) at row q * m_u + p
+    uv = np.stack([uu.ravel(), vv.ravel()], axis=1)
+    p, q = np.meshgrid(np.arange(m_u - 1), np.arange(m_v - 1))
+    a = (q * m_u + p).ravel()
+    tris = np.concatenate([np.stack([a, a + 1, a + m_u + 1], 1), np.stack([a, a + m_u + 1, a + m_u], 1)])
+    return uv, tris.astype(np.int64), (m_u, m_v)
+
+
+def contact_pairs(uv: np.ndarray, tris: np.ndarray, grid: tuple, n_pairs: int, seed: int = 7,
+                  fold: float = 0.5, scale: float = 1.0):
+    """Synthetic contact pairs of a sheet folded onto itself across the line u = fold * u_max,
+    the dense self-contact of a folded cloth: each pair couples a vertex (or an edge) of one
+    layer with the nearest triangle (or edge) of the mirrored layer. The mix is 70% point-
+    triangle (4 vertices), 20% edge-edge (4), 7% point-edge (3) and 3% point-point (2); unused
+    slots hold -1. Each pair gets a Hessian D^T Q D with Q a random symmetric positive
+    semi-definite 9x9 matrix and D the map from the pair's vertex positions to the positions of
+    vertices 1..k-1 relative to vertex 0, so it only depends on relative positions, like a
+    barrier; its gradient is D^T q for a random q. Returns (verts (n_pairs, 4) int32,
+    hess (n_pairs, 12, 12), grad (n_pairs, 12))."""
+    g = rng(seed)
+    m_u, m_v = grid
+    umax = uv[:, 0].max()
+    cols = np.rint(uv[:, 0] / umax * (m_u - 1)).astype(np.int64)
+    rows_ = np.arange(uv.shape[0]) // m_u
+    left = np.nonzero(cols < fold * (m_u - 1))[0]
+    verts = -np.ones((n_pairs, 4), dtype=np.int32)
+    kinds = g.choice(4, size=n_pairs, p=[0.7, 0.2, 0.07, 0.03])
+
+    def mirror(a):
+        c = int(round(2 * fold * (m_u - 1))) - cols[a]
+        c = min(max(c, 0), m_u - 1)
+        return rows_[a] * m_u + c
+
+    for t in range(n_pairs):
+        a = int(g.choice(left))
+        b = mirror(a)
+        bi, bj = b % m_u, b // m_u
+        bi, bj = min(bi, m_u - 2), min(bj, m_v - 2)
+        cell = bj * (m_u - 1) + bi
+        tri = tris[cell + (g.integers(2) * (m_u - 1) * (m_v - 1))]
+        ai, aj = min(a % m_u, m_u - 2), min(a // m_u, m_v - 2)
+        if kinds[t] == 0:
+            verts[t] = [a, tri[0], tri[1], tri[2]]
+        elif kinds[t] == 1:
+            verts[t] = [a, aj * m_u + ai + 1, tri[0], tri[1]]
+        elif kinds[t] == 2:
+            verts[t, :3] = [a, tri[0], tri[2]]
+        else:
+            verts[t, :2] = [a, b]
+    hess = np.zeros((n_pairs, 12, 12))
+    grad = np.zeros((n_pairs, 12))
+    for t in range(n_pairs):
+        k = int((verts[t] >= 0).sum())
+        D = np.zeros((3 * (k - 1), 12))
+        for s in range(1, k):
+            D[3 * (s - 1):3 * s, 3 * s:3 * s + 3] = np.eye(3)
+            D[3 * (s - 1):3 * s, 0:3] = -np.eye(3)
+        R = g.standard_normal((3 * (k - 1), 2))
+        Q = scale * (R @ R.T + 0.1 * np.eye(3 * (k - 1)))
+        hess[t] = D.T @ Q @ D
+        grad[t] = D.T @ (scale * g.standard_normal(3 * (k - 1)))
+    return verts, hess, grad
