@@ -85,6 +85,8 @@ def parse():
                    help="steps of the quadrature-ablation leg (reduced vs 2x2 interior rule; 0: skip)")
     p.add_argument("--general-steps", type=int, default=3,
                    help="steps of the general-rest leg (the same driven sheet on a curved domain; 0: skip)")
+    p.add_argument("--contact-pairs", type=int, default=100000,
+                   help="contact pairs of the contact-Hessian conversion leg (0: skip)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run the traffic-counter calibration: one device-to-device copy of MIB MiB whose "
                         "source has been evicted from the caches, then exit")
@@ -263,6 +265,34 @@ def main():
                                  "assembly_fp32_ms": round(ms_a32, 4), "assembly_fp64_ms": round(ms_a64, 4)}
             del gctx
 
+    # Contact-Hessian conversion (Sec. 5.2, Alg. "Contact Hessian conversion and assembly"): a contact
+    # mesh of twice the sheet's DOFs embedded in it, dense self-contact of the sheet folded onto
+    # itself; wall-clock per call (the call synchronises twice), median of 5 after a warm-up.
+    contact_leg = None
+    if args.contact_pairs > 0:
+        uvc, tris, cgrid = syn.contact_mesh(sc.n_u, sc.n_v)
+        pvc, Hcp, gcp = syn.contact_pairs(uvc, tris, cgrid, args.contact_pairs, seed=args.seed)
+        ctx.bsc_contact_setup(uvc, args.contact_pairs)
+        dpv = torch.from_numpy(pvc).cuda()
+        dH = torch.from_numpy(Hcp).cuda()
+        dg = torch.from_numpy(gcp).cuda()
+        res = ctx.bsc_contact_hessian(dpv, dH, dg)
+        outc = (res[0], torch.empty(res[1].numel(), dtype=torch.int32, device="cuda"),
+                torch.empty(res[1].numel(), 9, dtype=torch.float64, device="cuda"), res[3])
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.bsc_contact_hessian(dpv, dH, dg, out=outc)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ms_c = 1e3 * float(np.median(times))
+        nblk = int(res[1].numel())
+        contact_leg = {"n_vertices": int(uvc.shape[0]), "pairs": args.contact_pairs, "cp_blocks": nblk,
+                       "ms_per_call": round(ms_c, 3), "mpairs_per_s": round(args.contact_pairs / ms_c / 1e3, 3),
+                       "mblocks_per_s": round(nblk / ms_c / 1e3, 2)}
+        del dpv, dH, dg, outc, res
+
     # per-kernel timings at the current state (same stream as the library)
     n, ne = sc.n_cp, sc.n_elem
     xhat = x.clone()
@@ -355,6 +385,7 @@ def main():
                  "fp32_gb_s": round(spmv_bytes32 / ms_spmv32 / 1e6, 1), "fp64_gb_s": round(spmv_bytes64 / ms_spmv64 / 1e6, 1)},
         "quadrature_ablation": quad_leg,
         "general_rest": general_leg,
+        "contact_conversion": contact_leg,
         "roofline": roof,
         "cpu_baseline": None,
     }

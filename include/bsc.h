@@ -255,6 +255,44 @@ bsc_status bsc_adam_step(bsc_ctx *ctx, int32_t n, float *d_param, const float *d
 bsc_status bsc_net_loss(bsc_ctx *ctx, int32_t batch, const float *d_in, const float *d_pred,
                         const float *d_target, float *d_loss, float *d_dpred);
 
+/* ---- Contact Hessian conversion (Sec. 3.3 contact barrier; Sec. 5.2 Alg. "Contact Hessian
+ * conversion and assembly") ---------------------------------------------------------------
+ * A triangle contact mesh is embedded in the surface: vertex a has fixed parametric coordinates,
+ * so its position is sum_ij N_ij(u_a, v_a) C^{ij} over the 9 CPs of its span (Eq. "trig mesh node
+ * from control points"). A contact model (not part of this library) gives, per contact pair of
+ * 2 to 4 mesh vertices, the Hessian and gradient of its energy with respect to those vertices.
+ * The conversion applies the chain rule (Eq. "gradient and hessian of contact barrier"; the
+ * second-derivative term vanishes because vertices are linear in the CPs):
+ *   H_CP(i, j) = sum over vertex pairs (a, b) of w_a(i) w_b(j) H(a, b),  g_CP(i) = sum_a w_a(i) g_a.
+ *
+ * bsc_contact_setup: host, synchronous. n_vert vertices at uv (host, 2*n_vert doubles, (u, v) per
+ *   vertex in the units of the knot vectors given to bsc_create, inside the parameter
+ *   rectangle). max_pairs (1..2^20) bounds n_pairs per call; max_vpairs bounds the distinct
+ *   vertex pairs per call (0: 16*max_pairs, the worst case). Sizes the contact workspace, which
+ *   grows by about 40 bytes x 81 per vertex pair of capacity. Replaces any earlier setup.
+ * bsc_contact_workspace_size / bsc_contact_bind_workspace: caller-owned device memory (256-byte
+ *   aligned) for the vertex tables and the sort buffers; binding uploads the tables and
+ *   synchronises the context's stream.
+ * bsc_contact_hessian: converts n_pairs contact pairs (0..max_pairs).
+ *   d_pair_verts: device, 4*n_pairs int32 vertex indices per pair; -1 marks an unused slot.
+ *   d_pair_hess: device, 144*n_pairs doubles: the 12x12 Hessian of each pair over (slot, xyz),
+ *     row-major, row 3*s + k; rows and columns of unused slots are ignored.
+ *   d_pair_grad: device, 12*n_pairs doubles (slot, xyz), or NULL.
+ *   Outputs (device, caller-owned): d_row_ptr (n_cp+1), d_col_idx (cap_blocks) and d_vals
+ *   (9*cap_blocks, row-major 3x3 per block): the CP Hessian as block CSR with both triangles,
+ *   columns ascending in each row, one block per CP pair reached by a nonzero weight product;
+ *   *nnzb (host) the block count; d_grad (3*n_cp, SoA like the state, or NULL) the CP gradient.
+ *   Enqueued on the context's stream; synchronises it twice (the sizes of the two sorts). The
+ *   result is bitwise reproducible. BSC_E_INVAL for a vertex index outside [-1, n_vert);
+ *   BSC_E_NOMEM if the distinct vertex pairs exceed max_vpairs or the blocks exceed cap_blocks
+ *   (then *nnzb holds the count needed). */
+bsc_status bsc_contact_setup(bsc_ctx *ctx, int32_t n_vert, const double *uv, int32_t max_pairs, int32_t max_vpairs);
+bsc_status bsc_contact_workspace_size(const bsc_ctx *ctx, size_t *bytes);
+bsc_status bsc_contact_bind_workspace(bsc_ctx *ctx, void *d_ws, size_t bytes);
+bsc_status bsc_contact_hessian(bsc_ctx *ctx, int32_t n_pairs, const int32_t *d_pair_verts, const double *d_pair_hess,
+                               const double *d_pair_grad, int32_t cap_blocks, int32_t *d_row_ptr, int32_t *d_col_idx,
+                               double *d_vals, int32_t *nnzb, double *d_grad);
+
 const char *bsc_status_string(bsc_status s);
 const char *bsc_last_error(const bsc_ctx *ctx);
 void bsc_destroy(bsc_ctx *ctx);

@@ -21,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbsc.so")
 
 BSC_OK = 0
+BSC_E_INVAL = -1
+BSC_E_NOMEM = -3
 BSC_FP64 = 0
 BSC_FP32_MIXED = 1
 BSC_MEMBRANE_STVK = 0
@@ -103,6 +105,10 @@ def load():
         "bsc_net_loss": [P, I32, P, P, P, P, P],
         "bsc_set_sample_log": [P, P, P, I32],
         "bsc_sample_log_count": [P, ctypes.POINTER(I32)],
+        "bsc_contact_setup": [P, I32, P, I32, I32],
+        "bsc_contact_workspace_size": [P, ctypes.POINTER(SZ)],
+        "bsc_contact_bind_workspace": [P, P, SZ],
+        "bsc_contact_hessian": [P, I32, P, P, P, I32, P, P, P, ctypes.POINTER(I32), P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -122,8 +128,9 @@ def exported_symbols() -> list[str]:
     return ["bsc_create", "bsc_sizes", "bsc_workspace_size", "bsc_bind_workspace", "bsc_set_pins", "bsc_eval_egh",
             "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step",
             "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size", "bsc_adam_step",
-            "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_status_string", "bsc_last_error",
-            "bsc_destroy"]
+            "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_contact_setup",
+            "bsc_contact_workspace_size", "bsc_contact_bind_workspace", "bsc_contact_hessian", "bsc_status_string",
+            "bsc_last_error", "bsc_destroy"]
 
 
 def _ptr(t):
@@ -216,6 +223,55 @@ class Context:
         idx = np.ascontiguousarray(idx, dtype=np.int32)
         self._check(self.lib.bsc_set_pins(self.h, _np_ptr(idx) if idx.size else None, int(idx.size)), "bsc_set_pins")
         self.pins = idx
+
+    def bsc_contact_setup(self, uv, max_pairs, max_vpairs=0):
+        """Embeds a contact mesh (vertices at parametric (u, v), knot units) and binds a device
+        workspace for conversions of up to max_pairs contact pairs."""
+        import torch
+        uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
+        self._check(self.lib.bsc_contact_setup(self.h, int(uv.shape[0]), _np_ptr(uv), int(max_pairs), int(max_vpairs)),
+                    "bsc_contact_setup")
+        sz = ctypes.c_size_t()
+        self._check(self.lib.bsc_contact_workspace_size(self.h, ctypes.byref(sz)), "bsc_contact_workspace_size")
+        self.ct_ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.ct_ws.data_ptr() + 255) & ~255
+        self._check(self.lib.bsc_contact_bind_workspace(self.h, ctypes.c_void_p(aligned), ctypes.c_size_t(sz.value)),
+                    "bsc_contact_bind_workspace")
+        self.ct_nvert = int(uv.shape[0])
+
+    def bsc_contact_hessian(self, pair_verts, pair_hess, pair_grad=None, cap_blocks=None, want_grad=True, out=None):
+        """pair_verts: (n_pairs, 4) int32, pair_hess: (n_pairs, 12, 12) float64, pair_grad: (n_pairs, 12)
+        float64 or None (device tensors). Returns (row_ptr, col_idx, vals (nnzb, 3, 3), grad (3, n_cp) or None),
+        the device outputs trimmed to nnzb blocks."""
+        import torch
+        n_pairs = int(pair_verts.shape[0]) if pair_verts is not None else 0
+        dev = self.device
+        retry = out is None and cap_blocks is None
+        if out is None:
+            cap = int(cap_blocks) if cap_blocks is not None else 256 * n_pairs + 1024
+            row_ptr = torch.empty(self.n_cp + 1, dtype=torch.int32, device=dev)
+            col = torch.empty(cap, dtype=torch.int32, device=dev)
+            vals = torch.empty(cap, 9, dtype=torch.float64, device=dev)
+            grad = torch.empty(3, self.n_cp, dtype=torch.float64, device=dev) if want_grad else None
+        else:
+            row_ptr, col, vals, grad = out
+            cap = int(col.shape[0])
+        nnzb = ctypes.c_int32()
+
+        def call():
+            return self.lib.bsc_contact_hessian(self.h, n_pairs, _ptr(pair_verts) if n_pairs else None,
+                                                _ptr(pair_hess) if n_pairs else None,
+                                                _ptr(pair_grad) if (n_pairs and pair_grad is not None) else None, cap,
+                                                _ptr(row_ptr), _ptr(col), _ptr(vals), ctypes.byref(nnzb), _ptr(grad))
+        st = call()
+        if st == BSC_E_NOMEM and retry and nnzb.value > cap:     # output too small: size it and redo
+            cap = nnzb.value
+            col = torch.empty(cap, dtype=torch.int32, device=dev)
+            vals = torch.empty(cap, 9, dtype=torch.float64, device=dev)
+            st = call()
+        self._check(st, "bsc_contact_hessian")
+        k = nnzb.value
+        return row_ptr, col[:k], vals[:k].view(k, 3, 3), grad
 
     def bsc_eval_egh(self, x, precision=BSC_FP64, want_energy=True, want_grad=True, want_hess=True):
         import torch

@@ -158,10 +158,22 @@ struct DevBufs {
     int max_blocks;
 };
 
+// Contact-mesh conversion buffers (one caller-owned workspace, see contact.hip).
+struct ContactBufs {
+    int32_t *vspan, *voff, *vlist;           // span of each vertex; vertices grouped by span
+    double *vw;                              // 9 interpolation weights per vertex
+    unsigned long long *key1a, *key1b, *ukey1, *key2a, *key2b, *ukey2;
+    unsigned int *val1a, *val1b, *cnt1, *off1, *val2a, *val2b, *cnt2, *off2, *small;
+    double *hlin, *glin;                     // vertex-pair blocks, vertex gradients
+    void *tmp;                               // sort / run-length / scan temporary storage
+    size_t tmp_bytes;
+};
+
 }  // namespace bsc
 
 struct bsc_ctx {
     int n_u = 0, n_v = 0, Nu = 0, Nv = 0, n_cp = 0, n_elem = 0, n_mp = 0, n_be = 0;
+    double hu = 1.0, hv = 1.0;               // knot spacings (parameter units per span)
     bsc_material mat{};
     bsc::DevSheet dev{};
     hipStream_t stream = nullptr;
@@ -189,6 +201,14 @@ struct bsc_ctx {
     bool cg_ev_ok = false, cg_ev_tried = false;
     // pinned host buffer for the step's small read-backs (solver scalars followed by the flags)
     char *pinned = nullptr;
+    // contact mesh embedded in the surface (bsc_contact_setup): per-vertex span and weights
+    int ct_nvert = 0, ct_max_pairs = 0, ct_max_vpairs = 0;
+    std::vector<int32_t> ct_span, ct_voff, ct_vlist;
+    std::vector<double> ct_w;
+    size_t ct_tmp_bytes = 0;
+    char *ct_ws = nullptr;
+    size_t ct_ws_bytes = 0;
+    bsc::ContactBufs ct{};
     ~bsc_ctx() {
         for (auto &g : cg_graph)
             if (g) (void)hipGraphExecDestroy(g);
@@ -205,6 +225,10 @@ namespace bsc {
 bsc_status fail(bsc_ctx *ctx, bsc_status st, const std::string &msg);
 bsc_status hip_check(bsc_ctx *ctx, hipError_t e, const char *what);
 size_t layout_workspace(const bsc_ctx *ctx, DevBufs *b, char *base);
+size_t contact_layout(const bsc_ctx *ctx, ContactBufs *b, char *base);
+size_t contact_tmp_bytes(int max_pairs, int max_vpairs);
+// Quadratic B-spline pieces on a span (type 0 first, 1 inner, 2 last), local t in [0, 1].
+void host_pieces(int type, double t, double N[3], double D[3], double D2[3]);
 DevSheet dev_sheet(const bsc_ctx *ctx);
 
 // ---- launchers (eval.hip) ----

@@ -219,6 +219,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 DevSheet dev_sheet(const bsc_ctx *ctx) { return ctx->dev; }
 
+void host_pieces(int type, double t, double N[3], double D[3], double D2[3]) { pieces(type, t, N, D, D2); }
+
 size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -512,7 +514,8 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
         }
         if (S.asm_ty[kind] == 0) { delete c; return BSC_E_INVAL; }
     }
-    (void)hu; (void)hv;
+    c->hu = hu;
+    c->hv = hv;
     *out = c;
     return BSC_OK;
 }

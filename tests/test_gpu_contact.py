@@ -1,0 +1,110 @@
+"""GPU parity of the contact-Hessian conversion (Sec. 3.3, Sec. 5.2 Alg. "Contact Hessian
+conversion and assembly") against the oracle's plain chain-rule products, through the C ABI.
+
+The block pattern must equal the oracle's exactly (CP pairs reached by nonzero weight products),
+the CSR must be well formed (row pointers monotone, columns strictly ascending in each row), and
+the block values and the CP gradient must match within 1e-12 (FP64; only the summation order
+differs). Sizes: small sheets with ragged contact sets, knot spacing 2, n_u != n_v, and the full
+226 x 226 sheet with a contact mesh of twice its DOFs. Edge cases: no pairs, a vertex index out
+of range, too small an output capacity, too small a vertex-pair capacity."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg  # noqa: F401
+
+import oracle
+import synthetic as syn
+from oracle import contact_ref as cr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2506_18867_amd import bsc  # noqa: E402
+
+
+def _case(n_u, n_v, n_pairs, seed=3, spacing=1):
+    ku, kv = syn.open_uniform_knots(n_u, spacing), syn.open_uniform_knots(n_v, spacing)
+    _, _, rest = syn.flat_sheet(n_u, n_v, spacing=spacing)
+    sh = oracle.Sheet(n_u, n_v, ku, kv, rest, 0, 1e4, 0.3, 1e-3, 0, 0, 0, 1e-3, 0.2)
+    uv, tris, grid = syn.contact_mesh(n_u, n_v, spacing=spacing)
+    pv, H, g = syn.contact_pairs(uv, tris, grid, n_pairs, seed=seed)
+    ctx = bsc.Context(n_u, n_v, ku, kv, rest, bsc.make_material(0, 1e4, 0.3, 1e-3, mu_bend=1e-3, rho_area=0.2))
+    return sh, ctx, uv, pv, H, g
+
+
+def _dev(pv, H, g):
+    return (torch.from_numpy(np.ascontiguousarray(pv, dtype=np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(H)).cuda(), torch.from_numpy(np.ascontiguousarray(g)).cuda())
+
+
+def _check(sh, ctx, uv, pv, H, g, tol=1e-12):
+    ctx.bsc_contact_setup(uv, max(1, pv.shape[0]))
+    dpv, dH, dg = _dev(pv, H, g)
+    row_ptr, col, vals, grad = ctx.bsc_contact_hessian(dpv, dH, dg)
+    torch.cuda.synchronize()
+    rp, cl, vl, gr = row_ptr.cpu().numpy(), col.cpu().numpy(), vals.cpu().numpy(), grad.cpu().numpy()
+    n = sh.n_cp
+    assert rp[0] == 0 and rp[-1] == len(cl) and np.all(np.diff(rp) >= 0)
+    for i in range(n):
+        assert np.all(np.diff(cl[rp[i]:rp[i + 1]]) > 0)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    got = {(int(i), int(j)) for i, j in zip(rows, cl)}
+    assert got == cr.cp_block_pattern(sh, uv, pv)
+    Hc, gc = cr.contact_to_cp(sh, uv, pv, H, g)
+    G = sp.bsr_matrix((vl, cl, rp), shape=(3 * n, 3 * n)).tocsr()
+    err = sp.linalg.norm(G - Hc) / sp.linalg.norm(Hc)
+    gerr = np.linalg.norm(gr.T - gc) / np.linalg.norm(gc)
+    print(f"[contact] n={sh.n_u}x{sh.n_v} pairs={pv.shape[0]} blocks={len(cl)} rel err H {err:.2e} g {gerr:.2e}")
+    assert err < tol and gerr < tol
+    return row_ptr, col, vals, grad
+
+
+@pytest.mark.parametrize("n_u,n_v,n_pairs,spacing", [(12, 12, 300, 1), (17, 9, 500, 2), (40, 31, 2000, 1)])
+def test_contact_conversion_matches_oracle(n_u, n_v, n_pairs, spacing):
+    print(f"[contact] {n_u}x{n_v} pairs={n_pairs} spacing={spacing}", flush=True)
+    sh, ctx, uv, pv, H, g = _case(n_u, n_v, n_pairs, spacing=spacing)
+    _check(sh, ctx, uv, pv, H, g)
+
+
+def test_contact_conversion_full_size():
+    """226 x 226 CPs, a contact mesh of twice their DOFs (about 102k vertices), 20k pairs."""
+    print("[contact] 226x226 pairs=20000", flush=True)
+    sh, ctx, uv, pv, H, g = _case(226, 226, 20000, seed=11)
+    _check(sh, ctx, uv, pv, H, g)
+
+
+def test_contact_conversion_is_bitwise_reproducible():
+    sh, ctx, uv, pv, H, g = _case(20, 20, 800, seed=4)
+    ctx.bsc_contact_setup(uv, 800)
+    dpv, dH, dg = _dev(pv, H, g)
+    a = [t.clone() for t in ctx.bsc_contact_hessian(dpv, dH, dg)]
+    b = ctx.bsc_contact_hessian(dpv, dH, dg)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_contact_edge_cases():
+    sh, ctx, uv, pv, H, g = _case(10, 10, 50, seed=2)
+    ctx.bsc_contact_setup(uv, 50, max_vpairs=0)
+    dpv, dH, dg = _dev(pv, H, g)
+    # no pairs: empty matrix, zero gradient
+    row_ptr, col, vals, grad = ctx.bsc_contact_hessian(dpv[:0], dH[:0], dg[:0])
+    assert col.numel() == 0 and int(row_ptr.abs().sum()) == 0 and float(grad.abs().sum()) == 0.0
+    # a vertex index out of range
+    bad = dpv.clone()
+    bad[3, 1] = len(uv)
+    with pytest.raises(bsc.BscError) as e:
+        ctx.bsc_contact_hessian(bad, dH, dg)
+    assert e.value.status == bsc.BSC_E_INVAL
+    # output capacity too small: the count needed is reported
+    with pytest.raises(bsc.BscError) as e:
+        ctx.bsc_contact_hessian(dpv, dH, dg, cap_blocks=10)
+    assert e.value.status == bsc.BSC_E_NOMEM
+    # vertex-pair capacity too small
+    ctx.bsc_contact_setup(uv, 50, max_vpairs=20)
+    with pytest.raises(bsc.BscError) as e:
+        ctx.bsc_contact_hessian(dpv, dH, dg)
+    assert e.value.status == bsc.BSC_E_NOMEM
+    # a valid call after the errors still matches the oracle
+    ctx.bsc_contact_setup(uv, 50)
+    _check(sh, ctx, uv, pv, H, g)
