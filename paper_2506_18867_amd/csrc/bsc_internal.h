@@ -165,6 +165,11 @@ struct ContactBufs {
     unsigned long long *key1a, *key1b, *ukey1, *key2a, *key2b, *ukey2;
     unsigned int *val1a, *val1b, *cnt1, *off1, *val2a, *val2b, *cnt2, *off2, *small;
     double *hlin, *glin;                     // vertex-pair blocks, vertex gradients
+    int32_t *pa, *pb;                        // vertices of each distinct vertex pair
+    double *hsp;                             // vertex-pair blocks in span-pair order
+    int32_t *pas, *pbs;                      // their vertices, same order
+    unsigned long long *spk, *spk_s, *uksp;  // span-pair keys of the vertex pairs (sorted, distinct)
+    unsigned int *spv, *spv_s, *cntsp, *offsp;
     void *tmp;                               // sort / run-length / scan temporary storage
     size_t tmp_bytes;
 };

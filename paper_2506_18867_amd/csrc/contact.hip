@@ -35,11 +35,11 @@ inline unsigned bit_width(u64 v) {
     return b;
 }
 
-// Step 1 expansion: entry t = 16 c + 4 s + s' for slots s, s' of pair c. Key (a * n_vert + b),
-// or the sentinel (sorted after every valid key) for unused slots. Out-of-range vertex indices
-// raise the error flag and are skipped.
-__global__ void k_ct_expand_v(int n_pairs, int n_vert, const int32_t *__restrict__ verts, u64 sent, u64 *__restrict__ key,
-                              u32 *__restrict__ val, int32_t *__restrict__ flag) {
+// Step 1 expansion: entry t = 16 c + 4 s + s' for slots s, s' of pair c. Key (a << vbits) | b,
+// or the sentinel (all used bits set, sorted after every valid key) for unused slots.
+// Out-of-range vertex indices raise the error flag and are skipped.
+__global__ void k_ct_expand_v(int n_pairs, int n_vert, unsigned vbits, const int32_t *__restrict__ verts, u64 sent,
+                              u64 *__restrict__ key, u32 *__restrict__ val, int32_t *__restrict__ flag) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 16 * n_pairs) return;
     const int c = t >> 4, s = (t >> 2) & 3, s2 = t & 3;
@@ -47,7 +47,7 @@ __global__ void k_ct_expand_v(int n_pairs, int n_vert, const int32_t *__restrict
     const bool bad = va < -1 || vb < -1 || va >= n_vert || vb >= n_vert;
     if (bad) atomicOr(flag, 1);
     const bool ok = !bad && va >= 0 && vb >= 0;
-    key[t] = ok ? u64(va) * u64(n_vert) + u64(vb) : sent;
+    key[t] = ok ? (u64(va) << vbits) | u64(vb) : sent;
     val[t] = u32(t);
 }
 
@@ -57,11 +57,14 @@ __global__ void k_ct_zero(double *__restrict__ p, size_t n) {
 }
 
 // Step 1 sums: one thread per distinct vertex pair u, summing the 3x3 blocks of its run in the
-// sorted (stable, hence original) order. The diagonal pair (a, a) also sums the pair gradients
-// of the slots holding a.
-__global__ void k_ct_vpair_sum(int n1, int n_vert, const u64 *__restrict__ ukey, const u32 *__restrict__ cnt,
+// sorted (stable, hence original) order. Also records the pair's vertices and its span-pair key
+// (e_a << ebits) | e_b, and, for the diagonal pair (a, a), the pair gradients of the slots
+// holding a.
+__global__ void k_ct_vpair_sum(int n1, unsigned vbits, unsigned ebits, const u64 *__restrict__ ukey, const u32 *__restrict__ cnt,
                                const u32 *__restrict__ off, const u32 *__restrict__ val, const double *__restrict__ pair_hess,
-                               const double *__restrict__ pair_grad, double *__restrict__ hlin, double *__restrict__ glin) {
+                               const double *__restrict__ pair_grad, const int32_t *__restrict__ vspan, double *__restrict__ hlin,
+                               int32_t *__restrict__ pa, int32_t *__restrict__ pb, u64 *__restrict__ spkey, u32 *__restrict__ spval,
+                               double *__restrict__ glin) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n1) return;
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
@@ -82,59 +85,100 @@ __global__ void k_ct_vpair_sum(int n1, int n_vert, const u64 *__restrict__ ukey,
 #pragma unroll
     for (int r = 0; r < 9; ++r) hlin[size_t(u) * 9 + r] = h[r];
     const u64 k = ukey[u];
-    const int a = int(k / u64(n_vert)), b = int(k % u64(n_vert));
+    const int a = int(k >> vbits), b = int(k & ((u64(1) << vbits) - 1));
+    pa[u] = a;
+    pb[u] = b;
+    spkey[u] = (u64(vspan[a]) << ebits) | u64(vspan[b]);
+    spval[u] = u32(u);
     if (pair_grad && a == b) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) glin[size_t(a) * 3 + r] = g[r];
     }
 }
 
-// Step 2 expansion: entry t = 81 u + 9 m + m' for the CPs m, m' of the supports of a and b.
-__global__ void k_ct_expand_cp(int n1, int n_vert, int n_cp, int n_u, int Nu, const u64 *__restrict__ ukey,
-                               const int32_t *__restrict__ vspan, const double *__restrict__ vw, u64 sent,
-                               u64 *__restrict__ key, u32 *__restrict__ val) {
+// Vertex-pair data in span-pair order (so that the vertex pairs of one span pair are contiguous).
+__global__ void k_ct_permute(int n1, const u32 *__restrict__ spv, const double *__restrict__ hlin, const int32_t *__restrict__ pa,
+                             const int32_t *__restrict__ pb, double *__restrict__ hsp, int32_t *__restrict__ pas,
+                             int32_t *__restrict__ pbs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    const u32 v = spv[r];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) hsp[size_t(r) * 9 + e] = hlin[size_t(v) * 9 + e];
+    pas[r] = pa[v];
+    pbs[r] = pb[v];
+}
+
+// Step 2 expansion: entry t = 81 w + 9 m + m' for the CPs m, m' of the two spans of span pair w.
+// Valid only if some vertex pair of the span pair has a nonzero weight product there.
+template <typename K>
+__global__ void k_ct_expand_cp(int n2, unsigned ebits, unsigned cbits, int n_u, int Nu, const u64 *__restrict__ ukeysp,
+                               const u32 *__restrict__ cntsp, const u32 *__restrict__ offsp, const int32_t *__restrict__ pas,
+                               const int32_t *__restrict__ pbs, const double *__restrict__ vw, K sent, K *__restrict__ key,
+                               u32 *__restrict__ val) {
     const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= size_t(n1) * 81) return;
-    const int u = int(t / 81), mm = int(t % 81), m = mm / 9, m2 = mm % 9;
-    const u64 k = ukey[u];
-    const int a = int(k / u64(n_vert)), b = int(k % u64(n_vert));
-    const double w = vw[size_t(a) * 9 + m] * vw[size_t(b) * 9 + m2];
-    const int ea = vspan[a], eb = vspan[b];
+    if (t >= size_t(n2) * 81) return;
+    const int w = int(t / 81), mm = int(t % 81), m = mm / 9, m2 = mm % 9;
+    bool nz = false;
+    const u32 o = offsp[w], n = cntsp[w];
+    for (u32 q = o; q < o + n && !nz; ++q) nz = vw[size_t(pas[q]) * 9 + m] * vw[size_t(pbs[q]) * 9 + m2] != 0.0;
+    const u64 k = ukeysp[w];
+    const int ea = int(k >> ebits), eb = int(k & ((u64(1) << ebits) - 1));
     const int i = (ea / Nu + m / 3) * n_u + (ea % Nu + m % 3);
     const int j = (eb / Nu + m2 / 3) * n_u + (eb % Nu + m2 % 3);
-    key[t] = w != 0.0 ? u64(i) * u64(n_cp) + u64(j) : sent;
+    key[t] = nz ? (K(i) << cbits) | K(j) : sent;
     val[t] = u32(t);
 }
 
-// Step 2 sums: one thread per CP block, in the run's sorted order.
-__global__ void k_ct_cpair_sum(int nnzb, int n_vert, int n_cp, const u64 *__restrict__ ukey2, const u32 *__restrict__ cnt2,
-                               const u32 *__restrict__ off2, const u32 *__restrict__ val2, const u64 *__restrict__ ukey1,
-                               const double *__restrict__ vw, const double *__restrict__ hlin, int32_t *__restrict__ col,
-                               double *__restrict__ out) {
-    const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= nnzb) return;
+// Step 2 sums: a group of kCtLanes lanes per CP block. Lane l takes the entries l, l + kCtLanes,
+// ... of the block's run (each entry sums over the vertex pairs of its span pair in their sorted
+// order), then the group adds its lanes in a fixed tree. The order depends only on the run, so
+// the result is reproducible; the lanes hide the latency of the dependent loads of each entry.
+constexpr int kCtLanes = 8;
+
+template <typename K>
+__global__ void __launch_bounds__(kCtBlock) k_ct_cpair_sum(int nnzb, unsigned cbits, const K *__restrict__ ukey2,
+                                                           const u32 *__restrict__ cnt2, const u32 *__restrict__ off2,
+                                                           const u32 *__restrict__ val2, const u32 *__restrict__ cntsp,
+                                                           const u32 *__restrict__ offsp, const int32_t *__restrict__ pas,
+                                                           const int32_t *__restrict__ pbs, const double *__restrict__ vw,
+                                                           const double *__restrict__ hsp,
+                                                           int32_t *__restrict__ col, double *__restrict__ out) {
+    const int gid = int((size_t(blockIdx.x) * blockDim.x + threadIdx.x) / kCtLanes);
+    const int lane = threadIdx.x % kCtLanes;
+    const bool live = gid < nnzb;
     double h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const u32 o = off2[z], n = cnt2[z];
-    for (u32 q = o; q < o + n; ++q) {
-        const u32 t = val2[q];
-        const int u = int(t / 81), mm = int(t % 81), m = mm / 9, m2 = mm % 9;
-        const u64 k = ukey1[u];
-        const int a = int(k / u64(n_vert)), b = int(k % u64(n_vert));
-        const double w = vw[size_t(a) * 9 + m] * vw[size_t(b) * 9 + m2];
-        const double *H = hlin + size_t(u) * 9;
+    if (live) {
+        const u32 o = off2[gid], n = cnt2[gid];
+        for (u32 q = o + lane; q < o + n; q += kCtLanes) {
+            const u32 t = val2[q];
+            const int w = int(t / 81), mm = int(t % 81), m = mm / 9, m2 = mm % 9;
+            const u32 o2 = offsp[w], n2 = cntsp[w];
+            for (u32 r = o2; r < o2 + n2; ++r) {
+                const double wt = vw[size_t(pas[r]) * 9 + m] * vw[size_t(pbs[r]) * 9 + m2];
+                const double *H = hsp + size_t(r) * 9;
 #pragma unroll
-        for (int r = 0; r < 9; ++r) h[r] += w * H[r];
+                for (int e = 0; e < 9; ++e) h[e] += wt * H[e];
+            }
+        }
     }
-    col[z] = int32_t(ukey2[z] % u64(n_cp));
 #pragma unroll
-    for (int r = 0; r < 9; ++r) out[size_t(z) * 9 + r] = h[r];
+    for (int d = kCtLanes / 2; d > 0; d >>= 1)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) h[e] += __shfl_xor(h[e], d, kCtLanes);
+    if (live && lane == 0) {
+        col[gid] = int32_t(ukey2[gid] & ((K(1) << cbits) - 1));
+#pragma unroll
+        for (int r = 0; r < 9; ++r) out[size_t(gid) * 9 + r] = h[r];
+    }
 }
 
 // CSR row pointers: row_ptr[i] = first block whose row is >= i (lower bound over sorted keys).
-__global__ void k_ct_rowptr(int n_cp, int nnzb, const u64 *__restrict__ ukey2, int32_t *__restrict__ row_ptr) {
+template <typename K>
+__global__ void k_ct_rowptr(int n_cp, int nnzb, unsigned cbits, const K *__restrict__ ukey2, int32_t *__restrict__ row_ptr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n_cp) return;
-    const u64 target = u64(i) * u64(n_cp);
+    const K target = K(i) << cbits;
     int lo = 0, hi = nnzb;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -168,6 +212,109 @@ __global__ void k_ct_grad(int n_u, int n_v, int Nu, int Nv, const int32_t *__res
 
 inline unsigned grid(size_t n) { return unsigned((n + kCtBlock - 1) / kCtBlock); }
 
+// Key widths: vertex pairs (a << vbits) | b; span pairs (e_a << ebits) | e_b; CP pairs
+// (i << cbits) | j, held in 32 bits when they fit.
+struct CtBits {
+    unsigned vbits, ebits, cbits;
+    bool cp32;
+};
+inline CtBits ct_bits(const bsc_ctx *c) {
+    CtBits b;
+    // bit_width(n) > bit_width(n - 1) when n is a power of two: indices stay below the all-ones
+    // pattern, so the sentinel key (all used bits set) never equals a valid key
+    b.vbits = bit_width(u64(c->ct_nvert));
+    b.ebits = bit_width(u64(c->n_elem));
+    b.cbits = bit_width(u64(c->n_cp));
+    b.cp32 = 2 * b.cbits <= 32;
+    return b;
+}
+
+// Step 2 (span pairs onward) for the CP-key type K. Returns the block count in *nnzb.
+template <typename K>
+bsc_status ct_step2(bsc_ctx *c, int n1, const CtBits &bits, int32_t cap_blocks, int32_t *d_col_idx, double *d_vals,
+                    int32_t *d_row_ptr, int *nnzb_out) {
+    const ContactBufs &B = c->ct;
+    hipStream_t st = c->stream;
+    auto ok = [&](hipError_t e, const char *what) { return hip_check(c, e, what); };
+    bsc_status s;
+    size_t tb;
+    u32 host_small[4] = {0, 0, 0, 0};
+    K *key2a = (K *)B.key2a, *key2b = (K *)B.key2b, *ukey2 = (K *)B.ukey2;
+    const K sent2 = K((u64(1) << (2 * bits.cbits)) - 1);
+    int nnzb = 0;
+    if (n1 > 0) {
+        // 2a. vertex pairs grouped by span pair
+        tb = B.tmp_bytes;
+        if ((s = ok(rocprim::radix_sort_pairs(B.tmp, tb, B.spk, B.spk_s, B.spv, B.spv_s, unsigned(n1), 0, 2 * bits.ebits, st),
+                    "contact sort span pairs")) != BSC_OK) return s;
+        tb = B.tmp_bytes;
+        if ((s = ok(rocprim::run_length_encode(B.tmp, tb, B.spk_s, unsigned(n1), B.uksp, B.cntsp, B.small + 3, st),
+                    "contact runs span pairs")) != BSC_OK) return s;
+        if ((s = ok(hipMemcpyAsync(host_small, B.small, 16, hipMemcpyDeviceToHost, st), "contact read 2a")) != BSC_OK) return s;
+        if ((s = ok(hipStreamSynchronize(st), "contact sync 2a")) != BSC_OK) return s;
+        const int n2 = int(host_small[3]);
+        tb = B.tmp_bytes;
+        if ((s = ok(rocprim::exclusive_scan(B.tmp, tb, B.cntsp, B.offsp, u32(0), size_t(n2), rocprim::plus<u32>(), st),
+                    "contact scan span pairs")) != BSC_OK) return s;
+        k_ct_permute<<<grid(n1), kCtBlock, 0, st>>>(n1, B.spv_s, B.hlin, B.pa, B.pb, B.hsp, B.pas, B.pbs);
+        if ((s = ok(hipGetLastError(), "contact permute")) != BSC_OK) return s;
+        // 2b. CP-pair entries, sorted; runs
+        const unsigned e2 = 81u * unsigned(n2);
+        k_ct_expand_cp<K><<<grid(e2), kCtBlock, 0, st>>>(n2, bits.ebits, bits.cbits, c->n_u, c->Nu, B.uksp, B.cntsp, B.offsp,
+                                                         B.pas, B.pbs, B.vw, sent2, key2a, B.val2a);
+        if ((s = ok(hipGetLastError(), "contact expand 2")) != BSC_OK) return s;
+        tb = B.tmp_bytes;
+        if ((s = ok(rocprim::radix_sort_pairs(B.tmp, tb, key2a, key2b, B.val2a, B.val2b, e2, 0, 2 * bits.cbits, st),
+                    "contact sort 2")) != BSC_OK) return s;
+        tb = B.tmp_bytes;
+        if ((s = ok(rocprim::run_length_encode(B.tmp, tb, key2b, e2, ukey2, B.cnt2, B.small + 1, st), "contact runs 2")) != BSC_OK)
+            return s;
+        if ((s = ok(hipMemcpyAsync(host_small, B.small, 16, hipMemcpyDeviceToHost, st), "contact read 2")) != BSC_OK) return s;
+        if ((s = ok(hipStreamSynchronize(st), "contact sync 2")) != BSC_OK) return s;
+        nnzb = int(host_small[1]);
+        K last = 0;
+        if (nnzb > 0) {
+            if ((s = ok(hipMemcpy(&last, ukey2 + (nnzb - 1), sizeof(K), hipMemcpyDeviceToHost), "contact read last")) != BSC_OK)
+                return s;
+            if (last == sent2) --nnzb;
+        }
+        if (nnzb > cap_blocks) {
+            *nnzb_out = nnzb;
+            return fail(c, BSC_E_NOMEM, "more CP blocks than cap_blocks (nnzb holds the count needed)");
+        }
+        if (nnzb > 0) {
+            // 2c. sums
+            tb = B.tmp_bytes;
+            if ((s = ok(rocprim::exclusive_scan(B.tmp, tb, B.cnt2, B.off2, u32(0), size_t(nnzb), rocprim::plus<u32>(), st),
+                        "contact scan 2")) != BSC_OK) return s;
+            k_ct_cpair_sum<K><<<grid(size_t(nnzb) * kCtLanes), kCtBlock, 0, st>>>(
+                nnzb, bits.cbits, ukey2, B.cnt2, B.off2, B.val2b, B.cntsp, B.offsp, B.pas, B.pbs, B.vw, B.hsp, d_col_idx, d_vals);
+            if ((s = ok(hipGetLastError(), "contact sum 2")) != BSC_OK) return s;
+        }
+    }
+    k_ct_rowptr<K><<<grid(size_t(c->n_cp) + 1), kCtBlock, 0, st>>>(c->n_cp, nnzb, bits.cbits, ukey2, d_row_ptr);
+    if ((s = ok(hipGetLastError(), "contact row pointers")) != BSC_OK) return s;
+    *nnzb_out = nnzb;
+    return BSC_OK;
+}
+
+template <typename K>
+size_t sort_tmp(unsigned n) {
+    size_t s = 0, need = 0;
+    const K *k = nullptr;
+    K *ko = nullptr;
+    const u32 *v = nullptr;
+    u32 *vo = nullptr;
+    (void)rocprim::radix_sort_pairs(nullptr, s, k, ko, v, vo, n, 0, 8 * unsigned(sizeof(K)), hipStream_t(0));
+    need = std::max(need, s);
+    s = 0;
+    (void)rocprim::run_length_encode(nullptr, s, k, n, ko, vo, vo, hipStream_t(0));
+    need = std::max(need, s);
+    s = 0;
+    (void)rocprim::exclusive_scan(nullptr, s, v, vo, u32(0), size_t(n), rocprim::plus<u32>(), hipStream_t(0));
+    return std::max(need, s);
+}
+
 }  // namespace
 
 // Layout of the contact workspace; base == nullptr only sizes it.
@@ -192,6 +339,18 @@ size_t contact_layout(const bsc_ctx *c, ContactBufs *b, char *base) {
     t.cnt1 = (u32 *)take(4 * e1);
     t.off1 = (u32 *)take(4 * e1);
     t.hlin = (double *)take(72 * u1);
+    t.hsp = (double *)take(72 * u1);
+    t.pas = (int32_t *)take(4 * u1);
+    t.pbs = (int32_t *)take(4 * u1);
+    t.pa = (int32_t *)take(4 * u1);
+    t.pb = (int32_t *)take(4 * u1);
+    t.spk = (u64 *)take(8 * u1);
+    t.spk_s = (u64 *)take(8 * u1);
+    t.spv = (u32 *)take(4 * u1);
+    t.spv_s = (u32 *)take(4 * u1);
+    t.uksp = (u64 *)take(8 * u1);
+    t.cntsp = (u32 *)take(4 * u1);
+    t.offsp = (u32 *)take(4 * u1);
     t.glin = (double *)take(24 * nv);
     t.key2a = (u64 *)take(8 * e2);
     t.key2b = (u64 *)take(8 * e2);
@@ -200,7 +359,7 @@ size_t contact_layout(const bsc_ctx *c, ContactBufs *b, char *base) {
     t.ukey2 = (u64 *)take(8 * e2);
     t.cnt2 = (u32 *)take(4 * e2);
     t.off2 = (u32 *)take(4 * e2);
-    t.small = (u32 *)take(256);                     // [0] runs 1, [1] runs 2, [2] error flag
+    t.small = (u32 *)take(256);                     // [0] runs 1, [1] runs 2, [2] error flag, [3] span-pair runs
     t.tmp = take(c->ct_tmp_bytes);
     t.tmp_bytes = c->ct_tmp_bytes;
     if (b) *b = t;
@@ -210,22 +369,8 @@ size_t contact_layout(const bsc_ctx *c, ContactBufs *b, char *base) {
 // Temporary storage that the sorts, run-length encodings and scans need at the largest sizes.
 size_t contact_tmp_bytes(int max_pairs, int max_vpairs) {
     const unsigned e1 = unsigned(16 * max_pairs), u1 = unsigned(max_vpairs), e2 = 81u * u1;
-    size_t need = 0, s = 0;
-    const u64 *k = nullptr;
-    u64 *ko = nullptr;
-    const u32 *v = nullptr;
-    u32 *vo = nullptr;
-    for (unsigned n : {e1, e2}) {
-        s = 0;
-        (void)rocprim::radix_sort_pairs(nullptr, s, k, ko, v, vo, n, 0, 64, hipStream_t(0));
-        need = std::max(need, s);
-        s = 0;
-        (void)rocprim::run_length_encode(nullptr, s, k, n, ko, vo, vo, hipStream_t(0));
-        need = std::max(need, s);
-        s = 0;
-        (void)rocprim::exclusive_scan(nullptr, s, v, vo, u32(0), size_t(n), rocprim::plus<u32>(), hipStream_t(0));
-        need = std::max(need, s);
-    }
+    size_t need = std::max(sort_tmp<u64>(e1), sort_tmp<u64>(u1));
+    need = std::max(need, std::max(sort_tmp<u64>(e2), sort_tmp<u32>(e2)));
     return need + 256;
 }
 
@@ -317,10 +462,9 @@ bsc_status bsc_contact_hessian(bsc_ctx *c, int32_t n_pairs, const int32_t *d_pai
         return fail(c, BSC_E_INVAL, "null or negative argument");
     const ContactBufs &B = c->ct;
     hipStream_t st = c->stream;
-    const int n_vert = c->ct_nvert, n_cp = c->n_cp;
-    const u64 key1_bits = bit_width(u64(n_vert) * u64(n_vert));
-    const u64 key2_bits = bit_width(u64(n_cp) * u64(n_cp));
-    const u64 sent1 = (u64(1) << key1_bits) - 1, sent2 = (u64(1) << key2_bits) - 1;
+    const int n_vert = c->ct_nvert;
+    const CtBits bits = ct_bits(c);
+    const u64 sent1 = (u64(1) << (2 * bits.vbits)) - 1;
     size_t tb = B.tmp_bytes;
     auto ok = [&](hipError_t e, const char *what) { return hip_check(c, e, what); };
     bsc_status s;
@@ -336,10 +480,11 @@ bsc_status bsc_contact_hessian(bsc_ctx *c, int32_t n_pairs, const int32_t *d_pai
     if (n_pairs > 0) {
         // 1. vertex-pair entries, sorted; runs; sums
         const unsigned e1 = unsigned(16 * n_pairs);
-        k_ct_expand_v<<<grid(e1), kCtBlock, 0, st>>>(n_pairs, n_vert, d_pair_verts, sent1, B.key1a, B.val1a, (int32_t *)(B.small + 2));
+        k_ct_expand_v<<<grid(e1), kCtBlock, 0, st>>>(n_pairs, n_vert, bits.vbits, d_pair_verts, sent1, B.key1a, B.val1a,
+                                                     (int32_t *)(B.small + 2));
         if ((s = ok(hipGetLastError(), "contact expand 1")) != BSC_OK) return s;
         tb = B.tmp_bytes;
-        if ((s = ok(rocprim::radix_sort_pairs(B.tmp, tb, B.key1a, B.key1b, B.val1a, B.val1b, e1, 0, unsigned(key1_bits), st),
+        if ((s = ok(rocprim::radix_sort_pairs(B.tmp, tb, B.key1a, B.key1b, B.val1a, B.val1b, e1, 0, 2 * bits.vbits, st),
                     "contact sort 1")) != BSC_OK) return s;
         tb = B.tmp_bytes;
         if ((s = ok(rocprim::run_length_encode(B.tmp, tb, B.key1b, e1, B.ukey1, B.cnt1, B.small, st), "contact runs 1")) != BSC_OK)
@@ -355,51 +500,25 @@ bsc_status bsc_contact_hessian(bsc_ctx *c, int32_t n_pairs, const int32_t *d_pai
             if (last == sent1) --n1;
         }
         if (n1 > c->ct_max_vpairs) return fail(c, BSC_E_NOMEM, "more distinct vertex pairs than max_vpairs");
+        if (n1 > 0) {
+            tb = B.tmp_bytes;
+            if ((s = ok(rocprim::exclusive_scan(B.tmp, tb, B.cnt1, B.off1, u32(0), size_t(n1), rocprim::plus<u32>(), st),
+                        "contact scan 1")) != BSC_OK) return s;
+            k_ct_vpair_sum<<<grid(n1), kCtBlock, 0, st>>>(n1, bits.vbits, bits.ebits, B.ukey1, B.cnt1, B.off1, B.val1b, d_pair_hess,
+                                                          d_grad ? d_pair_grad : nullptr, B.vspan, B.hlin, B.pa, B.pb, B.spk,
+                                                          B.spv, B.glin);
+            if ((s = ok(hipGetLastError(), "contact sum 1")) != BSC_OK) return s;
+        }
     }
     int nnzb = 0;
-    if (n1 > 0) {
-        tb = B.tmp_bytes;
-        if ((s = ok(rocprim::exclusive_scan(B.tmp, tb, B.cnt1, B.off1, u32(0), size_t(n1), rocprim::plus<u32>(), st),
-                    "contact scan 1")) != BSC_OK) return s;
-        k_ct_vpair_sum<<<grid(n1), kCtBlock, 0, st>>>(n1, n_vert, B.ukey1, B.cnt1, B.off1, B.val1b, d_pair_hess,
-                                                      d_grad ? d_pair_grad : nullptr, B.hlin, B.glin);
-        if ((s = ok(hipGetLastError(), "contact sum 1")) != BSC_OK) return s;
-        // 2. CP-pair entries, sorted; runs; sums
-        const unsigned e2 = 81u * unsigned(n1);
-        k_ct_expand_cp<<<grid(e2), kCtBlock, 0, st>>>(n1, n_vert, n_cp, c->n_u, c->Nu, B.ukey1, B.vspan, B.vw, sent2,
-                                                      B.key2a, B.val2a);
-        if ((s = ok(hipGetLastError(), "contact expand 2")) != BSC_OK) return s;
-        tb = B.tmp_bytes;
-        if ((s = ok(rocprim::radix_sort_pairs(B.tmp, tb, B.key2a, B.key2b, B.val2a, B.val2b, e2, 0, unsigned(key2_bits), st),
-                    "contact sort 2")) != BSC_OK) return s;
-        tb = B.tmp_bytes;
-        if ((s = ok(rocprim::run_length_encode(B.tmp, tb, B.key2b, e2, B.ukey2, B.cnt2, B.small + 1, st), "contact runs 2")) != BSC_OK)
-            return s;
-        if ((s = ok(hipMemcpyAsync(host_small, B.small, 16, hipMemcpyDeviceToHost, st), "contact read 2")) != BSC_OK) return s;
-        if ((s = ok(hipStreamSynchronize(st), "contact sync 2")) != BSC_OK) return s;
-        nnzb = int(host_small[1]);
-        u64 last = 0;
-        if (nnzb > 0) {
-            if ((s = ok(hipMemcpy(&last, B.ukey2 + (nnzb - 1), 8, hipMemcpyDeviceToHost), "contact read last")) != BSC_OK) return s;
-            if (last == sent2) --nnzb;
-        }
-        if (nnzb > cap_blocks) {
-            *nnzb_out = nnzb;
-            return fail(c, BSC_E_NOMEM, "more CP blocks than cap_blocks (nnzb holds the count needed)");
-        }
-        if (nnzb > 0) {
-            tb = B.tmp_bytes;
-            if ((s = ok(rocprim::exclusive_scan(B.tmp, tb, B.cnt2, B.off2, u32(0), size_t(nnzb), rocprim::plus<u32>(), st),
-                        "contact scan 2")) != BSC_OK) return s;
-            k_ct_cpair_sum<<<grid(nnzb), kCtBlock, 0, st>>>(nnzb, n_vert, n_cp, B.ukey2, B.cnt2, B.off2, B.val2b, B.ukey1, B.vw,
-                                                            B.hlin, d_col_idx, d_vals);
-            if ((s = ok(hipGetLastError(), "contact sum 2")) != BSC_OK) return s;
-        }
+    s = bits.cp32 ? ct_step2<u32>(c, n1, bits, cap_blocks, d_col_idx, d_vals, d_row_ptr, &nnzb)
+                  : ct_step2<u64>(c, n1, bits, cap_blocks, d_col_idx, d_vals, d_row_ptr, &nnzb);
+    if (s != BSC_OK) {
+        *nnzb_out = nnzb;
+        return s;
     }
-    k_ct_rowptr<<<grid(size_t(n_cp) + 1), kCtBlock, 0, st>>>(n_cp, nnzb, B.ukey2, d_row_ptr);
-    if ((s = ok(hipGetLastError(), "contact row pointers")) != BSC_OK) return s;
     if (d_grad) {
-        k_ct_grad<<<grid(n_cp), kCtBlock, 0, st>>>(c->n_u, c->n_v, c->Nu, c->Nv, B.voff, B.vlist, B.vw, B.glin, d_grad);
+        k_ct_grad<<<grid(c->n_cp), kCtBlock, 0, st>>>(c->n_u, c->n_v, c->Nu, c->Nv, B.voff, B.vlist, B.vw, B.glin, d_grad);
         if ((s = ok(hipGetLastError(), "contact gradient")) != BSC_OK) return s;
     }
     *nnzb_out = nnzb;

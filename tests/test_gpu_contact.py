@@ -4,7 +4,8 @@ conversion and assembly") against the oracle's plain chain-rule products, throug
 The block pattern must equal the oracle's exactly (CP pairs reached by nonzero weight products),
 the CSR must be well formed (row pointers monotone, columns strictly ascending in each row), and
 the block values and the CP gradient must match within 1e-12 (FP64; only the summation order
-differs). Sizes: small sheets with ragged contact sets, knot spacing 2, n_u != n_v, and the full
+differs). Sizes: small sheets with ragged contact sets (including 64 mesh vertices, a power of two,
+where the largest vertex-pair key is closest to the sort sentinel), knot spacing 2, n_u != n_v, and the full
 226 x 226 sheet with a contact mesh of twice its DOFs. Edge cases: no pairs, a vertex index out
 of range, too small an output capacity, too small a vertex-pair capacity."""
 import numpy as np
@@ -59,7 +60,7 @@ def _check(sh, ctx, uv, pv, H, g, tol=1e-12):
     return row_ptr, col, vals, grad
 
 
-@pytest.mark.parametrize("n_u,n_v,n_pairs,spacing", [(12, 12, 300, 1), (17, 9, 500, 2), (40, 31, 2000, 1)])
+@pytest.mark.parametrize("n_u,n_v,n_pairs,spacing", [(6, 6, 40, 1), (12, 12, 300, 1), (17, 9, 500, 2), (40, 31, 2000, 1)])
 def test_contact_conversion_matches_oracle(n_u, n_v, n_pairs, spacing):
     print(f"[contact] {n_u}x{n_v} pairs={n_pairs} spacing={spacing}", flush=True)
     sh, ctx, uv, pv, H, g = _case(n_u, n_v, n_pairs, spacing=spacing)
