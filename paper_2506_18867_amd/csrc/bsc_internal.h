@@ -195,7 +195,8 @@ struct bsc_ctx {
     bool net_loaded = false;
     std::string err;
     // replayable chunk of CG iterations (kernel arguments depend only on the workspace)
-    hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
+    // graphs of 1..8 chunks of CG launches per precision (index [precision][chunks])
+    hipGraphExec_t cg_graph[2][9] = {};
     bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
     float *log_g = nullptr, *log_p = nullptr;
@@ -215,8 +216,9 @@ struct bsc_ctx {
     size_t ct_ws_bytes = 0;
     bsc::ContactBufs ct{};
     ~bsc_ctx() {
-        for (auto &g : cg_graph)
-            if (g) (void)hipGraphExecDestroy(g);
+        for (auto &row : cg_graph)
+            for (auto &g : row)
+                if (g) (void)hipGraphExecDestroy(g);
         for (auto &e : cg_ev)
             if (e) (void)hipEventDestroy(e);
         for (auto &e : ph_ev)

@@ -575,8 +575,9 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     c->net_loaded = false;
     c->log_g = c->log_p = nullptr;
     c->log_cap = c->log_count = 0;
-    for (auto &g : c->cg_graph)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto &row : c->cg_graph)
+        for (auto &g : row)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     DevSheet &S = c->dev;
     S.mp_elem = B.mp_elem; S.mp_off = B.mp_off; S.mp_tu = B.mp_tu; S.mp_tv = B.mp_tv; S.mp_w = B.mp_w;
     S.be_elem = B.be_elem; S.be_off = B.be_off; S.be_tu = B.be_tu; S.be_tv = B.be_tv; S.be_w = B.be_w;

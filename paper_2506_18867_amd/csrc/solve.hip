@@ -1063,39 +1063,45 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                     k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
             }
         };
-        // The chunk is captured once into a graph (on a private stream) and replayed on the
-        // context's stream; its kernel arguments depend only on the bound workspace.
-        hipGraphExec_t &gxe = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1];
-        if (!gxe && ctx->use_graphs) {
-            hipStream_t cs = nullptr;
-            hipGraph_t graph = nullptr;
-            bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-            ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            if (ok) {
-                enqueue_chunk(cs);
-                ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+        // A burst of K chunks (K = 1..8) is one graph of 8K launches, captured the first time it
+        // is needed (on a private stream) and replayed on the context's stream; the kernel
+        // arguments depend only on the bound workspace. One graph launch per burst avoids the
+        // gap between successive graph launches.
+        auto graph_for = [&](int K) -> hipGraphExec_t {
+            hipGraphExec_t &gxe = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1][K];
+            if (!gxe && ctx->use_graphs) {
+                hipStream_t cs = nullptr;
+                hipGraph_t graph = nullptr;
+                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    for (int k = 0; k < K; ++k) enqueue_chunk(cs);
+                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+                }
+                ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+                if (cs) (void)hipStreamDestroy(cs);
+                if (!ok) {
+                    if (gxe) { (void)hipGraphExecDestroy(gxe); gxe = nullptr; }
+                    (void)hipGetLastError();
+                }
             }
-            ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
-            if (graph) (void)hipGraphDestroy(graph);
-            if (cs) (void)hipStreamDestroy(cs);
-            if (!ok) {
-                if (gxe) { (void)hipGraphExecDestroy(gxe); gxe = nullptr; }
-                (void)hipGetLastError();
-            }
-        }
+            return gxe;
+        };
         // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
-        // exit at once). The first burst is two chunks; after each burst the host extrapolates the
-        // residual's geometric decay to the stopping threshold and sizes the next burst to about
-        // nine tenths of the iterations that remain.
+        // exit at once, in about 3 us, while a burst boundary costs a host round trip of tens of
+        // us). The first burst is two chunks; after each burst the host extrapolates the
+        // residual's geometric decay to the stopping threshold and sizes the next burst to cover
+        // the iterations that remain plus half a chunk.
         int burst = 2, done_prev = 0;
         double lrho_prev = 0.0;
         bool have_prev = false;
         while (true) {
             if (evok) HIPX(hipEventRecord(ctx->cg_ev[0], st), "cg event");
-            for (int bi = 0; bi < burst; ++bi) {
-                if (gxe) HIPX(hipGraphLaunch(gxe, st), "cg graph");
-                else enqueue_chunk(st);
-            }
+            hipGraphExec_t gx = graph_for(burst);
+            if (gx) HIPX(hipGraphLaunch(gx, st), "cg graph");
+            else
+                for (int bi = 0; bi < burst; ++bi) enqueue_chunk(st);
             HIPX(hipGetLastError(), "cg");
             if (evok) HIPX(hipEventRecord(ctx->cg_ev[1], st), "cg event");
             HIPX(pull(), "read cg state");
@@ -1122,7 +1128,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 const double rate = (std::log(rho) - lrho_prev) / double(done - done_prev);
                 if (rate < 0.0) {
                     const double remaining = (std::log(tol2) - std::log(rho)) / rate;
-                    burst = std::max(1, std::min(8, int(0.9 * remaining) / chunk));
+                    burst = std::max(1, std::min(8, int(std::ceil((remaining + 0.5 * chunk) / chunk))));
                 }
                 lrho_prev = std::log(rho);
                 done_prev = done;
