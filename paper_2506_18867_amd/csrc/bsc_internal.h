@@ -207,6 +207,8 @@ struct bsc_ctx {
     bool cg_ev_ok = false, cg_ev_tried = false;
     // pinned host buffer for the step's small read-backs (solver scalars followed by the flags)
     char *pinned = nullptr;
+    char *pinned_dev = nullptr;              // its device address (host-mapped, coherent), or null
+    int32_t pub_seq = 0;                     // sequence number of the last published read-back
     // contact mesh embedded in the surface (bsc_contact_setup): per-vertex span and weights
     int ct_nvert = 0, ct_max_pairs = 0, ct_max_vpairs = 0;
     std::vector<int32_t> ct_span, ct_voff, ct_vlist;

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "bsc_internal.h"
 
@@ -799,6 +800,19 @@ __global__ void k_sum2_into(const double *__restrict__ p, int n0, const double *
     if (threadIdx.x == 0) scal[slot] = v;
 }
 
+// Copies the solver scalars and flags into host-mapped coherent pinned memory, then publishes the
+// sequence number seq behind a system-scope fence. The host polls that number instead of waiting
+// for a stream synchronisation, which wakes it sooner.
+__global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal, const int32_t *__restrict__ flags,
+                                                double *host_scal, int32_t *host_flags, int32_t *host_seq, int32_t seq) {
+    const int t = threadIdx.x;
+    if (t < kScalars) host_scal[t] = scal[t];
+    if (t < 8) host_flags[t] = flags[t];
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_update(int n, double alpha, const double *__restrict__ p, double *__restrict__ x) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] += alpha * p[t];
@@ -904,18 +918,53 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const bool evok = ctx->cg_ev_ok;
     // read-backs: the scalars and, right after them in the workspace, the int flags, in one copy
     // into pinned host memory
-    if (!ctx->pinned) HIPX(hipHostMalloc((void **)&ctx->pinned, 1024, hipHostMallocDefault), "pinned host buffer");
+    if (!ctx->pinned) {
+        HIPX(hipHostMalloc((void **)&ctx->pinned, 1024, hipHostMallocMapped | hipHostMallocCoherent), "pinned host buffer");
+        std::memset(ctx->pinned, 0, 1024);
+        if (hipHostGetDevicePointer((void **)&ctx->pinned_dev, ctx->pinned, 0) != hipSuccess) {
+            ctx->pinned_dev = nullptr;
+            (void)hipGetLastError();
+        }
+    }
     if ((const char *)B.iscalars != (const char *)B.scalars + 8 * kScalars) return fail(ctx, BSC_E_STATE, "workspace layout");
     const double *hs = (const double *)ctx->pinned;
     const int32_t *hf = (const int32_t *)(ctx->pinned + 8 * kScalars);
+    // The sequence number sits after the flags. The host spins on it and, every 1024 spins, asks
+    // the runtime whether the stream has failed or gone idle (then the number must be visible;
+    // if it is not, the read-back falls back to a copy and a synchronisation).
+    int32_t *hseq = (int32_t *)(ctx->pinned + 8 * kScalars + 64);
     auto pull = [&]() -> hipError_t {
+        if (ctx->pinned_dev) {
+            if (ctx->pub_seq == 0x7fffffff) ctx->pub_seq = 0;
+            const int32_t seq = ++ctx->pub_seq;
+            k_publish<<<1, 64, 0, st>>>(B.scalars, B.iscalars, (double *)ctx->pinned_dev,
+                                        (int32_t *)(ctx->pinned_dev + 8 * kScalars), (int32_t *)(ctx->pinned_dev + 8 * kScalars + 64),
+                                        seq);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            for (long spin = 1;; ++spin) {
+                if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+                if ((spin & 1023) == 0) {
+                    e = hipStreamQuery(st);
+                    if (e == hipSuccess) {
+                        if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+                        break;
+                    }
+                    if (e != hipErrorNotReady) return e;
+                }
+#if !defined(__HIP_DEVICE_COMPILE__)
+                __builtin_ia32_pause();
+#endif
+            }
+        }
         hipError_t e = hipMemcpyAsync(ctx->pinned, B.scalars, 8 * kScalars + 4 * 8, hipMemcpyDeviceToHost, st);
         return e == hipSuccess ? hipStreamSynchronize(st) : e;
     };
     auto mark = [&](int i) -> hipError_t { return evok ? hipEventRecord(ctx->ph_ev[i], st) : hipSuccess; };
     auto span_ms = [&](int i, int j) -> double {      // both events complete (after a synchronisation)
         float ms = 0.f;
-        if (evok && hipEventElapsedTime(&ms, ctx->ph_ev[i], ctx->ph_ev[j]) != hipSuccess) {
+        if (evok && (hipEventSynchronize(ctx->ph_ev[j]) != hipSuccess ||
+                     hipEventElapsedTime(&ms, ctx->ph_ev[i], ctx->ph_ev[j]) != hipSuccess)) {
             (void)hipGetLastError();
             ms = 0.f;
         }
@@ -1109,6 +1158,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             const double *cgs = hs;
             if (evok) {
                 float ms = 0.f;
+                HIPX(hipEventSynchronize(ctx->cg_ev[1]), "cg event");
                 HIPX(hipEventElapsedTime(&ms, ctx->cg_ev[0], ctx->cg_ev[1]), "cg event time");
                 s.ms_cg_kernels += ms;
             }
