@@ -197,18 +197,22 @@ struct bsc_ctx {
     // replayable chunk of CG iterations (kernel arguments depend only on the workspace)
     // graphs of 1..8 chunks of CG launches per precision (index [precision][chunks])
     hipGraphExec_t cg_graph[2][9] = {};
+    // captured kernel sequences of a Newton iteration, keyed by their launch parameters
+    struct SeqGraph {
+        unsigned char key[64];
+        hipGraphExec_t exec;
+    };
+    std::vector<SeqGraph> seq_graphs;
     bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
     float *log_g = nullptr, *log_p = nullptr;
     int log_cap = 0, log_count = 0;
-    // events around the CG chunks and the step's phases (created at the first Newton step)
-    hipEvent_t cg_ev[2] = {nullptr, nullptr};
-    hipEvent_t ph_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    bool cg_ev_ok = false, cg_ev_tried = false;
+    // timing events of a step (a pool that grows to the largest step; read at the step's end)
+    std::vector<hipEvent_t> ev_pool;
+    bool ev_failed = false;
     // pinned host buffer for the step's small read-backs (solver scalars followed by the flags)
     char *pinned = nullptr;
     char *pinned_dev = nullptr;              // its device address (host-mapped, coherent), or null
-    int32_t pub_seq = 0;                     // sequence number of the last published read-back
     // contact mesh embedded in the surface (bsc_contact_setup): per-vertex span and weights
     int ct_nvert = 0, ct_max_pairs = 0, ct_max_vpairs = 0;
     std::vector<int32_t> ct_span, ct_voff, ct_vlist;
@@ -221,10 +225,8 @@ struct bsc_ctx {
         for (auto &row : cg_graph)
             for (auto &g : row)
                 if (g) (void)hipGraphExecDestroy(g);
-        for (auto &e : cg_ev)
-            if (e) (void)hipEventDestroy(e);
-        for (auto &e : ph_ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto &g : seq_graphs) (void)hipGraphExecDestroy(g.exec);
+        for (auto &e : ev_pool) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
     }
 };

@@ -30,6 +30,7 @@ inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
        S_WS0, S_WS1, S_WS2, S_WS3, S_RHO };
 enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
+constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
 
 constexpr int kRowsPerTile = 64;     // one wave of rows per SpMV block
 constexpr int kGroups = 8;           // waves per SpMV block, one group of block products each
@@ -801,16 +802,26 @@ __global__ void k_sum2_into(const double *__restrict__ p, int n0, const double *
 }
 
 // Copies the solver scalars and flags into host-mapped coherent pinned memory, then publishes the
-// sequence number seq behind a system-scope fence. The host polls that number instead of waiting
-// for a stream synchronisation, which wakes it sooner.
-__global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal, const int32_t *__restrict__ flags,
-                                                double *host_scal, int32_t *host_flags, int32_t *host_seq, int32_t seq) {
+// next sequence number (kept in the device flags, so that the kernel can sit in a replayed
+// graph) behind a system-scope fence. The host polls that number instead of waiting for a
+// stream synchronisation, which wakes it sooner.
+__global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal, int32_t *__restrict__ flags,
+                                                double *host_scal, int32_t *host_flags, int32_t *host_seq) {
     const int t = threadIdx.x;
     if (t < kScalars) host_scal[t] = scal[t];
     if (t < 8) host_flags[t] = flags[t];
+    const int32_t seq = flags[I_PUBSEQ] + 1;
     __threadfence_system();
     __syncthreads();
-    if (t == 0) __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (t == 0) {
+        flags[I_PUBSEQ] = seq;
+        __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__global__ void k_zero(int n, double *__restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = 0.0;
 }
 
 __global__ void k_update(int n, double alpha, const double *__restrict__ p, double *__restrict__ x) {
@@ -869,10 +880,10 @@ struct Timer {
     } while (0)
 
 // Assembles E, g (double) and H (working precision) at x for one Newton iteration.
-bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *xhat, double inv_dt2, const double *grav) {
+bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *xhat, double inv_dt2, const double *grav,
+                         hipStream_t st) {
     const DevSheet &S = ctx->dev;
     const DevBufs &B = ctx->buf;
-    hipStream_t st = ctx->stream;
     // FP32-mixed: the Hessian from FP32 points; the gradient (and energy) from FP64 points
     if (prec == BSC_FP64) {
         HIPX(launch_points(S, B, BSC_FP64, true, false, x, st), "points");
@@ -884,6 +895,48 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st), "assemble");
     HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st), "energy");
     return BSC_OK;
+}
+
+// Runs the kernels that enqueue(stream) launches: from a graph captured the first time this key
+// is seen (on a private stream) and replayed on st, or directly on st when graphs are off or the
+// capture fails. The key holds every launch parameter that is not fixed by the workspace.
+template <typename F>
+hipError_t run_seq(bsc_ctx *ctx, const void *key, size_t klen, hipStream_t st, F &&enqueue) {
+    if (!ctx->use_graphs || klen > sizeof(bsc_ctx::SeqGraph::key)) {
+        enqueue(st);
+        return hipGetLastError();
+    }
+    unsigned char k[sizeof(bsc_ctx::SeqGraph::key)] = {};
+    std::memcpy(k, key, klen);
+    for (const auto &g : ctx->seq_graphs)
+        if (std::memcmp(g.key, k, sizeof(k)) == 0) return hipGraphLaunch(g.exec, st);
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t ge = nullptr;
+    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        enqueue(cs);
+        ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+    }
+    ok = ok && hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (!ok) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGetLastError();
+        enqueue(st);
+        return hipGetLastError();
+    }
+    if (ctx->seq_graphs.size() >= 64) {          // bounded cache: drop the oldest
+        (void)hipGraphExecDestroy(ctx->seq_graphs.front().exec);
+        ctx->seq_graphs.erase(ctx->seq_graphs.begin());
+    }
+    bsc_ctx::SeqGraph g;
+    std::memcpy(g.key, k, sizeof(k));
+    g.exec = ge;
+    ctx->seq_graphs.push_back(g);
+    return hipGraphLaunch(ge, st);
 }
 
 }  // namespace
@@ -907,15 +960,35 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const bool deferred = step_rule && !o->warm_start;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
-    if (!ctx->cg_ev_tried) {
-        ctx->cg_ev_tried = true;
-        bool ok = true;
-        for (auto &e : ctx->cg_ev) ok = ok && hipEventCreate(&e) == hipSuccess;
-        for (auto &e : ctx->ph_ev) ok = ok && hipEventCreate(&e) == hipSuccess;
-        ctx->cg_ev_ok = ok;
-        if (!ok) (void)hipGetLastError();
-    }
-    const bool evok = ctx->cg_ev_ok;
+    // Phase timing: events from a pool, recorded as the step goes and read once at its end (a
+    // read in the middle of the step would wait for the event and delay the next launch).
+    size_t ev_used = 0;
+    auto rec = [&]() -> hipEvent_t {
+        if (ctx->ev_failed) return nullptr;
+        if (ev_used == ctx->ev_pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->ev_failed = true;
+                return nullptr;
+            }
+            ctx->ev_pool.push_back(e);
+        }
+        hipEvent_t e = ctx->ev_pool[ev_used++];
+        if (hipEventRecord(e, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    };
+    struct Span {
+        hipEvent_t a, b;
+        double *acc;
+    };
+    std::vector<Span> spans;
+    auto span = [&](hipEvent_t a, hipEvent_t b, double *acc) {
+        if (a && b) spans.push_back({a, b, acc});
+    };
     // read-backs: the scalars and, right after them in the workspace, the int flags, in one copy
     // into pinned host memory
     if (!ctx->pinned) {
@@ -929,47 +1002,43 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     if ((const char *)B.iscalars != (const char *)B.scalars + 8 * kScalars) return fail(ctx, BSC_E_STATE, "workspace layout");
     const double *hs = (const double *)ctx->pinned;
     const int32_t *hf = (const int32_t *)(ctx->pinned + 8 * kScalars);
-    // The sequence number sits after the flags. The host spins on it and, every 1024 spins, asks
-    // the runtime whether the stream has failed or gone idle (then the number must be visible;
-    // if it is not, the read-back falls back to a copy and a synchronisation).
+    // The sequence number sits after the flags. The host records it, enqueues work that ends in
+    // k_publish, and spins until it moves on; every 1024 spins it asks the runtime whether the
+    // stream has failed or gone idle (then the number must have moved; if it has not, the
+    // read-back falls back to a copy and a synchronisation).
     int32_t *hseq = (int32_t *)(ctx->pinned + 8 * kScalars + 64);
-    auto pull = [&]() -> hipError_t {
-        if (ctx->pinned_dev) {
-            if (ctx->pub_seq == 0x7fffffff) ctx->pub_seq = 0;
-            const int32_t seq = ++ctx->pub_seq;
-            k_publish<<<1, 64, 0, st>>>(B.scalars, B.iscalars, (double *)ctx->pinned_dev,
-                                        (int32_t *)(ctx->pinned_dev + 8 * kScalars), (int32_t *)(ctx->pinned_dev + 8 * kScalars + 64),
-                                        seq);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            for (long spin = 1;; ++spin) {
-                if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
-                if ((spin & 1023) == 0) {
-                    e = hipStreamQuery(st);
-                    if (e == hipSuccess) {
-                        if (__atomic_load_n(hseq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
-                        break;
-                    }
-                    if (e != hipErrorNotReady) return e;
-                }
-#if !defined(__HIP_DEVICE_COMPILE__)
-                __builtin_ia32_pause();
-#endif
-            }
-        }
+    const bool pub = ctx->pinned_dev != nullptr;
+    auto seen = [&]() { return __atomic_load_n(hseq, __ATOMIC_ACQUIRE); };
+    auto publish = [&](hipStream_t cs) {
+        k_publish<<<1, 64, 0, cs>>>(B.scalars, B.iscalars, (double *)ctx->pinned_dev, (int32_t *)(ctx->pinned_dev + 8 * kScalars),
+                                    (int32_t *)(ctx->pinned_dev + 8 * kScalars + 64));
+    };
+    auto copy_sync = [&]() -> hipError_t {
         hipError_t e = hipMemcpyAsync(ctx->pinned, B.scalars, 8 * kScalars + 4 * 8, hipMemcpyDeviceToHost, st);
         return e == hipSuccess ? hipStreamSynchronize(st) : e;
     };
-    auto mark = [&](int i) -> hipError_t { return evok ? hipEventRecord(ctx->ph_ev[i], st) : hipSuccess; };
-    auto span_ms = [&](int i, int j) -> double {      // both events complete (after a synchronisation)
-        float ms = 0.f;
-        if (evok && (hipEventSynchronize(ctx->ph_ev[j]) != hipSuccess ||
-                     hipEventElapsedTime(&ms, ctx->ph_ev[i], ctx->ph_ev[j]) != hipSuccess)) {
-            (void)hipGetLastError();
-            ms = 0.f;
+    auto wait_pub = [&](int32_t last) -> hipError_t {
+        for (long spin = 1;; ++spin) {
+            if (seen() != last) return hipSuccess;
+            if ((spin & 1023) == 0) {
+                const hipError_t e = hipStreamQuery(st);
+                if (e == hipSuccess) return seen() != last ? hipSuccess : copy_sync();
+                if (e != hipErrorNotReady) return e;
+            }
+#if !defined(__HIP_DEVICE_COMPILE__)
+            __builtin_ia32_pause();
+#endif
         }
-        return ms;
     };
+    auto pull = [&]() -> hipError_t {
+        if (!pub) return copy_sync();
+        const int32_t last = seen();
+        publish(st);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? wait_pub(last) : e;
+    };
+    // keys of the captured sequences: launch parameters as 64-bit words
+    auto bits = [](double d) { uint64_t u; std::memcpy(&u, &d, 8); return u; };
 
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
@@ -984,20 +1053,23 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     int it = 0;
     for (;; ++it) {
         // ---- assembly: E, g, H at x ---------------------------------------------------------
-        HIPX(mark(0), "event");
+        hipEvent_t e0 = rec();
         {
-            bsc_status as = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav);
-            if (as != BSC_OK) return as;
+            const uint64_t key[8] = {1, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
+                                     bits(gz), 0};
+            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
+                     (void)assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, cs);
+                     k_dot_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.g, B.g, B.partials + 7 * stride);
+                     k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
+                 }), "assembly");
         }
-        k_dot_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.g, B.partials + 7 * stride);
-        k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
-        HIPX(mark(1), "event");
+        hipEvent_t e1 = rec();
         int eta_mode = ETA_EXPLICIT;
         if (!deferred) {
             HIPX(pull(), "read norms");
             host[0] = hs[S_E];
             host[1] = hs[S_GG];
-            s.ms_assemble += span_ms(0, 1);
+            span(e0, e1, &s.ms_assemble);
             const double E = host[0], gn = std::sqrt(host[1]);
             if (!std::isfinite(E) || !std::isfinite(gn)) { result = BSC_E_NONFINITE; break; }
             if (g0 < 0.0) g0 = gn;
@@ -1030,7 +1102,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 host[1] = hs[S_GG];
                 s.energy = host[0];
                 s.g_norm = std::sqrt(host[1]);
-                s.ms_assemble += span_ms(0, 1);
+                span(e0, e1, &s.ms_assemble);
                 result = std::isfinite(host[0]) && std::isfinite(host[1]) ? BSC_E_NOT_CONVERGED : BSC_E_NONFINITE;
                 break;
             }
@@ -1039,11 +1111,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         }
 
         // ---- direction: PCG on H p = -g -----------------------------------------------------
-        HIPX(mark(2), "event");
-        if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const double *)B.hess, B.pinv);
-        else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv);
-        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);          // b = -g
-        HIPX(hipMemsetAsync(B.dir, 0, 8 * size_t(n3), st), "zero dir");
+        hipEvent_t e2 = rec();
         // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
         // is recomputed where it is needed)
         double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
@@ -1051,40 +1119,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
         const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
         double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
-        const double *q0 = nullptr;
-        if (o->warm_start) {
-            // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
-            // kept only when |b - H x0| < |b| (else zero start)
-            Timer tw(st);
-            k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
-            HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
-                                  B.net_scale, B.net_w_fwd, true, st), "warm start forward");
-            k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
-            HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
-            k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
-            k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
-            HIPX(hipGetLastError(), "warm start");
-            HIPX(pull(), "read ws");
-            const double gp = hs[S_WS0], pw = hs[S_WS1], gw = hs[S_WS2], ww = hs[S_WS3], bb = host[1];
-            bool use = false;
-            if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
-                // energy-optimal multiple of p_hat (either sign: the training loss fixes the
-                // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
-                const double as = -gp / pw;
-                const double rr = bb + 2.0 * as * gw + as * as * ww;
-                if (as != 0.0 && rr < bb) {
-                    use = true;
-                    k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
-                    k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
-                }
-            }
-            if (use) s.warm_start_used++;
-            else s.warm_start_fallbacks++;
-            s.ms_warmstart += tw.stop();
-            q0 = use ? hq : nullptr;
-        }
-        k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, q0, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
-                                           eta_mode, it == 0 ? 1 : 0, eta, o->pcg_rtol);
         auto bufs = [&](int j) {
             CgBufs c{};
             c.x = B.dir; c.p = p; c.pinv = B.pinv;
@@ -1097,11 +1131,68 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
             return c;
         };
-        if (prec == BSC_FP64)
-            k_cg_fused<double, true><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
-        else
-            k_cg_fused<float, true><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
-        HIPX(hipGetLastError(), "cg init");
+        const int first = it == 0 ? 1 : 0;
+        const double eta_arg = eta_mode == ETA_EXPLICIT ? eta : 0.0;     // used by the explicit mode only
+        // block-Jacobi inverse, b = -g, x0 = 0
+        auto enqueue_prep = [&](hipStream_t cs) {
+            if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, B.pinv);
+            else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv);
+            k_axpby<<<blocks(n3), kBlock, 0, cs>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);
+            k_zero<<<blocks(n3), kBlock, 0, cs>>>(n3, B.dir);
+        };
+        // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
+        auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
+            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, q0_, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode,
+                                               first, eta_arg, o->pcg_rtol);
+            if (prec == BSC_FP64)
+                k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+            else
+                k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+        };
+        if (!o->warm_start) {
+            const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
+                                     uint64_t(o->max_pcg), 0};
+            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
+                     enqueue_prep(cs);
+                     enqueue_init(cs, nullptr);
+                 }), "cg init");
+        } else {
+            enqueue_prep(st);
+            const double *q0 = nullptr;
+            {
+                // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
+                // kept only when |b - H x0| < |b| (else zero start)
+                Timer tw(st);
+                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
+                HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
+                                      B.net_scale, B.net_w_fwd, true, st), "warm start forward");
+                k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
+                HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
+                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
+                k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
+                HIPX(hipGetLastError(), "warm start");
+                HIPX(pull(), "read ws");
+                const double gp = hs[S_WS0], pw = hs[S_WS1], gw = hs[S_WS2], ww = hs[S_WS3], bb = host[1];
+                bool use = false;
+                if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
+                    // energy-optimal multiple of p_hat (either sign: the training loss fixes the
+                    // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
+                    const double as = -gp / pw;
+                    const double rr = bb + 2.0 * as * gw + as * as * ww;
+                    if (as != 0.0 && rr < bb) {
+                        use = true;
+                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
+                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
+                    }
+                }
+                if (use) s.warm_start_used++;
+                else s.warm_start_fallbacks++;
+                s.ms_warmstart += tw.stop();
+                q0 = use ? hq : nullptr;
+            }
+            enqueue_init(st, q0);
+            HIPX(hipGetLastError(), "cg init");
+        }
         int32_t flags[6] = {0, 0, 0, 0, 0, 0};
         const int chunk = 8;                    // even: every chunk starts on an odd launch
         auto enqueue_chunk = [&](hipStream_t cs) {
@@ -1125,6 +1216,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
                 if (ok) {
                     for (int k = 0; k < K; ++k) enqueue_chunk(cs);
+                    if (pub) publish(cs);
                     ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
                 }
                 ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -1146,22 +1238,20 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         double lrho_prev = 0.0;
         bool have_prev = false;
         while (true) {
-            if (evok) HIPX(hipEventRecord(ctx->cg_ev[0], st), "cg event");
+            hipEvent_t c0 = rec();
+            const int32_t last = seen();
             hipGraphExec_t gx = graph_for(burst);
-            if (gx) HIPX(hipGraphLaunch(gx, st), "cg graph");
-            else
+            if (gx) {
+                HIPX(hipGraphLaunch(gx, st), "cg graph");
+            } else {
                 for (int bi = 0; bi < burst; ++bi) enqueue_chunk(st);
+                if (pub) publish(st);
+            }
             HIPX(hipGetLastError(), "cg");
-            if (evok) HIPX(hipEventRecord(ctx->cg_ev[1], st), "cg event");
-            HIPX(pull(), "read cg state");
+            span(c0, rec(), &s.ms_cg_kernels);
+            HIPX(pub ? wait_pub(last) : copy_sync(), "read cg state");
             for (int k = 0; k < 6; ++k) flags[k] = hf[k];
             const double *cgs = hs;
-            if (evok) {
-                float ms = 0.f;
-                HIPX(hipEventSynchronize(ctx->cg_ev[1]), "cg event");
-                HIPX(hipEventElapsedTime(&ms, ctx->cg_ev[0], ctx->cg_ev[1]), "cg event time");
-                s.ms_cg_kernels += ms;
-            }
             s.cg_launches += chunk * burst;
             if (flags[I_DONE]) break;
             // iterations done so far: the launches of the bursts minus the first (which forms w_0)
@@ -1184,7 +1274,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 done_prev = done;
             }
         }
-        HIPX(mark(3), "event");
+        hipEvent_t e3 = rec();
         s.cg_active_launches += flags[I_ITERS];
         s.pcg_iters_total += flags[I_ITERS];
         if (flags[I_BREAK]) { result = BSC_E_PCG_BREAKDOWN; break; }
@@ -1199,26 +1289,33 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // ---- |p|_inf for the step rule, line-search coefficients and the trial at alpha = 1 ---
         // The energy difference along p: the inertia, gravity and bending terms are quadratics in
         // alpha (coefficients c1, c2), the membrane term is summed point by point.
-        HIPX(mark(4), "event");
-        if (step_rule) {
-            k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.dir, B.partials + 7 * stride);
-            k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
+        hipEvent_t e4 = rec(), e5 = nullptr;
+        {
+            double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
+            const int32_t last = seen();
+            const uint64_t key[8] = {3, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
+                                     bits(gz), uint64_t(step_rule ? 1 : 0) | (pub ? 2u : 0u)};
+            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
+                     if (step_rule) {
+                         k_absmax_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.dir, B.partials + 7 * stride);
+                         k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
+                     }
+                     k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
+                     k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pb, stride);
+                     k_sum2_into<<<1, kBlock, 0, cs>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
+                     k_sum2_into<<<1, kBlock, 0, cs>>>(pa + stride, blocks(S.n_cp), pb + stride, blocks(S.n_be), B.scalars, S_C2);
+                     k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials + 6 * stride);
+                     k_sum_into<<<1, kBlock, 0, cs>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
+                     if (pub) publish(cs);
+                 }), "line search setup");
+            e5 = rec();
+            HIPX(pub ? wait_pub(last) : copy_sync(), "read scalars");
         }
-        double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
-        k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
-        k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, B.dir, pb, stride);
-        k_sum2_into<<<1, kBlock, 0, st>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
-        k_sum2_into<<<1, kBlock, 0, st>>>(pa + stride, blocks(S.n_cp), pb + stride, blocks(S.n_be), B.scalars, S_C2);
-        k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, 1.0, B.partials + 6 * stride);
-        k_sum_into<<<1, kBlock, 0, st>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
-        HIPX(hipGetLastError(), "line search setup");
-        HIPX(mark(5), "event");
-        HIPX(pull(), "read scalars");
         double sc[S_GPREV - S_E + 1];
         for (int k = S_E; k <= S_GPREV; ++k) sc[k - S_E] = hs[k];
-        if (deferred) s.ms_assemble += span_ms(0, 1);
-        s.ms_pcg += span_ms(2, 3);
-        s.ms_linesearch += span_ms(4, 5);
+        if (deferred) span(e0, e1, &s.ms_assemble);
+        span(e2, e3, &s.ms_pcg);
+        span(e4, e5, &s.ms_linesearch);
         auto scal = [&](int i) { return sc[i - S_E]; };
         if (deferred) {
             const double E = scal(S_E), gn = std::sqrt(scal(S_GG));
@@ -1264,6 +1361,11 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0 / dt, x, -1.0 / dt, B.xn, v);
     HIPX(hipGetLastError(), "velocity");
     HIPX(hipStreamSynchronize(st), "sync end");
+    for (const Span &sp : spans) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
+        else (void)hipGetLastError();
+    }
     s.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (stats) *stats = s;
     return result;
