@@ -81,6 +81,8 @@ def parse():
     p.add_argument("--pcg-rtol", type=float, default=1e-3)
     p.add_argument("--grad-steps", type=int, default=2, help="steps of the |g|<=1e-6|g0| leg (0: skip)")
     p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
+    p.add_argument("--precond", choices=["jacobi", "mg"], default="jacobi",
+                   help="PCG preconditioner: block Jacobi (fused kernel) or the multigrid V-cycle")
     p.add_argument("--quad-steps", type=int, default=3,
                    help="steps of the quadrature-ablation leg (reduced vs 2x2 interior rule; 0: skip)")
     p.add_argument("--general-steps", type=int, default=3,
@@ -115,7 +117,9 @@ def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
     opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=args.rtol,
                          atol=args.atol, stop_mode=bsc.BSC_STOP_GRAD if args.stop == "grad" else bsc.BSC_STOP_STEP,
                          pcg_rtol=args.pcg_rtol, max_newton=args.max_newton, max_pcg=4000,
-                         pcg_adaptive=getattr(args, "adaptive", 0))
+                         pcg_adaptive=getattr(args, "adaptive", 0),
+                         preconditioner=bsc.BSC_PRECOND_MULTIGRID if getattr(args, "precond", "jacobi") == "mg"
+                         else bsc.BSC_PRECOND_JACOBI)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -203,6 +207,7 @@ def main():
         ga = _A()
         ga.rtol, ga.atol, ga.stop, ga.pcg_rtol, ga.max_newton = 1e-6, args.atol, "grad", args.pcg_rtol, args.max_newton
         ga.adaptive = args.adaptive
+        ga.precond = args.precond
         grad_leg = {}
         for name, prec in (("fp32_mixed", bsc.BSC_FP32_MIXED), ("fp64", bsc.BSC_FP64)):
             xg, vg = x0.clone(), v0.clone()

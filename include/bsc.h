@@ -91,6 +91,12 @@ typedef struct {
  *   pcg_adaptive: 1 chooses the PCG tolerance per Newton iteration by the Eisenstat-Walker rule
  *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2, clamped to [pcg_rtol, 0.1] (eta_0 = 0.1); with
  *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
+/* PCG preconditioners. JACOBI: 3x3 block Jacobi, one fused kernel per iteration. MULTIGRID: one
+ * symmetric V(1,1) cycle on the hierarchy of the patch's knot halvings (exact B-spline
+ * prolongation, Galerkin coarse operators, damped block-Jacobi smoothing); used when both span
+ * counts are even (otherwise, and with the warm start, the step falls back to JACOBI). */
+enum { BSC_PRECOND_JACOBI = 0, BSC_PRECOND_MULTIGRID = 1 };
+
 typedef struct {
     double dt;
     double gravity[3];
@@ -102,6 +108,7 @@ typedef struct {
     int32_t warm_start;
     int32_t fixed_newton_iters;
     int32_t pcg_adaptive;
+    int32_t preconditioner;     /* BSC_PRECOND_JACOBI (default) or BSC_PRECOND_MULTIGRID */
 } bsc_step_opts;
 
 /* Statistics of one step. ms_* are wall-clock phase times on the host (each phase ends with a

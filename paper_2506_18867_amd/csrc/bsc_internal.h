@@ -57,6 +57,21 @@ __host__ __device__ inline int upper_slot(int di, int dj) {
     return 3 + (dj - 1) * 5 + (di + 2);
 }
 
+// Solver scalars (doubles) and flags (int32) in the workspace, shared by the solvers and read
+// back by the host in one copy.
+enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
+       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_MGRHO0 = 40, S_MGRHO1 = 41 };
+enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
+constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
+
+// Multigrid levels below the fine grid (knot halvings), at most kMgMaxLevels.
+constexpr int kMgMaxLevels = 6;
+struct MgLevel {
+    int n_u, n_v;
+    void *H, *pinv, *Hmid;                   // Galerkin operator, its block-Jacobi inverse, the u-pass result
+    double *r, *xa, *xb, *t;                 // restricted residual, smoothed iterate, level output, residual
+};
+
 // Everything a kernel needs to know about the sheet (passed by value).
 struct DevSheet {
     int n_u, n_v, Nu, Nv, n_cp, n_elem, n_mp, n_be;
@@ -156,6 +171,10 @@ struct DevBufs {
     float *net_w, *net_w_fwd, *net_wr, *net_in, *net_out, *net_act0, *net_act1, *net_scale;
     double *net_lpart;                        // loss partials: 1024 samples x 64 blocks x 3
     int max_blocks;
+    // multigrid hierarchy (mg_levels = 0: not available for this grid)
+    int mg_levels;
+    MgLevel mg[kMgMaxLevels];
+    double *mg_x0, *mg_t0;                   // fine-level smoother vectors
 };
 
 // Contact-mesh conversion buffers (one caller-owned workspace, see contact.hip).
@@ -197,6 +216,7 @@ struct bsc_ctx {
     // replayable chunk of CG iterations (kernel arguments depend only on the workspace)
     // graphs of 1..8 chunks of CG launches per precision (index [precision][chunks])
     hipGraphExec_t cg_graph[2][9] = {};
+    hipGraphExec_t mg_graph[2][9] = {};      // the same for multigrid-preconditioned CG iterations
     // captured kernel sequences of a Newton iteration, keyed by their launch parameters
     struct SeqGraph {
         unsigned char key[64];
@@ -225,6 +245,9 @@ struct bsc_ctx {
         for (auto &row : cg_graph)
             for (auto &g : row)
                 if (g) (void)hipGraphExecDestroy(g);
+        for (auto &row : mg_graph)
+            for (auto &g : row)
+                if (g) (void)hipGraphExecDestroy(g);
         for (auto &g : seq_graphs) (void)hipGraphExecDestroy(g.exec);
         for (auto &e : ev_pool) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
@@ -237,6 +260,10 @@ bsc_status fail(bsc_ctx *ctx, bsc_status st, const std::string &msg);
 bsc_status hip_check(bsc_ctx *ctx, hipError_t e, const char *what);
 size_t layout_workspace(const bsc_ctx *ctx, DevBufs *b, char *base);
 size_t contact_layout(const bsc_ctx *ctx, ContactBufs *b, char *base);
+int mg_level_count(int n_u, int n_v);
+hipError_t mg_setup(const DevSheet &S, const DevBufs &B, int prec, hipStream_t st);
+hipError_t mg_cg_iteration(const DevSheet &S, const DevBufs &B, int prec, double *r, double *z, double *p, double *q,
+                           double *rz_part, double *pq_part, double *rr_part, hipStream_t st);
 size_t contact_tmp_bytes(int max_pairs, int max_vpairs);
 // Quadratic B-spline pieces on a span (type 0 first, 1 inner, 2 last), local t in [0, 1].
 void host_pieces(int type, double t, double N[3], double D[3], double D2[3]);

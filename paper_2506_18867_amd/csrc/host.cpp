@@ -271,6 +271,27 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2};
     for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
     t.pinv = (double *)take(8 * 6 * ncp);
+    t.mg_x0 = t.r2;                                // unused by the multigrid solver otherwise
+    t.mg_t0 = t.q2;
+    t.mg_levels = mg_level_count(c->n_u, c->n_v);
+    {
+        int nuf = c->n_u, nvf = c->n_v;
+        for (int l = 0; l < t.mg_levels; ++l) {
+            MgLevel &L = t.mg[l];
+            L.n_u = (nuf - 2) / 2 + 2;
+            L.n_v = (nvf - 2) / 2 + 2;
+            const size_t nl = size_t(L.n_u) * L.n_v;
+            L.H = take(8 * size_t(kHessEntries) * nl);
+            L.pinv = take(8 * 6 * nl);
+            L.Hmid = take(8 * size_t(kHessEntries) * size_t(L.n_u) * nvf);
+            L.r = (double *)take(24 * nl);
+            L.xa = (double *)take(24 * nl);
+            L.xb = (double *)take(24 * nl);
+            L.t = (double *)take(24 * nl);
+            nuf = L.n_u;
+            nvf = L.n_v;
+        }
+    }
     t.hess = take(8 * size_t(kHessEntries) * ncp);
     t.net_w = (float *)take(4 * BSC_NET_PARAMS);
     t.net_w_fwd = (float *)take(4 * BSC_NET_PARAMS);
@@ -576,6 +597,9 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     c->log_g = c->log_p = nullptr;
     c->log_cap = c->log_count = 0;
     for (auto &row : c->cg_graph)
+        for (auto &g : row)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto &row : c->mg_graph)
         for (auto &g : row)
             if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     for (auto &g : c->seq_graphs) (void)hipGraphExecDestroy(g.exec);

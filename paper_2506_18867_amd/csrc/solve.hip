@@ -27,10 +27,6 @@ namespace {
 
 inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 
-enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
-       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO };
-enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
-constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
 
 constexpr int kRowsPerTile = 64;     // one wave of rows per SpMV block
 constexpr int kGroups = 8;           // waves per SpMV block, one group of block products each
@@ -958,6 +954,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     // the assembly: the PCG tolerance is formed on the device and E, |g| are read back with |p|
     // and the line search's first trial after the solve, in one synchronisation.
     const bool deferred = step_rule && !o->warm_start;
+    const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !o->warm_start;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
     // Phase timing: events from a pool, recorded as the step goes and read once at its end (a
@@ -1149,7 +1146,19 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             else
                 k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
         };
-        if (!o->warm_start) {
+        if (use_mg) {
+            // multigrid: Galerkin hierarchy and block-Jacobi inverses of every level, then r = b,
+            // p = 0, the flags and the tolerance (the first iteration's stop test sets |b|-relative
+            // tolerance from the partials of |b|^2)
+            const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
+                                     uint64_t(o->max_pcg), 1};
+            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
+                     enqueue_prep(cs);
+                     (void)mg_setup(S, B, prec, cs);
+                     k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
+                                                        eta_mode, first, eta_arg, o->pcg_rtol);
+                 }), "mg init");
+        } else if (!o->warm_start) {
             const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
                                      uint64_t(o->max_pcg), 0};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
@@ -1194,8 +1203,14 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             HIPX(hipGetLastError(), "cg init");
         }
         int32_t flags[6] = {0, 0, 0, 0, 0, 0};
-        const int chunk = 8;                    // even: every chunk starts on an odd launch
+        // a chunk: 8 fused block-Jacobi CG launches (even: every chunk starts on an odd launch),
+        // or one multigrid-preconditioned CG iteration
+        const int chunk = use_mg ? 1 : 8;
         auto enqueue_chunk = [&](hipStream_t cs) {
+            if (use_mg) {
+                (void)mg_cg_iteration(S, B, prec, rb[0], sb[0], p, wb[0], B.partials, B.partials + stride, pbb, cs);
+                return;
+            }
             for (int c = 1; c <= chunk; ++c) {
                 if (prec == BSC_FP64)
                     k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
@@ -1208,7 +1223,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // arguments depend only on the bound workspace. One graph launch per burst avoids the
         // gap between successive graph launches.
         auto graph_for = [&](int K) -> hipGraphExec_t {
-            hipGraphExec_t &gxe = ctx->cg_graph[prec == BSC_FP64 ? 0 : 1][K];
+            hipGraphExec_t &gxe = (use_mg ? ctx->mg_graph : ctx->cg_graph)[prec == BSC_FP64 ? 0 : 1][K];
             if (!gxe && ctx->use_graphs) {
                 hipStream_t cs = nullptr;
                 hipGraph_t graph = nullptr;
