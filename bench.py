@@ -364,7 +364,7 @@ def main():
         "config": {"workload": f"driven sheet {args.n}x{args.n} CPs ({ne} elements), E=1e4 Pa, t=1 mm, dt=0.01 s, "
                                + (f"|g|<={args.rtol:g}|g0|" if args.stop == "grad" else f"|p|inf/dt<={args.atol:g}")
                                + ", FP32-mixed", "n_cp": n, "n_elem": ne, "seed": args.seed, "noise": args.noise,
-                   "pcg": "block-Jacobi PCG, " + ("Eisenstat-Walker tolerance in [%g, 0.1]" % args.pcg_rtol if args.adaptive
+                   "pcg": "block-Jacobi PCG, " + ("Eisenstat-Walker tolerance in [%g, 0.5]" % args.pcg_rtol if args.adaptive
                                                   else "fixed tolerance %g" % args.pcg_rtol),
                    "parallelism": "single GPU"},
         "newton_step_ms": {"fp32_mixed": round(ms_step32, 3),

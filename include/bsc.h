@@ -89,7 +89,9 @@ typedef struct {
  *   pcg_rtol: PCG stops when |r|_2 <= pcg_rtol |g|_2. warm_start: 1 uses the loaded network as
  *   the PCG initial guess (falls back to zero when it does not reduce the residual).
  *   pcg_adaptive: 1 chooses the PCG tolerance per Newton iteration by the Eisenstat-Walker rule
- *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2, clamped to [pcg_rtol, 0.1] (eta_0 = 0.1); with
+ *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2 (not below 0.9 eta_{k-1}^2 when that exceeds 0.1),
+ *   clamped to [pcg_rtol, eta_max] (eta_0 = eta_max), eta_max = 0.5 under BSC_STOP_STEP and
+ *   0.1 under BSC_STOP_GRAD; with
  *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
 /* PCG preconditioners. JACOBI: 3x3 block Jacobi, one fused kernel per iteration. MULTIGRID: one
  * symmetric V(1,1) cycle on the hierarchy of the patch's knot halvings (exact B-spline

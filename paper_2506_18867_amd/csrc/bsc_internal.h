@@ -63,6 +63,10 @@ enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2
        S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_MGRHO0 = 40, S_MGRHO1 = 41 };
 enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
 constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
+// Largest PCG relative tolerance of the Eisenstat-Walker forcing term (and its first value):
+// loose under the step-length stopping rule, tighter under the gradient rule, which has to reach
+// the region of fast local convergence.
+constexpr double kEtaMaxStep = 0.5, kEtaMaxGrad = 0.1;
 
 // Multigrid levels below the fine grid (knot halvings), at most kMgMaxLevels.
 constexpr int kMgMaxLevels = 6;
@@ -274,7 +278,7 @@ DevSheet dev_sheet(const bsc_ctx *ctx);
 // tiled assembly of the per-CP gradient and (hess != NULL) the upper-stencil Hessian blocks
 // (kind: AsmKind); energy reduction (n_cp_partials: the assembly's tile count, or 0).
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
-                         const double *x, hipStream_t st);
+                         const double *x, hipStream_t st, bool bending);
 int assemble_tiles(const DevSheet &S, int kind);
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
                            double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st);

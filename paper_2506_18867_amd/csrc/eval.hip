@@ -869,7 +869,7 @@ inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 }  // namespace
 
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
-                         const double *x, hipStream_t st) {
+                         const double *x, hipStream_t st, bool bending) {
     // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch.
     double *pm = B.partials, *pb = B.partials + B.max_blocks;
     auto go = [&](auto curved) {
@@ -886,7 +886,7 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
             else
                 k_membrane<float, false, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
         }
-        k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+        if (bending) k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
@@ -953,7 +953,7 @@ bsc_status bsc_eval_egh(bsc_ctx *c, int32_t precision, const double *d_x, double
     if (!d_x || !d_energy) return fail(c, BSC_E_INVAL, "null pointer");
     if (precision != BSC_FP64 && precision != BSC_FP32_MIXED) return fail(c, BSC_E_INVAL, "bad precision");
     const DevSheet &S = c->dev;
-    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_elem_hess != nullptr, false, d_x, c->stream), "eval points");
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_elem_hess != nullptr, false, d_x, c->stream, true), "eval points");
     if (st != BSC_OK) return st;
     st = hip_check(c, launch_energy_reduce(S, c->buf, 0, d_energy, c->stream), "energy reduce");
     if (st != BSC_OK) return st;
@@ -972,7 +972,7 @@ bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const 
         inv_dt2 = 1.0 / (dt * dt);
     }
     const DevSheet &S = c->dev;
-    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream), "eval points");
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream, true), "eval points");
     if (st != BSC_OK) return st;
     const int kind = precision == BSC_FP64 ? kAsmF64 : kAsmF32;
     st = hip_check(c, launch_assemble(S, c->buf, kind, d_x, d_xhat, inv_dt2, gravity, d_grad, d_hess, c->stream), "assemble");

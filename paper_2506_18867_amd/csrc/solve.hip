@@ -312,23 +312,24 @@ __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, T *__restric
 // assembly from the solve.
 enum { ETA_EXPLICIT = 0, ETA_FIXED = 1, ETA_ADAPTIVE = 2, ETA_TIGHT = 3 };
 
-__device__ double forcing_term(int mode, int first, double eta_host, double rtol_min, double gn, double g_prev,
+__device__ double forcing_term(int mode, int first, double eta_host, double rtol_min, double eta_max, double gn, double g_prev,
                                double eta_prev) {
     if (mode == ETA_EXPLICIT) return eta_host;
     if (mode != ETA_ADAPTIVE) return rtol_min;
-    if (first) return fmax(rtol_min, 0.1);
+    if (first) return fmax(rtol_min, eta_max);
     const double ratio = gn / g_prev;
     double e = 0.9 * ratio * ratio;
     const double guard = 0.9 * eta_prev * eta_prev;
     if (guard > 0.1) e = fmax(e, guard);
-    return fmin(0.1, fmax(rtol_min, e));
+    return fmin(eta_max, fmax(rtol_min, e));
 }
 
 // r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b; the solve's tolerance.
 __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
                                                     double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
-                                                    int eta_mode, int first, double eta_host, double rtol_min) {
+                                                    int eta_mode, int first, double eta_host, double rtol_min,
+                                                    double eta_max) {
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
@@ -347,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         isc[I_DONE] = 0; isc[I_ITA] = 0; isc[I_ITB] = 0; isc[I_BREAK] = 0; isc[I_MAXIT] = maxit; isc[I_ITERS] = 0;
         const double gn = sqrt(scal[S_GG]);
-        const double eta = forcing_term(eta_mode, first, eta_host, rtol_min, gn, scal[S_GPREV], scal[S_ETA]);
+        const double eta = forcing_term(eta_mode, first, eta_host, rtol_min, eta_max, gn, scal[S_GPREV], scal[S_ETA]);
         scal[S_RTOL] = eta;
         scal[S_ETA] = eta;
         scal[S_GPREV] = gn;
@@ -882,10 +883,11 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     const DevBufs &B = ctx->buf;
     // FP32-mixed: the Hessian from FP32 points; the gradient (and energy) from FP64 points
     if (prec == BSC_FP64) {
-        HIPX(launch_points(S, B, BSC_FP64, true, false, x, st), "points");
+        HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true), "points");
     } else {
-        HIPX(launch_points(S, B, BSC_FP32_MIXED, true, false, x, st), "points32");
-        HIPX(launch_points(S, B, BSC_FP64, false, true, x, st), "points64");
+        // (the bending evaluations are FP64 in both passes: once is enough)
+        HIPX(launch_points(S, B, BSC_FP32_MIXED, true, false, x, st, true), "points32");
+        HIPX(launch_points(S, B, BSC_FP64, false, true, x, st, false), "points64");
     }
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
     HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st), "assemble");
@@ -1044,7 +1046,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
     bsc_status result = BSC_OK;
     double g0 = -1.0, g_prev = -1.0;
-    double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, 0.1) : o->pcg_rtol;   // PCG tolerance (host-side modes)
+    const double eta_max = step_rule ? kEtaMaxStep : kEtaMaxGrad;
+    double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, eta_max) : o->pcg_rtol;   // PCG tolerance (host-side modes)
     bool force_tight = false;
     double host[2];
     int it = 0;
@@ -1089,7 +1092,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 double e = 0.9 * ratio * ratio;
                 const double guard = 0.9 * eta * eta;
                 if (guard > 0.1) e = std::max(e, guard);
-                eta = std::min(0.1, std::max(o->pcg_rtol, e));
+                eta = std::min(eta_max, std::max(o->pcg_rtol, e));
             }
             g_prev = gn;
         } else {
@@ -1140,7 +1143,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
         auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
             k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, q0_, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode,
-                                               first, eta_arg, o->pcg_rtol);
+                                               first, eta_arg, o->pcg_rtol, eta_max);
             if (prec == BSC_FP64)
                 k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
             else
@@ -1151,16 +1154,16 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             // p = 0, the flags and the tolerance (the first iteration's stop test sets |b|-relative
             // tolerance from the partials of |b|^2)
             const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), 1};
+                                     uint64_t(o->max_pcg), 1 | (step_rule ? 2u : 0u)};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                      enqueue_prep(cs);
                      (void)mg_setup(S, B, prec, cs);
                      k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
-                                                        eta_mode, first, eta_arg, o->pcg_rtol);
+                                                        eta_mode, first, eta_arg, o->pcg_rtol, eta_max);
                  }), "mg init");
         } else if (!o->warm_start) {
             const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), 0};
+                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                      enqueue_prep(cs);
                      enqueue_init(cs, nullptr);
