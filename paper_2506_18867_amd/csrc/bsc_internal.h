@@ -276,14 +276,18 @@ DevSheet dev_sheet(const bsc_ctx *ctx);
 // ---- launchers (eval.hip) ----
 // Membrane points (w Psi, w P and, with hess, w A+), bending evaluations; element gather;
 // tiled assembly of the per-CP gradient and (hess != NULL) the upper-stencil Hessian blocks
-// (kind: AsmKind); energy reduction (n_cp_partials: the assembly's tile count, or 0).
+// (kind: AsmKind; gnorm: also per-tile partials of |g|^2); energy reduction (n_cp_partials: the
+// assembly's tile count, or 0; out_gg: where |g|^2 goes, from an assembly run with gnorm). The
+// mixed-precision Newton points: FP64 arithmetic, FP32 Hessian and FP64 stresses in one pass.
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
                          const double *x, hipStream_t st, bool bending);
+hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st);
 int assemble_tiles(const DevSheet &S, int kind);
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
-                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st);
+                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st,
+                           bool gnorm = false);
 hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out,
-                                hipStream_t st);
+                                hipStream_t st, double *out_gg = nullptr);
 hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,
                        hipStream_t st);
 

@@ -452,9 +452,10 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
 
 // ---- stage 1 kernels ------------------------------------------------------------------------
 
-template <typename T, bool HESS, bool CURVED>
-__global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *__restrict__ x, T *__restrict__ ptA,
-                                                     T *__restrict__ ptP, double *__restrict__ ptE,
+// T: arithmetic; TA, TP: stored precision of the weighted density Hessian and stress.
+template <typename T, bool HESS, bool CURVED, typename TA = T, typename TP = T>
+__global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
+                                                     TP *__restrict__ ptP, double *__restrict__ ptE,
                                                      double *__restrict__ partials) {
     __shared__ double sh[kBlock / 64];
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
 #pragma unroll
         for (int g = 0; g < 2; ++g)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) ptP[(2 * i + g) * S.n_mp + q] = T(w * double(P[i][g]));
+            for (int i = 0; i < 3; ++i) ptP[(2 * i + g) * S.n_mp + q] = TP(w * double(P[i][g]));
         if (HESS) {
             double Ad[6][6];
 #pragma unroll
@@ -501,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
 #pragma unroll
             for (int r = 0; r < 6; ++r)
 #pragma unroll
-                for (int c = r; c < 6; ++c) ptA[u6(r, c) * S.n_mp + q] = T(w * Ad[r][c]);
+                for (int c = r; c < 6; ++c) ptA[u6(r, c) * S.n_mp + q] = TA(w * Ad[r][c]);
         }
     }
     const double s = block_sum(e_loc, sh);
@@ -554,7 +555,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                                                                const double *__restrict__ x, const double *__restrict__ xhat,
                                                                double inv_dt2, double gx, double gy, double gz,
                                                                TA *__restrict__ hess, TG *__restrict__ gout,
-                                                               double *__restrict__ partials) {
+                                                               double *__restrict__ partials, double *__restrict__ gg_partials) {
     constexpr bool STAGE_DN = sizeof(TA) == 4;
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
@@ -632,7 +633,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     const int nchunks = (nitems + 63) / 64;
     const size_t ncp = S.n_cp;
     const int lane = threadIdx.x & 63;
-    double e_loc = 0.0;
+    double e_loc = 0.0, gg_loc = 0.0;
     for (;;) {
         int ch = 0;
         if (lane == 0) ch = atomicAdd(counter, 1);
@@ -775,12 +776,18 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 }
                 gs -= M * grav[cc];
                 e_loc -= M * grav[cc] * xc;
-                gout[cc * ncp + a] = pin ? TG(0) : TG(gs);
+                const TG gv = pin ? TG(0) : TG(gs);
+                gout[cc * ncp + a] = gv;
+                gg_loc += double(gv) * double(gv);
             }
         }
     }
     const double tot = block_sum(e_loc, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (gg_partials) {
+        const double gg = block_sum(gg_loc, sh);
+        if (threadIdx.x == 0) gg_partials[blockIdx.x] = gg;
+    }
 }
 
 // ---- per-element outputs -------------------------------------------------------------------
@@ -851,10 +858,12 @@ __global__ void __launch_bounds__(kBlock) k_elem_grad(DevSheet S, const T *__res
     }
 }
 
-// Sums up to four partial arrays (each of length n) in a fixed order into out[0].
+// Sums three partial arrays in a fixed order into out[0] (the energy) and, if pg is given, the
+// partials pg (|g|^2 of the assembly tiles) into out_g[0].
 __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ p0, int n0, const double *__restrict__ p1,
                                                    int n1, const double *__restrict__ p2, int n2,
-                                                   double *__restrict__ out) {
+                                                   double *__restrict__ out, const double *__restrict__ pg, int ng,
+                                                   double *__restrict__ out_g) {
     __shared__ double sh[kBlock / 64];
     double v = 0.0;
     for (int t = threadIdx.x; t < n0; t += blockDim.x) v += p0[t];
@@ -862,6 +871,12 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ p0
     for (int t = threadIdx.x; t < n2; t += blockDim.x) v += p2[t];
     const double s = block_sum(v, sh);
     if (threadIdx.x == 0) out[0] = s;
+    if (pg) {
+        double u = 0.0;
+        for (int t = threadIdx.x; t < ng; t += blockDim.x) u += pg[t];
+        const double sg = block_sum(u, sh);
+        if (threadIdx.x == 0) out_g[0] = sg;
+    }
 }
 
 inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
@@ -893,13 +908,27 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
     return hipGetLastError();
 }
 
+// The Newton step's mixed-precision points in one pass: FP64 arithmetic, the stresses (for the
+// FP64 gradient) stored in double and the projected density Hessian stored in float.
+hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st) {
+    double *pm = B.partials, *pb = B.partials + B.max_blocks;
+    auto go = [&](auto curved) {
+        constexpr bool C = decltype(curved)::value;
+        k_membrane<double, true, C, float, double><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, B.ptP64, B.ptE, pm);
+        k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+    };
+    if (S.curved) go(std::true_type{});
+    else go(std::false_type{});
+    return hipGetLastError();
+}
+
 int assemble_tiles(const DevSheet &S, int kind) {
     return ((S.n_u + kAsmTileU - 1) / kAsmTileU) * ((S.n_v + S.asm_ty[kind] - 1) / S.asm_ty[kind]);
 }
 
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
-                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st) {
-    double *pc = B.partials + 2 * B.max_blocks;
+                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st, bool gnorm) {
+    double *pc = B.partials + 2 * B.max_blocks, *pg = gnorm ? B.partials + 4 * B.max_blocks : nullptr;
     const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
     const int sa = kind == kAsmF64 ? 8 : 4;
     const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], sa, S.curved != 0).total;
@@ -908,22 +937,24 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const 
         constexpr bool C = decltype(curved)::value;
         if (kind == kAsmF32)
             k_assemble_tile<float, float, float, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, (const float *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc);
+                S, kind, (const float *)B.ptA, (const float *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc, pg);
         else if (kind == kAsmF64)
             k_assemble_tile<double, double, double, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const double *)B.ptA, (const double *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc);
+                S, kind, (const double *)B.ptA, (const double *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc, pg);
         else
             k_assemble_tile<float, double, double, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, B.ptP64, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc);
+                S, kind, (const float *)B.ptA, B.ptP64, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc, pg);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
     return hipGetLastError();
 }
 
-hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out, hipStream_t st) {
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out, hipStream_t st,
+                                double *out_gg) {
     k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
-                                   B.partials + 2 * B.max_blocks, n_cp_partials, out);
+                                   B.partials + 2 * B.max_blocks, n_cp_partials, out,
+                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_cp_partials, out_gg);
     return hipGetLastError();
 }
 

@@ -227,16 +227,7 @@ __global__ void k_apply_pins(int n_cp, int npins, const int32_t *__restrict__ id
     for (int c = 0; c < 3; ++c) x[c * n_cp + a] = tgt[c * npins + t];
 }
 
-// Per-block partials of x.y (grid of kReduceBlocks); k_finish sums them into scal[slot].
-__global__ void __launch_bounds__(kBlock) k_dot_part(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                     double *__restrict__ partials) {
-    __shared__ double sh[kBlock / 64];
-    double v = 0.0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) v += x[t] * y[t];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = v;
-}
-
+// Per-block partials of max |x| (grid of kReduceBlocks); k_finish reduces them into scal[slot].
 __global__ void __launch_bounds__(kBlock) k_absmax_part(int n, const double *__restrict__ x, double *__restrict__ partials) {
     __shared__ double sh[kBlock / 64];
     double v = 0.0;
@@ -876,22 +867,18 @@ struct Timer {
         if (e_ != hipSuccess) return hip_check(ctx, e_, what);      \
     } while (0)
 
-// Assembles E, g (double) and H (working precision) at x for one Newton iteration.
+// Assembles E, g (double), |g|^2 and H (working precision) at x for one Newton iteration.
 bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *xhat, double inv_dt2, const double *grav,
                          hipStream_t st) {
     const DevSheet &S = ctx->dev;
     const DevBufs &B = ctx->buf;
-    // FP32-mixed: the Hessian from FP32 points; the gradient (and energy) from FP64 points
-    if (prec == BSC_FP64) {
-        HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true), "points");
-    } else {
-        // (the bending evaluations are FP64 in both passes: once is enough)
-        HIPX(launch_points(S, B, BSC_FP32_MIXED, true, false, x, st, true), "points32");
-        HIPX(launch_points(S, B, BSC_FP64, false, true, x, st, false), "points64");
-    }
+    // FP32-mixed: the points in FP64 arithmetic, the Hessian stored in FP32 and the stresses (for
+    // the FP64 gradient and energy) in FP64
+    if (prec == BSC_FP64) HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true), "points");
+    else HIPX(launch_points_mixed(S, B, x, st), "points");
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
-    HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st), "assemble");
-    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st), "energy");
+    HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st, true), "assemble");
+    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG), "energy");
     return BSC_OK;
 }
 
@@ -1059,8 +1046,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                      bits(gz), 0};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                      (void)assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, cs);
-                     k_dot_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.g, B.g, B.partials + 7 * stride);
-                     k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 0, B.scalars, S_GG);
                  }), "assembly");
         }
         hipEvent_t e1 = rec();
