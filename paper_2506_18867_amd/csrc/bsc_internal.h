@@ -30,6 +30,9 @@ constexpr int kSlots = 13;            // diagonal + 12 upper offsets
 constexpr int kHessEntries = BSC_HESS_ENTRIES;
 // CG iteration tile: kCgTileU x kCgTileV control points per workgroup (one wave of rows)
 constexpr int kCgTileU = 64, kCgTileV = 2;
+// Hessian blocks per wave that the FP32 CG kernel loads before its prologue reduction (3 or more
+// need more than the 128 VGPRs that keep two workgroups on a CU)
+constexpr int kCgPrefetch = 2;
 
 // Upper-stencil slot offsets (di, dj); slot 0 is the diagonal.
 constexpr int kSlotDi[kSlots] = {0, 1, 2, -2, -1, 0, 1, 2, -2, -1, 0, 1, 2};

@@ -379,7 +379,7 @@ struct CgBufs {
 };
 
 template <typename T, bool FIRST>
-__global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restrict__ H, CgBufs B, double *scal,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_cg_fused(DevSheet S, const T *__restrict__ H, CgBufs B, double *scal,
                                                   int32_t *isc) {
     constexpr int TX = kCgTileU, TY = kCgTileV, HX = TX + 4, HY = TY + 4, R = TX * TY;
     constexpr int RS = R / 64, PG = 8 / RS;      // 64-row sets, product groups per set
@@ -443,21 +443,47 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     const bool fp = t < HX * HY && fi >= 0 && fi < S.n_u && fj >= 0 && fj < S.n_v;
     const bool own = fp && hx >= 2 && hx < 2 + TX && hy >= 2 && hy < 2 + TY;
     const int fa = fp ? fj * S.n_u + fi : 0;
-    double rin[3] = {0.0, 0.0, 0.0}, win[3] = {0.0, 0.0, 0.0}, sin_[3] = {0.0, 0.0, 0.0};
-    double po[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0}, pv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // (w and M^-1 stay in the working precision until phase 3: a conversion here would wait for
+    // the loads before the prologue)
+    double rin[3] = {0.0, 0.0, 0.0}, sin_[3] = {0.0, 0.0, 0.0};
+    double po[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0};
+    T win_t[3] = {T(0), T(0), T(0)}, pv_t[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if (fp) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) rin[c] = B.r_in[c * n + fa];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) pv[k] = double(pinv[k * n + fa]);
+        for (int k = 0; k < 6; ++k) pv_t[k] = pinv[k * n + fa];
         if (!FIRST) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { win[c] = double(w_in[c * n + fa]); sin_[c] = B.s_in[c * n + fa]; }
+            for (int c = 0; c < 3; ++c) { win_t[c] = w_in[c * n + fa]; sin_[c] = B.s_in[c * n + fa]; }
             if (own) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { po[c] = B.p[c * n + fa]; xo[c] = B.x[c * n + fa]; }
             }
         }
+    }
+    // the wave's first NPRE Hessian blocks (FP32: they depend on nothing computed below), issued
+    // now so that their latency overlaps the prologue; at most 63 loads are outstanding per wave.
+    // The scheduling fence keeps them behind the footprint loads, which phase 3 waits for.
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr bool BRANCH_FREE = sizeof(T) == 4;
+    constexpr int NPRE = BRANCH_FREE ? (kCgPrefetch < NP ? kCgPrefetch : NP) : 0;
+    // One straight-line sequence of 9 loads per block on every path (the diagonal block's 6
+    // planes padded with repeats), so that the wait for the footprint loads in phase 3 does not
+    // have to cover these.
+    static_assert(NPRE == 0 || PG * NPRE <= 25, "prefetched products are all real");
+    T hpre[NPRE > 0 ? NPRE : 1][9];
+#pragma unroll
+    for (int m = 0; m < NPRE; ++m) {
+        const int pid = pg + PG * m;
+        const bool diag = pid == 0, upper = pid <= 12;
+        const int sl = diag ? 1 : (upper ? pid : pid - 12);
+        const int di = slot_di(sl), dj = slot_dj(sl), e0 = slot_entry(sl);
+        const int ib = upper ? ri_ + di : ri_ - di, jb = upper ? rj_ + dj : rj_ - dj;
+        const bool ok = row_ok && ib >= 0 && ib < S.n_u && jb >= 0 && jb < S.n_v;
+        const int src = (upper || !ok) ? ra : jb * S.n_u + ib;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) hpre[m][k] = H[size_t(diag ? (k < 6 ? k : 5) : e0 + k) * n + src];
     }
 
     // (2) prologue: the scalars of iteration j-1 (bitwise the same in every block)
@@ -500,7 +526,11 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     if (t < HX * HY) {
         double uv[3] = {0.0, 0.0, 0.0};
         if (fp) {
-            double rv[3], sc[3];
+            double rv[3], sc[3], win[3], pv[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) win[c] = double(win_t[c]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pv[k] = double(pv_t[k]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 sc[c] = win[c] + beta * sin_[c];
@@ -543,7 +573,6 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
     //     a valid row and take u = 0, so the body has no data-dependent branch and the compiler
     //     keeps several products' loads in flight; FP64 blocks take twice the registers, so there
     //     they are skipped by a branch (higher occupancy).
-    constexpr bool BRANCH_FREE = sizeof(T) == 4;
     {
         T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -553,7 +582,7 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
             if (pid == 0) {
                 T h[6];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) h[k] = H[k * n + ra];
+                for (int k = 0; k < 6; ++k) h[k] = m < NPRE ? hpre[m < NPRE ? m : 0][k] : H[k * n + ra];
                 const T u0 = us[0][ly + 2][lx + 2], u1 = us[1][ly + 2][lx + 2], u2 = us[2][ly + 2][lx + 2];
                 acc[0] += h[0] * u0 + h[1] * u1 + h[2] * u2;
                 acc[1] += h[1] * u0 + h[3] * u1 + h[4] * u2;
@@ -572,7 +601,7 @@ __global__ void __launch_bounds__(512) k_cg_fused(DevSheet S, const T *__restric
             const int src = (upper || !ok) ? ra : jb * S.n_u + ib;
             T h[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) h[k] = H[(e0 + k) * n + src];
+            for (int k = 0; k < 9; ++k) h[k] = m < NPRE ? hpre[m < NPRE ? m : 0][k] : H[(e0 + k) * n + src];
             const int yy = ly + 2 + sgn * dj, xx = lx + 2 + sgn * di;
             const T u0 = ok ? us[0][yy][xx] : T(0), u1 = ok ? us[1][yy][xx] : T(0), u2 = ok ? us[2][yy][xx] : T(0);
             if (upper) {
