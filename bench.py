@@ -216,7 +216,7 @@ def main():
                               "newton": [s["newton_iters"] for s in stg], "pcg": [s["pcg_iters_total"] for s in stg],
                               "g_rel": [float("%.3g" % (s["g_norm"] / s["g0_norm"])) for s in stg]}
 
-    # Quadrature ablation (Sec. 6.4, timing breakdown (A) vs (B)): the standard 2x2 Gauss rule on
+    # Quadrature ablation (Sec. 6.5, timing breakdown (A) vs (B)): the standard 2x2 Gauss rule on
     # the interior spans against the reduced rule, a few FP32-mixed steps from the same start state.
     quad_leg = None
     if args.quad_steps > 0:
@@ -241,7 +241,7 @@ def main():
                               "assembly_fp32_ms": round(ms_a, 4)}
             del qctx
 
-    # General rest shapes (Sec. 6.5, non-rectangular domains): the same driven sheet with its rest
+    # General rest shapes (Sec. 6.2, non-rectangular domains): the same driven sheet with its rest
     # CPs on a domain whose rest map is not affine, so the library takes per-point rest geometry.
     # FP32-mixed steps from the flat start state, the flat square timed the same way beside it.
     general_leg = None
@@ -364,8 +364,9 @@ def main():
         "config": {"workload": f"driven sheet {args.n}x{args.n} CPs ({ne} elements), E=1e4 Pa, t=1 mm, dt=0.01 s, "
                                + (f"|g|<={args.rtol:g}|g0|" if args.stop == "grad" else f"|p|inf/dt<={args.atol:g}")
                                + ", FP32-mixed", "n_cp": n, "n_elem": ne, "seed": args.seed, "noise": args.noise,
-                   "pcg": "block-Jacobi PCG, " + ("Eisenstat-Walker tolerance in [%g, 0.5]" % args.pcg_rtol if args.adaptive
-                                                  else "fixed tolerance %g" % args.pcg_rtol),
+                   "pcg": ("multigrid V(1,1)" if args.precond == "mg" else "block-Jacobi") + " PCG, "
+                          + ("Eisenstat-Walker tolerance in [%g, %g]" % (args.pcg_rtol, 0.1 if args.stop == "grad" else 0.5)
+                             if args.adaptive else "fixed tolerance %g" % args.pcg_rtol),
                    "parallelism": "single GPU"},
         "newton_step_ms": {"fp32_mixed": round(ms_step32, 3),
                            "fp64": round(1e3 * sec64 / args.steps, 3) if sec64 else None},

@@ -61,7 +61,7 @@ enum { BSC_STOP_GRAD = 0, BSC_STOP_STEP = 1 };
  * reduced integration (Sec. 4.1 and 4.2, Fig. "quadrature"): 3x3 Gauss on corner spans, 3x2 on
  * side spans, alternating 1x2 / 2x1 Gauss on the dual-grid cells of the interior for the
  * membrane; span centres on the boundary and the interior knots for bending. The others are the
- * comparison rules of the ablation (Sec. 6.4), all with the same boundary placement except as
+ * comparison rules of the ablation (Sec. 6.5), all with the same boundary placement except as
  * stated: BSC_QUAD_GAUSS2 the standard 2x2 Gauss rule on every interior span for membrane and
  * bending; BSC_QUAD_INTERIOR1 one midpoint per interior span for the membrane (admits hourglass
  * modes); BSC_QUAD_CORNER2 2x2 instead of 3x3 Gauss on the four corner spans for the membrane. */
@@ -142,7 +142,8 @@ typedef struct {
  *     gets them per quadrature point (Sec. 4.1 inverse function theorem; Sec. 4.2 Laplacian in
  *     parametric space, with its first-derivative terms): 32 more workspace bytes per membrane
  *     point, 40 per bending evaluation and 16 per CP.
- *   mat: host; E, thickness, rho_area > 0, nu in (-1, 0.5) for StVK; mu_* >= 0 for FBW.
+ *   mat: host; E, thickness, rho_area > 0, nu in (-1, 0.5] for StVK (plane stress stays finite at
+ *   0.5); mu_* >= 0 for FBW.
  *   hip_stream: hipStream_t on which all work is enqueued (NULL = default stream).
  * On success *out owns the host tables; free it with bsc_destroy. Host-only, synchronous. */
 bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *knots_u,
@@ -264,7 +265,7 @@ bsc_status bsc_adam_step(bsc_ctx *ctx, int32_t n, float *d_param, const float *d
 bsc_status bsc_net_loss(bsc_ctx *ctx, int32_t batch, const float *d_in, const float *d_pred,
                         const float *d_target, float *d_loss, float *d_dpred);
 
-/* ---- Contact Hessian conversion (Sec. 3.3 contact barrier; Sec. 5.2 Alg. "Contact Hessian
+/* ---- Contact Hessian conversion (Sec. 4.3 contact barrier; Sec. 5.2 Alg. "Contact Hessian
  * conversion and assembly") ---------------------------------------------------------------
  * A triangle contact mesh is embedded in the surface: vertex a has fixed parametric coordinates,
  * so its position is sum_ij N_ij(u_a, v_a) C^{ij} over the 9 CPs of its span (Eq. "trig mesh node

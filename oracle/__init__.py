@@ -178,7 +178,7 @@ def _quad(q) -> int:
 
 def membrane_rule(Nu: int, Nv: int, quadrature=QUAD_REDUCED) -> np.ndarray:
     """(M, 5) array of (u, v, wbar, k, l) in span units. QUAD_REDUCED is the paper's rule
-    (Sec. 4.1, Reduced Integration); the others are the comparison rules of Sec. 6.4 (standard
+    (Sec. 4.1, Reduced Integration); the others are the comparison rules of Sec. 6.5 (standard
     2x2 Gauss on interior spans, 1x1 interior, 2x2 corners)."""
     lib = _load()
     q = _quad(quadrature)
@@ -190,7 +190,7 @@ def membrane_rule(Nu: int, Nv: int, quadrature=QUAD_REDUCED) -> np.ndarray:
 
 def bending_rule(Nu: int, Nv: int, quadrature=QUAD_REDUCED) -> np.ndarray:
     """(B', 5) array of bending evaluations (u, v, wbar, k, l) (Sec. 4.2; reading R2). With
-    QUAD_GAUSS2 the interior spans take 2x2 Gauss points (Sec. 6.4, configuration (A))."""
+    QUAD_GAUSS2 the interior spans take 2x2 Gauss points (Sec. 6.5, configuration (A))."""
     lib = _load()
     q = _quad(quadrature)
     n = lib.or_bending_rule_q(Nu, Nv, q, None, 0)

@@ -135,7 +135,7 @@ static int push(double *out, int cap, int cnt, double u, double v, double w, int
 static int imin(int a, int b) { return a < b ? a : b; }
 
 /* Quadrature variants. OR_QUAD_REDUCED is the paper's scheme (Sec. 4.1, 4.2). The others are
- * the comparison rules of its ablation study (Sec. 6.4): the standard 2x2 Gauss rule on every
+ * the comparison rules of its ablation study (Sec. 6.5): the standard 2x2 Gauss rule on every
  * interior knot span for membrane and bending (boundary spans unchanged), a single midpoint
  * per interior span for the membrane ("1x1", which admits hourglass modes), and 2x2 instead of
  * 3x3 Gauss on the four corner spans for the membrane. */

@@ -1,7 +1,7 @@
 """Contact Hessian conversion to the control points, the plain definition (TEST INFRASTRUCTURE:
 only tests, the smoke check and the benchmark's CPU-baseline leg may use it).
 
-Sec. 3.3 (contact barrier): a vertex a of the triangle contact mesh sits at fixed parametric
+Sec. 4.3 (contact barrier): a vertex a of the triangle contact mesh sits at fixed parametric
 coordinates (u_a, v_a), so its position is x_a = sum_ij N_ij(u_a, v_a) C^{ij} (Eq. "trig mesh node
 from control points"). The chain rule (Eq. "gradient and hessian of contact barrier", whose
 second-derivative term vanishes because x_a is linear in the CPs) gives

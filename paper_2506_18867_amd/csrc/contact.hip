@@ -1,5 +1,5 @@
 // contact.hip -- conversion of contact Hessians and gradients from the triangle contact mesh
-// embedded in the B-spline surface to the control points (Sec. 3.3, contact barrier, Eq.
+// embedded in the B-spline surface to the control points (Sec. 4.3, contact barrier, Eq.
 // "gradient and hessian of contact barrier"; Sec. 5.2, Alg. "Contact Hessian conversion and
 // assembly").
 //

@@ -104,7 +104,7 @@ const double kG3 = 0.38729833462074168852;   // sqrt(3/5) / 2
 // clipped to the region (two points on the knot line for edge half cells, one at the knot
 // for corner quarter cells). Weights: Gauss weights times the clipped cell area.
 //
-// Comparison rules (Sec. 6.4, selected by bsc_material.quadrature): BSC_QUAD_GAUSS2 puts 2x2
+// Comparison rules (Sec. 6.5, selected by bsc_material.quadrature): BSC_QUAD_GAUSS2 puts 2x2
 // Gauss on every interior span instead of the dual-grid cells, BSC_QUAD_INTERIOR1 one point at
 // the centre of every interior span, BSC_QUAD_CORNER2 2x2 instead of 3x3 Gauss on the corner
 // spans.
@@ -342,7 +342,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     double hu = 0, hv = 0;
     if (!knots_ok(knots_u, n_u, &hu) || !knots_ok(knots_v, n_v, &hv)) return BSC_E_KNOTS;
     if (mat->membrane == BSC_MEMBRANE_STVK) {
-        if (!(mat->young >= 0.0) || !(mat->thickness > 0.0) || !(mat->poisson > -1.0 && mat->poisson < 0.5))
+        if (!(mat->young >= 0.0) || !(mat->thickness > 0.0) || !(mat->poisson > -1.0 && mat->poisson <= 0.5))
             return BSC_E_INVAL;
     } else if (mat->membrane == BSC_MEMBRANE_FBW) {
         if (!(mat->mu_st1 >= 0.0 && mat->mu_st2 >= 0.0 && mat->mu_sh >= 0.0)) return BSC_E_INVAL;

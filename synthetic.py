@@ -242,6 +242,30 @@ def driven_sheet(n: int = 226, seed: int = 300, cell: int | None = None, noise: 
                  0.01, np.array([0.0, 0.0, -9.81]), drive_cp=0, drive_amp=0.05, drive_hz=1.0)
 
 
+def wrinkling_sheet(n_width: int, thickness: float = 1e-3, stretch: float = 1.1, amp: float = 0.02,
+                    mode: int = 1) -> Scene:
+    """The stretched-plate wrinkling benchmark (Sec. 6.2, convergence under refinement of the
+    membrane): a flat W x L = 1.0 m x 2.5 m plate, n_width spans across the width and
+    2.5 n_width along the length, both short edges clamped (their two CP rows held) and pulled
+    apart so that the length grows by ``stretch`` about the middle, no gravity. StVK with E = 1e6 Pa, nu = 0.5 and the given
+    thickness (the paper gives none; 1 mm here), bending stiffness D. The start state is the
+    uniform stretch plus the perturbation amp sin(pi Y / L) sin(mode pi X / W) in z (zero on
+    the clamped rows); dt = 1e4 s, so one implicit-Euler step is the quasi-static solve."""
+    W, L = 1.0, 2.5
+    n_len = int(round(2.5 * n_width))
+    n_u, n_v = n_width + 2, n_len + 2
+    ku, kv, rest = flat_sheet(n_u, n_v, L_u=W, L_v=L)
+    x0 = embed(rest)
+    x0[:, 1] = stretch * (rest[:, 1] - 0.5 * L) + 0.5 * L
+    x0[:, 2] = amp * np.sin(np.pi * rest[:, 1] / L) * np.sin(mode * np.pi * rest[:, 0] / W)
+    rows = (0, 1, n_v - 2, n_v - 1)
+    pins = np.array([cp_index(n_u, i, j) for j in rows for i in range(n_u)], dtype=np.int64)
+    x0[pins, 2] = 0.0
+    mat = stvk_material(young=1e6, poisson=0.5, thickness=thickness, rho_area=0.2)
+    return Scene("wrinkling", n_u, n_v, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(),
+                 1e4, np.array([0.0, 0.0, 0.0]))
+
+
 def smooth_field(n_u: int, n_v: int, seed: int, amp: float = 0.05, modes: int = 3) -> np.ndarray:
     """A smooth random displacement field on the CP grid (sum of low sine modes), (n_cp, 3)."""
     g = rng(seed)

@@ -89,7 +89,7 @@ class Tiny:
 
     # quadrature, rebuilt from the wording of the paper (span units)
     def membrane_points(self, full_gauss=False, rule="reduced"):
-        """rule: "reduced" (Sec. 4.1), or the comparison rules of Sec. 6.4: "gauss2" (2x2 on the
+        """rule: "reduced" (Sec. 4.1), or the comparison rules of Sec. 6.5: "gauss2" (2x2 on the
         interior spans), "interior1" (one midpoint per interior span), "corner2" (2x2 on the
         corner spans instead of 3x3)."""
         g2 = 0.5 / math.sqrt(3.0)

@@ -1,4 +1,4 @@
-"""GPU parity of the contact-Hessian conversion (Sec. 3.3, Sec. 5.2 Alg. "Contact Hessian
+"""GPU parity of the contact-Hessian conversion (Sec. 4.3, Sec. 5.2 Alg. "Contact Hessian
 conversion and assembly") against the oracle's plain chain-rule products, through the C ABI.
 
 The block pattern must equal the oracle's exactly (CP pairs reached by nonzero weight products),

@@ -1,5 +1,5 @@
 """GPU parity on general (non-affine) rest shapes, through the C ABI: the distorted patches of
-the paper's robustness study (Sec. 6.5, "Support of Non-Rectangular Domains": aspect ratio,
+the paper's robustness study (Sec. 6.2, "Support of Non-Rectangular Domains": aspect ratio,
 skewed corners, sharp turns within an edge) and a curved quarter annulus. The library switches
 to per-point rest geometry (inverse Jacobian per membrane point, Laplacian coefficients with
 their first-derivative terms per bending evaluation, rest CPs for the displacement) when the
@@ -134,7 +134,7 @@ def test_newton_converges_on_mapped_rest(precision):
 
 
 def test_newton_iterations_on_distorted_patches():
-    """Sec. 6.5 reports solver iteration counts within a small constant factor of the
+    """Sec. 6.2 reports solver iteration counts within a small constant factor of the
     rectangular baseline for its three distortion categories (aspect ratio, skewed corners,
     sharp turns within an edge). Hanging 40 x 40 sheets, 6 steps each with the paper's stopping
     rule, FP64: Newton iterations of each distorted patch against the square. The quarter

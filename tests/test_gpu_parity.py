@@ -303,7 +303,7 @@ def test_quadrature_variants_match_oracle(rule):
 
 
 def test_standard_2x2_rule_needs_as_many_newton_iterations():
-    """Sec. 6.4: reduced integration converges in about as many Newton iterations as the
+    """Sec. 6.5: reduced integration converges in about as many Newton iterations as the
     standard 2x2 rule on the interior spans (paper's stopping rule, dt = 0.01 s). Driven sheet,
     60 x 60 CPs, 8 steps, FP64, same start state."""
     sc = syn.driven_sheet(60, seed=12, cell=7)

@@ -1,4 +1,4 @@
-"""Pins for the oracle's contact-Hessian conversion (Sec. 3.3 contact barrier, Eq. "gradient and
+"""Pins for the oracle's contact-Hessian conversion (Sec. 4.3 contact barrier, Eq. "gradient and
 hessian of contact barrier"; Sec. 5.2 Alg. "Contact Hessian conversion and assembly").
 
 Checked against what the definitions fix, not against the oracle's own products:

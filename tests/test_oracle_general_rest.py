@@ -1,5 +1,5 @@
 """Pins for the oracle on general (non-affine) rest shapes: the distorted patches of the paper's
-robustness study of its reduced quadrature (Sec. 6.5, "Support of Non-Rectangular Domains":
+robustness study of its reduced quadrature (Sec. 6.2, "Support of Non-Rectangular Domains":
 aspect ratio, skewed corners, sharp turns within an edge) and a curved quarter annulus.
 
 Checked against what the definitions fix, independently of the oracle's code:

@@ -1,7 +1,7 @@
 """Pins for the oracle's implicit-Euler / projected-Newton step (CPU only).
 
 Pinned against: conservation of linear momentum without pins or gravity (the contact-free
-form of the paper's two-plate test, Sec. 6.2), the Kirchhoff simply-supported plate closed
+form of the paper's two-plate test, Sec. 6.1), the Kirchhoff simply-supported plate closed
 form of the paper's bending benchmark (Sec. 6.2, "Convergence under Refinement (Bending)"),
 and one-iteration exactness on a quadratic energy checked by an independent dense solve."""
 import numpy as np

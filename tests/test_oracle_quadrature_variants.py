@@ -1,4 +1,4 @@
-"""Pins for the oracle's comparison quadrature rules (Sec. 6.4, "Effectiveness and Minimality of
+"""Pins for the oracle's comparison quadrature rules (Sec. 6.5, "Effectiveness and Minimality of
 Reduced Integration"): the standard 2x2 Gauss rule on the interior knot spans for membrane and
 bending (configuration (A) of the timing breakdown), a single midpoint per interior span for
 the membrane (the "1x1" rule that admits hourglass modes), and 2x2 instead of 3x3 Gauss on the
@@ -116,7 +116,7 @@ def test_rigid_motions_are_the_only_zero_modes():
 
 
 def test_interior_1x1_rule_has_hourglass_modes():
-    """Sec. 6.4: one point per interior span lets an oscillating displacement escape the
+    """Sec. 6.5: one point per interior span lets an oscillating displacement escape the
     membrane energy everywhere but on the boundary ring, so its stiffness relative to the
     reduced rule falls as the sheet is refined; under the reduced rule and the denser
     comparison rules it stays of the same order."""
