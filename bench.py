@@ -89,6 +89,9 @@ def parse():
                    help="steps of the general-rest leg (the same driven sheet on a curved domain; 0: skip)")
     p.add_argument("--contact-pairs", type=int, default=100000,
                    help="contact pairs of the contact-Hessian conversion leg (0: skip)")
+    p.add_argument("--wrinkle-levels", default="16,32,48,64,80,96,112,128",
+                   help="spans across the width of the wrinkling-plate convergence leg, comma-separated "
+                        "('': skip)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run the traffic-counter calibration: one device-to-device copy of MIB MiB whose "
                         "source has been evicted from the caches, then exit")
@@ -130,6 +133,15 @@ def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
         stats.append(s.as_dict())
     torch.cuda.synchronize()
     return time.perf_counter() - t0, stats
+
+
+def max_deflection(sc, x):
+    """Largest |z| of the B-spline surface with CPs x (n_cp, 3) over a 401 x 1001 parameter grid."""
+    from scipy.interpolate import BSpline
+    ku, kv = sc.knots_u / sc.knots_u[-1], sc.knots_v / sc.knots_v[-1]
+    Bu = BSpline.design_matrix(np.linspace(0.0, 1.0, 401), ku, 2).toarray()
+    Bv = BSpline.design_matrix(np.linspace(0.0, 1.0, 1001), kv, 2).toarray()
+    return float(np.abs(Bv @ x[:, 2].reshape(sc.n_v, sc.n_u) @ Bu.T).max())
 
 
 def time_kernel(fn, reps, torch):
@@ -298,6 +310,31 @@ def main():
                        "mblocks_per_s": round(nblk / ms_c / 1e3, 2)}
         del dpv, dH, dg, outc, res
 
+    # Membrane convergence under refinement (Sec. 6.2, the stretched-plate wrinkling benchmark):
+    # per resolution one quasi-static FP64 solve (dt = 1e4 s) from the perturbed start to
+    # |g| <= 1e-9 |g0|, and the largest out-of-plane deflection of the surface. The paper's
+    # reference value is 3.45 mm; it gives no thickness (1 mm here).
+    wrinkle_leg = None
+    if args.wrinkle_levels:
+        wrinkle_leg = {"reference_mm": 3.45, "thickness_m": 1e-3, "levels": []}
+        for nw in [int(a) for a in args.wrinkle_levels.split(",")]:
+            wsc = syn.wrinkling_sheet(nw)
+            wctx = bsc.context_for_scene(wsc)
+            xw, vw = bsc.to_soa(wsc.x0), bsc.to_soa(wsc.v0)
+            wopts = bsc.make_opts(dt=wsc.dt, gravity=(0.0, 0.0, 0.0), precision=bsc.BSC_FP64,
+                                  stop_mode=bsc.BSC_STOP_GRAD, rtol=1e-9, max_newton=4000, max_pcg=5000,
+                                  pcg_rtol=1e-3, pcg_adaptive=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, wst = wctx.bsc_newton_step(xw, vw, bsc.to_soa(wsc.pin_targets(0)), wopts)
+            torch.cuda.synchronize()
+            secw = time.perf_counter() - t0
+            wrinkle_leg["levels"].append({"spans": [nw, wsc.n_v - 2], "n_cp": wsc.n_cp, "newton": wst.newton_iters,
+                                          "pcg": wst.pcg_iters_total, "seconds": round(secw, 3),
+                                          "energy": wst.energy,
+                                          "max_deflection_mm": round(1e3 * max_deflection(wsc, bsc.to_aos(xw)), 4)})
+            del wctx
+
     # per-kernel timings at the current state (same stream as the library)
     n, ne = sc.n_cp, sc.n_elem
     xhat = x.clone()
@@ -392,6 +429,7 @@ def main():
         "quadrature_ablation": quad_leg,
         "general_rest": general_leg,
         "contact_conversion": contact_leg,
+        "wrinkling_convergence": wrinkle_leg,
         "roofline": roof,
         "cpu_baseline": None,
     }
