@@ -133,7 +133,9 @@ typedef struct {
 
 /* Creates a context for an n_u x n_v control grid (Sec. 3.1.2, Eq. "general B-spline patch").
  *   knots_u / knots_v: host, n_u+3 / n_v+3 doubles; must be open uniform quadratic knot vectors
- *     starting at 0 with integer knots (Sec. 3.1.2); n_u, n_v >= 5 (at least 3 spans).
+ *     starting at 0 with integer knots (Sec. 3.1.2); n_u, n_v >= 5 (at least 3 spans), each at
+ *     most 32768, and n_u*n_v <= 2^24 (16.7 M CPs: every offset into the device tables, such as
+ *     entry * n_cp for the 114 Hessian entries, stays below 2^31); otherwise BSC_E_INVAL.
  *   rest_xy: host, 2*n_u*n_v doubles, AoS (X1, X2) per CP (Sec. 3.2). Any rest map whose
  *     Jacobian determinant is positive at every quadrature point (membrane, bending and the
  *     3x3 Gauss mass points) is accepted; otherwise BSC_E_INVAL. An affine rest (control points

@@ -302,6 +302,8 @@ class Context:
 
     def bsc_spmv(self, H, v, precision=BSC_FP64, out=None):
         import torch
+        if v.dtype != torch.float64 or (out is not None and out.dtype != torch.float64):
+            raise BscError("bsc_spmv takes double vectors in both precisions")
         y = torch.empty_like(v) if out is None else out
         self._check(self.lib.bsc_spmv(self.h, precision, _ptr(H), _ptr(v), _ptr(y)), "bsc_spmv")
         return y

@@ -466,14 +466,19 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
         const double w = S.mp_w[q];
         T dN[9][2];
         local_grads<T>(S, mp_geo_t<CURVED>(S, q), k, l, tu, tv, dN);
+        // G from the displacements relative to the span's centre CP, formed in FP64: the basis
+        // gradients sum to zero, so this is the same G, and in FP32 its rounding follows the local
+        // variation of the displacement, not its size (which grows with the sheet)
         T G[3][2] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+        double dref[3];
+        displacement_t<CURVED>(S, x, k + 1, l + 1, dref);
 #pragma unroll
         for (int m = 0; m < 9; ++m) {
             double d[3];
             displacement_t<CURVED>(S, x, k + m % 3, l + m / 3, d);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T dc = T(d[c]);
+                const T dc = T(d[c] - dref[c]);
                 G[c][0] += dc * dN[m][0];
                 G[c][1] += dc * dN[m][1];
             }

@@ -337,7 +337,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     if (!out) return BSC_E_INVAL;
     *out = nullptr;
     if (!knots_u || !knots_v || !rest_xy || !mat) return BSC_E_INVAL;
-    if (n_u < 5 || n_v < 5 || n_u > 32768 || n_v > 32768 || int64_t(n_u) * n_v > (int64_t(1) << 28))
+    if (n_u < 5 || n_v < 5 || n_u > 32768 || n_v > 32768 || int64_t(n_u) * n_v > (int64_t(1) << 24))
         return BSC_E_INVAL;
     double hu = 0, hv = 0;
     if (!knots_ok(knots_u, n_u, &hu) || !knots_ok(knots_v, n_v, &hv)) return BSC_E_KNOTS;

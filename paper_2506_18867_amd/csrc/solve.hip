@@ -374,6 +374,7 @@ struct CgBufs {
     const double *part_in;                        // 3 arrays (stride) from K_{j-1}
     double *part_out;                             // 3 arrays (stride) for K_{j+1}
     const double *pbb;                            // b.b partials of the init kernel (FIRST)
+    const double *pre;                            // the sums of part_in (large grids), or null
     int stride, nb_init;
     int slot_in, slot_out;                        // iteration-counter slots (alternate)
 };
@@ -412,15 +413,17 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         tol2 = scal[S_TOL2];
         gam01[0] = scal[S_GAMMA0]; gam01[1] = scal[S_GAMMA1];
         alp01[0] = scal[S_ALPHA0]; alp01[1] = scal[S_ALPHA1];
-        if (int(threadIdx.x) < nb) {
-            v[0] = B.part_in[threadIdx.x];
-            v[1] = B.part_in[B.stride + threadIdx.x];
-            v[2] = B.part_in[2 * B.stride + threadIdx.x];
-        }
-        for (int t = threadIdx.x + blockDim.x; t < nb; t += blockDim.x) {
-            v[0] += B.part_in[t];
-            v[1] += B.part_in[B.stride + t];
-            v[2] += B.part_in[2 * B.stride + t];
+        if (!B.pre) {
+            if (int(threadIdx.x) < nb) {
+                v[0] = B.part_in[threadIdx.x];
+                v[1] = B.part_in[B.stride + threadIdx.x];
+                v[2] = B.part_in[2 * B.stride + threadIdx.x];
+            }
+            for (int t = threadIdx.x + blockDim.x; t < nb; t += blockDim.x) {
+                v[0] += B.part_in[t];
+                v[1] += B.part_in[B.stride + t];
+                v[2] += B.part_in[2 * B.stride + t];
+            }
         }
     } else if (blockIdx.x == 0) {
         for (int t = threadIdx.x; t < B.nb_init; t += blockDim.x) v[0] += B.pbb[t];
@@ -490,6 +493,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     double alpha = 0.0, beta = 0.0;
     if (!FIRST) {
         wave_totals3(v, sh);
+        if (B.pre) {
+            v[0] = B.pre[0];
+            v[1] = B.pre[1];
+            v[2] = B.pre[2];
+        }
         const double gam = v[0], del = v[1], rho = v[2];
         if (rho <= tol2 || it >= maxit || !(rho == rho)) {
             if (lead) { isc[I_ITERS] = it; isc[I_DONE] = 1; }
@@ -639,6 +647,26 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         B.part_out[blockIdx.x] = w3[0];
         B.part_out[B.stride + blockIdx.x] = w3[1];
         B.part_out[2 * B.stride + blockIdx.x] = w3[2];
+    }
+}
+
+// Large grids: the sums of one fused launch's partials (r.u, w.u, r.r) in a fixed order, formed
+// once for the next launch to read.
+__global__ void __launch_bounds__(1024) k_cg_sum(const double *__restrict__ part, int stride, int nb,
+                                                 const int32_t *__restrict__ isc, double *__restrict__ out) {
+    __shared__ double sh[48];
+    if (isc[I_DONE]) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+        v[0] += part[t];
+        v[1] += part[stride + t];
+        v[2] += part[2 * stride + t];
+    }
+    block_sum3(v, sh);
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = v[1];
+        out[2] = v[2];
     }
 }
 
@@ -1133,10 +1161,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
         const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
         double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
+        const bool presum = nbc > kCgPreSumBlocks;
         auto bufs = [&](int j) {
             CgBufs c{};
             c.x = B.dir; c.p = p; c.pinv = B.pinv;
             c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
+            c.pre = presum ? B.scalars + S_CGSUM : nullptr;
             const int cur = j & 1, prev = (j + 1) & 1;
             c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
             c.w_in = wb[prev]; c.w_out = wb[cur];
@@ -1162,6 +1192,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
             else
                 k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+            if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
         };
         if (use_mg) {
             // multigrid: Galerkin hierarchy and block-Jacobi inverses of every level, then r = b,
@@ -1233,6 +1264,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                     k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
                 else
                     k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
+                if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[c & 1], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
             }
         };
         // A burst of K chunks (K = 1..8) is one graph of 8K launches, captured the first time it

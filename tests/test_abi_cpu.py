@@ -84,6 +84,15 @@ def test_create_rejects_bad_inputs():
     nan_rest = rest.copy()
     nan_rest[3, 1] = np.nan
     assert _create(8, 8, ku, kv, nan_rest)[0] == -1
+    # plane stress is finite at nu = 0.5 (accepted), not beyond
+    st, h = _create(8, 8, ku, kv, rest, bsc.make_material(0, 1e6, 0.5, 1e-3, rho_area=0.2))
+    assert st == 0
+    lib.bsc_destroy(h)
+    assert _create(8, 8, ku, kv, rest, bsc.make_material(0, 1e6, 0.5000001, 1e-3, rho_area=0.2))[0] == -1
+    # more than 2^24 CPs: offsets into the device tables would leave int32
+    n_u, n_v = 4097, 4096
+    big = np.zeros((n_u * n_v, 2))
+    assert _create(n_u, n_v, syn.open_uniform_knots(n_u), syn.open_uniform_knots(n_v), big)[0] == -1
 
 
 @pytest.mark.parametrize("kind", syn.MAPPED_KINDS)
