@@ -66,13 +66,16 @@ __host__ __device__ inline int upper_slot(int di, int dj) {
 // Solver scalars (doubles) and flags (int32) in the workspace, shared by the solvers and read
 // back by the host in one copy.
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
-       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */ };
+       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
+       S_XMAX = 47 };
 enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
 constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
 // Largest PCG relative tolerance of the Eisenstat-Walker forcing term (and its first value):
 // loose under the step-length stopping rule, tighter under the gradient rule, which has to reach
 // the region of fast local convergence.
 constexpr double kEtaMaxStep = 0.5, kEtaMaxGrad = 0.1;
+// Relative size (to |x0|_inf) below which a Newton direction only moves x by rounding.
+constexpr double kStagnation = 16.0 * 2.220446049250313e-16;
 
 // Multigrid levels below the fine grid (knot halvings), at most kMgMaxLevels.
 constexpr int kMgMaxLevels = 6;

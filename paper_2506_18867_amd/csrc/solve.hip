@@ -1086,6 +1086,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
     if (npins > 0) k_apply_pins<<<blocks(npins), kBlock, 0, st>>>(S.n_cp, npins, B.pin_idx, pin_tgt, x);
+    // |x0|_inf: the scale below which a Newton update only moves x by rounding
+    k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, x, B.partials + 7 * stride);
+    k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_XMAX);
     HIPX(hipGetLastError(), "step setup");
 
     bsc_status result = BSC_OK;
@@ -1350,7 +1353,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             ctx->log_count++;
         }
 
-        // ---- |p|_inf for the step rule, line-search coefficients and the trial at alpha = 1 ---
+        // ---- |p|_inf for the stop tests, line-search coefficients and the trial at alpha = 1 ---
         // The energy difference along p: the inertia, gravity and bending terms are quadratics in
         // alpha (coefficients c1, c2), the membrane term is summed point by point.
         hipEvent_t e4 = rec(), e5 = nullptr;
@@ -1360,10 +1363,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             const uint64_t key[8] = {3, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
                                      bits(gz), uint64_t(step_rule ? 1 : 0) | (pub ? 2u : 0u)};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     if (step_rule) {
-                         k_absmax_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.dir, B.partials + 7 * stride);
-                         k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
-                     }
+                     k_absmax_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.dir, B.partials + 7 * stride);
+                     k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
                      k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
                      k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pb, stride);
                      k_sum2_into<<<1, kBlock, 0, cs>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
@@ -1393,6 +1394,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             if (eta <= o->pcg_rtol) break;
             force_tight = true;        // confirm the stop on a direction solved to pcg_rtol
         }
+        // gradient rule: a direction that moves no coordinate by more than a few ulps of |x0|_inf
+        // cannot improve x any further (e.g. a sheet at rest without forces, whose gradient is
+        // rounding alone); the step has converged
+        if (!step_rule && o->fixed_newton_iters <= 0 && scal(S_PMAX) <= kStagnation * hs[S_XMAX]) break;
 
         // ---- backtracking line search on the energy difference ------------------------------
         {
