@@ -184,8 +184,9 @@ def cpu_baseline(bsc_unused=None):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU; runs on several GPUs are not supported "
+              "(a sheet would shard by CP-row strips with a 2-row halo exchange per CG iteration)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_probe > 0:
