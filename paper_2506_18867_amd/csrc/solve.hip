@@ -276,11 +276,22 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // M is the block-Jacobi preconditioner (inverse 3x3 diagonal blocks, in double). One launch of
 // k_cg_fused per iteration (below).
 
+// The PCG set-up of a Newton iteration in one pass over the CPs: the block-Jacobi inverse (the
+// inverse of the 3x3 diagonal block, or its inverse diagonal where that block is not positive
+// definite), the right-hand side b = -g (written 0 - g, so that a zero gradient gives +0) and
+// the initial direction x0 = 0.
 template <typename T>
-__global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv) {
+__global__ void __launch_bounds__(kBlock) k_cg_prep(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv,
+                                                    const double *__restrict__ g, double *__restrict__ b,
+                                                    double *__restrict__ x0) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.n_cp) return;
     const size_t n = S.n_cp;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        b[c * n + a] = 0.0 - g[c * n + a];
+        x0[c * n + a] = 0.0;
+    }
     const double a00 = H[a], a01 = H[n + a], a02 = H[2 * n + a], a11 = H[3 * n + a], a12 = H[4 * n + a], a22 = H[5 * n + a];
     const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
     const double det = a00 * c00 + a01 * c01 + a02 * c02;
@@ -293,6 +304,7 @@ __global__ void k_block_jacobi(DevSheet S, const T *__restrict__ H, T *__restric
         inv[0] = a00 > 0.0 ? 1.0 / a00 : 1.0; inv[1] = inv[2] = 0.0;
         inv[3] = a11 > 0.0 ? 1.0 / a11 : 1.0; inv[4] = 0.0; inv[5] = a22 > 0.0 ? 1.0 / a22 : 1.0;
     }
+#pragma unroll
     for (int t = 0; t < 6; ++t) pinv[t * n + a] = T(inv[t]);
 }
 
@@ -712,28 +724,71 @@ __global__ void k_finish4(const double *__restrict__ part, int stride, int n, do
 
 // ---- line search -------------------------------------------------------------------------
 
-// Quadratic coefficients of the inertia + gravity + bending energy along p:
-// dE(alpha) = alpha c1 + alpha^2 c2 / 2.
-__global__ void __launch_bounds__(kBlock) k_ls_quad_cp(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
-                                                       const double *__restrict__ p, double inv_dt2, double gx, double gy,
-                                                       double gz, double *partials, int stride) {
+// The energy difference along p is dE(alpha) = alpha c1 + alpha^2 c2 / 2 for the inertia,
+// gravity and bending terms (quadratics in alpha) plus the membrane term, summed point by point.
+// Per CP, in one pass over p: partials of c1 and c2 of the inertia and gravity terms and of
+// max |p| (the stop tests).
+__global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
+                                                  const double *__restrict__ p, double inv_dt2, double gx, double gy,
+                                                  double gz, double *partials, int stride, double *__restrict__ pmax_part) {
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
-    double c1 = 0.0, c2 = 0.0;
+    double c1 = 0.0, c2 = 0.0, m = 0.0;
     if (a < S.n_cp) {
         const double M = S.mass[a], g[3] = {gx, gy, gz};
         for (int c = 0; c < 3; ++c) {
             const double pc = p[c * n + a];
             c1 += M * inv_dt2 * pc * (x[c * n + a] - xhat[c * n + a]) - M * g[c] * pc;
             c2 += M * inv_dt2 * pc * pc;
+            m = fmax(m, fabs(pc));
         }
     }
     c1 = block_sum(c1, sh);
     c2 = block_sum(c2, sh);
     if (threadIdx.x == 0) { partials[blockIdx.x] = c1; partials[stride + blockIdx.x] = c2; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
+        pmax_part[blockIdx.x] = m;
+    }
 }
 
+// The line-search scalars in one block, each in a fixed order: max |p| (exact in any order),
+// c1 and c2 over the CP and bending partials, the membrane energy difference at alpha = 1.
+__global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa,
+                                                      const double *__restrict__ pb, int n_beb, int stride,
+                                                      const double *__restrict__ pd, int n_mpb, double *scal) {
+    __shared__ double sh[kBlock / 64];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) m = fmax(m, pm[t]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
+        scal[S_PMAX] = m;
+    }
+    for (int k = 0; k < 2; ++k) {
+        double v = 0.0;
+        for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) v += pa[k * stride + t];
+        for (int t = threadIdx.x; t < n_beb; t += blockDim.x) v += pb[k * stride + t];
+        v = block_sum(v, sh);
+        if (threadIdx.x == 0) scal[S_C1 + k] = v;
+    }
+    double v = 0.0;
+    for (int t = threadIdx.x; t < n_mpb; t += blockDim.x) v += pd[t];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) scal[S_DEM] = v;
+}
+
+// Per bending evaluation: partials of c1 and c2 of the bending term, whose Laplacian is linear
+// in the CPs.
 __global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const double *__restrict__ beD, const double *__restrict__ p,
                                                          double *partials, int stride) {
     __shared__ double sh[kBlock / 64];
@@ -837,14 +892,6 @@ __global__ void k_sum_into(const double *__restrict__ p, int n, double *scal, in
     if (threadIdx.x == 0) scal[slot] = v;
 }
 
-__global__ void k_sum2_into(const double *__restrict__ p, int n0, const double *__restrict__ p1, int n1, double *scal, int slot) {
-    __shared__ double sh[kBlock / 64];
-    double v = 0.0;
-    for (int t = threadIdx.x; t < n0; t += blockDim.x) v += p[t];
-    for (int t = threadIdx.x; t < n1; t += blockDim.x) v += p1[t];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) scal[slot] = v;
-}
 
 // Copies the solver scalars and flags into host-mapped coherent pinned memory, then publishes the
 // next sequence number (kept in the device flags, so that the kernel can sit in a replayed
@@ -862,11 +909,6 @@ __global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal,
         flags[I_PUBSEQ] = seq;
         __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-}
-
-__global__ void k_zero(int n, double *__restrict__ x) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) x[t] = 0.0;
 }
 
 __global__ void k_update(int n, double alpha, const double *__restrict__ p, double *__restrict__ x) {
@@ -1182,10 +1224,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         const double eta_arg = eta_mode == ETA_EXPLICIT ? eta : 0.0;     // used by the explicit mode only
         // block-Jacobi inverse, b = -g, x0 = 0
         auto enqueue_prep = [&](hipStream_t cs) {
-            if (prec == BSC_FP64) k_block_jacobi<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, B.pinv);
-            else k_block_jacobi<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv);
-            k_axpby<<<blocks(n3), kBlock, 0, cs>>>(n3, -1.0, B.g, 0.0, B.g, B.tmp);
-            k_zero<<<blocks(n3), kBlock, 0, cs>>>(n3, B.dir);
+            if (prec == BSC_FP64)
+                k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
+            else
+                k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
         };
         // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
         auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
@@ -1363,14 +1405,14 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             const uint64_t key[8] = {3, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
                                      bits(gz), uint64_t(step_rule ? 1 : 0) | (pub ? 2u : 0u)};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     k_absmax_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.dir, B.partials + 7 * stride);
-                     k_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_PMAX);
-                     k_ls_quad_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride);
+                     // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at
+                     // 7; the membrane difference at 0, free once PCG has finished)
+                     k_ls_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
+                                                                 B.partials + 7 * stride);
                      k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pb, stride);
-                     k_sum2_into<<<1, kBlock, 0, cs>>>(pa, blocks(S.n_cp), pb, blocks(S.n_be), B.scalars, S_C1);
-                     k_sum2_into<<<1, kBlock, 0, cs>>>(pa + stride, blocks(S.n_cp), pb + stride, blocks(S.n_be), B.scalars, S_C2);
-                     k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials + 6 * stride);
-                     k_sum_into<<<1, kBlock, 0, cs>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
+                     k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials);
+                     k_ls_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
+                                                       B.partials, blocks(S.n_mp), B.scalars);
                      if (pub) publish(cs);
                  }), "line search setup");
             e5 = rec();
