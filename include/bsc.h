@@ -118,7 +118,8 @@ typedef struct {
  * iteration, replayed in fixed-size chunks; launches after convergence exit at once):
  * cg_launches counts them, cg_active_launches those that performed an iteration, and
  * ms_cg_kernels is their GPU time from HIP events recorded on the context's stream around
- * each chunk. */
+ * each burst of chunks (one graph launch, which ends with the kernel that publishes the solver
+ * state to the host). */
 typedef struct {
     int32_t newton_iters, pcg_iters_total, ls_halvings, warm_start_used, warm_start_fallbacks;
     double g0_norm, g_norm, energy;

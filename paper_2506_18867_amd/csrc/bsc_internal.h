@@ -226,8 +226,8 @@ struct bsc_ctx {
     bsc::DevBufs buf{};
     bool net_loaded = false;
     std::string err;
-    // replayable chunk of CG iterations (kernel arguments depend only on the workspace)
-    // graphs of 1..8 chunks of CG launches per precision (index [precision][chunks])
+    // replayable bursts of CG iterations (kernel arguments depend only on the workspace): graphs
+    // of 1..8 chunks of launches per precision (index [precision][chunks])
     hipGraphExec_t cg_graph[2][9] = {};
     hipGraphExec_t mg_graph[2][9] = {};      // the same for multigrid-preconditioned CG iterations
     // captured kernel sequences of a Newton iteration, keyed by their launch parameters

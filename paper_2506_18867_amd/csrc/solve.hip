@@ -5,10 +5,12 @@
 // products; the 13 stored blocks of a row (diagonal + upper offsets) are read at the row's own
 // index in 114 coalesced planes, the 12 lower blocks are the transposes of the upper blocks
 // stored at the neighbour rows a - d_s (also coalesced, usually from the same XCD's L2).
-// PCG (Chronopoulos-Gear form): two kernels per iteration, an SpMV that also emits per-block
-// partial dot products and a vector update whose blocks all re-sum those partials in the same
-// fixed order. Scalars live in device memory, nothing uses atomics or in-kernel fences, results
-// are deterministic, and the host only polls a convergence flag every few iterations.
+// PCG (Chronopoulos-Gear form): one fused kernel per iteration (k_cg_fused: the previous
+// iteration's scalars from the partial dot products, the vector updates, the block-Jacobi
+// preconditioner, the SpMV and the new partials); every block re-sums the partials in the same
+// fixed order (large grids: a one-block kernel sums them once per launch). Scalars live in
+// device memory, nothing uses atomics or in-kernel fences, results are deterministic, and the
+// host reads the solver state once per burst of graph-replayed launches.
 // Line search: the energy difference E(x + alpha p) - E(x) is evaluated in double without
 // forming the two energies: the inertia, gravity and bending terms are exact quadratics in
 // alpha (coefficients computed once), and each membrane point evaluates Psi(F + alpha dF) -
