@@ -113,8 +113,9 @@ typedef struct {
     int32_t preconditioner;     /* BSC_PRECOND_JACOBI (default) or BSC_PRECOND_MULTIGRID */
 } bsc_step_opts;
 
-/* Statistics of one step. ms_* are wall-clock phase times on the host (each phase ends with a
- * stream synchronisation). The PCG iterations run as launches of one fused kernel (one per
+/* Statistics of one step. ms_assemble, ms_pcg, ms_linesearch and ms_warmstart are GPU phase
+ * times from HIP events on the context's stream (read once at the end of the step); ms_total is
+ * the host wall-clock time of the call. The PCG iterations run as launches of one fused kernel (one per
  * iteration, replayed in fixed-size chunks; launches after convergence exit at once):
  * cg_launches counts them, cg_active_launches those that performed an iteration, and
  * ms_cg_kernels is their GPU time from HIP events recorded on the context's stream around
