@@ -89,6 +89,8 @@ def parse():
                    help="steps of the general-rest leg (the same driven sheet on a curved domain; 0: skip)")
     p.add_argument("--contact-pairs", type=int, default=100000,
                    help="contact pairs of the contact-Hessian conversion leg (0: skip)")
+    p.add_argument("--start", choices=["predictor", "previous"], default="predictor",
+                   help="first Newton iterate: the inertial predictor x^n + dt v^n, or x^n")
     p.add_argument("--wrinkle-levels", default="16,32,48,64,80,96,112,128",
                    help="spans across the width of the wrinkling-plate convergence leg, comma-separated "
                         "('': skip)")
@@ -122,7 +124,9 @@ def run_steps(ctx, sc, x, v, steps, step0, precision, bsc, torch, args):
                          pcg_rtol=args.pcg_rtol, max_newton=args.max_newton, max_pcg=4000,
                          pcg_adaptive=getattr(args, "adaptive", 0),
                          preconditioner=bsc.BSC_PRECOND_MULTIGRID if getattr(args, "precond", "jacobi") == "mg"
-                         else bsc.BSC_PRECOND_JACOBI)
+                         else bsc.BSC_PRECOND_JACOBI,
+                         start=bsc.BSC_START_PREVIOUS if getattr(args, "start", "predictor") == "previous"
+                         else bsc.BSC_START_PREDICTOR)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -211,6 +215,18 @@ def main():
     if not args.no_fp64:
         x64, v64 = xs.clone(), vs.clone()
         sec64, st64 = run_steps(ctx, sc, x64, v64, args.steps, args.warmup, bsc.BSC_FP64, bsc, torch, args)
+    # the same FP32-mixed steps from the same state, started at x^n instead of the predictor
+    start_leg = None
+    if args.start == "predictor":
+        class _S:
+            pass
+        sa = _S()
+        sa.__dict__.update(vars(args))
+        sa.start = "previous"
+        xp, vp = xs.clone(), vs.clone()
+        secp, stp = run_steps(ctx, sc, xp, vp, args.steps, args.warmup, bsc.BSC_FP32_MIXED, bsc, torch, sa)
+        start_leg = {"ms_per_step": round(1e3 * secp / args.steps, 3),
+                     "newton": sum(s_["newton_iters"] for s_ in stp), "pcg": sum(s_["pcg_iters_total"] for s_ in stp)}
 
     # the configs' gradient tolerance |g| <= 1e-6 |g0| on the first steps from the start state
     grad_leg = None
@@ -221,6 +237,7 @@ def main():
         ga.rtol, ga.atol, ga.stop, ga.pcg_rtol, ga.max_newton = 1e-6, args.atol, "grad", args.pcg_rtol, args.max_newton
         ga.adaptive = args.adaptive
         ga.precond = args.precond
+        ga.start = args.start
         grad_leg = {}
         for name, prec in (("fp32_mixed", bsc.BSC_FP32_MIXED), ("fp64", bsc.BSC_FP64)):
             xg, vg = x0.clone(), v0.clone()
@@ -405,10 +422,12 @@ def main():
                    "pcg": ("multigrid V(1,1)" if args.precond == "mg" else "block-Jacobi") + " PCG, "
                           + ("Eisenstat-Walker tolerance in [%g, %g]" % (args.pcg_rtol, 0.1 if args.stop == "grad" else 0.5)
                              if args.adaptive else "fixed tolerance %g" % args.pcg_rtol),
+                   "newton_start": "inertial predictor x^n + dt v^n" if args.start == "predictor" else "x^n",
                    "parallelism": "single GPU"},
         "newton_step_ms": {"fp32_mixed": round(ms_step32, 3),
                            "fp64": round(1e3 * sec64 / args.steps, 3) if sec64 else None},
         "speedup_vs_fp64": round(sec64 / sec32, 3) if sec64 else None,
+        "start_previous_fp32_mixed": start_leg,
         "grad_tol_1e-6": grad_leg,
         "per_step": {"newton_fp32": [s["newton_iters"] for s in st32], "pcg_fp32": [s["pcg_iters_total"] for s in st32],
                      "halvings_fp32": [s["ls_halvings"] for s in st32],

@@ -98,6 +98,11 @@ typedef struct {
  * prolongation, Galerkin coarse operators, damped block-Jacobi smoothing); used when both span
  * counts are even (otherwise, and with the warm start, the step falls back to JACOBI). */
 enum { BSC_PRECOND_JACOBI = 0, BSC_PRECOND_MULTIGRID = 1 };
+/* First Newton iterate x0 (pinned CPs at their targets in both). PREVIOUS: x^n. PREDICTOR: the
+ * inertial prediction xhat = x^n + dt v^n, the minimiser of the inertia term alone; the paper
+ * leaves the start open (Sec. 5.1 follows IPC, whose x^n start keeps a contact barrier finite;
+ * without contact any start is admissible). */
+enum { BSC_START_PREVIOUS = 0, BSC_START_PREDICTOR = 1 };
 
 typedef struct {
     double dt;
@@ -111,6 +116,7 @@ typedef struct {
     int32_t fixed_newton_iters;
     int32_t pcg_adaptive;
     int32_t preconditioner;     /* BSC_PRECOND_JACOBI (default) or BSC_PRECOND_MULTIGRID */
+    int32_t start;              /* BSC_START_PREVIOUS (default) or BSC_START_PREDICTOR */
 } bsc_step_opts;
 
 /* Statistics of one step. ms_assemble, ms_pcg, ms_linesearch and ms_warmstart are GPU phase
@@ -212,8 +218,8 @@ bsc_status bsc_bsr_pattern(const bsc_ctx *ctx, int32_t *row_ptr, int32_t *col_id
  * values (row-major 3x3 blocks in the order of bsc_bsr_pattern), same precision as d_hess. */
 bsc_status bsc_export_bsr(bsc_ctx *ctx, int32_t precision, const void *d_hess, void *d_bsr_vals);
 
-/* One implicit-Euler step by projected Newton (Sec. 5.1): x0 = x^n with pinned CPs at their
- * targets, xhat = x^n + dt v^n; per iteration assemble, stop test, block-Jacobi PCG for the
+/* One implicit-Euler step by projected Newton (Sec. 5.1): x0 = x^n (or xhat, opts.start) with
+ * pinned CPs at their targets, xhat = x^n + dt v^n; per iteration assemble, stop test, block-Jacobi PCG for the
  * direction on the free DOFs, backtracking from alpha = 1 halving until the energy difference
  * (computed in double) is <= 0, update; finally v = (x - x^n)/dt.
  *   d_x: in x^n, out x^{n+1} (3*n_cp doubles); d_v: in v^n, out v^{n+1}.

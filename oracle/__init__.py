@@ -334,9 +334,12 @@ class NewtonResult:
 
 def newton_step(sheet: Sheet, x_n, v_n, dt: float, gravity, pins=None, pin_targets=None,
                 rtol: float = 1e-6, atol: float | None = None, max_newton: int = 100,
-                fixed_iters: int | None = None, max_halvings: int = 20) -> NewtonResult:
+                fixed_iters: int | None = None, max_halvings: int = 20,
+                start: str = "previous") -> NewtonResult:
     """One implicit-Euler step: minimise E(x) = |x - xhat|_M^2/(2 dt^2) + V(x) from
-    x0 = x_n with pinned CPs at their targets, xhat = x_n + dt v_n.
+    x0 = x_n (``start="previous"``) or x0 = xhat (``start="predictor"``), with pinned CPs at
+    their targets, xhat = x_n + dt v_n. The paper leaves the first iterate open (Sec. 5.1 refers
+    to IPC, whose x_n start serves a contact barrier); both are the same minimisation.
 
     Each iteration: gradient and projected Hessian; stop when |g_free| <= rtol |g0_free|
     (or, with ``atol``, when |p|_inf / dt <= atol); exact direction by sparse LU;
@@ -346,7 +349,9 @@ def newton_step(sheet: Sheet, x_n, v_n, dt: float, gravity, pins=None, pin_targe
     x_n = _f64(x_n).reshape(-1, 3)
     v_n = _f64(v_n).reshape(-1, 3)
     xhat = x_n + dt * v_n
-    x = x_n.copy()
+    if start not in ("previous", "predictor"):
+        raise ValueError("start must be 'previous' or 'predictor'")
+    x = (xhat if start == "predictor" else x_n).copy()
     mask = np.zeros(sheet.n_cp, dtype=bool)
     if pins is not None and len(pins):
         pins = np.asarray(pins, dtype=np.int64)

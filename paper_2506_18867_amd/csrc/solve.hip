@@ -1129,6 +1129,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
+    if (o->start == BSC_START_PREDICTOR)
+        HIPX(hipMemcpyAsync(x, B.xhat, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "predictor start");
     if (npins > 0) k_apply_pins<<<blocks(npins), kBlock, 0, st>>>(S.n_cp, npins, B.pin_idx, pin_tgt, x);
     // |x0|_inf: the scale below which a Newton update only moves x by rounding
     k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, x, B.partials + 7 * stride);
@@ -1514,6 +1516,7 @@ bsc_status bsc_newton_step(bsc_ctx *c, const bsc_step_opts *o, double *d_x, doub
     if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(c, BSC_E_INVAL, "dt must be positive");
     if (o->precision != BSC_FP64 && o->precision != BSC_FP32_MIXED) return fail(c, BSC_E_INVAL, "bad precision");
     if (o->stop_mode != BSC_STOP_GRAD && o->stop_mode != BSC_STOP_STEP) return fail(c, BSC_E_INVAL, "bad stop mode");
+    if (o->start != BSC_START_PREVIOUS && o->start != BSC_START_PREDICTOR) return fail(c, BSC_E_INVAL, "bad start");
     if (o->max_newton < 1 || o->max_pcg < 1 || !(o->pcg_rtol > 0.0)) return fail(c, BSC_E_INVAL, "bad iteration limits");
     if (!c->pins.empty() && !d_pin_targets) return fail(c, BSC_E_INVAL, "pins set but no targets");
     if (o->warm_start && !c->net_loaded) return fail(c, BSC_E_STATE, "warm start requested but no network loaded");

@@ -200,6 +200,48 @@ def test_newton_fp64_iterates_match_oracle(iters):
     assert abs(stats.g0_norm - ref.g0_norm) < 1e-10 * ref.g0_norm
 
 
+@pytest.mark.parametrize("iters", [1, 2])
+def test_newton_predictor_start_iterates_match_oracle(iters):
+    """BSC_START_PREDICTOR: the first iterate is xhat = x_n + dt v_n (pins at their targets).
+    A hanging sheet moving with a smooth velocity field; FP64 iterates against the oracle's exact
+    solves from the same start."""
+    sc = syn.hanging_sheet(20, seed=1)
+    v0 = syn.smooth_field(20, 20, 9, amp=0.3)
+    v0[sc.pins] = 0.0
+    sh = oracle_sheet(sc)
+    ctx = _ctx(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), fixed_newton_iters=iters, pcg_rtol=1e-14, max_pcg=20000,
+                         start=bsc.BSC_START_PREDICTOR)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    ref = oracle.newton_step(sh, sc.x0, v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=iters,
+                             start="predictor")
+    err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
+    print(f"[newton predictor fp64] iters={iters} rel err of x - x0: {err:.2e}")
+    assert err < TOL64
+    assert relerr(bsc.to_aos(v), ref.v) < TOL64
+    assert abs(stats.g0_norm - ref.g0_norm) < 1e-10 * ref.g0_norm
+
+
+@pytest.mark.parametrize("precision", [bsc.BSC_FP64, bsc.BSC_FP32_MIXED])
+@pytest.mark.parametrize("start", [bsc.BSC_START_PREVIOUS, bsc.BSC_START_PREDICTOR])
+def test_predictor_start_step_rule_converges(precision, start):
+    """Both starts under the paper's step rule on the driven sheet over three steps (velocities
+    from the previous steps): every step meets |p|_inf / dt <= atol with status OK."""
+    sc = syn.driven_sheet(60, seed=305)
+    ctx = _ctx(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, stop_mode=bsc.BSC_STOP_STEP,
+                         atol=1e-2, pcg_adaptive=1, pcg_rtol=1e-3, start=start)
+    its = []
+    for k in range(3):
+        st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(k)), opts)
+        assert st == 0
+        its.append(stats.newton_iters)
+    print(f"[start {start} precision {precision}] Newton iterations per step {its}")
+
+
 @pytest.mark.parametrize("precision", [bsc.BSC_FP64, bsc.BSC_FP32_MIXED])
 @pytest.mark.parametrize("scene", ["compressed2", "driven"])
 def test_newton_converges_to_fp64_tolerance(precision, scene):

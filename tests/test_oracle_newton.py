@@ -47,6 +47,26 @@ def test_hanging_step_converges_and_is_a_stationary_point():
     assert res.v[~mask, 1].mean() < 0
 
 
+def test_both_starts_reach_the_same_step():
+    """The paper leaves the first Newton iterate open: x_n and the inertial prediction
+    xhat = x_n + dt v_n start the same minimisation. On a sheet moving with a smooth velocity
+    field both reach the same stationary point, and the predictor start, where the inertia term's
+    gradient vanishes, begins with a smaller gradient."""
+    sc = syn.hanging_sheet(10, seed=2)
+    sh = sheet_from_scene(sc)
+    v = syn.smooth_field(10, 10, 8, amp=0.3)
+    v[sc.pins] = 0.0
+    # (1e-7: tighter, the oracle's plain energy comparison meets FP64 rounding of E)
+    a = oracle.newton_step(sh, sc.x0, v, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), rtol=1e-7)
+    b = oracle.newton_step(sh, sc.x0, v, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), rtol=1e-7,
+                           start="predictor")
+    d = np.linalg.norm(b.x - a.x) / np.linalg.norm(a.x - sc.x0)
+    assert d < 1e-5
+    assert b.g0_norm < a.g0_norm
+    with pytest.raises(ValueError):
+        oracle.newton_step(sh, sc.x0, v, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), start="xhat")
+
+
 def test_quadratic_energy_needs_one_newton_iteration():
     """Bending plus inertia only (zero membrane stiffness) is quadratic: one Newton iteration
     lands on the minimiser, which equals a dense solve of the same linear system."""
