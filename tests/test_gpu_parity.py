@@ -201,6 +201,39 @@ def test_newton_fp64_iterates_match_oracle(iters):
 
 
 @pytest.mark.parametrize("iters", [1, 2])
+def test_newton_fbw_iterates_match_oracle(iters):
+    """The FBW membrane (Sec. 4.1) through the whole Newton step: assembly, PCG and the line
+    search's per-point energy difference, FP64 iterates against the oracle's exact solves. A
+    hanging sheet compressed by 10% across, so that the projection clamps at many points."""
+    sc = syn.hanging_sheet(14, seed=6, material=syn.Material(1, 0.0, 0.0, 0.0, 3.0, 2.0, 0.7, 1e-3, 0.2))
+    sc.x0[:, 0] *= 0.9
+    sc.pin_rest = sc.x0[sc.pins].copy()
+    sh = oracle_sheet(sc)
+    ctx = _ctx(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), fixed_newton_iters=iters, pcg_rtol=1e-14, max_pcg=20000)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=iters)
+    err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
+    print(f"[newton fbw fp64] iters={iters} halvings={stats.ls_halvings} (oracle {ref.alphas}) rel err of x - x0: {err:.2e}")
+    assert err < TOL64
+    assert relerr(bsc.to_aos(v), ref.v) < TOL64
+
+
+@pytest.mark.parametrize("precision", [bsc.BSC_FP64, bsc.BSC_FP32_MIXED])
+def test_newton_fbw_converges(precision):
+    sc = syn.hanging_sheet(20, seed=7, material=syn.Material(1, 0.0, 0.0, 0.0, 3.0, 2.0, 0.7, 1e-3, 0.2))
+    ctx = _ctx(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=1e-6, pcg_rtol=1e-3,
+                         pcg_adaptive=1, max_newton=200)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    assert stats.g_norm <= 1e-6 * stats.g0_norm
+
+
+@pytest.mark.parametrize("iters", [1, 2])
 def test_newton_predictor_start_iterates_match_oracle(iters):
     """BSC_START_PREDICTOR: the first iterate is xhat = x_n + dt v_n (pins at their targets).
     A hanging sheet moving with a smooth velocity field; FP64 iterates against the oracle's exact
