@@ -221,6 +221,34 @@ def test_newton_fbw_iterates_match_oracle(iters):
     assert relerr(bsc.to_aos(v), ref.v) < TOL64
 
 
+@pytest.mark.parametrize("variant", ["spacing2_sheared", "gauss2", "corner2"])
+def test_newton_iterates_match_oracle_on_variants(variant):
+    """Two Newton iterates (FP64, PCG to 1e-14) against the oracle on a knot spacing of 2 with a
+    sheared, non-square rest, and on two of the ablation's comparison rules (the line search then
+    sums the energy difference over those rules' points)."""
+    n_u, n_v = 11, 9
+    spacing, shear, rule = (2, 0.25, bsc.BSC_QUAD_REDUCED) if variant == "spacing2_sheared" else \
+        (1, 0.0, bsc.BSC_QUAD_GAUSS2 if variant == "gauss2" else bsc.BSC_QUAD_CORNER2)
+    ku, kv, rest = syn.flat_sheet(n_u, n_v, 1.0, 0.8, spacing=spacing, shear=shear)
+    mat = syn.stvk_material(young=1e4, thickness=1e-3, mu_bend=2e-3)
+    x0 = syn.embed(rest)
+    x0[:, 2] += 0.002 * syn.smooth_field(n_u, n_v, 11, amp=1.0)[:, 2]
+    pins = np.array([0, n_u - 1], dtype=np.int64)
+    sc = syn.Scene(variant, n_u, n_v, ku, kv, rest, mat, x0, np.zeros_like(x0), pins, x0[pins].copy(), 0.01,
+                   np.array([0.0, -9.81, 0.0]))
+    sh = oracle_sheet(sc)
+    sh.quadrature = rule
+    ctx = bsc.context_for_scene(sc, quadrature=rule)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), fixed_newton_iters=2, pcg_rtol=1e-14, max_pcg=20000)
+    st, _ = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=2)
+    err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
+    print(f"[newton {variant}] rel err of x - x0: {err:.2e}")
+    assert err < TOL64
+
+
 @pytest.mark.parametrize("precision", [bsc.BSC_FP64, bsc.BSC_FP32_MIXED])
 def test_newton_fbw_converges(precision):
     sc = syn.hanging_sheet(20, seed=7, material=syn.Material(1, 0.0, 0.0, 0.0, 3.0, 2.0, 0.7, 1e-3, 0.2))
