@@ -237,6 +237,8 @@ struct bsc_ctx {
     };
     std::vector<SeqGraph> seq_graphs;
     bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
+    // PCG iterations of the previous step's solves, by Newton iteration (sizes first bursts)
+    int pcg_hist[64] = {};
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)
     float *log_g = nullptr, *log_p = nullptr;
     int log_cap = 0, log_count = 0;

@@ -1343,11 +1343,14 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             return gxe;
         };
         // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
-        // exit at once, in about 3 us, while a burst boundary costs a host round trip of tens of
-        // us). The first burst is two chunks; after each burst the host extrapolates the
+        // exit at once, in about 3 us, while a burst boundary costs a host round trip). The first
+        // burst covers the iterations that the same Newton iteration of the previous step needed
+        // plus four (two chunks without such a record); after each burst the host extrapolates the
         // residual's geometric decay to the stopping threshold and sizes the next burst to cover
         // the iterations that remain plus half a chunk.
         int burst = 2, done_prev = 0;
+        if (!use_mg && it < 64 && ctx->pcg_hist[it] > 0)
+            burst = std::max(1, std::min(8, (ctx->pcg_hist[it] + 4 + chunk) / chunk));
         double lrho_prev = 0.0;
         bool have_prev = false;
         while (true) {
@@ -1389,6 +1392,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         }
         hipEvent_t e3 = rec();
         s.cg_active_launches += flags[I_ITERS];
+        if (it < 64) ctx->pcg_hist[it] = flags[I_ITERS];
         s.pcg_iters_total += flags[I_ITERS];
         if (flags[I_BREAK]) { result = BSC_E_PCG_BREAKDOWN; break; }
         if (ctx->log_count < ctx->log_cap) {
