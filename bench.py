@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # was evicted first (`bench.py --copy-probe 1024`: FETCH_SIZE 0.500, WRITE_SIZE 1.000 of the
 # bytes). Summary and commands: profiles/k_cg_fused_226_traffic.md. Valid only for the kernel
 # source it was measured on (hash of its text in solve.hip); otherwise reported as null.
-CG_TRAFFIC = {"kernel_sha256_16": "9020f57fa3cbcbc5", "fetch_kib": 16387.5, "write_kib": 5442.0,
+CG_TRAFFIC = {"kernel_sha256_16": "9020f57fa3cbcbc5", "fetch_kib": 16388.2, "write_kib": 5441.9,
               "fetch_factor": 0.500, "write_factor": 1.000}
 
 
