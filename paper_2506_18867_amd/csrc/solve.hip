@@ -52,19 +52,6 @@ __device__ double block_sum(double v, double *sh) {
     return v;          // valid in thread 0
 }
 
-// Every block of a kernel re-sums the partials of the previous kernel in the same order, so
-// all blocks obtain bitwise-identical scalars without atomics or fences; the result is
-// broadcast to the whole block.
-__device__ double sum_partials(const double *p, int n, double *sh, double *bcast) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) v += p[t];
-    v = block_sum(v, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) *bcast = v;
-    __syncthreads();
-    return *bcast;
-}
-
 // Block-wide sums of three values at once (one LDS round trip); valid in every thread.
 __device__ void block_sum3(double v[3], double *sh /* 3 * 16 */) {
 #pragma unroll
