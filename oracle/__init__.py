@@ -29,23 +29,29 @@ _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 _lib = None
 
 
-def build() -> str:
-    """Compiles ``bsc_oracle.c`` with gcc into ``oracle/_build/liboracle.so``."""
-    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+def build(src: str = _SRC, out: str = _LIB_PATH) -> str:
+    """Compiles ``bsc_oracle.c`` (or another copy of it) with gcc into ``oracle/_build/liboracle.so``
+    (or ``out``)."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    # BSC_ORACLE_LIB names another build of the C source (the pin-strength test loads copies
+    # with planted mistakes this way); without it the library is rebuilt when stale.
+    path = os.environ.get("BSC_ORACLE_LIB")
+    if not path:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        path = _LIB_PATH
+    lib = ctypes.CDLL(path)
     d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
     lib.or_basis.restype = d
     lib.or_basis.argtypes = [p, i, i, d]

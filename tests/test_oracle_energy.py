@@ -110,6 +110,22 @@ def test_affine_deformation_is_exact(shear, spacing):
     assert abs(E - area * psi) < 1e-12 * area * psi
 
 
+def test_fbw_affine_field_energy_closed_form():
+    """FBW on a whole sheet (Sec. 4.1, warp along u, weft along v): x = (s1 X + c Y, s2 Y, 0)
+    gives f1 = (s1, 0, 0), f2 = (c, s2, 0) at every point, so E = area * (mu_sh (s1 c)^2 +
+    mu_st1 (s1 - 1)^2 + mu_st2 (sqrt(c^2 + s2^2) - 1)^2), with three distinct moduli so that
+    each is matched to its own invariant."""
+    mu1, mu2, msh = 2.0, 5.0, 0.7
+    sh = make_sheet(9, 7, 1.0, 0.8, membrane=1, mu_fbw=(mu1, mu2, msh))
+    s1, s2, c = 1.15, 0.9, 0.25
+    X, Y = sh.rest[:, 0], sh.rest[:, 1]
+    x = np.stack([s1 * X + c * Y, s2 * Y, np.zeros_like(X)], axis=1)
+    E, _, _ = oracle.assemble(sh, x, want_hessian=False)
+    psi = msh * (s1 * c) ** 2 + mu1 * (s1 - 1) ** 2 + mu2 * (np.hypot(c, s2) - 1) ** 2
+    area = 1.0 * 0.8
+    assert abs(E - area * psi) < 1e-12 * area * psi
+
+
 def test_rigid_motion_has_zero_energy_and_gradient():
     sh = make_sheet(10, shear=0.2)
     from scipy.spatial.transform import Rotation

@@ -1,0 +1,184 @@
+"""Strength of the oracle's pins (CPU only).
+
+Each case plants one plausible mistake in a copy of the C oracle: a dropped factor, a flipped
+sign, a transposed operand or index, a misplaced quadrature point or weight. The copy is built
+with gcc and the oracle's pin tests (``tests/test_oracle_*.py``) run against it in a child
+process; the loader takes the library from ``BSC_ORACLE_LIB``. Every mutant must make at least
+one pin fail with an assertion, and the unmodified copy, built and loaded the same way, must pass
+all of them. The pins compare the oracle with closed forms, brute force, finite differences,
+library routines and the invariants of the method, never with the oracle itself, so a mutant
+that no pin catches would be a mistake that the GPU parity tests inherit unseen.
+
+The Python parts of the oracle (the Newton loop, the contact conversion, the network) are pinned
+by their own tests and are not mutated here.
+"""
+from __future__ import annotations
+
+import os
+import re
+import shutil
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "bsc_oracle.c")
+
+# (name, [(old, new), ...]): each old text must occur in the source; its first occurrence is
+# replaced.
+MUTANTS = [
+    # basis (Sec. 3.1.1)
+    ("basis_right_term_index",
+     [("* or_basis(xi, i + 1, p - 1, u);", "* or_basis(xi, i, p - 1, u);")]),
+    ("basis_derivative_sign", [("    return left - right;\n}", "    return left + right;\n}")]),
+    ("dv_along_u", [("B->Nv[m] = Ru[a][0] * Rv[b][1] * hv;", "B->Nv[m] = Ru[a][1] * Rv[b][0] * hv;")]),
+    ("duv_missing_v_derivative",
+     [("B->Nuv[m] = Ru[a][1] * hu * Rv[b][1] * hv;", "B->Nuv[m] = Ru[a][1] * hu * Rv[b][0] * hv;")]),
+    ("du_missing_knot_spacing", [("B->Nu[m] = Ru[a][1] * hu * Rv[b][0];", "B->Nu[m] = Ru[a][1] * Rv[b][0];")]),
+    # rest geometry (Sec. 4.1 inverse function theorem, Sec. 4.2 second derivatives)
+    ("inverse_jacobian_transposed",
+     [("K[0][1] = -J[0][1] / det;", "K[0][1] = -J[1][0] / det;"),
+      ("K[1][0] = -J[1][0] / det;", "K[1][0] = -J[0][1] / det;")]),
+    ("inverse_derivative_sign", [("dK[p][r][c] = -s;", "dK[p][r][c] = s;")]),
+    ("laplacian_cross_term_halved", [("lap[4] = 2.0 * (", "lap[4] = (")]),
+    ("weight_without_jacobian", [("return wbar * fabs(detJ);", "return wbar;")]),
+    # membrane densities (Sec. 4.1)
+    ("stvk_energy_lambda_doubled",
+     [("*psi = mu * EE + 0.5 * lam * trE * trE;", "*psi = mu * EE + lam * trE * trE;")]),
+    ("stvk_hessian_term_transposed", [("mu * F[i][d] * F[j][g]", "mu * F[i][g] * F[j][d]")]),
+    ("green_strain_offdiagonal_unhalved", [("0.5 * C[0][1]}", "C[0][1]}")]),
+    ("shear_modulus_unhalved",
+     [("double mu = S->young * S->thickness / (2.0 * (1.0 + S->poisson));",
+       "double mu = S->young * S->thickness / (1.0 + S->poisson);")]),
+    ("lambda_of_3d_elasticity",
+     [("double lam = S->young * S->thickness * S->poisson / (1.0 - S->poisson * S->poisson);",
+       "double lam = S->young * S->thickness * S->poisson / ((1.0 + S->poisson) * (1.0 - 2.0 * S->poisson));")]),
+    ("fbw_stretch_stress_halved",
+     [("2.0 * mu[g] * (1.0 - 1.0 / len[g]) * f[g][i];", "mu[g] * (1.0 - 1.0 / len[g]) * f[g][i];")]),
+    ("fbw_shear_hessian_transposed",
+     [("(f[d][i] * f[g][j] + (i == j ? I6 : 0.0))", "(f[g][i] * f[d][j] + (i == j ? I6 : 0.0))")]),
+    # projection (Sec. 5.1)
+    ("projection_absolute_eigenvalues", [("lam[r] = A[r][r] > 0.0 ? A[r][r] : 0.0;", "lam[r] = fabs(A[r][r]);")]),
+    # element gradient and Hessian (Sec. 4.1, 4.2)
+    ("membrane_gradient_wrong_direction",
+     [("P[i][0] * dN[m][0] + P[i][1] * dN[m][1]", "P[i][0] * dN[m][0] + P[i][1] * dN[m][0]")]),
+    ("membrane_hessian_operands_transposed",
+     [("s += dN[m][ga] * A[3 * ga + i][3 * de + j] * dN[n][de];",
+       "s += dN[m][de] * A[3 * ga + i][3 * de + j] * dN[n][ga];")]),
+    ("bending_laplacian_first_order_swapped",
+     [("lap[2] * B.Nu[m] + lap[3] * B.Nv[m]", "lap[3] * B.Nu[m] + lap[2] * B.Nv[m]")]),
+    ("bending_energy_unhalved", [("*E += w * 0.5 * mu * (dphi[0]", "*E += w * mu * (dphi[0]")]),
+    # quadrature (Appendix A)
+    ("gauss2_offset_not_in_span_units", [("G2 = 0.28867513459481288225", "G2 = 0.57735026918962576451")]),
+    ("gauss3_equal_weights",
+     [("w[0] = 5.0 / 18.0; w[1] = 8.0 / 18.0; w[2] = 5.0 / 18.0;", "w[0] = 1.0 / 3.0; w[1] = 1.0 / 3.0; w[2] = 1.0 / 3.0;")]),
+    ("side_spans_points_swapped", [("nu = bu ? 3 : 2; nv = bv ? 3 : 2;", "nu = bu ? 2 : 3; nv = bv ? 2 : 3;")]),
+    ("checkerboard_flipped", [("} else if ((a + b) % 2 == 0) {", "} else if ((a + b) % 2 == 1) {")]),
+    ("edge_half_cell_full_weight", [("np = 2; w = 0.25;", "np = 2; w = 0.5;")]),
+    ("bending_knot_weight_not_quartered", [("double w = lu * lv * 0.25;", "double w = lu * lv;")]),
+    ("bending_knot_wrong_span",
+     [("cnt = push(out, cap, cnt, a, b, w, a - 1, b);", "cnt = push(out, cap, cnt, a, b, w, a - 1, b - 1);")]),
+    # mass, inertia, gravity, assembly and pins (Sec. 3.2, 5.1)
+    ("mass_diagonal_instead_of_row_sum",
+     [("row += S->rho_area * B.N[m] * B.N[n];", "row += S->rho_area * B.N[m] * B.N[m];")]),
+    ("inertia_energy_unhalved", [("E += 0.5 * M[a] * inv_dt2 * d * d;", "E += M[a] * inv_dt2 * d * d;")]),
+    ("inertia_hessian_without_dt", [("+= M[a] * inv_dt2;", "+= M[a];")]),
+    ("gravity_gradient_sign", [("g[3 * a + i] -= M[a] * grav[i];", "g[3 * a + i] += M[a] * grav[i];")]),
+    ("stencil_slot_transposed",
+     [("int s = (bn - bm + 2) * 5 + (an - am + 2);", "int s = (an - am + 2) * 5 + (bn - bm + 2);")]),
+    ("pin_mirror_block_not_mirrored",
+     [("int sb = (-dj + 2) * 5 + (-di + 2);", "int sb = (dj + 2) * 5 + (di + 2);")]),
+    ("pinned_gradient_kept",
+     [("for (int i = 0; i < 3; ++i) g[3 * a + i] = 0.0;", "for (int i = 0; i < 3; ++i) g[3 * a + i] += 0.0;")]),
+    # further consistent mistakes (energy, gradient and Hessian all agree) and variant rules
+    ("laplacian_u_term_transposed",
+     [("lap[0] = K[0][0] * K[0][0] + K[0][1] * K[0][1];", "lap[0] = K[0][0] * K[0][0] + K[1][0] * K[1][0];")]),
+    ("bending_modulus_doubled", [("double mu = S->mu_bend;", "double mu = 2.0 * S->mu_bend;")]),
+    ("stvk_stress_mu_halved", [("Sm[g][d] = 2.0 * mu * E[g][d]", "Sm[g][d] = mu * E[g][d]")]),
+    ("green_strain_diagonal_sign", [("0.5 * (C[0][0] - 1.0)", "0.5 * (1.0 - C[0][0])")]),
+    ("fbw_moduli_swapped_at_points",
+     [("fbw_density(F, S->mu_st1, S->mu_st2, S->mu_sh, &psi, P, A);",
+       "fbw_density(F, S->mu_st2, S->mu_st1, S->mu_sh, &psi, P, A);")]),
+    ("jacobi_single_sweep", [("sweep < 100;", "sweep < 1;")]),
+    ("jacobi_rotation_sign", [("A[k][p] = c * akp - s * akq;", "A[k][p] = c * akp + s * akq;")]),
+    ("bending_boundary_span_half_weight",
+     [("cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 1.0, k, l);\n    if (quad == OR_QUAD_GAUSS2) {",
+       "cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 0.5, k, l);\n    if (quad == OR_QUAD_GAUSS2) {")]),
+    ("interior1_midpoint_half_weight",
+     [("cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 1.0, k, l);   /* span midpoint */",
+       "cnt = push(out, cap, cnt, k + 0.5, l + 0.5, 0.5, k, l);   /* span midpoint */")]),
+    ("corner2_rule_ignored", [("nu = nv = (quad == OR_QUAD_CORNER2) ? 2 : 3;", "nu = nv = 3;")]),
+    ("gauss2_bending_interior_weight",
+     [("l + 0.5 + o[b], w[a] * w[b], k, l);", "l + 0.5 + o[b], w[a], k, l);")]),
+    ("surface_top_edge_not_clamped", [("if (v >= vmax) v = vmax * (1.0 - 1e-15);", "(void)vmax;")]),
+    ("surface_basis_in_wrong_parameter",
+     [("double Ni = or_basis(S->knots_u, i, 2, u);", "double Ni = or_basis(S->knots_u, i, 2, v);")]),
+]
+
+PIN_FILES = sorted(f for f in os.listdir(os.path.join(ROOT, "tests"))
+                   if f.startswith("test_oracle_") and f.endswith(".py"))
+
+
+def _mutate(text: str, edits) -> str:
+    for old, new in edits:
+        assert old in text, "mutation site not found: %r" % old
+        text = text.replace(old, new, 1)
+    return text
+
+
+def _run_pins(tmp: str, name: str, text: str):
+    """Builds one copy of the source and runs the pin tests against it; returns
+    (return code, first failing test or None, tail of the output)."""
+    src = os.path.join(tmp, name + ".c")
+    with open(src, "w") as f:
+        f.write(text)
+    lib = oracle.build(src, os.path.join(tmp, name + ".so"))
+    env = dict(os.environ, BSC_ORACLE_LIB=lib, PYTHONDONTWRITEBYTECODE="1")
+    env.setdefault("OMP_NUM_THREADS", "1")
+    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-rf", "-p", "no:cacheprovider", "-m", "not gpu"]
+    cmd += [os.path.join("tests", f) for f in PIN_FILES]
+    res = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    out = res.stdout + res.stderr
+    m = re.search(r"^FAILED (\S+)", out, re.M)
+    return res.returncode, (m.group(1) if m else None), out[-1500:]
+
+
+@pytest.fixture(scope="module")
+def mutant_results():
+    base = open(SRC).read()
+    tmp = tempfile.mkdtemp(prefix="bsc_mutants_")
+    jobs = [("control", base)] + [(name, _mutate(base, edits)) for name, edits in MUTANTS]
+    try:
+        with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+            futs = {name: ex.submit(_run_pins, tmp, name, text) for name, text in jobs}
+            res = {name: f.result() for name, f in futs.items()}
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    for name, (rc, first, _) in res.items():
+        print("%-40s rc=%d  %s" % (name, rc, first or "-"))
+    return res
+
+
+def test_every_mutation_site_exists():
+    base = open(SRC).read()
+    for name, edits in MUTANTS:
+        text = _mutate(base, edits)
+        assert text != base, name
+
+
+def test_unmodified_copy_passes_every_pin(mutant_results):
+    rc, first, tail = mutant_results["control"]
+    assert rc == 0, tail
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+def test_pins_catch_mutant(mutant_results, name):
+    rc, first, tail = mutant_results[name]
+    # 1 = some test failed (an assertion or an error raised by the oracle); anything else would
+    # be a crash or a collection problem, which says nothing about the pins
+    assert rc == 1 and first is not None, "mutant %s survived the pins (rc=%d):\n%s" % (name, rc, tail)
