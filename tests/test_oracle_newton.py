@@ -3,7 +3,9 @@
 Pinned against: conservation of linear momentum without pins or gravity (the contact-free
 form of the paper's two-plate test, Sec. 6.1), the Kirchhoff simply-supported plate closed
 form of the paper's bending benchmark (Sec. 6.2, "Convergence under Refinement (Bending)"),
-and one-iteration exactness on a quadratic energy checked by an independent dense solve."""
+one-iteration exactness on a quadratic energy checked by an independent dense solve, pinned
+CPs at moved targets, the step rule's stop against dense-solve directions, and the first
+direction against a dense solve with the projected Hessian where projection matters."""
 import numpy as np
 import pytest
 
@@ -83,6 +85,66 @@ def test_quadratic_energy_needs_one_newton_iteration():
     dense = oracle.stencil_to_csr(sh, H0).toarray()
     p = np.linalg.solve(dense, -g0.reshape(-1))
     assert np.allclose(res.x.reshape(-1), x0.reshape(-1) + p, atol=1e-12 * np.abs(x0).max())
+
+
+def test_pinned_cps_reach_moved_targets():
+    """Dirichlet conditions (Sec. 5.1): pinned CPs end at their targets whatever x_n was, and
+    their velocity is (target - x_n) / dt; the free CPs end at a stationary point."""
+    sc = syn.hanging_sheet(10, seed=5)
+    sh = sheet_from_scene(sc)
+    targets = sc.x0[sc.pins] + np.array([[0.02, -0.01, 0.015], [-0.02, 0.005, 0.01]])
+    # (1e-6: tighter, the oracle's plain energy comparison meets FP64 rounding of E)
+    res = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, targets, rtol=1e-6)
+    assert np.array_equal(res.x[sc.pins], targets)
+    assert np.allclose(res.v[sc.pins], (targets - sc.x0[sc.pins]) / sc.dt, rtol=1e-12, atol=0)
+    assert res.g_norm <= 1e-6 * res.g0_norm
+
+
+def _dense_direction(sh, x, xhat, dt, gravity, mask, project=True):
+    _, g, H = oracle.assemble(sh, x, xhat, dt, gravity, mask, project=project)
+    A = oracle.stencil_to_csr(sh, H).toarray()
+    return np.linalg.solve(A, -g.reshape(-1)).reshape(-1, 3), A
+
+
+def test_step_rule_stops_at_the_first_small_direction():
+    """The paper's stopping rule (Sec. 6): stop once the Newton direction p at the current
+    iterate has |p|_inf / dt <= atol. At the returned iterate the direction (recomputed by a
+    dense solve) meets the bound and at the iterate before it does not; dt = 0.01 makes the
+    division by dt matter."""
+    sc = syn.compressed_sheet(10, seed=3)
+    sh = sheet_from_scene(sc)
+    v = syn.smooth_field(10, 10, 9, amp=0.5)
+    v[sc.pins] = 0.0
+    xhat = sc.x0 + sc.dt * v
+    mask = np.zeros(sh.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    atol = 1e-3
+    res = oracle.newton_step(sh, sc.x0, v, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), atol=atol)
+    assert res.iters >= 2
+    p, _ = _dense_direction(sh, res.x, xhat, sc.dt, sc.gravity, mask)
+    assert np.abs(p).max() / sc.dt <= atol
+    prev = oracle.newton_step(sh, sc.x0, v, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0),
+                              fixed_iters=res.iters - 1)
+    p, _ = _dense_direction(sh, prev.x, xhat, sc.dt, sc.gravity, mask)
+    assert np.abs(p).max() / sc.dt > atol
+
+
+def test_newton_direction_uses_the_projected_hessian():
+    """Projected Newton (Sec. 5.1): on a compressed sheet, where per-point projection changes
+    the Hessian and the unprojected system is indefinite, the first step is alpha_0 times the
+    dense solve with the projected Hessian, and that direction descends."""
+    sc = syn.compressed_sheet(10, seed=4, compression=0.2)
+    sh = sheet_from_scene(sc)
+    mask = np.zeros(sh.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    p, A = _dense_direction(sh, sc.x0, sc.x0, 1.0, sc.gravity, mask)
+    _, A_raw = _dense_direction(sh, sc.x0, sc.x0, 1.0, sc.gravity, mask, project=False)
+    assert np.linalg.eigvalsh(A).min() > 0 > np.linalg.eigvalsh(A_raw).min()
+    _, g, _ = oracle.assemble(sh, sc.x0, sc.x0, 1.0, sc.gravity, mask, want_hessian=False)
+    assert float(np.sum(g * p)) < 0
+    res = oracle.newton_step(sh, sc.x0, sc.v0, 1.0, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=1)
+    step = res.x - sc.x0
+    assert np.allclose(step, res.alphas[0] * p, rtol=0, atol=1e-10 * np.abs(step).max())
 
 
 def plate_deflection(N):

@@ -1,16 +1,14 @@
 """Strength of the oracle's pins (CPU only).
 
-Each case plants one plausible mistake in a copy of the C oracle: a dropped factor, a flipped
-sign, a transposed operand or index, a misplaced quadrature point or weight. The copy is built
-with gcc and the oracle's pin tests (``tests/test_oracle_*.py``) run against it in a child
-process; the loader takes the library from ``BSC_ORACLE_LIB``. Every mutant must make at least
-one pin fail with an assertion, and the unmodified copy, built and loaded the same way, must pass
-all of them. The pins compare the oracle with closed forms, brute force, finite differences,
-library routines and the invariants of the method, never with the oracle itself, so a mutant
-that no pin catches would be a mistake that the GPU parity tests inherit unseen.
-
-The Python parts of the oracle (the Newton loop, the contact conversion, the network) are pinned
-by their own tests and are not mutated here.
+Each case plants one plausible mistake in a copy of the oracle package: a dropped factor, a
+flipped sign, a transposed operand or index, a misplaced quadrature point or weight, a wrong
+update in the Newton loop. The copy's C source is built with gcc (the loader takes the library
+from ``BSC_ORACLE_LIB``) and the oracle's pin tests (``tests/test_oracle_*.py``) run in a child
+process that imports the copy as ``oracle``. Every mutant must make at least one pin fail, and
+the unmodified copy, built and imported the same way, must pass all of them. The pins compare
+the oracle with closed forms, brute force, finite differences, library routines and the
+invariants of the method, never with the oracle itself, so a mutant that no pin catches would be
+a mistake that the GPU parity tests inherit unseen.
 """
 from __future__ import annotations
 
@@ -27,11 +25,10 @@ import pytest
 import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "oracle", "bsc_oracle.c")
 
-# (name, [(old, new), ...]): each old text must occur in the source; its first occurrence is
-# replaced.
-MUTANTS = [
+# (name, [(old, new), ...]) in the C source: each old text must occur; its first occurrence is
+# replaced (an edit listed twice replaces two occurrences).
+C_MUTANTS = [
     # basis (Sec. 3.1.1)
     ("basis_right_term_index",
      [("* or_basis(xi, i + 1, p - 1, u);", "* or_basis(xi, i, p - 1, u);")]),
@@ -120,6 +117,46 @@ MUTANTS = [
      [("double Ni = or_basis(S->knots_u, i, 2, u);", "double Ni = or_basis(S->knots_u, i, 2, v);")]),
 ]
 
+# (name, file of the package, [(old, new), ...]) in the Python parts
+PY_MUTANTS = [
+    # projected Newton (Sec. 3.2, 5.1)
+    ("predictor_sign", "__init__.py", [("xhat = x_n + dt * v_n", "xhat = x_n - dt * v_n")]),
+    ("velocity_from_predictor", "__init__.py", [("v=(x - x_n) / dt", "v=(x - xhat) / dt")]),
+    ("pins_left_at_previous_position", "__init__.py",
+     [("x[pins] = _f64(pin_targets).reshape(-1, 3)", "x[pins] = x[pins]")]),
+    ("step_rule_without_dt", "__init__.py",
+     [("np.abs(p).max() / dt <= atol", "np.abs(p).max() <= atol")]),
+    ("gradient_rule_absolute", "__init__.py", [("gn <= rtol * g0", "gn <= rtol")]),
+    ("newton_without_projection", "__init__.py",
+     [("assemble(sheet, x, xhat, dt, gravity, mask, project=True)",
+       "assemble(sheet, x, xhat, dt, gravity, mask, project=False)")]),
+    ("line_search_never_halves", "__init__.py", [("alpha *= 0.5", "alpha *= 1.0")]),
+    ("inertia_over_dt", "__init__.py",
+     [("inv_dt2 = 0.0 if dt is None else 1.0 / (dt * dt)", "inv_dt2 = 0.0 if dt is None else 1.0 / dt"),
+      ("inv_dt2 = 0.0 if dt is None else 1.0 / (dt * dt)", "inv_dt2 = 0.0 if dt is None else 1.0 / dt")]),
+    ("csr_blocks_transposed", "__init__.py",
+     [("rows.append(3 * A + r)\n                cols.append(3 * B + c)",
+       "rows.append(3 * A + c)\n                cols.append(3 * B + r)")]),
+    # contact conversion (Sec. 4.3)
+    ("contact_right_end_not_clamped", "contact_ref.py",
+     [("k = min(int(math.floor(u / hu)), Nu - 1)", "k = int(math.floor(u / hu))")]),
+    ("contact_weights_transposed", "contact_ref.py", [("w = wu[c] * wv[b]", "w = wu[b] * wv[c]")]),
+    ("contact_cp_index_swapped", "contact_ref.py",
+     [("cols.append((l + b) * sheet.n_u + (k + c))", "cols.append((l + c) * sheet.n_u + (k + b))")]),
+    ("contact_gradient_sign", "contact_ref.py",
+     [("g[a] += pair_grad[c, 3 * s:3 * s + 3]", "g[a] -= pair_grad[c, 3 * s:3 * s + 3]")]),
+    # learned warm start (network reference)
+    ("net_taps_flipped", "net_ref.py",
+     [("out += np.tensordot(W[:, :, ky, kx], patch", "out += np.tensordot(W[:, :, 2 - ky, 2 - kx], patch")]),
+    ("net_backward_relu_derivative", "net_ref.py",
+     [("np.where(inputs[l] > 0, 1.0, SLOPE)", "np.where(inputs[l] > 0, 1.0, 0.0)")]),
+    ("net_input_not_normalised", "net_ref.py", [("s = 1.0 / rms if rms > 0 else 0.0", "s = 1.0")]),
+    ("net_loss_mask_inverted", "net_ref.py",
+     [("m = (np.abs(x[b]).sum(axis=0) != 0)", "m = (np.abs(x[b]).sum(axis=0) == 0)")]),
+]
+
+MUTANTS = [(name, "bsc_oracle.c", edits) for name, edits in C_MUTANTS] + PY_MUTANTS
+
 PIN_FILES = sorted(f for f in os.listdir(os.path.join(ROOT, "tests"))
                    if f.startswith("test_oracle_") and f.endswith(".py"))
 
@@ -131,18 +168,41 @@ def _mutate(text: str, edits) -> str:
     return text
 
 
-def _run_pins(tmp: str, name: str, text: str):
-    """Builds one copy of the source and runs the pin tests against it; returns
-    (return code, first failing test or None, tail of the output)."""
-    src = os.path.join(tmp, name + ".c")
-    with open(src, "w") as f:
-        f.write(text)
-    lib = oracle.build(src, os.path.join(tmp, name + ".so"))
+# The child imports the copy as the package ``oracle`` before pytest starts, so every later
+# ``import oracle`` (and its submodules) resolves to the copy.
+_BOOT = """
+import importlib.util, sys
+pkg = sys.argv[1]
+spec = importlib.util.spec_from_file_location("oracle", pkg + "/__init__.py", submodule_search_locations=[pkg])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle"] = mod
+spec.loader.exec_module(mod)
+assert mod.__file__.startswith(pkg)
+import pytest
+sys.exit(pytest.main(sys.argv[2:]))
+"""
+
+PKG_FILES = ("__init__.py", "bsc_oracle.c", "contact_ref.py", "net_ref.py")
+
+
+def _run_pins(tmp: str, name: str, fname: str | None, edits):
+    """Copies the package, plants the edits, builds the copy's C source and runs the pin tests
+    against the copy; returns (return code, first failing test or None, tail of the output)."""
+    pkg = os.path.join(tmp, name, "oracle")
+    os.makedirs(pkg)
+    for f in PKG_FILES:
+        text = open(os.path.join(ROOT, "oracle", f)).read()
+        if f == fname:
+            text = _mutate(text, edits)
+        with open(os.path.join(pkg, f), "w") as fh:
+            fh.write(text)
+    lib = oracle.build(os.path.join(pkg, "bsc_oracle.c"), os.path.join(tmp, name, "liboracle.so"))
     env = dict(os.environ, BSC_ORACLE_LIB=lib, PYTHONDONTWRITEBYTECODE="1")
     env.setdefault("OMP_NUM_THREADS", "1")
-    cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-rf", "-p", "no:cacheprovider", "-m", "not gpu"]
-    cmd += [os.path.join("tests", f) for f in PIN_FILES]
-    res = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    args = ["-x", "-q", "-rf", "-p", "no:cacheprovider", "-m", "not gpu"]
+    args += [os.path.join("tests", f) for f in PIN_FILES]
+    res = subprocess.run([sys.executable, "-c", _BOOT, pkg] + args, cwd=ROOT, env=env,
+                         capture_output=True, text=True, timeout=600)
     out = res.stdout + res.stderr
     m = re.search(r"^FAILED (\S+)", out, re.M)
     return res.returncode, (m.group(1) if m else None), out[-1500:]
@@ -150,13 +210,12 @@ def _run_pins(tmp: str, name: str, text: str):
 
 @pytest.fixture(scope="module")
 def mutant_results():
-    base = open(SRC).read()
     tmp = tempfile.mkdtemp(prefix="bsc_mutants_")
-    jobs = [("control", base)] + [(name, _mutate(base, edits)) for name, edits in MUTANTS]
+    jobs = [("control", None, [])] + MUTANTS
     try:
         with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
-            futs = {name: ex.submit(_run_pins, tmp, name, text) for name, text in jobs}
-            res = {name: f.result() for name, f in futs.items()}
+            futs = {name: ex.submit(_run_pins, tmp, name, f, edits) for name, f, edits in jobs}
+            res = {name: fut.result() for name, fut in futs.items()}
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     for name, (rc, first, _) in res.items():
@@ -165,10 +224,9 @@ def mutant_results():
 
 
 def test_every_mutation_site_exists():
-    base = open(SRC).read()
-    for name, edits in MUTANTS:
-        text = _mutate(base, edits)
-        assert text != base, name
+    for name, f, edits in MUTANTS:
+        base = open(os.path.join(ROOT, "oracle", f)).read()
+        assert _mutate(base, edits) != base, name
 
 
 def test_unmodified_copy_passes_every_pin(mutant_results):
