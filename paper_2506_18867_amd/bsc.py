@@ -141,6 +141,28 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _need(t, dtype, numel, name, optional=False):
+    """Checks a tensor before its raw pointer crosses the C ABI: a contiguous GPU tensor of
+    ``dtype`` holding at least ``numel`` elements, the extent the library reads or writes
+    through it. A smaller or mistyped buffer would be accessed out of bounds on the device, so
+    it is refused here with BSC_E_INVAL. None passes only where the ABI takes NULL."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise BscError(BSC_E_INVAL, f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise BscError(BSC_E_INVAL, f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise BscError(BSC_E_INVAL, f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise BscError(BSC_E_INVAL, f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise BscError(BSC_E_INVAL, f"{name} holds {t.numel()} elements, needs {numel}")
+    if not t.is_cuda:
+        raise BscError(BSC_E_INVAL, f"{name} must be a device (GPU) tensor")
+
+
 def _np_ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -249,6 +271,10 @@ class Context:
         the device outputs trimmed to nnzb blocks."""
         import torch
         n_pairs = int(pair_verts.shape[0]) if pair_verts is not None else 0
+        if n_pairs:
+            _need(pair_verts, torch.int32, 4 * n_pairs, "pair_verts")
+            _need(pair_hess, torch.float64, 144 * n_pairs, "pair_hess")
+            _need(pair_grad, torch.float64, 12 * n_pairs, "pair_grad", optional=True)
         dev = self.device
         retry = out is None and cap_blocks is None
         if out is None:
@@ -260,6 +286,10 @@ class Context:
         else:
             row_ptr, col, vals, grad = out
             cap = int(col.shape[0])
+            _need(row_ptr, torch.int32, self.n_cp + 1, "row_ptr")
+            _need(col, torch.int32, cap, "col_idx")
+            _need(vals, torch.float64, 9 * cap, "vals")
+            _need(grad, torch.float64, 3 * self.n_cp, "grad", optional=True)
         nnzb = ctypes.c_int32()
 
         def call():
@@ -280,6 +310,7 @@ class Context:
     def bsc_eval_egh(self, x, precision=BSC_FP64, want_energy=True, want_grad=True, want_hess=True):
         import torch
         dt = torch.float64 if precision == BSC_FP64 else torch.float32
+        _need(x, torch.float64, 3 * self.n_cp, "x")
         E = torch.zeros(1, dtype=torch.float64, device=x.device)
         eE = torch.empty(self.n_elem, dtype=dt, device=x.device) if want_energy else None
         eg = torch.empty(27, self.n_elem, dtype=dt, device=x.device) if want_grad else None
@@ -291,12 +322,17 @@ class Context:
     def bsc_assemble(self, x, xhat=None, dt=0.0, gravity=None, precision=BSC_FP64, want_hess=True, out=None):
         import torch
         tdt = torch.float64 if precision == BSC_FP64 else torch.float32
+        _need(x, torch.float64, 3 * self.n_cp, "x")
+        _need(xhat, torch.float64, 3 * self.n_cp, "xhat", optional=True)
         if out is None:
             E = torch.zeros(1, dtype=torch.float64, device=x.device)
             g = torch.empty(3, self.n_cp, dtype=tdt, device=x.device)
             H = torch.empty(BSC_HESS_ENTRIES, self.n_cp, dtype=tdt, device=x.device) if want_hess else None
         else:
             E, g, H = out
+            _need(E, torch.float64, 1, "energy")
+            _need(g, tdt, 3 * self.n_cp, "grad")
+            _need(H, tdt, BSC_HESS_ENTRIES * self.n_cp, "hess", optional=True)
         grav = (ctypes.c_double * 3)(*gravity) if gravity is not None else None
         self._check(self.lib.bsc_assemble(self.h, precision, _ptr(x), _ptr(xhat), float(dt), grav, _ptr(E), _ptr(g),
                                           _ptr(H)), "bsc_assemble")
@@ -304,8 +340,10 @@ class Context:
 
     def bsc_spmv(self, H, v, precision=BSC_FP64, out=None):
         import torch
-        if v.dtype != torch.float64 or (out is not None and out.dtype != torch.float64):
-            raise BscError("bsc_spmv takes double vectors in both precisions")
+        tdt = torch.float64 if precision == BSC_FP64 else torch.float32
+        _need(H, tdt, BSC_HESS_ENTRIES * self.n_cp, "hess")
+        _need(v, torch.float64, 3 * self.n_cp, "in")       # double vectors in both precisions
+        _need(out, torch.float64, 3 * self.n_cp, "out", optional=True)
         y = torch.empty_like(v) if out is None else out
         self._check(self.lib.bsc_spmv(self.h, precision, _ptr(H), _ptr(v), _ptr(y)), "bsc_spmv")
         return y
@@ -320,13 +358,18 @@ class Context:
 
     def bsc_export_bsr(self, H, precision=BSC_FP64):
         import torch
+        _need(H, torch.float64 if precision == BSC_FP64 else torch.float32, BSC_HESS_ENTRIES * self.n_cp, "hess")
         rp, ci = self.bsc_bsr_pattern()
         vals = torch.empty(ci.size, 3, 3, dtype=H.dtype, device=H.device)
         self._check(self.lib.bsc_export_bsr(self.h, precision, _ptr(H), _ptr(vals)), "bsc_export_bsr")
         return rp, ci, vals
 
     def bsc_newton_step(self, x, v, pin_targets=None, opts: StepOpts | None = None, raise_on_error=True):
+        import torch
         opts = opts or make_opts()
+        _need(x, torch.float64, 3 * self.n_cp, "x")
+        _need(v, torch.float64, 3 * self.n_cp, "v")
+        _need(pin_targets, torch.float64, 3 * int(self.pins.size), "pin_targets", optional=True)
         stats = StepStats()
         st = self.lib.bsc_newton_step(self.h, ctypes.byref(opts), _ptr(x), _ptr(v), _ptr(pin_targets),
                                       ctypes.byref(stats))
@@ -335,6 +378,10 @@ class Context:
         return st, stats
 
     def bsc_set_sample_log(self, g_buf, p_buf, capacity):
+        import torch
+        if int(capacity) > 0:
+            _need(g_buf, torch.float32, 3 * self.n_cp * int(capacity), "g_buf")
+            _need(p_buf, torch.float32, 3 * self.n_cp * int(capacity), "p_buf")
         self._check(self.lib.bsc_set_sample_log(self.h, _ptr(g_buf), _ptr(p_buf), int(capacity)), "bsc_set_sample_log")
 
     def bsc_sample_log_count(self):
@@ -343,11 +390,16 @@ class Context:
         return c.value
 
     def bsc_warmstart_load(self, weights):
+        import torch
+        _need(weights, torch.float32, BSC_NET_PARAMS, "weights")
         self._check(self.lib.bsc_warmstart_load(self.h, _ptr(weights), int(weights.numel())), "bsc_warmstart_load")
 
     def bsc_net_forward(self, weights, inp, acts=None):
         import torch
         batch = inp.shape[0]
+        _need(weights, torch.float32, BSC_NET_PARAMS, "weights")
+        _need(inp, torch.float32, batch * 3 * self.n_cp, "inp")
+        _need(acts, torch.float32, batch * 5 * 32 * self.n_cp, "acts", optional=True)
         out = torch.empty_like(inp)
         self._check(self.lib.bsc_net_forward(self.h, batch, _ptr(weights), _ptr(inp), _ptr(out), _ptr(acts)),
                     "bsc_net_forward")
@@ -361,20 +413,31 @@ class Context:
     def bsc_net_backward(self, weights, inp, acts, dout, want_din=False, scratch=None):
         import torch
         batch = inp.shape[0]
+        _need(weights, torch.float32, BSC_NET_PARAMS, "weights")
+        _need(inp, torch.float32, batch * 3 * self.n_cp, "inp")
+        _need(acts, torch.float32, batch * 5 * 32 * self.n_cp, "acts")
+        _need(dout, torch.float32, batch * 3 * self.n_cp, "dout")
         dw = torch.empty_like(weights)
         din = torch.empty_like(inp) if want_din else None
         if scratch is None:
             scratch = torch.empty(max(1, self.bsc_net_scratch_size(batch)), dtype=torch.uint8, device=inp.device)
+        _need(scratch, torch.uint8, self.bsc_net_scratch_size(batch), "scratch")
         self._check(self.lib.bsc_net_backward(self.h, batch, _ptr(weights), _ptr(inp), _ptr(acts), _ptr(dout),
                                               _ptr(dw), _ptr(din), _ptr(scratch)), "bsc_net_backward")
         return dw, din
 
     def bsc_adam_step(self, param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        for name, a in (("param", param), ("grad", grad), ("m", m), ("v", v)):
+            _need(a, torch.float32, param.numel(), name)
         self._check(self.lib.bsc_adam_step(self.h, int(param.numel()), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
                                            lr, beta1, beta2, eps, int(t)), "bsc_adam_step")
 
     def bsc_net_loss(self, inp, pred, target):
         import torch
+        n = pred.shape[0] * 3 * self.n_cp
+        for name, a in (("inp", inp), ("pred", pred), ("target", target)):
+            _need(a, torch.float32, n, name)
         loss = torch.zeros(1, dtype=torch.float32, device=pred.device)
         dpred = torch.empty_like(pred)
         self._check(self.lib.bsc_net_loss(self.h, pred.shape[0], _ptr(inp), _ptr(pred), _ptr(target), _ptr(loss),

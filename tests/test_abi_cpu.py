@@ -149,3 +149,23 @@ def test_bsr_pattern_is_the_5x5_neighbourhood():
         want += row
     assert nnzb.value == len(want) == (5 * n_u - 6) * (5 * n_v - 6)
     lib.bsc_destroy(h)
+
+
+def test_binding_refuses_mistyped_or_short_buffers():
+    """Before a device pointer crosses the C ABI the binding checks the tensor: type, dtype,
+    contiguity, element count and device. Each failure is BSC_E_INVAL, raised on the host, so a
+    wrong buffer never reaches a kernel."""
+    import torch
+    cases = [(np.zeros(6), "torch tensor"),
+             (torch.zeros(6, dtype=torch.float32), "must be torch.float64"),
+             (torch.zeros(3, 4, dtype=torch.float64).t(), "contiguous"),
+             (torch.zeros(5, dtype=torch.float64), "needs 6"),
+             (torch.zeros(6, dtype=torch.float64), "device")]
+    for t, msg in cases:
+        with pytest.raises(bsc.BscError) as e:
+            bsc._need(t, torch.float64, 6, "x")
+        assert e.value.status == bsc.BSC_E_INVAL and msg in str(e.value)
+    bsc._need(None, torch.float64, 6, "x", optional=True)
+    with pytest.raises(bsc.BscError) as e:
+        bsc._need(None, torch.float64, 6, "x")
+    assert e.value.status == bsc.BSC_E_INVAL

@@ -9,7 +9,9 @@
   is quadratic and its minimiser is x_n + dt v_n + dt^2 g (Sec. 3.2, implicit Euler); the step
   must reach it.
 - The smallest grid the library accepts (5 x 5 CPs, 3 x 3 spans, every span a boundary span):
-  two Newton iterates against the oracle's exact solves, FP64 within 1e-10."""
+  two Newton iterates against the oracle's exact solves, FP64 within 1e-10.
+- Mistyped or short buffers are refused by the binding with BSC_E_INVAL before any launch, and
+  the context keeps working afterwards."""
 import numpy as np
 import pytest
 
@@ -95,3 +97,29 @@ def test_smallest_grid_iterates_match_oracle():
     err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
     print(f"[5 x 5] rel err of x - x0: {err:.2e}", flush=True)
     assert err < 1e-10
+
+
+def test_binding_refuses_wrong_buffers_before_launch():
+    sc = syn.driven_sheet(20, seed=306)
+    ctx = bsc.context_for_scene(sc)
+    n = sc.n_cp
+    x = bsc.to_soa(sc.x0)
+    bad = [
+        lambda: ctx.bsc_assemble(x.float()),                                    # FP32 state
+        lambda: ctx.bsc_assemble(x[:, : n - 1].contiguous()),                   # short state
+        lambda: ctx.bsc_assemble(x, xhat=x.t()),                                # not contiguous
+        lambda: ctx.bsc_spmv(torch.zeros(10, dtype=torch.float64, device="cuda"), x.reshape(-1)),
+        lambda: ctx.bsc_spmv(torch.zeros(bsc.BSC_HESS_ENTRIES * n, dtype=torch.float64, device="cuda"),
+                             x.reshape(-1).float()),
+        lambda: ctx.bsc_newton_step(x, torch.zeros(3, n, dtype=torch.float64)),  # host tensor
+        lambda: ctx.bsc_newton_step(x, torch.zeros_like(x), torch.zeros(2, dtype=torch.float64, device="cuda")),
+    ]
+    for call in bad:
+        with pytest.raises(bsc.BscError) as e:
+            call()
+        assert e.value.status == bsc.BSC_E_INVAL
+    # the context still works: FP64 elastic energy of a deformed state against the oracle
+    xs = sc.x0 + syn.smooth_field(20, 20, 3, amp=0.02)
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(xs), precision=bsc.BSC_FP64)
+    E_o, _, _ = oracle.assemble(oracle_sheet(sc), xs, want_hessian=False)
+    assert E_o > 0 and relerr(float(E.item()), E_o) < 1e-12
