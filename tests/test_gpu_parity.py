@@ -177,6 +177,37 @@ def test_fp32_gradient_and_hessian_within_bounds(kind, n):
     assert relerr(E.item(), rE) < 1e-5
 
 
+def test_compressed_100_sheet_matches_oracle():
+    """The 100 x 100 CP sheet with 10% in-plane compression and +-2 mm z-noise, both side
+    columns held (the workload of the FP64 against FP32 comparison): FP64 assembly within 1e-10
+    of the oracle, FP32-mixed gradient and Hessian within their bars, and the first FP64 Newton
+    iterate within 1e-10 of the oracle's exact solve."""
+    n = 100
+    print(f"[compressed {n}] assembly in both precisions and one Newton iterate", flush=True)
+    sc = syn.compressed_sheet(n, seed=2)
+    sh = oracle_sheet(sc)
+    ctx = _ctx(sc)
+    mask = np.zeros(sc.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    xhat = sc.x0 + sc.dt * sc.v0
+    rE, rg, rH = oracle.assemble(sh, sc.x0, xhat, sc.dt, sc.gravity, mask)
+    rHu = oracle_stencil_to_upper(rH, n, n)
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(sc.x0), bsc.to_soa(xhat), sc.dt, tuple(sc.gravity), bsc.BSC_FP64)
+    assert relerr(E.item(), rE) < TOL64
+    assert relerr(bsc.to_aos(g), rg) < TOL64
+    assert relerr(H.cpu().numpy(), rHu) < TOL64
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(sc.x0), bsc.to_soa(xhat), sc.dt, tuple(sc.gravity), bsc.BSC_FP32_MIXED)
+    assert relerr(bsc.to_aos(g), rg) < 1e-4
+    assert relerr(H.cpu().numpy(), rHu) < 1e-5
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), fixed_newton_iters=1, pcg_rtol=1e-14, max_pcg=50000)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=1)
+    err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
+    print(f"[compressed {n}] pcg={stats.pcg_iters_total} rel err of x - x0: {err:.2e}", flush=True)
+    assert err < TOL64
+
+
 # ---- Newton step --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("iters", [1, 2])
