@@ -230,6 +230,23 @@ bsc_status bsc_export_bsr(bsc_ctx *ctx, int32_t precision, const void *d_hess, v
 bsc_status bsc_newton_step(bsc_ctx *ctx, const bsc_step_opts *opts, double *d_x, double *d_v,
                            const double *d_pin_targets, bsc_step_stats *stats);
 
+/* Energy difference of the incremental potential along a direction, as the line search of
+ * bsc_newton_step evaluates it (Sec. 5.1, backtracking on a monotone decrease of the potential
+ * of Sec. 3.2, Eq. "incremental_potential"): d_de[k] = E(x + alphas[k] p) - E(x) with E as in
+ * bsc_assemble without pins (inertia with d_xhat and dt, gravity, membrane and bending). The
+ * inertia, gravity and bending terms are quadratics in alpha whose coefficients are summed over
+ * CPs and bending evaluations; the membrane term is summed point by point as
+ * w (Psi(F + alpha dF) - Psi(F)) from the strain increment, so the difference carries no
+ * cancellation against E itself. All arithmetic is double.
+ *   d_x, d_p: 3*n_cp doubles (SoA); d_xhat: 3*n_cp doubles or NULL (no inertia term; dt is then
+ *     ignored); gravity: host, 3 doubles or NULL.
+ *   alphas: host, n_alpha step lengths (1 <= n_alpha <= 64, finite); d_de: n_alpha doubles.
+ *   Uses the workspace's per-point buffers (overwrites what bsc_eval_egh / bsc_assemble left
+ *   there). Asynchronous. */
+bsc_status bsc_energy_difference(bsc_ctx *ctx, const double *d_x, const double *d_xhat, double dt,
+                                 const double *gravity, const double *d_p, int32_t n_alpha,
+                                 const double *alphas, double *d_de);
+
 /* Sample log for training the warm start: while capacity > 0, every Newton iteration of
  * bsc_newton_step appends its free-DOF gradient g and its PCG direction p (the solve of
  * H p = -g at the step's pcg_rtol) as floats, SoA [c][a], at d_g + 3*n_cp*k and d_p + 3*n_cp*k

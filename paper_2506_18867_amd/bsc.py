@@ -101,6 +101,7 @@ def load():
         "bsc_bsr_pattern": [P, P, P, ctypes.POINTER(I32)],
         "bsc_export_bsr": [P, I32, P, P],
         "bsc_newton_step": [P, ctypes.POINTER(StepOpts), P, P, P, ctypes.POINTER(StepStats)],
+        "bsc_energy_difference": [P, P, P, D, P, P, I32, P, P],
         "bsc_warmstart_load": [P, P, I32],
         "bsc_net_forward": [P, I32, P, P, P, P],
         "bsc_net_backward": [P, I32, P, P, P, P, P, P, P],
@@ -130,7 +131,7 @@ def load():
 
 def exported_symbols() -> list[str]:
     return ["bsc_create", "bsc_sizes", "bsc_workspace_size", "bsc_bind_workspace", "bsc_set_pins", "bsc_eval_egh",
-            "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step",
+            "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step", "bsc_energy_difference",
             "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size", "bsc_adam_step",
             "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_contact_setup",
             "bsc_contact_workspace_size", "bsc_contact_bind_workspace", "bsc_contact_hessian", "bsc_status_string",
@@ -376,6 +377,19 @@ class Context:
         if st != BSC_OK and raise_on_error:
             self._check(st, "bsc_newton_step")
         return st, stats
+
+    def bsc_energy_difference(self, x, p, alphas, xhat=None, dt=0.0, gravity=None):
+        """E(x + alpha p) - E(x) for each alpha (float64 device tensor of len(alphas))."""
+        import torch
+        _need(x, torch.float64, 3 * self.n_cp, "x")
+        _need(p, torch.float64, 3 * self.n_cp, "p")
+        _need(xhat, torch.float64, 3 * self.n_cp, "xhat", optional=True)
+        al = np.ascontiguousarray(alphas, dtype=np.float64).reshape(-1)
+        out = torch.empty(max(1, al.size), dtype=torch.float64, device=x.device)
+        grav = (ctypes.c_double * 3)(*gravity) if gravity is not None else None
+        self._check(self.lib.bsc_energy_difference(self.h, _ptr(x), _ptr(xhat), float(dt), grav, _ptr(p), int(al.size),
+                                                   _np_ptr(al), _ptr(out)), "bsc_energy_difference")
+        return out
 
     def bsc_set_sample_log(self, g_buf, p_buf, capacity):
         import torch

@@ -1,7 +1,12 @@
 """Builds libbsc.so (the HIP library behind include/bsc.h) for gfx950 with hipcc.
 
-Every source is compiled with packed-FP32 instructions disabled and the objects are linked
-into ``paper_2506_18867_amd/libbsc.so``. Run ``python -m paper_2506_18867_amd.build``."""
+Every HIP source is compiled with the device target feature ``-packed-fp32-ops``, so the
+compiler does not pair float operations into packed-FP32 instructions, and the objects are
+linked into ``paper_2506_18867_amd/libbsc.so``. hipcc passes the feature to both of its
+passes: the host pass does not know it and prints "not a recognized feature ... ignoring",
+which is harmless; the gfx950 device pass applies it (a float2 multiply-add compiles to one
+packed FMA without the feature and to two scalar FMAs with it). Run
+``python -m paper_2506_18867_amd.build``."""
 from __future__ import annotations
 
 import concurrent.futures as cf

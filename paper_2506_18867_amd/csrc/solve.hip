@@ -905,6 +905,12 @@ __global__ void k_update(int n, double alpha, const double *__restrict__ p, doub
     if (t < n) x[t] += alpha * p[t];
 }
 
+// dE(alpha) = alpha c1 + alpha^2 c2 / 2 + (membrane difference at alpha), the line search's
+// energy difference, written to device memory (bsc_energy_difference).
+__global__ void k_de_combine(const double *__restrict__ scal, double alpha, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = alpha * scal[S_C1] + 0.5 * alpha * alpha * scal[S_C2] + scal[S_DEM];
+}
+
 }  // namespace
 
 inline int spmv_blocks(int n_cp) { return (n_cp + kRowsPerTile - 1) / kRowsPerTile; }
@@ -1516,6 +1522,43 @@ bsc_status bsc_newton_step(bsc_ctx *c, const bsc_step_opts *o, double *d_x, doub
     bsc_status st = newton_step(c, o, d_x, d_v, d_pin_targets, stats);
     if (st != BSC_OK && c->err.empty()) c->err = bsc_status_string(st);
     return st;
+}
+
+bsc_status bsc_energy_difference(bsc_ctx *c, const double *d_x, const double *d_xhat, double dt, const double *gravity,
+                                 const double *d_p, int32_t n_alpha, const double *alphas, double *d_de) {
+    if (!c) return BSC_E_INVAL;
+    if (!c->ws) return fail(c, BSC_E_STATE, "no workspace bound");
+    if (!d_x || !d_p || !d_de || !alphas) return fail(c, BSC_E_INVAL, "null pointer");
+    if (n_alpha < 1 || n_alpha > 64) return fail(c, BSC_E_INVAL, "n_alpha must be in 1..64");
+    for (int k = 0; k < n_alpha; ++k)
+        if (!std::isfinite(alphas[k])) return fail(c, BSC_E_INVAL, "step lengths must be finite");
+    double inv_dt2 = 0.0;
+    if (d_xhat) {
+        if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, BSC_E_INVAL, "dt must be positive");
+        inv_dt2 = 1.0 / (dt * dt);
+    }
+    const double gx = gravity ? gravity[0] : 0.0, gy = gravity ? gravity[1] : 0.0, gz = gravity ? gravity[2] : 0.0;
+    if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz)) return fail(c, BSC_E_INVAL, "gravity must be finite");
+    const DevSheet &S = c->dev;
+    const DevBufs &B = c->buf;
+    hipStream_t st = c->stream;
+    const int stride = B.max_blocks;
+    // the bending term's coefficients need w mu Laplacian(phi(x)) at every bending evaluation
+    bsc_status r = hip_check(c, launch_points(S, B, BSC_FP64, false, false, d_x, st, true), "energy difference points");
+    if (r != BSC_OK) return r;
+    double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
+    // without xhat the inertia term is dropped: inv_dt2 = 0 and x stands in for xhat
+    k_ls_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, d_x, d_xhat ? d_xhat : d_x, d_p, inv_dt2, gx, gy, gz, pa, stride,
+                                                B.partials + 7 * stride);
+    k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, d_p, pb, stride);
+    k_ls_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
+                                      B.partials, 0, B.scalars);
+    for (int k = 0; k < n_alpha; ++k) {
+        k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, d_x, d_p, alphas[k], B.partials + 6 * stride);
+        k_sum_into<<<1, kBlock, 0, st>>>(B.partials + 6 * stride, blocks(S.n_mp), B.scalars, S_DEM);
+        k_de_combine<<<1, 64, 0, st>>>(B.scalars, alphas[k], d_de + k);
+    }
+    return hip_check(c, hipGetLastError(), "energy difference");
 }
 
 }  // extern "C"

@@ -1,8 +1,8 @@
 """Trains the learned PCG warm start (a method extension) on the method's own solves.
 
 Data: 128 x 128-control-point sheets with materials drawn from the (E, t) grid; half are driven
-sheets with random held CPs (config-3 style), half are compressed-and-draped sheets (10 %
-compression between two held columns, config-2 style). Every Newton iteration of their
+sheets with random held CPs and a driven corner, half are compressed-and-draped sheets (10 %
+compression between two held columns). Every Newton iteration of their
 implicit-Euler steps logs the free gradient g and the PCG direction p solved to a relative
 residual of 1e-8 (bsc_set_sample_log). Training: the library's forward, backward, loss and Adam
 kernels (bsc_net_*), batch 16, Adam 1e-3 with cosine decay, 10 % of the pairs held out.

@@ -23,6 +23,26 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def rowwise_err(got, ref, axis=-1, floor=1e-3):
+    """Worst entry error of ``got`` against ``ref``, each entry scaled by the largest magnitude
+    of its row (the entries that share an index along ``axis``: one element, one CP), the scale
+    floored at ``floor`` times the largest magnitude of the whole array.
+
+    A single norm over a whole array (``relerr``) lets an error confined to a few rows pass at
+    up to sqrt(rows) times its bound; this bounds every row against its own size."""
+    g = np.asarray(got, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    assert g.shape == r.shape, (g.shape, r.shape)
+    if g.ndim == 0:
+        g, r = g.reshape(1), r.reshape(1)
+    ax = axis % g.ndim
+    g = np.moveaxis(g, ax, 0).reshape(g.shape[ax], -1)
+    r = np.moveaxis(r, ax, 0).reshape(r.shape[ax], -1)
+    scale = np.abs(r).max(axis=1)
+    scale = np.maximum(scale, floor * max(float(scale.max()), 1e-300))
+    return float((np.abs(g - r).max(axis=1) / scale).max())
+
+
 def upper27(H):
     """(ne, 27, 27) -> (378, ne) upper triangle, row-major over r <= c."""
     iu = np.triu_indices(27)

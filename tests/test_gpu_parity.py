@@ -1,7 +1,9 @@
 """GPU parity of the HIP path against the CPU oracle, through the C ABI.
 
 FP64 bar: normwise relative error <= 1e-10 for energies, gradients, element and assembled
-Hessians and Newton iterates. FP32-mixed bar: gradient within 1e-4 relative of the FP64
+Hessians and Newton iterates, and the same bound on every entry against the size of its own
+row (one element, or one CP: ``rowwise_err``), so that an error confined to a few elements
+cannot hide in a norm over the whole array. FP32-mixed bar: gradient within 1e-4 relative of the FP64
 oracle, Hessian within 1e-5, and the Newton step reaching the same FP64 residual tolerance.
 Sizes span several tiles with ragged tails (n = 5..23 and non-square), the 100 x 100 sheet,
 and the full 226 x 226 sheet compared element by element."""
@@ -10,7 +12,7 @@ import pytest
 
 import oracle
 import synthetic as syn
-from tests.helpers import deformed, oracle_sheet, oracle_stencil_to_upper, relerr, upper27
+from tests.helpers import deformed, oracle_sheet, oracle_stencil_to_upper, relerr, rowwise_err, upper27
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +20,16 @@ torch = pytest.importorskip("torch")
 from paper_2506_18867_amd import bsc  # noqa: E402
 
 TOL64 = 1e-10
+
+
+def check64(got, ref, axis, what=""):
+    """FP64 bar, normwise and row by row (``axis`` indexes the rows: elements or CPs)."""
+    got = np.asarray(got.cpu().numpy() if hasattr(got, "cpu") else got, dtype=np.float64)
+    en, er = relerr(got, ref), rowwise_err(got, ref, axis=axis)
+    if what:
+        print(f"  {what}: normwise {en:.2e}, worst row {er:.2e}")
+    assert en < TOL64, (what, en)
+    assert er < TOL64, (what, er)
 
 
 def _scene(kind, n, seed=1, **kw):
@@ -48,9 +60,9 @@ def test_eval_egh_fp64_matches_oracle(n_u, n_v, shear, spacing):
     torch.cuda.synchronize()
     rE, rg, rH = oracle.element_egh(sh, x, project=True)
     assert relerr(E.item(), rE.sum()) < TOL64
-    assert relerr(eE.cpu().numpy(), rE) < TOL64
-    assert relerr(eg.cpu().numpy(), rg.T) < TOL64
-    assert relerr(eH.cpu().numpy(), upper27(rH)) < TOL64
+    check64(eE, rE, 0, "element energy")
+    check64(eg, rg.T, 1, "element gradient")
+    check64(eH, upper27(rH), 1, "element Hessian")
 
 
 def test_eval_egh_fbw_matches_oracle():
@@ -63,9 +75,9 @@ def test_eval_egh_fbw_matches_oracle():
     ctx = bsc.Context(n, n, ku, kv, rest, bsc.make_material(1, 0, 0, 0, 3.0, 2.0, 0.7, 1e-3, 0.2))
     E, eE, eg, eH = ctx.bsc_eval_egh(bsc.to_soa(x), bsc.BSC_FP64)
     rE, rg, rH = oracle.element_egh(sh, x, project=True)
-    assert relerr(eE.cpu().numpy(), rE) < TOL64
-    assert relerr(eg.cpu().numpy(), rg.T) < TOL64
-    assert relerr(eH.cpu().numpy(), upper27(rH)) < TOL64
+    check64(eE, rE, 0, "element energy")
+    check64(eg, rg.T, 1, "element gradient")
+    check64(eH, upper27(rH), 1, "element Hessian")
 
 
 # ---- assembled incremental potential ----------------------------------------------------------
@@ -85,8 +97,8 @@ def test_assemble_fp64_matches_oracle(kind, n):
     mask[sc.pins] = True
     rE, rg, rH = oracle.assemble(sh, x, xhat, sc.dt, sc.gravity, mask)
     assert relerr(E.item(), rE) < TOL64
-    assert relerr(bsc.to_aos(g), rg) < TOL64
-    assert relerr(H.cpu().numpy(), oracle_stencil_to_upper(rH, n, n)) < TOL64
+    check64(bsc.to_aos(g), rg, 0, "gradient")
+    check64(H, oracle_stencil_to_upper(rH, n, n), 1, "Hessian")
 
 
 def test_assemble_without_inertia_or_gravity():
@@ -98,8 +110,8 @@ def test_assemble_without_inertia_or_gravity():
     E, g, H = ctx.bsc_assemble(bsc.to_soa(x), None, 0.0, None, bsc.BSC_FP64)
     rE, rg, rH = oracle.assemble(sh, x)
     assert relerr(E.item(), rE) < TOL64
-    assert relerr(bsc.to_aos(g), rg) < TOL64
-    assert relerr(H.cpu().numpy(), oracle_stencil_to_upper(rH, 8, 8)) < TOL64
+    check64(bsc.to_aos(g), rg, 0, "gradient")
+    check64(H, oracle_stencil_to_upper(rH, 8, 8), 1, "Hessian")
 
 
 def test_full_size_226_matches_oracle():
@@ -116,8 +128,8 @@ def test_full_size_226_matches_oracle():
     mask[sc.pins] = True
     rE, rg, rH = oracle.assemble(sh, x, sc.x0, sc.dt, sc.gravity, mask)
     assert relerr(E.item(), rE) < TOL64
-    assert relerr(bsc.to_aos(g), rg) < TOL64
-    assert relerr(H.cpu().numpy(), oracle_stencil_to_upper(rH, 226, 226)) < TOL64
+    check64(bsc.to_aos(g), rg, 0, "gradient")
+    check64(H, oracle_stencil_to_upper(rH, 226, 226), 1, "Hessian")
 
 
 def test_spmv_and_bsr_export_match_oracle_matrix():
@@ -194,8 +206,8 @@ def test_compressed_100_sheet_matches_oracle():
     rHu = oracle_stencil_to_upper(rH, n, n)
     E, g, H = ctx.bsc_assemble(bsc.to_soa(sc.x0), bsc.to_soa(xhat), sc.dt, tuple(sc.gravity), bsc.BSC_FP64)
     assert relerr(E.item(), rE) < TOL64
-    assert relerr(bsc.to_aos(g), rg) < TOL64
-    assert relerr(H.cpu().numpy(), rHu) < TOL64
+    check64(bsc.to_aos(g), rg, 0, "gradient")
+    check64(H, rHu, 1, "Hessian")
     E, g, H = ctx.bsc_assemble(bsc.to_soa(sc.x0), bsc.to_soa(xhat), sc.dt, tuple(sc.gravity), bsc.BSC_FP32_MIXED)
     assert relerr(bsc.to_aos(g), rg) < 1e-4
     assert relerr(H.cpu().numpy(), rHu) < 1e-5
@@ -205,7 +217,7 @@ def test_compressed_100_sheet_matches_oracle():
     ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), fixed_iters=1)
     err = relerr(bsc.to_aos(x) - sc.x0, ref.x - sc.x0)
     print(f"[compressed {n}] pcg={stats.pcg_iters_total} rel err of x - x0: {err:.2e}", flush=True)
-    assert err < TOL64
+    check64(bsc.to_aos(x) - sc.x0, ref.x - sc.x0, 0, "x - x0")
 
 
 # ---- Newton step --------------------------------------------------------------------------
@@ -226,7 +238,7 @@ def test_newton_fp64_iterates_match_oracle(iters):
     got = bsc.to_aos(x)
     err = relerr(got - sc.x0, ref.x - sc.x0)
     print(f"[newton fp64] iters={iters} pcg={stats.pcg_iters_total} rel err of x - x0: {err:.2e}")
-    assert err < TOL64
+    check64(got - sc.x0, ref.x - sc.x0, 0, "x - x0")
     assert relerr(bsc.to_aos(v), ref.v) < TOL64
     assert abs(stats.g0_norm - ref.g0_norm) < 1e-10 * ref.g0_norm
 
@@ -499,3 +511,95 @@ def test_step_rule_stops_within_its_tolerance():
             assert st == 0
         out[mode] = x.cpu().numpy()
     assert np.abs(out["step"] - out["grad"]).max() <= 1e-2 * sc.dt
+
+
+# ---- a whole time step, and the FP32 element and SpMV paths -------------------------------------
+
+def test_hanging_20_full_time_step_matches_oracle():
+    """One complete implicit-Euler step of the 20 x 20 hanging sheet (E = 1e4 Pa, t = 1 mm, two
+    top corners pinned, dt = 0.01 s), each side under its own stopping test
+    |g| <= 1e-6 |g0| (Sec. 3.2, Eq. "incremental_potential"; Sec. 5.1): the same number of Newton
+    iterations, and C^{n+1} - C^n and the new velocity within 1e-10 of the oracle's (GPU PCG to
+    1e-14 against the oracle's sparse LU), normwise and CP by CP."""
+    sc = syn.hanging_sheet(20, seed=1)
+    sh = oracle_sheet(sc)
+    ctx = _ctx(sc)
+    x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
+    opts = bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=bsc.BSC_FP64, stop_mode=bsc.BSC_STOP_GRAD,
+                         rtol=1e-6, pcg_rtol=1e-14, max_pcg=20000, max_newton=50)
+    st, stats = ctx.bsc_newton_step(x, v, bsc.to_soa(sc.pin_targets(0)), opts)
+    assert st == 0
+    ref = oracle.newton_step(sh, sc.x0, sc.v0, sc.dt, sc.gravity, sc.pins, sc.pin_targets(0), rtol=1e-6)
+    print(f"[hanging 20x20 step] Newton gpu {stats.newton_iters} oracle {ref.iters} (alphas {ref.alphas}); "
+          f"|g|/|g0| gpu {stats.g_norm / stats.g0_norm:.2e} oracle {ref.g_norm / ref.g0_norm:.2e}")
+    assert stats.newton_iters == ref.iters
+    check64(bsc.to_aos(x) - sc.x0, ref.x - sc.x0, 0, "C^{n+1} - C^n")
+    check64(bsc.to_aos(v), ref.v, 0, "v^{n+1}")
+    assert stats.g_norm <= 1e-6 * stats.g0_norm
+
+
+# FP32 element bar: the element gradient within 1e-4 of the FP64 oracle (the FP32 path's bar),
+# the element Hessian within 1e-5 normwise; row by row both within 1e-4 of their element's size
+# (floor 1e-2 of the array's largest entry: FP32 rounds each of the ~30 terms of an entry at
+# u = 6e-8 of the terms' size, which can exceed a near-zero entry's size)
+TOL32_G, TOL32_H, TOL32_ROW = 1e-4, 1e-5, 1e-4
+
+
+@pytest.mark.parametrize("n_u,n_v,shear", [(20, 20, 0.0), (23, 9, 0.1)])
+def test_eval_egh_fp32_within_bounds(n_u, n_v, shear):
+    """bsc_eval_egh in BSC_FP32_MIXED (points evaluated and accumulated in float, PSD eigen-problem
+    in double) against the FP64 oracle on a compressed, bent sheet."""
+    print(f"[eval_egh fp32] n={n_u}x{n_v} shear={shear}", flush=True)
+    ku, kv, rest = syn.flat_sheet(n_u, n_v, 1.0, 0.8, shear=shear)
+    mat = syn.stvk_material(young=1e4, thickness=1e-3, mu_bend=2e-3)
+    sh = oracle_sheet((n_u, n_v, ku, kv, rest), mat)
+    x = syn.embed(rest) + syn.smooth_field(n_u, n_v, 7, amp=0.05)
+    x[:, 0] *= 0.93
+    ctx = bsc.Context(n_u, n_v, ku, kv, rest, bsc.make_material(0, mat.young, mat.poisson, mat.thickness,
+                                                               mu_bend=mat.mu_bend, rho_area=mat.rho_area))
+    E, eE, eg, eH = ctx.bsc_eval_egh(bsc.to_soa(x), bsc.BSC_FP32_MIXED)
+    assert eE.dtype == torch.float32 and eg.dtype == torch.float32 and eH.dtype == torch.float32
+    rE, rg, rH = oracle.element_egh(sh, x, project=True)
+    eg_n, eh_n = relerr(eg.cpu().numpy(), rg.T), relerr(eH.cpu().numpy(), upper27(rH))
+    eg_r = rowwise_err(eg.cpu().numpy(), rg.T, axis=1, floor=1e-2)
+    eh_r = rowwise_err(eH.cpu().numpy(), upper27(rH), axis=1, floor=1e-2)
+    ee = relerr(E.item(), rE.sum())
+    print(f"  energy {ee:.2e}; gradient normwise {eg_n:.2e} worst element {eg_r:.2e}; "
+          f"Hessian normwise {eh_n:.2e} worst element {eh_r:.2e}")
+    assert ee < TOL32_H
+    assert relerr(eE.cpu().numpy(), rE) < TOL32_H
+    assert eg_n < TOL32_G and eh_n < TOL32_H
+    assert eg_r < TOL32_ROW and eh_r < TOL32_ROW
+
+
+def test_spmv_fp32_within_rounding_bound():
+    """bsc_spmv in BSC_FP32_MIXED: the input vector rounded to float and the 75 products of a row
+    summed in float. Input: the oracle's Hessian rounded to float32 (an input array of the call,
+    in its upper-stencil layout). Reference: the same float32 values times the FP64 vector in
+    FP64. Every entry must meet the standard bound for a rounded dot product,
+    |y - A v| <= gamma_{n+1} (|A| |v|) with n = 75 terms (one more rounding for v), u = 2^-24."""
+    sc = syn.compressed_sheet(37, seed=4)
+    sh = oracle_sheet(sc)
+    x = deformed(sc, 3, amp=0.03)
+    mask = np.zeros(sc.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    _, _, rH = oracle.assemble(sh, x, sc.x0, sc.dt, sc.gravity, mask)
+    H32 = oracle_stencil_to_upper(rH, sc.n_u, sc.n_v).astype(np.float32)
+    # the same float32 values back in the oracle's stencil form, as a sparse matrix
+    rH32 = rH.astype(np.float32).astype(np.float64)
+    A = oracle.stencil_to_csr(sh, rH32)
+    v = np.random.default_rng(3).standard_normal((sc.n_cp, 3))
+    ctx = _ctx(sc)
+    y = ctx.bsc_spmv(torch.from_numpy(H32).cuda(), bsc.to_soa(v), bsc.BSC_FP32_MIXED)
+    want = (A @ v.reshape(-1)).reshape(-1, 3)
+    bound_terms = (abs(A) @ np.abs(v).reshape(-1)).reshape(-1, 3)
+    u = 2.0 ** -24
+    n = 76
+    gamma = n * u / (1 - n * u)
+    got = bsc.to_aos(y)
+    ratio = np.abs(got - want) / np.maximum(gamma * bound_terms, 1e-300)
+    print(f"[spmv fp32] normwise {relerr(got, want):.2e}; worst entry at {ratio.max():.3f} of the rounding bound")
+    assert ratio.max() <= 1.0
+    # and against the FP64 product of the unrounded matrix: the float storage of H adds u |A| |v|
+    want64 = (oracle.stencil_to_csr(sh, rH) @ v.reshape(-1)).reshape(-1, 3)
+    assert np.all(np.abs(got - want64) <= (gamma + 2 * u) * bound_terms + 1e-300)
