@@ -280,6 +280,21 @@ bsc_status bsc_net_backward(bsc_ctx *ctx, int32_t batch, const float *d_weights,
                             void *d_scratch);
 bsc_status bsc_net_scratch_size(const bsc_ctx *ctx, int32_t batch, size_t *bytes);
 
+/* bsc_net_backward without the d_scratch argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, kernels and results as bsc_net_backward; the scratch is a static
+ * device array of BSC_NET_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends. Calls no
+ * hipMalloc, hipFree or allocating library routine.
+ *   Limit: bsc_net_scratch_size(ctx, batch) must not exceed BSC_NET_NOALLOC_SCRATCH_BYTES
+ *   (32 MiB: a 226 x 226 grid at batch 1, a 128 x 128 grid up to batch 5); larger requests return
+ *   BSC_E_INVAL before anything is enqueued.
+ *   Every call on one GPU shares that GPU's array and leaves its contents behind (the kernels
+ *   overwrite every byte they read, so nothing needs clearing): calls that overlap on one GPU,
+ *   from any context or stream, race. Asynchronous on the context's stream. */
+#define BSC_NET_NOALLOC_SCRATCH_BYTES (32u << 20)
+bsc_status bsc_net_backward_noalloc(bsc_ctx *ctx, int32_t batch, const float *d_weights, const float *d_in,
+                                    const float *d_acts, const float *d_dout, float *d_dweights, float *d_din);
+
 /* Adam update of n parameters in place (step counter t >= 1). */
 bsc_status bsc_adam_step(bsc_ctx *ctx, int32_t n, float *d_param, const float *d_grad, float *d_m,
                          float *d_v, float lr, float beta1, float beta2, float eps, int32_t t);

@@ -35,6 +35,7 @@ BSC_START_PREVIOUS = 0
 BSC_START_PREDICTOR = 1
 BSC_HESS_ENTRIES = 114
 BSC_NET_PARAMS = 38592
+BSC_NET_NOALLOC_SCRATCH_BYTES = 32 << 20   # static scratch of bsc_net_backward_noalloc, per GPU
 STATUS = {0: "BSC_OK", -1: "BSC_E_INVAL", -2: "BSC_E_KNOTS", -3: "BSC_E_NOMEM", -4: "BSC_E_HIP",
           -5: "BSC_E_NOT_CONVERGED", -6: "BSC_E_LINESEARCH", -7: "BSC_E_NONFINITE",
           -8: "BSC_E_PCG_BREAKDOWN", -9: "BSC_E_STATE"}
@@ -106,6 +107,7 @@ def load():
         "bsc_net_forward": [P, I32, P, P, P, P],
         "bsc_net_backward": [P, I32, P, P, P, P, P, P, P],
         "bsc_net_scratch_size": [P, I32, ctypes.POINTER(SZ)],
+        "bsc_net_backward_noalloc": [P, I32, P, P, P, P, P, P],
         "bsc_adam_step": [P, I32, P, P, P, P, F, F, F, F, I32],
         "bsc_net_loss": [P, I32, P, P, P, P, P],
         "bsc_set_sample_log": [P, P, P, I32],
@@ -132,7 +134,8 @@ def load():
 def exported_symbols() -> list[str]:
     return ["bsc_create", "bsc_sizes", "bsc_workspace_size", "bsc_bind_workspace", "bsc_set_pins", "bsc_eval_egh",
             "bsc_assemble", "bsc_spmv", "bsc_bsr_pattern", "bsc_export_bsr", "bsc_newton_step", "bsc_energy_difference",
-            "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size", "bsc_adam_step",
+            "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size",
+            "bsc_net_backward_noalloc", "bsc_adam_step",
             "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_contact_setup",
             "bsc_contact_workspace_size", "bsc_contact_bind_workspace", "bsc_contact_hessian", "bsc_status_string",
             "bsc_last_error", "bsc_destroy"]
@@ -438,6 +441,21 @@ class Context:
         _need(scratch, torch.uint8, self.bsc_net_scratch_size(batch), "scratch")
         self._check(self.lib.bsc_net_backward(self.h, batch, _ptr(weights), _ptr(inp), _ptr(acts), _ptr(dout),
                                               _ptr(dw), _ptr(din), _ptr(scratch)), "bsc_net_backward")
+        return dw, din
+
+    def bsc_net_backward_noalloc(self, weights, inp, acts, dout, dw, din=None):
+        """The no-allocation variant: writes into the caller's dw (and din, if given) and passes
+        no scratch (the library's static per-GPU array serves)."""
+        import torch
+        batch = inp.shape[0]
+        _need(weights, torch.float32, BSC_NET_PARAMS, "weights")
+        _need(inp, torch.float32, batch * 3 * self.n_cp, "inp")
+        _need(acts, torch.float32, batch * 5 * 32 * self.n_cp, "acts")
+        _need(dout, torch.float32, batch * 3 * self.n_cp, "dout")
+        _need(dw, torch.float32, BSC_NET_PARAMS, "dw")
+        _need(din, torch.float32, batch * 3 * self.n_cp, "din", optional=True)
+        self._check(self.lib.bsc_net_backward_noalloc(self.h, batch, _ptr(weights), _ptr(inp), _ptr(acts), _ptr(dout),
+                                                      _ptr(dw), _ptr(din)), "bsc_net_backward_noalloc")
         return dw, din
 
     def bsc_adam_step(self, param, grad, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):

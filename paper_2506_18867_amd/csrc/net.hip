@@ -14,6 +14,9 @@
 // positively homogeneous, so the normalisation only keeps FP32 in range.
 #include "bsc_internal.h"
 
+#include <mutex>
+#include <string>
+
 namespace bsc {
 namespace {
 
@@ -368,6 +371,41 @@ hipError_t net_loss(int n_cp, int batch, const float *in, const float *pred, con
     return hipGetLastError();
 }
 
+// Scratch of bsc_net_backward_noalloc: one static array per device, reached from host code only
+// through the address hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in there). Looked up once per device, under a lock, the first time a context on that
+// device calls the entry point.
+static __device__ __align__(256) unsigned char scratch[BSC_NET_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+bsc_status static_scratch_address(bsc_ctx *c, void **out) {
+    if (c->device < 0 || c->device >= kMaxDevices) return fail(c, BSC_E_INVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        int prev = 0;
+        bsc_status st = hip_check(c, hipGetDevice(&prev), "hipGetDevice");
+        if (st != BSC_OK) return st;
+        if (prev != c->device) {
+            st = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+            if (st != BSC_OK) return st;
+        }
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != c->device) (void)hipSetDevice(prev);
+        st = hip_check(c, e, "hipGetSymbolAddress(scratch)");
+        if (st != BSC_OK) return st;
+        if (!p) return fail(c, BSC_E_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[c->device] = p;
+    }
+    *out = g_scratch_ptr[c->device];
+    return BSC_OK;
+}
+
 }  // namespace bsc
 
 using namespace bsc;
@@ -411,6 +449,25 @@ bsc_status bsc_net_backward(bsc_ctx *c, int32_t batch, const float *d_weights, c
         return fail(c, BSC_E_INVAL, "bad arguments");
     return hip_check(c, net_backward(c->n_u, c->n_v, batch, d_weights, d_in, d_acts, d_dout, d_dweights, d_din, d_scratch,
                                      c->stream), "net backward");
+}
+
+bsc_status bsc_net_backward_noalloc(bsc_ctx *c, int32_t batch, const float *d_weights, const float *d_in,
+                                    const float *d_acts, const float *d_dout, float *d_dweights, float *d_din) {
+    if (!c) return BSC_E_INVAL;
+    if (!c->ws) return fail(c, BSC_E_STATE, "no workspace bound");
+    if (batch < 1 || batch > 1024 || !d_weights || !d_in || !d_acts || !d_dout || !d_dweights)
+        return fail(c, BSC_E_INVAL, "bad arguments");
+    const size_t need = net_scratch_bytes(c->n_u, c->n_v, batch);
+    if (need > size_t(BSC_NET_NOALLOC_SCRATCH_BYTES))
+        return fail(c, BSC_E_INVAL, "bsc_net_backward_noalloc: this grid and batch need " + std::to_string(need) +
+                                        " scratch bytes, more than the static " +
+                                        std::to_string(size_t(BSC_NET_NOALLOC_SCRATCH_BYTES)) +
+                                        "; use bsc_net_backward with a caller workspace");
+    void *base = nullptr;
+    bsc_status st = static_scratch_address(c, &base);
+    if (st != BSC_OK) return st;
+    return hip_check(c, net_backward(c->n_u, c->n_v, batch, d_weights, d_in, d_acts, d_dout, d_dweights, d_din, base,
+                                     c->stream), "net backward (static scratch)");
 }
 
 bsc_status bsc_net_loss(bsc_ctx *c, int32_t batch, const float *d_in, const float *d_pred, const float *d_target,

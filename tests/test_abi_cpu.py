@@ -126,6 +126,7 @@ def test_calls_without_workspace_fail_cleanly():
     assert lib.bsc_spmv(h, 0, None, None, None) == -9
     opts = bsc.make_opts()
     assert lib.bsc_newton_step(h, ctypes.byref(opts), None, None, None, None) == -9
+    assert lib.bsc_net_backward_noalloc(h, 1, None, None, None, None, None, None) == -9
     assert b"workspace" in lib.bsc_last_error(h)
     lib.bsc_destroy(h)
     assert lib.bsc_status_string(-6) == b"line search failed"
