@@ -90,8 +90,8 @@ typedef struct {
  *   the PCG initial guess (falls back to zero when it does not reduce the residual).
  *   pcg_adaptive: 1 chooses the PCG tolerance per Newton iteration by the Eisenstat-Walker rule
  *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2 (not below 0.9 eta_{k-1}^2 when that exceeds 0.1),
- *   clamped to [pcg_rtol, eta_max] (eta_0 = eta_max), eta_max = 0.5 under BSC_STOP_STEP and
- *   0.1 under BSC_STOP_GRAD; with
+ *   clamped to [pcg_rtol, eta_max] (eta_0 = eta_max), eta_max = pcg_eta_max if set, else 0.5
+ *   under BSC_STOP_STEP and 0.1 under BSC_STOP_GRAD; with
  *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
 /* PCG preconditioners. JACOBI: 3x3 block Jacobi, one fused kernel per iteration. MULTIGRID: one
  * symmetric V(1,1) cycle on the hierarchy of the patch's knot halvings (exact B-spline
@@ -117,6 +117,8 @@ typedef struct {
     int32_t pcg_adaptive;
     int32_t preconditioner;     /* BSC_PRECOND_JACOBI (default) or BSC_PRECOND_MULTIGRID */
     int32_t start;              /* BSC_START_PREVIOUS (default) or BSC_START_PREDICTOR */
+    double pcg_eta_max;         /* cap of the adaptive PCG tolerance; 0 = 0.5 under BSC_STOP_STEP,
+                                   0.1 under BSC_STOP_GRAD; else in [pcg_rtol, 0.9] */
 } bsc_step_opts;
 
 /* Statistics of one step. ms_assemble, ms_pcg, ms_linesearch and ms_warmstart are GPU phase

@@ -1132,7 +1132,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
     bsc_status result = BSC_OK;
     double g0 = -1.0, g_prev = -1.0;
-    const double eta_max = step_rule ? kEtaMaxStep : kEtaMaxGrad;
+    const double eta_max = o->pcg_eta_max > 0.0 ? o->pcg_eta_max : (step_rule ? kEtaMaxStep : kEtaMaxGrad);
     double eta = o->pcg_adaptive ? std::max(o->pcg_rtol, eta_max) : o->pcg_rtol;   // PCG tolerance (host-side modes)
     bool force_tight = false;
     double host[2];
@@ -1240,8 +1240,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             // multigrid: Galerkin hierarchy and block-Jacobi inverses of every level, then r = b,
             // p = 0, the flags and the tolerance (the first iteration's stop test sets |b|-relative
             // tolerance from the partials of |b|^2)
-            const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), 1 | (step_rule ? 2u : 0u)};
+            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
+                                     uint64_t(o->max_pcg), 1 | (step_rule ? 2u : 0u), bits(eta_max)};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                      enqueue_prep(cs);
                      (void)mg_setup(S, B, prec, cs);
@@ -1249,8 +1249,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                         eta_mode, first, eta_arg, o->pcg_rtol, eta_max);
                  }), "mg init");
         } else if (!o->warm_start) {
-            const uint64_t key[8] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u};
+            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
+                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u, bits(eta_max)};
             HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                      enqueue_prep(cs);
                      enqueue_init(cs, nullptr);
@@ -1515,6 +1515,8 @@ bsc_status bsc_newton_step(bsc_ctx *c, const bsc_step_opts *o, double *d_x, doub
     if (o->stop_mode != BSC_STOP_GRAD && o->stop_mode != BSC_STOP_STEP) return fail(c, BSC_E_INVAL, "bad stop mode");
     if (o->start != BSC_START_PREVIOUS && o->start != BSC_START_PREDICTOR) return fail(c, BSC_E_INVAL, "bad start");
     if (o->max_newton < 1 || o->max_pcg < 1 || !(o->pcg_rtol > 0.0)) return fail(c, BSC_E_INVAL, "bad iteration limits");
+    if (!(o->pcg_eta_max == 0.0 || (o->pcg_eta_max >= o->pcg_rtol && o->pcg_eta_max <= 0.9)))
+        return fail(c, BSC_E_INVAL, "pcg_eta_max must be 0 or in [pcg_rtol, 0.9]");
     if (!c->pins.empty() && !d_pin_targets) return fail(c, BSC_E_INVAL, "pins set but no targets");
     if (o->warm_start && !c->net_loaded) return fail(c, BSC_E_STATE, "warm start requested but no network loaded");
     for (int k = 0; k < 3; ++k)
