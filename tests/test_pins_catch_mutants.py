@@ -153,6 +153,15 @@ PY_MUTANTS = [
     ("net_input_not_normalised", "net_ref.py", [("s = 1.0 / rms if rms > 0 else 0.0", "s = 1.0")]),
     ("net_loss_mask_inverted", "net_ref.py",
      [("m = (np.abs(x[b]).sum(axis=0) != 0)", "m = (np.abs(x[b]).sum(axis=0) == 0)")]),
+    # partial factorization (Sec. 5.3)
+    ("neumann_term_sign", "partial_ref.py", [("t = -lu.solve(B @ t)", "t = lu.solve(B @ t)")]),
+    ("gershgorin_without_abs", "partial_ref.py", [("A = abs(B).tolil()", "A = B.tolil()")]),
+    ("lambda_min_mass_over_dt", "partial_ref.py",
+     [("best = min(best, mass[a] / (dt * dt) + max(0.0, g))", "best = min(best, mass[a] / dt + max(0.0, g))")]),
+    ("barrier_pins_not_dropped", "partial_ref.py",
+     [("P = sp.diags(dof_mask(n_cp, pinned))", "P = sp.identity(3 * n_cp)")]),
+    ("merged_branch_drops_b", "partial_ref.py",
+     [("x = spla.spsolve((D + B).tocsc(), bb)", "x = spla.spsolve(D, bb)")]),
 ]
 
 MUTANTS = [(name, "bsc_oracle.c", edits) for name, edits in C_MUTANTS] + PY_MUTANTS
@@ -182,7 +191,7 @@ import pytest
 sys.exit(pytest.main(sys.argv[2:]))
 """
 
-PKG_FILES = ("__init__.py", "bsc_oracle.c", "contact_ref.py", "net_ref.py")
+PKG_FILES = ("__init__.py", "bsc_oracle.c", "contact_ref.py", "net_ref.py", "partial_ref.py")
 
 
 def _run_pins(tmp: str, name: str, fname: str | None, edits):
