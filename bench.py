@@ -22,6 +22,8 @@ Further legs (each a field of the one JSON line):
   assembly, spmv    the eval+assembly pass and the plain SpMV timed on their own;
   ceilings          measured copy bandwidth from HBM and from the caches (footprints that stay
                     resident in the L2s and the 256 MB Infinity Cache);
+  partial_factorization  the Newton system with a contact Hessian at several contact
+                    intensities: the Gershgorin trigger, the series and the merged solve;
   quadrature_ablation, general_rest, contact_conversion, wrinkling_convergence.
 The roofline object covers the kernel with the largest share of the step (the fused PCG-iteration
 kernel), timed live by the library with HIP events around its graph chunks on its stream (the
@@ -114,6 +116,10 @@ def parse(argv=None):
                    help="steps of the general-rest leg (the same driven sheet on a curved domain; 0: skip)")
     p.add_argument("--contact-pairs", type=int, default=100000,
                    help="contact pairs of the contact-Hessian conversion leg (0: skip)")
+    p.add_argument("--pf-pairs", type=int, default=20000,
+                   help="contact pairs of the partial-factorization leg (0: skip)")
+    p.add_argument("--pf-scales", default="1e-6,1e-5,3e-5,1e-4,1e-3,1e-2",
+                   help="contact-Hessian scales of the partial-factorization leg, comma-separated")
     p.add_argument("--wrinkle-levels", default="16,32,48,64,80,96,112,128",
                    help="spans across the width of the wrinkling-plate convergence leg, comma-separated "
                         "('': skip)")
@@ -472,6 +478,44 @@ def main():
                        "mblocks_per_s": round(nblk / ms_c / 1e3, 2)}
         del dpv, dH, dg, outc, res
 
+    # ---- partial factorization (Sec. 5.3): the Newton system with a contact Hessian ----
+    # At the headline's last state: H (FP32-mixed, as the Newton step forms it) plus a contact
+    # Hessian from the folded-sheet pairs at several intensities (the pair Hessians scaled). Per
+    # intensity: the Gershgorin bound and the branch it picks, and the time of both branches
+    # (the series at the bound's number of terms, the merged PCG), each PCG solve to the Newton
+    # step's first forcing term (0.1) and the series truncated at 0.1 likewise.
+    pf_leg = None
+    if args.pf_pairs > 0:
+        uvc, tris, cgrid = syn.contact_mesh(sc.n_u, sc.n_v)
+        ctx.bsc_contact_setup(uvc, args.pf_pairs)
+        _, _, Hpf = ctx.bsc_assemble(x, x, sc.dt, tuple(sc.gravity), bsc.BSC_FP32_MIXED)
+        _, gpf, _ = ctx.bsc_assemble(x, x, sc.dt, tuple(sc.gravity), bsc.BSC_FP64, want_hess=False)
+        bpf = (-gpf).contiguous()
+        pf_leg = {"pairs": args.pf_pairs, "pcg_rtol": 0.1, "series_tol": 0.1, "rho_max": 0.5, "cases": []}
+        for scale in [float(a) for a in args.pf_scales.split(",")]:
+            pv, Hp, _ = syn.contact_pairs(uvc, tris, cgrid, args.pf_pairs, seed=args.seed, scale=scale)
+            rp, ci, cv, _ = ctx.bsc_contact_hessian(torch.from_numpy(pv).cuda(), torch.from_numpy(Hp).cuda(),
+                                                    want_grad=False)
+            case = {"scale": scale, "cp_blocks": int(ci.numel())}
+            for name, force in (("auto", 0), ("series", 1), ("merged", 2)):
+                # the series is timed only where the bound guarantees convergence (rho < 1); above
+                # it a forced series would sum max_terms terms of a possibly divergent expansion
+                if name == "series" and not case["rho_bound"] < 1.0:
+                    case[name] = None
+                    continue
+                kw = dict(precision=bsc.BSC_FP32_MIXED, rho_max=0.5, series_tol=0.1, pcg_rtol=0.1, max_pcg=6000,
+                          force=force, max_terms=64)
+                ctx.bsc_contact_solve(Hpf, sc.dt, rp, ci, cv, bpf, **kw)                  # warm-up
+                _, stp = ctx.bsc_contact_solve(Hpf, sc.dt, rp, ci, cv, bpf, **kw)
+                case[name] = {"ms": round(stp.ms_total, 3), "pcg_iters": stp.pcg_iters, "terms": stp.terms,
+                              "triggered": stp.triggered}
+                case["rho_bound"] = float("%.4g" % stp.rho_bound)
+            pf_leg["cases"].append(case)
+        pf_leg["trigger_rate"] = round(sum(c["auto"]["triggered"] for c in pf_leg["cases"]) / len(pf_leg["cases"]), 3)
+        log("[bench] partial factorization: " + " ".join(
+            f"{c['scale']:g}: rho {c['rho_bound']:.3g} {'S' if c['auto']['triggered'] else 'M'} "
+            f"series {c['series']['ms'] if c['series'] else '-'}ms merged {c['merged']['ms']}ms" for c in pf_leg["cases"]))
+
     # ---- membrane convergence under refinement (Sec. 6.2, the stretched-plate wrinkling benchmark) ----
     # Per resolution one quasi-static FP64 solve (dt = 1e4 s) from the perturbed start to
     # |g| <= 1e-9 |g0|, and the largest out-of-plane deflection of the surface. The paper's
@@ -606,6 +650,7 @@ def main():
         "quadrature_ablation": quad_leg,
         "general_rest": general_leg,
         "contact_conversion": contact_leg,
+        "partial_factorization": pf_leg,
         "wrinkling_convergence": wrinkle_leg,
         "roofline": roof,
         "cpu_baseline": None,

@@ -347,6 +347,45 @@ bsc_status bsc_contact_hessian(bsc_ctx *ctx, int32_t n_pairs, const int32_t *d_p
                                const double *d_pair_grad, int32_t cap_blocks, int32_t *d_row_ptr, int32_t *d_col_idx,
                                double *d_vals, int32_t *nnzb, double *d_grad);
 
+/* ---- Partial factorization (Sec. 5.3, Eq. "per iteration solve", Eq. "Woodbury", Eq. "Neumann
+ * expansion", the Gershgorin bound) ------------------------------------------------------------
+ * Solves the Newton system with a contact Hessian, (H + H_c) x = b.
+ *   H: d_hess, the inertia-plus-elasticity Hessian in upper-stencil form and the given precision,
+ *     as bsc_assemble writes it (pinned CPs with identity diagonal blocks); H_c: the contact
+ *     (barrier) Hessian in block CSR with both triangles, as bsc_contact_hessian writes it
+ *     (d_row_ptr: n_cp + 1 ints with d_row_ptr[n_cp] == nnzb, d_col_idx: nnzb ints in
+ *     [0, n_cp), d_vals: 9 nnzb doubles, row-major 3x3 per block); H_c must be positive
+ *     semi-definite (as a projected barrier Hessian is). dt: the step, for the lumped inertia
+ *     M_a / dt^2 in the bound. d_b, d_x: 3 n_cp doubles (SoA), distinct.
+ * Split: H_c = (its 3x3 CP self-blocks) + B; D = H + self-blocks keeps the stencil pattern.
+ * Rows and columns of H_c at pinned CPs are dropped. Trigger: rho = max_i sum_j |B_ij| /
+ * min over free CPs of (M_a / dt^2 + max(0, Gershgorin lower bound of H_c[a, a])) bounds
+ * |D^-1 B|_op (H's elastic part and H_c are PSD). If rho <= rho_max (and < 1), the Neumann series
+ * x = sum_{k<=K} (-D^-1 B)^k D^-1 b with K the smallest integer such that rho^(K+1)/(1-rho) <=
+ * series_tol (at most max_terms terms), each D^-1 by the fused block-Jacobi stencil PCG to
+ * pcg_rtol; else PCG on D + B (block Jacobi on D's diagonal blocks) to pcg_rtol. force: 0 lets
+ * the bound decide, 1 takes the series (max_terms terms if rho >= 1), 2 the merged solve.
+ * Uses the workspace's Hessian buffer and solver vectors (overwrites what bsc_assemble or
+ * bsc_newton_step left there); d_hess must be a caller buffer. Synchronous. BSC_E_INVAL for a
+ * column index outside [0, n_cp) or d_row_ptr[n_cp] != nnzb; BSC_E_PCG_BREAKDOWN if an inner
+ * solve meets p^T A p <= 0. */
+typedef struct {
+    double rho_max;        /* trigger threshold of the bound (e.g. 0.5) */
+    double series_tol;     /* truncation target of the series (e.g. 1e-12) */
+    int32_t max_terms;     /* 1..1000 */
+    double pcg_rtol;       /* relative residual of every inner and merged PCG solve */
+    int32_t max_pcg;       /* iterations per PCG solve */
+    int32_t force;         /* 0 bound decides, 1 series, 2 merged */
+} bsc_pf_opts;
+typedef struct {
+    int32_t triggered, terms, pcg_iters;     /* series taken; terms summed; PCG iterations in all */
+    double rho_bound, b_bound, d_bound;      /* the bound, its numerator and denominator */
+    double ms_total;                         /* host wall-clock time of the call */
+} bsc_pf_stats;
+bsc_status bsc_contact_solve(bsc_ctx *ctx, int32_t precision, const void *d_hess, double dt, const int32_t *d_row_ptr,
+                             const int32_t *d_col_idx, const double *d_vals, int32_t nnzb, const double *d_b,
+                             double *d_x, const bsc_pf_opts *opts, bsc_pf_stats *stats);
+
 const char *bsc_status_string(bsc_status s);
 const char *bsc_last_error(const bsc_ctx *ctx);
 void bsc_destroy(bsc_ctx *ctx);

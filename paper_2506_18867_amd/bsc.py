@@ -65,6 +65,20 @@ class StepOpts(ctypes.Structure):
                 ("pcg_eta_max", ctypes.c_double)]
 
 
+class PfOpts(ctypes.Structure):
+    _fields_ = [("rho_max", ctypes.c_double), ("series_tol", ctypes.c_double), ("max_terms", ctypes.c_int32),
+                ("pcg_rtol", ctypes.c_double), ("max_pcg", ctypes.c_int32), ("force", ctypes.c_int32)]
+
+
+class PfStats(ctypes.Structure):
+    _fields_ = [("triggered", ctypes.c_int32), ("terms", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("rho_bound", ctypes.c_double), ("b_bound", ctypes.c_double), ("d_bound", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class StepStats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
                 ("ls_halvings", ctypes.c_int32), ("warm_start_used", ctypes.c_int32),
@@ -117,6 +131,7 @@ def load():
         "bsc_contact_workspace_size": [P, ctypes.POINTER(SZ)],
         "bsc_contact_bind_workspace": [P, P, SZ],
         "bsc_contact_hessian": [P, I32, P, P, P, I32, P, P, P, ctypes.POINTER(I32), P],
+        "bsc_contact_solve": [P, I32, P, D, P, P, P, I32, P, P, ctypes.POINTER(PfOpts), ctypes.POINTER(PfStats)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -138,7 +153,8 @@ def exported_symbols() -> list[str]:
             "bsc_warmstart_load", "bsc_net_forward", "bsc_net_backward", "bsc_net_scratch_size",
             "bsc_net_backward_noalloc", "bsc_adam_step",
             "bsc_net_loss", "bsc_set_sample_log", "bsc_sample_log_count", "bsc_contact_setup",
-            "bsc_contact_workspace_size", "bsc_contact_bind_workspace", "bsc_contact_hessian", "bsc_status_string",
+            "bsc_contact_workspace_size", "bsc_contact_bind_workspace", "bsc_contact_hessian", "bsc_contact_solve",
+            "bsc_status_string",
             "bsc_last_error", "bsc_destroy"]
 
 
@@ -323,6 +339,30 @@ class Context:
         self._check(self.lib.bsc_eval_egh(self.h, precision, _ptr(x), _ptr(E), _ptr(eE), _ptr(eg), _ptr(eH)),
                     "bsc_eval_egh")
         return E, eE, eg, eH
+
+    def bsc_contact_solve(self, hess, dt, row_ptr, col_idx, vals, b, precision=BSC_FP64, x=None, rho_max=0.5,
+                          series_tol=1e-12, max_terms=64, pcg_rtol=1e-12, max_pcg=20000, force=0):
+        """(H + H_c) x = b by partial factorization (Sec. 5.3). hess: (114, n_cp) upper-stencil H in
+        the precision's dtype; row_ptr, col_idx, vals: H_c in block CSR as bsc_contact_hessian returns
+        it; b: (3, n_cp) float64. Returns (x, PfStats)."""
+        import torch
+        tdt = torch.float64 if precision == BSC_FP64 else torch.float32
+        nnzb = int(col_idx.numel()) if col_idx is not None else 0
+        _need(hess, tdt, BSC_HESS_ENTRIES * self.n_cp, "hess")
+        _need(row_ptr, torch.int32, self.n_cp + 1, "row_ptr")
+        if nnzb:
+            _need(col_idx, torch.int32, nnzb, "col_idx")
+            _need(vals, torch.float64, 9 * nnzb, "vals")
+        _need(b, torch.float64, 3 * self.n_cp, "b")
+        x = torch.empty_like(b) if x is None else x
+        _need(x, torch.float64, 3 * self.n_cp, "x")
+        opts = PfOpts(float(rho_max), float(series_tol), int(max_terms), float(pcg_rtol), int(max_pcg), int(force))
+        stats = PfStats()
+        self._check(self.lib.bsc_contact_solve(self.h, precision, _ptr(hess), float(dt), _ptr(row_ptr),
+                                               _ptr(col_idx) if nnzb else None, _ptr(vals) if nnzb else None, nnzb,
+                                               _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(stats)),
+                    "bsc_contact_solve")
+        return x, stats
 
     def bsc_assemble(self, x, xhat=None, dt=0.0, gravity=None, precision=BSC_FP64, want_hess=True, out=None):
         import torch

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbsc.so")
-SOURCES = ["host.cpp", "eval.hip", "solve.hip", "net.hip", "contact.hip", "mg.hip"]
+SOURCES = ["host.cpp", "eval.hip", "solve.hip", "net.hip", "contact.hip", "mg.hip", "partial.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

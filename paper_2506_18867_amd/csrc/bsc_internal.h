@@ -309,6 +309,9 @@ hipError_t launch_export_bsr(const DevSheet &S, int precision, const void *hess,
                              const int32_t *col_idx, void *vals, hipStream_t st);
 bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *v, const double *pin_tgt,
                        bsc_step_stats *stats);
+// H x = b for the upper-stencil matrix held in the workspace (B.hess) by the fused block-Jacobi PCG
+// from x0 = 0 to |r| <= rtol |b|; overwrites the workspace's CG vectors, B.g, B.tmp and B.dir.
+bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, double rtol, int max_iter, int *iters);
 
 // ---- launchers (net.hip) ----
 hipError_t net_forward_impl(int n_u, int n_v, int batch, const float *w, const float *in, float *out, float *acts,

@@ -1483,6 +1483,69 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     return result;
 }
 
+// Solves H x = b for the upper-stencil matrix in the workspace (B.hess, working precision prec)
+// with the fused block-Jacobi PCG from x0 = 0 until |r|_2 <= rtol |b|_2 or max_iter iterations.
+// The launches are enqueued in bursts of 16 with one flag read per burst. Uses the workspace's
+// CG vectors, partials and scalars and B.g, B.tmp, B.dir (overwritten). b and x may not alias
+// those buffers.
+bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, double rtol, int max_iter, int *iters) {
+    const DevSheet &S = ctx->dev;
+    const DevBufs &B = ctx->buf;
+    hipStream_t st = ctx->stream;
+    const int n3 = 3 * S.n_cp, stride = B.max_blocks;
+    const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
+    const bool presum = nbc > kCgPreSumBlocks;
+    double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
+    double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
+    auto bufs = [&](int j) {
+        CgBufs c{};
+        c.x = B.dir; c.p = B.p0; c.pinv = B.pinv;
+        c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
+        c.pre = presum ? B.scalars + S_CGSUM : nullptr;
+        const int cur = j & 1, prev = (j + 1) & 1;
+        c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
+        c.w_in = wb[prev]; c.w_out = wb[cur];
+        c.s_in = sb[prev]; c.s_out = sb[cur];
+        c.part_in = part[prev]; c.part_out = part[cur];
+        c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
+        return c;
+    };
+    auto fused = [&](int j) {
+        if (prec == BSC_FP64) {
+            if (j == 0) k_cg_fused<double, true><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+            else k_cg_fused<double, false><<<nbc, 512, 0, st>>>(S, (const double *)B.hess, bufs(j), B.scalars, B.iscalars);
+        } else {
+            if (j == 0) k_cg_fused<float, true><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+            else k_cg_fused<float, false><<<nbc, 512, 0, st>>>(S, (const float *)B.hess, bufs(j), B.scalars, B.iscalars);
+        }
+        if (presum) k_cg_sum<<<1, 1024, 0, st>>>(part[j & 1], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
+    };
+    // block-Jacobi inverse of the matrix, b (as 0 - (-b)) into B.tmp, x0 = 0 into B.dir
+    k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, b, 0.0, b, B.g);
+    if (prec == BSC_FP64)
+        k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
+    else
+        k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
+    k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
+                                       ETA_EXPLICIT, 1, rtol, rtol, rtol);
+    fused(0);
+    HIPX(hipGetLastError(), "stencil pcg");
+    int32_t flags[8] = {};
+    for (int launched = 1;;) {
+        for (int k = 0; k < 16; ++k) fused(launched++);
+        HIPX(hipGetLastError(), "stencil pcg");
+        HIPX(hipMemcpyAsync(flags, B.iscalars, sizeof(flags), hipMemcpyDeviceToHost, st), "stencil pcg flags");
+        HIPX(hipStreamSynchronize(st), "stencil pcg");
+        if (flags[I_DONE]) break;
+        if (launched > max_iter + 2) return fail(ctx, BSC_E_STATE, "stencil pcg: solver did not finish");
+    }
+    if (iters) *iters = flags[I_ITERS];
+    if (flags[I_BREAK])
+        return fail(ctx, BSC_E_PCG_BREAKDOWN, "stencil pcg: p^T H p <= 0 at iteration " + std::to_string(flags[I_ITERS]));
+    HIPX(hipMemcpyAsync(x, B.dir, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "stencil pcg result");
+    return BSC_OK;
+}
+
 }  // namespace bsc
 
 using namespace bsc;
