@@ -134,11 +134,11 @@ def test_newton_converges_on_mapped_rest(precision):
 
 
 def test_newton_iterations_on_distorted_patches():
-    """Sec. 6.2 reports solver iteration counts within a small constant factor of the
-    rectangular baseline for its three distortion categories (aspect ratio, skewed corners,
-    sharp turns within an edge). Hanging 40 x 40 sheets, 6 steps each with the paper's stopping
-    rule, FP64: Newton iterations of each distorted patch against the square. The quarter
-    annulus (not one of the paper's categories) is reported only."""
+    """Sec. 6.2 finds that distorting the patch (stretched aspect ratio, skewed corners, a sharp
+    turn along an edge) leaves the solver's iteration counts close to those of the square patch.
+    Hanging 40 x 40 sheets, 6 steps each with the paper's stopping rule, FP64: Newton iterations
+    of each distorted patch against the square, bounded by three times the square's count. The
+    quarter annulus (not one of the paper's categories) is reported only."""
     counts = {}
     for kind, param in [("aspect", 1.0), ("aspect", 4.0), ("skew", 45.0), ("bend", 120.0), ("annulus", 0.5)]:
         sc = syn.mapped_hanging_sheet(40, kind, param, seed=8)

@@ -3,9 +3,13 @@
 Uses the committed weights (paper_2506_18867_amd/weights/warmstart_c32.f32, trained by
 paper_2506_18867_amd/train_warmstart.py on the method's own 128 x 128 solves, seeds 4000+).
 On held-out sheets (seeds 9000+): the trained net's loss on freshly logged (g, p) pairs must be
-far below an untrained net's, and a warm-started Newton step must reach the same stopping rule
-as the zero-start step; the PCG-iteration and time ratios are printed (the measured gain is
-small, see the design notes), and the warm start must not cost more than 5 % of PCG iterations."""
+far below an untrained net's. The warm start itself does not pay: the residual test accepts its
+guess in a minority of Newton iterations, the PCG iterations it saves stay within a few
+percent, and the network's forward pass costs more time than those iterations, so a
+warm-started step is slower than a zero-start step (measured 2.2x slower on the held-out
+226 x 226 compressed drape at 1e-6 |g0|). The second test pins that negative result: the
+warm-started step meets the same stopping rule, and its PCG iterations stay within 5 % of the
+zero start's either way."""
 import os
 
 import numpy as np
@@ -55,7 +59,7 @@ def test_trained_net_beats_untrained_on_heldout_pairs():
     assert losses["trained"] < 0.6 * losses["untrained"]
 
 
-def test_warm_started_step_reaches_the_same_stopping_rule():
+def test_warm_start_gains_no_pcg_iterations_and_keeps_the_stopping_rule():
     sc = syn.driven_sheet(128, seed=9002, cell=7)                 # E = 1e5 Pa, t = 1 mm
     stats = {}
     for ws in (0, 1):
@@ -79,6 +83,7 @@ def test_warm_started_step_reaches_the_same_stopping_rule():
           f"{stats[0]['pcg'] / max(1, stats[1]['pcg']):.3f}, time ratio = {stats[0]['ms'] / stats[1]['ms']:.3f}")
     # one warm-start attempt per PCG solve; with the step rule the last solve of a step ends it
     assert stats[1]["newton"] <= stats[1]["used"] + stats[1]["fallbacks"] <= stats[1]["newton"] + 4
-    assert stats[1]["pcg"] <= 1.05 * stats[0]["pcg"]
+    # no gain and no loss beyond 5 % of the PCG iterations (a better network would move this)
+    assert 0.95 * stats[0]["pcg"] <= stats[1]["pcg"] <= 1.05 * stats[0]["pcg"]
     # both runs met the same stopping rule at every step (status 0 above); compressed sheets may
     # buckle into different but equally valid states, so the states themselves are not compared
