@@ -132,26 +132,64 @@ constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
 
 // LDS layout of one assembly tile (offsets in bytes): local membrane point offsets of the
 // (tx + 2) x (ty + 2) elements, the first global point of each element row, the work counter,
-// then one record per membrane point. FP32
-// record (kAsmRecF floats, 16-byte aligned): the weighted density Hessian A (21 entries, padded
-// to 24), then the gradients of the 9 local basis functions (18). FP64 record (kAsmRecD
-// doubles): A (21), then the span coordinates tu, tv (the gradients are recomputed), then for a
-// general (non-affine) rest map the point's inverse Jacobian K (4; kAsmRecDC doubles in all).
-constexpr int kAsmRecF = 44, kAsmRecD = 23, kAsmRecDC = 27;
+// then one record per membrane point holding what the tile's items read of that point:
+//   FP32 (kAsmF32, floats, 16-byte aligned): the weighted density Hessian A (21 entries, padded
+//     to 24), the gradients of the 9 local basis functions (18, from 24), the weighted first
+//     Piola stress P (6, from 44): kAsmRecF floats.
+//   mixed (kAsmMixed, floats, 16-byte aligned): A and the basis gradients as in FP32 (float, for
+//     the FP32 Hessian), then in double for the FP64 gradient P (from float 44), the span
+//     coordinates tu, tv (from 56) and, for a general rest map, the inverse Jacobian K (from 60):
+//     kAsmRecM / kAsmRecMC floats.
+//   FP64 (kAsmF64, doubles): A (21), tu, tv (21, 22; the gradients are recomputed), K (23..26
+//     for a general rest map), P (6, after them): kAsmRecD / kAsmRecDC doubles.
+// The record lengths in 16-byte units are odd or twice odd, so the neighbouring records that
+// the lanes of a wave read fall on different LDS banks.
+constexpr int kAsmRecF = 52, kAsmRecM = 60, kAsmRecMC = 68, kAsmRecD = 29, kAsmRecDC = 33;
 struct AsmLds {
     size_t el_off, rows, counter, rec, rec_bytes, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
-__host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int sizeA, bool curved) {
+__host__ __device__ inline size_t asm_rec_bytes(int kind, bool curved) {
+    return kind == kAsmF32 ? 4 * kAsmRecF
+                           : (kind == kAsmMixed ? 4 * (curved ? kAsmRecMC : kAsmRecM) : 8 * (curved ? kAsmRecDC : kAsmRecD));
+}
+__host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int kind, bool curved) {
     AsmLds L;
     const size_t ne = size_t(tx + 2) * (ty + 2);
     L.el_off = 0;                                   // local membrane point offsets (ne + 1)
     L.rows = align16(L.el_off + 4 * (ne + 1));      // global first point of each element row (ty + 2)
     L.counter = align16(L.rows + 4 * size_t(ty + 2));
     L.rec = align16(L.counter + 4);
-    L.rec_bytes = sizeA == 4 ? 4 * kAsmRecF : 8 * (curved ? kAsmRecDC : kAsmRecD);
+    L.rec_bytes = asm_rec_bytes(kind, curved);
     L.total = align16(L.rec + L.rec_bytes * size_t(maxp));
     return L;
+}
+// Tile rows of the assembly: the four CP rows at each edge of the sheet get tile rows of height
+// e = min(2, ty) (their elements, next to the boundary, carry the boundary spans' extra
+// quadrature points, which would otherwise set the LDS size of every tile), the interior rows
+// tile rows of height ty; sheets with fewer than 9 CP rows use height e throughout.
+__host__ __device__ inline int asm_tile_rows(int n_v, int ty) {
+    const int e = ty < 2 ? 1 : 2;
+    return n_v >= 9 ? 8 / e + (n_v - 8 + ty - 1) / ty : (n_v + e - 1) / e;
+}
+__host__ __device__ inline void asm_tile_row(int n_v, int ty, int tr, int &y0, int &h) {
+    const int e = ty < 2 ? 1 : 2;
+    if (n_v < 9) {
+        y0 = e * tr;
+        h = n_v - y0 < e ? n_v - y0 : e;
+        return;
+    }
+    const int ne = 4 / e, nint = (n_v - 8 + ty - 1) / ty;
+    if (tr < ne) {
+        y0 = e * tr;
+        h = e;
+    } else if (tr < ne + nint) {
+        y0 = 4 + (tr - ne) * ty;
+        h = n_v - 4 - y0 < ty ? n_v - 4 - y0 : ty;
+    } else {
+        y0 = n_v - 4 + e * (tr - ne - nint);
+        h = e;
+    }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every

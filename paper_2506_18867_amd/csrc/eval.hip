@@ -453,12 +453,9 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
 // ---- stage 1 kernels ------------------------------------------------------------------------
 
 // T: arithmetic; TA, TP: stored precision of the weighted density Hessian and stress.
-template <typename T, bool HESS, bool CURVED, typename TA = T, typename TP = T>
-__global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
-                                                     TP *__restrict__ ptP, double *__restrict__ ptE,
-                                                     double *__restrict__ partials) {
-    __shared__ double sh[kBlock / 64];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+template <typename T, bool HESS, bool CURVED, typename TA, typename TP>
+__device__ __forceinline__ double membrane_point(const DevSheet &S, const double *__restrict__ x, TA *__restrict__ ptA,
+                                                 TP *__restrict__ ptP, double *__restrict__ ptE, int q) {
     double e_loc = 0.0;
     if (q < S.n_mp) {
         const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
@@ -510,15 +507,12 @@ __global__ void __launch_bounds__(kBlock) k_membrane(DevSheet S, const double *_
                 for (int c = r; c < 6; ++c) ptA[u6(r, c) * S.n_mp + q] = TA(w * Ad[r][c]);
         }
     }
-    const double s = block_sum(e_loc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    return e_loc;
 }
 
 template <bool CURVED>
-__global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__restrict__ x, double *__restrict__ beD,
-                                                    double *__restrict__ beE, double *__restrict__ partials) {
-    __shared__ double sh[kBlock / 64];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ double bending_point(const DevSheet &S, const double *__restrict__ x, double *__restrict__ beD,
+                                                double *__restrict__ beE, int q) {
     double e_loc = 0.0;
     if (q < S.n_be) {
         const int e = S.be_elem[q], k = e % S.Nu, l = e / S.Nu;
@@ -538,8 +532,27 @@ __global__ void __launch_bounds__(kBlock) k_bending(DevSheet S, const double *__
 #pragma unroll
         for (int c = 0; c < 3; ++c) beD[c * S.n_be + q] = wm * lap[c];
     }
+    return e_loc;
+}
+
+// The membrane points and the bending evaluations in one launch: blocks [0, nbm) take membrane
+// points, the rest bending evaluations; each block writes the sum of its energies to its own
+// partial slot (membrane: pm[block], bending: pb[block - nbm]), so the sums keep the order of
+// separate launches. The two parts are independent, and one grid lets the light bending blocks
+// fill the slots that the register-heavy membrane blocks leave free.
+template <typename T, bool HESS, bool CURVED, typename TA = T, typename TP = T, bool BEND = true>
+__global__ void __launch_bounds__(kBlock) k_points(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
+                                                   TP *__restrict__ ptP, double *__restrict__ ptE,
+                                                   double *__restrict__ pm, double *__restrict__ beD,
+                                                   double *__restrict__ beE, double *__restrict__ pb, int nbm) {
+    __shared__ double sh[kBlock / 64];
+    const bool mem = !BEND || int(blockIdx.x) < nbm;
+    const int blk = mem ? int(blockIdx.x) : int(blockIdx.x) - nbm;
+    const int q = blk * kBlock + threadIdx.x;
+    const double e_loc = mem ? membrane_point<T, HESS, CURVED, TA, TP>(S, x, ptA, ptP, ptE, q)
+                             : bending_point<CURVED>(S, x, beD, beE, q);
     const double s = block_sum(e_loc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) (mem ? pm : pb)[blk] = s;
 }
 
 // ---- stage 2, tiled: Hessian blocks from LDS, gradient ------------------------------------------
@@ -562,68 +575,97 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                                                                TA *__restrict__ hess, TG *__restrict__ gout,
                                                                double *__restrict__ partials, double *__restrict__ gg_partials) {
     constexpr bool STAGE_DN = sizeof(TA) == 4;
+    // kind of record (see AsmLds): FP32, mixed (float Hessian, double stress) or FP64
+    constexpr int KIND = sizeof(TA) == 4 ? (sizeof(TP) == 4 ? kAsmF32 : kAsmMixed) : kAsmF64;
+    constexpr int REC = KIND == kAsmF32 ? kAsmRecF
+                      : (KIND == kAsmMixed ? (CURVED ? kAsmRecMC : kAsmRecM) : (CURVED ? kAsmRecDC : kAsmRecD));
+    // offsets (units of TA) of the stress P and, in mixed records, of the double tu, tv and K
+    constexpr int OFF_P = KIND == kAsmF64 ? (CURVED ? 27 : 23) : 44;
+    constexpr int OFF_T = 56, OFF_K = 60;
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
+    __shared__ int s_rowlen[16];                 // points per element row of the tile (ty + 2 rows)
     const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
-    const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, int(sizeof(TA)), CURVED);
+    const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, KIND, CURVED);
     int *el_off = (int *)(lds + L.el_off);
     int *mrow = (int *)(lds + L.rows);
     int *counter = (int *)(lds + L.counter);
-    constexpr int REC = STAGE_DN ? kAsmRecF : (CURVED ? kAsmRecDC : kAsmRecD);   // record length in TA units
     TA *prec = (TA *)(lds + L.rec);
 
+    // the tile: kAsmTileU CPs wide, h CP rows tall (ty inside, min(2, ty) near the edges)
     const int ntx = (S.n_u + kAsmTileU - 1) / kAsmTileU;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx0 = (tile % ntx) * kAsmTileU, ty0 = (tile / ntx) * ty;
+    const int tx0 = (tile % ntx) * kAsmTileU;
+    int ty0 = 0, h = 0;
+    asm_tile_row(S.n_v, ty, tile / ntx, ty0, h);
     const int k0 = max(0, tx0 - 2), k1 = min(S.Nu - 1, tx0 + kAsmTileU - 1);
-    const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + ty - 1);
+    const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + h - 1);
     const int nk = k1 - k0 + 1, nl = l1 - l0 + 1, ne = nk * nl;
 
-    // local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0)) and
-    // the global first point of each element row: the points of one element row are contiguous
-    // in the global tables
-    for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
-        const int r = t / nk, kk = t % nk;
-        int mb = 0;
-        for (int q = 0; q < r; ++q) {
-            const int e0 = (l0 + q) * S.Nu;
-            mb += S.mp_off[e0 + k1 + 1] - S.mp_off[e0 + k0];
-        }
-        if (r < nl) {
-            const int e0 = (l0 + r) * S.Nu + k0;
-            mb += S.mp_off[e0 + kk] - S.mp_off[e0];
-        }
-        el_off[t] = mb;
+    // Local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0)): the
+    // points of one element row are contiguous in the global tables, so an offset is the points
+    // of the rows before plus the offset within the row. One round of independent global loads
+    // (row starts and lengths, each element's first point), then the row prefix from LDS.
+    for (int r = threadIdx.x; r < nl; r += blockDim.x) {
+        const int e0 = (l0 + r) * S.Nu;
+        const int s0 = S.mp_off[e0 + k0];
+        mrow[r] = s0;
+        s_rowlen[r] = S.mp_off[e0 + k1 + 1] - s0;
     }
-    for (int r = threadIdx.x; r < nl; r += blockDim.x) mrow[r] = S.mp_off[(l0 + r) * S.Nu + k0];
+    for (int t = threadIdx.x; t < ne; t += blockDim.x) el_off[t] = S.mp_off[(l0 + t / nk) * S.Nu + k0 + t % nk];
     if (threadIdx.x == 0) *counter = 0;
     __syncthreads();
-    if (hess) {
+    for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
+        const int r = t < ne ? t / nk : nl;
+        int base = 0;
+        for (int q = 0; q < r; ++q) base += s_rowlen[q];
+        el_off[t] = t < ne ? base + (el_off[t] - mrow[r]) : base;
+    }
+    __syncthreads();
+    {
         const int np = el_off[ne];
         for (int t = threadIdx.x; t < np; t += blockDim.x) {
             int r = 0;
             while (r + 1 < nl && el_off[(r + 1) * nk] <= t) ++r;
             const int q = mrow[r] + (t - el_off[r * nk]);
             TA *rec = prec + size_t(t) * REC;
+            if (hess) {
 #pragma unroll
-            for (int c = 0; c < 21; ++c) rec[c] = ptA[c * S.n_mp + q];
+                for (int c = 0; c < 21; ++c) rec[c] = ptA[c * S.n_mp + q];
+            }
+            const double tu = S.mp_tu[q], tv = S.mp_tv[q];
             if constexpr (STAGE_DN) {
-                const int e = S.mp_elem[q], k = e % S.Nu, l = e / S.Nu;
+                // the element from the tile layout: row r, column k0 + (offset of t within the row)
+                int kk = 0;
+                while (kk + 1 < nk && el_off[r * nk + kk + 1] <= t) ++kk;
                 TA dN[9][2];
-                local_grads<TA>(S, mp_geo_t<CURVED>(S, q), k, l, TA(S.mp_tu[q]), TA(S.mp_tv[q]), dN);
+                local_grads<TA>(S, mp_geo_t<CURVED>(S, q), k0 + kk, l0 + r, TA(tu), TA(tv), dN);
 #pragma unroll
                 for (int m = 0; m < 9; ++m) {
                     rec[24 + 2 * m] = dN[m][0];
                     rec[24 + 2 * m + 1] = dN[m][1];
                 }
+                if constexpr (KIND == kAsmMixed) {
+                    double *d = (double *)(rec + OFF_T);
+                    d[0] = tu;
+                    d[1] = tv;
+                    if constexpr (CURVED) {
+                        const PtK K = mp_geo_t<true>(S, q);
+                        double *kq = (double *)(rec + OFF_K);
+                        kq[0] = K.k00; kq[1] = K.k01; kq[2] = K.k10; kq[3] = K.k11;
+                    }
+                }
             } else {
-                rec[21] = TA(S.mp_tu[q]);
-                rec[22] = TA(S.mp_tv[q]);
+                rec[21] = TA(tu);
+                rec[22] = TA(tv);
                 if constexpr (CURVED) {
                     const PtK K = mp_geo_t<true>(S, q);
                     rec[23] = K.k00; rec[24] = K.k01; rec[25] = K.k10; rec[26] = K.k11;
                 }
             }
+            TP *pp = (TP *)(rec + OFF_P);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) pp[c] = ptP[c * S.n_mp + q];
         }
     }
     __syncthreads();
@@ -633,7 +675,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     constexpr unsigned long long kPacked = kO[0] | kO[1] << 4 | kO[2] << 8 | kO[3] << 12 | kO[4] << 16 | kO[5] << 20 |
                                            kO[6] << 24 | kO[7] << 28 | kO[8] << 32 | kO[9] << 36 | kO[10] << 40 |
                                            kO[11] << 44 | kO[12] << 48 | kO[13] << 52;
-    const int R = kAsmTileU * ty;
+    const int R = kAsmTileU * h;
     const int nitems = (hess ? kSlots + 1 : 1) * R;
     const int nchunks = (nitems + 63) / 64;
     const size_t ncp = S.n_cp;
@@ -728,18 +770,37 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
             // gradient: membrane stresses and bending terms of the CP's elements, inertia, gravity
             TG acc[3] = {TG(0), TG(0), TG(0)};
             double accb[3] = {0.0, 0.0, 0.0};
-            // point ranges come from the LDS offsets, so every global load below is independent
+            // the stresses and basis gradients of the CP's points, all from the staged records
             for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
-                const int r = l - l0, mbase = mrow[r] - el_off[r * nk];
+                const int r = l - l0;
                 for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
                     const int el = r * nk + (k - k0), la = i - k, lb = j - l;
                     for (int t = el_off[el]; t < el_off[el + 1]; ++t) {
-                        const int q = mbase + t;
+                        const TA *rec = prec + size_t(t) * REC;
                         TG dn[2];
-                        grad_at<TG>(S, mp_geo_t<CURVED>(S, q), k, l, la, lb, TG(S.mp_tu[q]), TG(S.mp_tv[q]), dn);
+                        if constexpr (KIND == kAsmF32) {
+                            const float2 g2 = *(const float2 *)(rec + 24 + 2 * (3 * lb + la));
+                            dn[0] = g2.x;
+                            dn[1] = g2.y;
+                        } else if constexpr (KIND == kAsmMixed) {
+                            const double *d = (const double *)(rec + OFF_T);
+                            PtK K;
+                            if constexpr (CURVED) {
+                                const double *kq = (const double *)(rec + OFF_K);
+                                K = PtK{kq[0], kq[1], kq[2], kq[3]};
+                            } else {
+                                K = mp_geo_t<false>(S, 0);
+                            }
+                            grad_at<TG>(S, K, k, l, la, lb, TG(d[0]), TG(d[1]), dn);
+                        } else {
+                            PtK K;
+                            if constexpr (CURVED) K = PtK{rec[23], rec[24], rec[25], rec[26]};
+                            else K = mp_geo_t<false>(S, 0);
+                            grad_at<TG>(S, K, k, l, la, lb, TG(rec[21]), TG(rec[22]), dn);
+                        }
+                        const TP *pp = (const TP *)(rec + OFF_P);
 #pragma unroll
-                        for (int cc = 0; cc < 3; ++cc)
-                            acc[cc] += TG(ptP[(2 * cc) * S.n_mp + q]) * dn[0] + TG(ptP[(2 * cc + 1) * S.n_mp + q]) * dn[1];
+                        for (int cc = 0; cc < 3; ++cc) acc[cc] += TG(pp[2 * cc]) * dn[0] + TG(pp[2 * cc + 1]) * dn[1];
                     }
                 }
             }
@@ -892,24 +953,32 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
                          const double *x, hipStream_t st, bool bending) {
     // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch.
     double *pm = B.partials, *pb = B.partials + B.max_blocks;
-    auto go = [&](auto curved) {
-        constexpr bool C = decltype(curved)::value;
+    const int nbm = blocks(S.n_mp), nb = nbm + (bending ? blocks(S.n_be) : 0);
+    auto go = [&](auto curved, auto bend) {
+        constexpr bool C = decltype(curved)::value, BE = decltype(bend)::value;
         if (grad64 || precision == BSC_FP64) {
             double *P = grad64 ? B.ptP64 : (double *)B.ptP;
             if (hess && !grad64)
-                k_membrane<double, true, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+                k_points<double, true, C, double, double, BE><<<nb, kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm, B.beD,
+                                                                                      B.beE, pb, nbm);
             else
-                k_membrane<double, false, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm);
+                k_points<double, false, C, double, double, BE><<<nb, kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm, B.beD,
+                                                                                       B.beE, pb, nbm);
         } else {
             if (hess)
-                k_membrane<float, true, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+                k_points<float, true, C, float, float, BE><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm,
+                                                                                  B.beD, B.beE, pb, nbm);
             else
-                k_membrane<float, false, C><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm);
+                k_points<float, false, C, float, float, BE><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm,
+                                                                                   B.beD, B.beE, pb, nbm);
         }
-        if (bending) k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
     };
-    if (S.curved) go(std::true_type{});
-    else go(std::false_type{});
+    auto go2 = [&](auto curved) {
+        if (bending) go(curved, std::true_type{});
+        else go(curved, std::false_type{});
+    };
+    if (S.curved) go2(std::true_type{});
+    else go2(std::false_type{});
     return hipGetLastError();
 }
 
@@ -917,10 +986,11 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
 // FP64 gradient) stored in double and the projected density Hessian stored in float.
 hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st) {
     double *pm = B.partials, *pb = B.partials + B.max_blocks;
+    const int nbm = blocks(S.n_mp), nb = nbm + blocks(S.n_be);
     auto go = [&](auto curved) {
         constexpr bool C = decltype(curved)::value;
-        k_membrane<double, true, C, float, double><<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, (float *)B.ptA, B.ptP64, B.ptE, pm);
-        k_bending<C><<<blocks(S.n_be), kBlock, 0, st>>>(S, x, B.beD, B.beE, pb);
+        k_points<double, true, C, float, double><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, B.ptP64, B.ptE, pm, B.beD, B.beE,
+                                                                         pb, nbm);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
@@ -928,15 +998,14 @@ hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double
 }
 
 int assemble_tiles(const DevSheet &S, int kind) {
-    return ((S.n_u + kAsmTileU - 1) / kAsmTileU) * ((S.n_v + S.asm_ty[kind] - 1) / S.asm_ty[kind]);
+    return ((S.n_u + kAsmTileU - 1) / kAsmTileU) * asm_tile_rows(S.n_v, S.asm_ty[kind]);
 }
 
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
                            double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st, bool gnorm) {
     double *pc = B.partials + 2 * B.max_blocks, *pg = gnorm ? B.partials + 4 * B.max_blocks : nullptr;
     const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
-    const int sa = kind == kAsmF64 ? 8 : 4;
-    const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], sa, S.curved != 0).total;
+    const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], kind, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
     auto go = [&](auto curved) {
         constexpr bool C = decltype(curved)::value;

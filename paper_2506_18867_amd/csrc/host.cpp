@@ -236,7 +236,7 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     int asm_tiles = 0;                 // the assembly grid (energy partials), smallest tile height
     for (int kind = 0; kind < 3; ++kind)
         asm_tiles = std::max(asm_tiles, ((c->n_u + kAsmTileU - 1) / kAsmTileU) *
-                                            ((c->n_v + c->dev.asm_ty[kind] - 1) / std::max(1, c->dev.asm_ty[kind])));
+                                            asm_tile_rows(c->n_v, std::max(1, c->dev.asm_ty[kind])));
     const int max_blocks = std::max(std::max(256, std::max(cg_tiles, asm_tiles) + 1),
                                     std::max((max_items + kBlock - 1) / kBlock + 1, int(ncp / 64) + 2));
     DevBufs t{};
@@ -513,22 +513,24 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     S.mu1 = mat->mu_st1; S.mu2 = mat->mu_st2; S.msh = mat->mu_sh;
     S.mu_bend = mat->mu_bend;
 
-    // Tiled assembly: for each precision combination the tallest tile (16 x ty CPs, ty in
-    // 8, 4, 2, 1) whose staged points fit kAsmLdsMax bytes of LDS in every tile.
-    const int size_a[3] = {4, 8, 4};
+    // Tiled assembly: for each precision combination the tallest interior tile height (16 x ty
+    // CPs, ty in 8, 4, 2, 1; edge rows min(2, ty)) whose staged points fit kAsmLdsMax bytes of
+    // LDS in every tile.
     for (int kind = 0; kind < 3; ++kind) {
         S.asm_ty[kind] = 0;
         for (int ty = 8; ty >= 1 && S.asm_ty[kind] == 0; ty /= 2) {
             int maxp = 0;
-            for (int ty0 = 0; ty0 < n_v; ty0 += ty)
+            for (int tr = 0; tr < asm_tile_rows(n_v, ty); ++tr)
                 for (int tx0 = 0; tx0 < n_u; tx0 += kAsmTileU) {
+                    int ty0 = 0, h = 0;
+                    asm_tile_row(n_v, ty, tr, ty0, h);
                     const int k0 = std::max(0, tx0 - 2), k1 = std::min(Nu - 1, tx0 + kAsmTileU - 1);
-                    const int l0 = std::max(0, ty0 - 2), l1 = std::min(Nv - 1, ty0 + ty - 1);
+                    const int l0 = std::max(0, ty0 - 2), l1 = std::min(Nv - 1, ty0 + h - 1);
                     int np = 0;
                     for (int l = l0; l <= l1; ++l) np += c->mp_off[l * Nu + k1 + 1] - c->mp_off[l * Nu + k0];
                     maxp = std::max(maxp, np);
                 }
-            if (asm_lds_layout(kAsmTileU, ty, maxp, size_a[kind], curved).total <= kAsmLdsMax) {
+            if (asm_lds_layout(kAsmTileU, ty, maxp, kind, curved).total <= kAsmLdsMax) {
                 S.asm_ty[kind] = ty;
                 S.asm_maxp[kind] = maxp;
             }
