@@ -1149,8 +1149,71 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         }
         hipEvent_t e1 = rec();
         int eta_mode = ETA_EXPLICIT;
+        // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
+        // is recomputed where it is needed)
+        double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
+        double *p = B.p0;
+        double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
+        const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
+        double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
+        const bool presum = nbc > kCgPreSumBlocks;
+        auto bufs = [&](int j) {
+            CgBufs c{};
+            c.x = B.dir; c.p = p; c.pinv = B.pinv;
+            c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
+            c.pre = presum ? B.scalars + S_CGSUM : nullptr;
+            const int cur = j & 1, prev = (j + 1) & 1;
+            c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
+            c.w_in = wb[prev]; c.w_out = wb[cur];
+            c.s_in = sb[prev]; c.s_out = sb[cur];
+            c.part_in = part[prev]; c.part_out = part[cur];
+            c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
+            return c;
+        };
+        const int first = it == 0 ? 1 : 0;
+        double eta_arg = 0.0;                    // the explicit mode's tolerance (set before the solve)
+        // block-Jacobi inverse, b = -g, x0 = 0
+        auto enqueue_prep = [&](hipStream_t cs) {
+            if (prec == BSC_FP64)
+                k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
+            else
+                k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
+        };
+        // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
+        auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
+            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, q0_, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode,
+                                               first, eta_arg, o->pcg_rtol, eta_max);
+            if (prec == BSC_FP64)
+                k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+            else
+                k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+            if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
+        };
+        // the block-Jacobi solve's set-up (prep, init and the first launch) as one captured sequence
+        auto cg_setup = [&]() -> hipError_t {
+            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
+                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u, bits(eta_max)};
+            return run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
+                enqueue_prep(cs);
+                enqueue_init(cs, nullptr);
+            });
+        };
+        // Gradient rule (no warm start, no multigrid): the set-up is enqueued right behind the
+        // assembly with the forcing term formed on the device (the same formula as the host's),
+        // and the host reads E and |g| while the GPU runs it. A Newton iteration that turns out to
+        // have converged wastes only that set-up; x is not touched.
+        const bool early = !deferred && !o->warm_start && !use_mg;
+        hipEvent_t e2 = nullptr;
+        if (early) {
+            eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
+            const int32_t last = seen();
+            if (pub) publish(st);
+            e2 = rec();
+            HIPX(cg_setup(), "cg init");
+            HIPX(pub ? wait_pub(last) : copy_sync(), "read norms");
+        }
         if (!deferred) {
-            HIPX(pull(), "read norms");
+            if (!early) HIPX(pull(), "read norms");
             host[0] = hs[S_E];
             host[1] = hs[S_GG];
             span(e0, e1, &s.ms_assemble);
@@ -1195,48 +1258,11 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         }
 
         // ---- direction: PCG on H p = -g -----------------------------------------------------
-        hipEvent_t e2 = rec();
-        // CG vectors: p; r, w (= A M^-1 r) and s double-buffered by iteration parity (u = M^-1 r
-        // is recomputed where it is needed)
-        double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
-        double *p = B.p0;
-        double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
-        const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
-        double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
-        const bool presum = nbc > kCgPreSumBlocks;
-        auto bufs = [&](int j) {
-            CgBufs c{};
-            c.x = B.dir; c.p = p; c.pinv = B.pinv;
-            c.pbb = pbb; c.stride = stride; c.nb_init = nbi;
-            c.pre = presum ? B.scalars + S_CGSUM : nullptr;
-            const int cur = j & 1, prev = (j + 1) & 1;
-            c.r_in = rb[j == 0 ? 0 : prev]; c.r_out = rb[cur];
-            c.w_in = wb[prev]; c.w_out = wb[cur];
-            c.s_in = sb[prev]; c.s_out = sb[cur];
-            c.part_in = part[prev]; c.part_out = part[cur];
-            c.slot_in = prev ? I_ITB : I_ITA; c.slot_out = cur ? I_ITB : I_ITA;
-            return c;
-        };
-        const int first = it == 0 ? 1 : 0;
-        const double eta_arg = eta_mode == ETA_EXPLICIT ? eta : 0.0;     // used by the explicit mode only
-        // block-Jacobi inverse, b = -g, x0 = 0
-        auto enqueue_prep = [&](hipStream_t cs) {
-            if (prec == BSC_FP64)
-                k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
-            else
-                k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
-        };
-        // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
-        auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
-            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, q0_, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode,
-                                               first, eta_arg, o->pcg_rtol, eta_max);
-            if (prec == BSC_FP64)
-                k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
-            else
-                k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
-            if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
-        };
-        if (use_mg) {
+        if (!early) e2 = rec();
+        eta_arg = eta_mode == ETA_EXPLICIT ? eta : 0.0;
+        if (early) {
+            // set-up already enqueued behind the assembly
+        } else if (use_mg) {
             // multigrid: Galerkin hierarchy and block-Jacobi inverses of every level, then r = b,
             // p = 0, the flags and the tolerance (the first iteration's stop test sets |b|-relative
             // tolerance from the partials of |b|^2)
@@ -1249,12 +1275,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                         eta_mode, first, eta_arg, o->pcg_rtol, eta_max);
                  }), "mg init");
         } else if (!o->warm_start) {
-            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u, bits(eta_max)};
-            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     enqueue_prep(cs);
-                     enqueue_init(cs, nullptr);
-                 }), "cg init");
+            HIPX(cg_setup(), "cg init");
         } else {
             enqueue_prep(st);
             const double *q0 = nullptr;
