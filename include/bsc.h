@@ -86,13 +86,19 @@ typedef struct {
  *   stop_mode BSC_STOP_GRAD: stop when |g_free|_2 <= rtol |g0_free|_2 (g0 at the first iterate);
  *   stop_mode BSC_STOP_STEP: stop when |p|_inf / dt <= atol (the paper's rule).
  *   fixed_newton_iters > 0 runs exactly that many iterations instead (for comparisons).
- *   pcg_rtol: PCG stops when |r|_2 <= pcg_rtol |g|_2. warm_start: 1 uses the loaded network as
- *   the PCG initial guess (falls back to zero when it does not reduce the residual).
+ *   pcg_rtol: PCG stops when |r|_2 <= pcg_rtol |g|_2. warm_start: the PCG initial guess, one of
+ *   BSC_WARM_* below; a predicted start is scaled by its energy-optimal multiple and kept only
+ *   when it lowers the initial residual below |g|_2, else the solve starts from zero.
  *   pcg_adaptive: 1 chooses the PCG tolerance per Newton iteration by the Eisenstat-Walker rule
  *   eta_k = 0.9 (|g_k| / |g_{k-1}|)^2 (not below 0.9 eta_{k-1}^2 when that exceeds 0.1),
  *   clamped to [pcg_rtol, eta_max] (eta_0 = eta_max), eta_max = pcg_eta_max if set, else 0.5
  *   under BSC_STOP_STEP and 0.1 under BSC_STOP_GRAD; with
  *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
+/* PCG warm starts. NONE: x0 = 0. NET: the loaded network's prediction from the gradient (the
+ * learned warm start; needs bsc_warmstart_load). PREVIOUS: the previous Newton direction of this
+ * context (recycled: in the linearly converging phase of projected Newton successive directions
+ * are close; not in the paper). Both decide on the device, with no host round trip. */
+enum { BSC_WARM_NONE = 0, BSC_WARM_NET = 1, BSC_WARM_PREVIOUS = 2 };
 /* PCG preconditioners. JACOBI: 3x3 block Jacobi, one fused kernel per iteration. MULTIGRID: one
  * symmetric V(1,1) cycle on the hierarchy of the patch's knot halvings (exact B-spline
  * prolongation, Galerkin coarse operators, damped block-Jacobi smoothing); used when both span
@@ -122,7 +128,10 @@ typedef struct {
 } bsc_step_opts;
 
 /* Statistics of one step. ms_assemble, ms_pcg, ms_linesearch and ms_warmstart are GPU phase
- * times from HIP events on the context's stream (read once at the end of the step); ms_total is
+ * times from HIP events on the context's stream (read once at the end of the step; ms_warmstart
+ * is the network's forward pass, the warm start's product, dots and decision count in ms_pcg;
+ * warm_start_used / warm_start_fallbacks count the Newton iterations whose prediction was kept /
+ * dropped); ms_total is
  * the host wall-clock time of the call. The PCG iterations run as launches of one fused kernel (one per
  * iteration, replayed in fixed-size chunks; launches after convergence exit at once):
  * cg_launches counts them, cg_active_launches those that performed an iteration, and

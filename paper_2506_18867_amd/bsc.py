@@ -33,6 +33,9 @@ BSC_PRECOND_JACOBI = 0
 BSC_PRECOND_MULTIGRID = 1
 BSC_START_PREVIOUS = 0
 BSC_START_PREDICTOR = 1
+BSC_WARM_NONE = 0
+BSC_WARM_NET = 1
+BSC_WARM_PREVIOUS = 2
 BSC_HESS_ENTRIES = 114
 BSC_NET_PARAMS = 38592
 BSC_NET_NOALLOC_SCRATCH_BYTES = 32 << 20   # static scratch of bsc_net_backward_noalloc, per GPU

@@ -66,9 +66,9 @@ __host__ __device__ inline int upper_slot(int di, int dj) {
 // Solver scalars (doubles) and flags (int32) in the workspace, shared by the solvers and read
 // back by the host in one copy.
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
-       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
+       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_WSA, S_WSB, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
        S_XMAX = 47 };
-enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS };
+enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS, I_WS };   // I_WS: the warm start was used
 constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
 // Largest PCG relative tolerance of the Eisenstat-Walker forcing term (and its first value):
 // loose under the step-length stopping rule, tighter under the gradient rule, which has to reach
@@ -216,6 +216,7 @@ struct DevBufs {
     int32_t *iscalars;
     // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
     double *g, *xn, *xhat, *dir, *r, *p0, *p1, *q, *pinv, *tmp, *phat;
+    double *pprev;                               // the previous Newton direction (recycled warm start)
     double *r2, *q2, *p2;                    // second halves of the CG double buffers
     void *hess;                              // kHessEntries n_cp doubles
     // warm-start network

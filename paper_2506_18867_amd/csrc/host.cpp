@@ -268,7 +268,7 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.bsr_rowptr = (int32_t *)take(4 * (ncp + 1));
     t.scalars = (double *)take(8 * kScalars);
     t.iscalars = (int32_t *)take(4 * 64);          // directly after the scalars (kScalars * 8 is a multiple of 256)
-    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2};
+    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2, &t.pprev};
     for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
     t.pinv = (double *)take(8 * 6 * ncp);
     t.mg_x0 = t.r2;                                // unused by the multigrid solver otherwise
@@ -591,6 +591,10 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     st = hip_check(c, hipMemcpyAsync(B.bsr_rowptr, rowptr.data(), 4 * rowptr.size(), hipMemcpyHostToDevice, c->stream), "upload pattern");
     if (st != BSC_OK) return st;
     st = hip_check(c, hipMemsetAsync(B.iscalars, 0, 4 * 64, c->stream), "clear scalars");
+    if (st != BSC_OK) return st;
+    // the Newton direction starts at zero: the first recycled warm start of a context sees p = 0
+    // and falls back to the zero start
+    st = hip_check(c, hipMemsetAsync(B.dir, 0, 24 * size_t(c->n_cp), c->stream), "clear direction");
     if (st != BSC_OK) return st;
     st = hip_check(c, hipStreamSynchronize(c->stream), "bind workspace");
     if (st != BSC_OK) return st;

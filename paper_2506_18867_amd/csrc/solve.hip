@@ -268,17 +268,20 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // The PCG set-up of a Newton iteration in one pass over the CPs: the block-Jacobi inverse (the
 // inverse of the 3x3 diagonal block, or its inverse diagonal where that block is not positive
 // definite), the right-hand side b = -g (written 0 - g, so that a zero gradient gives +0) and
-// the initial direction x0 = 0.
+// the initial direction x0 = 0. With keep, the direction that x0 held (the previous Newton
+// direction) is saved there first, zero on pinned CPs.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_prep(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv,
                                                     const double *__restrict__ g, double *__restrict__ b,
-                                                    double *__restrict__ x0) {
+                                                    double *__restrict__ x0, double *__restrict__ keep) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.n_cp) return;
     const size_t n = S.n_cp;
+    const bool pinned = S.pinmask[a] != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         b[c * n + a] = 0.0 - g[c * n + a];
+        if (keep) keep[c * n + a] = pinned ? 0.0 : x0[c * n + a];
         x0[c * n + a] = 0.0;
     }
     const double a00 = H[a], a01 = H[n + a], a02 = H[2 * n + a], a11 = H[3 * n + a], a12 = H[4 * n + a], a22 = H[5 * n + a];
@@ -711,6 +714,35 @@ __global__ void k_finish4(const double *__restrict__ part, int stride, int n, do
     out[threadIdx.x] = s;
 }
 
+// The warm start's decision, on the device: with gp = g.p, pw = p.Hp, gw = g.Hp, ww = |Hp|^2 (at
+// S_WS0..3) and bb = |g|^2, the energy-optimal multiple a = -gp / pw of the prediction p (either
+// sign) gives the initial residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g; the start
+// x0 = a p is kept only when that is below bb (the zero start's residual), else a = 0. S_WSA
+// receives a, the flag I_WS whether the start was kept.
+__global__ void k_ws_decide(double *scal, int32_t *isc) {
+    if (threadIdx.x != 0) return;
+    const double gp = scal[S_WS0], pw = scal[S_WS1], gw = scal[S_WS2], ww = scal[S_WS3], bb = scal[S_GG];
+    double a = 0.0;
+    if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw) && std::isfinite(gw) && std::isfinite(ww)) {
+        const double as = -gp / pw;
+        const double rr = bb + 2.0 * as * gw + as * as * ww;
+        if (as != 0.0 && rr < bb) a = as;
+    }
+    scal[S_WSA] = a;
+    isc[I_WS] = a != 0.0 ? 1 : 0;
+}
+
+// x0 = a p and q0 = H x0 = a Hp for the decided multiple a (exact zeros when a = 0, whatever p
+// holds).
+__global__ void k_ws_apply(int n, const double *__restrict__ scal, const double *__restrict__ p, double *__restrict__ hp,
+                           double *__restrict__ x0) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double a = scal[S_WSA];
+    x0[t] = a != 0.0 ? a * p[t] : 0.0;
+    hp[t] = a != 0.0 ? a * hp[t] : 0.0;
+}
+
 // ---- line search -------------------------------------------------------------------------
 
 // The energy difference along p is dE(alpha) = alpha c1 + alpha^2 c2 / 2 for the inertia,
@@ -1036,8 +1068,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     // With the step rule (and no warm start) nothing the host decides before the solve depends on
     // the assembly: the PCG tolerance is formed on the device and E, |g| are read back with |p|
     // and the line search's first trial after the solve, in one synchronisation.
-    const bool deferred = step_rule && !o->warm_start;
-    const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !o->warm_start;
+    // warm starts: the learned prediction needs the host (the net's forward pass runs outside the
+    // captured sequences); the recycled previous direction runs entirely on the device
+    const int warm = o->warm_start;
+    const bool net_warm = warm == BSC_WARM_NET;
+    const bool deferred = step_rule && !net_warm;
+    const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !warm;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
     // Phase timing: events from a pool, recorded as the step goes and read once at its end (a
@@ -1172,12 +1208,24 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         };
         const int first = it == 0 ? 1 : 0;
         double eta_arg = 0.0;                    // the explicit mode's tolerance (set before the solve)
-        // block-Jacobi inverse, b = -g, x0 = 0
+        // block-Jacobi inverse, b = -g, x0 = 0 (the recycled warm start keeps the previous direction)
+        double *keep = warm == BSC_WARM_PREVIOUS ? B.pprev : nullptr;
         auto enqueue_prep = [&](hipStream_t cs) {
             if (prec == BSC_FP64)
-                k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
+                k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir,
+                                                                      keep);
             else
-                k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
+                k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir,
+                                                                     keep);
+        };
+        // warm start from the prediction ph: Hp into hq, the four dot products, the decision and
+        // x0 = a ph, q0 = a Hp (zero when the start is not kept), all on the device
+        auto enqueue_warm = [&](hipStream_t cs, const double *ph) {
+            (void)launch_spmv(S, prec, B.hess, ph, hq, cs);
+            k_dots4_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.g, ph, hq, B.partials + 4 * stride, stride);
+            k_finish4<<<1, 64, 0, cs>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
+            k_ws_decide<<<1, 64, 0, cs>>>(B.scalars, B.iscalars);
+            k_ws_apply<<<blocks(n3), kBlock, 0, cs>>>(n3, B.scalars, ph, hq, B.dir);
         };
         // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
         auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
@@ -1189,20 +1237,22 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
             if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
         };
-        // the block-Jacobi solve's set-up (prep, init and the first launch) as one captured sequence
+        // the block-Jacobi solve's set-up (prep, the recycled warm start, init and the first
+        // launch) as one captured sequence
         auto cg_setup = [&]() -> hipError_t {
             const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), step_rule ? 2u : 0u, bits(eta_max)};
+                                     uint64_t(o->max_pcg), (step_rule ? 2u : 0u) | (uint64_t(warm) << 4), bits(eta_max)};
             return run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
                 enqueue_prep(cs);
-                enqueue_init(cs, nullptr);
+                if (warm == BSC_WARM_PREVIOUS) enqueue_warm(cs, B.pprev);
+                enqueue_init(cs, warm == BSC_WARM_PREVIOUS ? hq : nullptr);
             });
         };
-        // Gradient rule (no warm start, no multigrid): the set-up is enqueued right behind the
-        // assembly with the forcing term formed on the device (the same formula as the host's),
-        // and the host reads E and |g| while the GPU runs it. A Newton iteration that turns out to
-        // have converged wastes only that set-up; x is not touched.
-        const bool early = !deferred && !o->warm_start && !use_mg;
+        // Gradient rule (no learned warm start, no multigrid): the set-up is enqueued right behind
+        // the assembly with the forcing term formed on the device (the same formula as the
+        // host's), and the host reads E and |g| while the GPU runs it. A Newton iteration that
+        // turns out to have converged wastes only that set-up; x is not touched.
+        const bool early = !deferred && !net_warm && !use_mg;
         hipEvent_t e2 = nullptr;
         if (early) {
             eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
@@ -1274,46 +1324,27 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                      k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
                                                         eta_mode, first, eta_arg, o->pcg_rtol, eta_max);
                  }), "mg init");
-        } else if (!o->warm_start) {
+        } else if (!net_warm) {
             HIPX(cg_setup(), "cg init");
         } else {
+            // learned warm start: p_hat = net(g) masked at pins, then the same device-side
+            // decision as the recycled start (x0 = a p_hat with the energy-optimal a, kept only
+            // when it lowers the initial residual)
             enqueue_prep(st);
-            const double *q0 = nullptr;
             {
-                // p_hat = net(g) masked at pins; x0 = alpha* p_hat with alpha* = -g.p_hat / p_hat.H p_hat,
-                // kept only when |b - H x0| < |b| (else zero start)
                 Timer tw(st);
                 k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
                 HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
                                       B.net_scale, B.net_w_fwd, true, st), "warm start forward");
                 k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
-                HIPX(launch_spmv(S, prec, B.hess, B.phat, hq, st), "warm start spmv");
-                k_dots4_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, B.g, B.phat, hq, B.partials + 4 * stride, stride);
-                k_finish4<<<1, 64, 0, st>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
                 HIPX(hipGetLastError(), "warm start");
-                HIPX(pull(), "read ws");
-                const double gp = hs[S_WS0], pw = hs[S_WS1], gw = hs[S_WS2], ww = hs[S_WS3], bb = host[1];
-                bool use = false;
-                if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw)) {
-                    // energy-optimal multiple of p_hat (either sign: the training loss fixes the
-                    // direction only up to sign); |b - as w|^2 with b = -g: |g|^2 + 2 as g.w + as^2 w.w
-                    const double as = -gp / pw;
-                    const double rr = bb + 2.0 * as * gw + as * as * ww;
-                    if (as != 0.0 && rr < bb) {
-                        use = true;
-                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, B.phat, 0.0, B.phat, B.dir);   // x0 = as p_hat
-                        k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, as, hq, 0.0, hq, hq);               // q0 = H x0
-                    }
-                }
-                if (use) s.warm_start_used++;
-                else s.warm_start_fallbacks++;
                 s.ms_warmstart += tw.stop();
-                q0 = use ? hq : nullptr;
             }
-            enqueue_init(st, q0);
+            enqueue_warm(st, B.phat);
+            enqueue_init(st, hq);
             HIPX(hipGetLastError(), "cg init");
         }
-        int32_t flags[6] = {0, 0, 0, 0, 0, 0};
+        int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
         // a chunk: 8 fused block-Jacobi CG launches (even: every chunk starts on an odd launch),
         // or one multigrid-preconditioned CG iteration
         const int chunk = use_mg ? 1 : 8;
@@ -1380,7 +1411,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             HIPX(hipGetLastError(), "cg");
             span(c0, rec(), &s.ms_cg_kernels);
             HIPX(pub ? wait_pub(last) : copy_sync(), "read cg state");
-            for (int k = 0; k < 6; ++k) flags[k] = hf[k];
+            for (int k = 0; k < 7; ++k) flags[k] = hf[k];
             const double *cgs = hs;
             s.cg_launches += chunk * burst;
             if (flags[I_DONE]) break;
@@ -1405,6 +1436,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             }
         }
         hipEvent_t e3 = rec();
+        if (warm) {
+            if (flags[I_WS]) s.warm_start_used++;
+            else s.warm_start_fallbacks++;
+        }
         s.cg_active_launches += flags[I_ITERS];
         if (it < 64) ctx->pcg_hist[it] = flags[I_ITERS];
         s.pcg_iters_total += flags[I_ITERS];
@@ -1544,9 +1579,9 @@ bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, doubl
     // block-Jacobi inverse of the matrix, b (as 0 - (-b)) into B.tmp, x0 = 0 into B.dir
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, b, 0.0, b, B.g);
     if (prec == BSC_FP64)
-        k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
+        k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir, nullptr);
     else
-        k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
+        k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir, nullptr);
     k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
                                        ETA_EXPLICIT, 1, rtol, rtol, rtol);
     fused(0);
@@ -1602,7 +1637,8 @@ bsc_status bsc_newton_step(bsc_ctx *c, const bsc_step_opts *o, double *d_x, doub
     if (!(o->pcg_eta_max == 0.0 || (o->pcg_eta_max >= o->pcg_rtol && o->pcg_eta_max <= 0.9)))
         return fail(c, BSC_E_INVAL, "pcg_eta_max must be 0 or in [pcg_rtol, 0.9]");
     if (!c->pins.empty() && !d_pin_targets) return fail(c, BSC_E_INVAL, "pins set but no targets");
-    if (o->warm_start && !c->net_loaded) return fail(c, BSC_E_STATE, "warm start requested but no network loaded");
+    if (o->warm_start < BSC_WARM_NONE || o->warm_start > BSC_WARM_PREVIOUS) return fail(c, BSC_E_INVAL, "bad warm start");
+    if (o->warm_start == BSC_WARM_NET && !c->net_loaded) return fail(c, BSC_E_STATE, "warm start requested but no network loaded");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(o->gravity[k])) return fail(c, BSC_E_INVAL, "gravity must be finite");
     bsc_status st = newton_step(c, o, d_x, d_v, d_pin_targets, stats);
