@@ -4,10 +4,13 @@ One step = one implicit-Euler step of the 226 x 226-control-point driven sheet (
 elements; material cell E = 1e4 Pa, t = 1 mm; random held CPs plus a sinusoidally driven corner;
 gravity): projected Newton with element evaluation, PSD projection, assembly, block-Jacobi PCG
 (Eisenstat-Walker tolerance) and line search, all in the library's HIP kernels, stopped at
-|g| <= 1e-6 |g0| (free-DOF gradient, evaluated in double). The headline path is FP32-mixed. Every
-step starts from the state of the FP32-mixed trajectory, and the same step is also solved in FP64
-from that identical state to the same residual, which gives the "vs FP64" ratio at equal final
-residual. The trajectory advances with the FP32-mixed result.
+|g| <= 1e-6 |g0| (free-DOF gradient, evaluated in double). The headline path is FP32-mixed with
+the PCG warm-started from the previous Newton direction (--warm). Every step starts from the
+state of the FP32-mixed trajectory, and the same step is also solved from that identical state
+to the same residual in plain FP64 (zero-start PCG), which gives the "vs FP64" ratio at equal
+final residual, and with the other start in each precision (FP32-mixed zero start, FP64 with the
+same warm start), each on a context of its own. The trajectory advances with the FP32-mixed
+result.
 
 value = elements advanced per second (n_elem * steps / timed seconds of the FP32-mixed steps) in
 Melem/s; ms_per_step is the mean FP32-mixed step time (each step bracketed by device syncs).
@@ -18,7 +21,8 @@ Further legs (each a field of the one JSON line):
                     identical FP64-trajectory state every step: per-step error and iteration counts;
   material_sweep    the nine (E, t) cells of the 226 x 226 driven sheet, FP32-mixed at 1e-6 |g0|;
   warm_start        the 226 x 226 held-out compressed drape: FP64, FP32-mixed, FP32-mixed with the
-                    learned PCG warm start, from the same FP64-trajectory state, all at 1e-6 |g0|;
+                    learned PCG warm start and with the recycled one, from the same
+                    FP64-trajectory state, all at 1e-6 |g0|;
   assembly, spmv    the eval+assembly pass and the plain SpMV timed on their own;
   ceilings          measured copy bandwidth from HBM and from the caches (footprints that stay
                     resident in the L2s and the 256 MB Infinity Cache);
@@ -99,6 +103,9 @@ def parse(argv=None):
     p.add_argument("--adaptive", type=int, default=1, help="Eisenstat-Walker PCG tolerance (1) or fixed (0)")
     p.add_argument("--eta-max", type=float, default=0.0,
                    help="cap of the Eisenstat-Walker PCG tolerance (0: the library's default for the stop rule)")
+    p.add_argument("--warm", choices=["previous", "none", "net"], default="previous",
+                   help="PCG warm start of the FP32-mixed headline (and of the step-rule, sweep and ablation legs): "
+                        "the previous Newton direction, none (zero start) or the learned network")
     p.add_argument("--precond", choices=["jacobi", "mg"], default="jacobi",
                    help="PCG preconditioner: block Jacobi (fused kernel) or the multigrid V-cycle")
     p.add_argument("--start", choices=["predictor", "previous"], default="previous",
@@ -166,7 +173,13 @@ def copy_bandwidth(footprint_bytes, reps, torch):
     return round(2 * half / (ms * 1e-3) / 1e9, 1)
 
 
-def step_opts(bsc, sc, precision, args, stop="grad", warm=0):
+def warm_mode(bsc, name):
+    return {"none": bsc.BSC_WARM_NONE, "net": bsc.BSC_WARM_NET, "previous": bsc.BSC_WARM_PREVIOUS}[name]
+
+
+def step_opts(bsc, sc, precision, args, stop="grad", warm=None):
+    """Options of one step; warm None takes --warm."""
+    warm = warm_mode(bsc, args.warm) if warm is None else warm
     start = args.start if stop == "grad" else args.step_rule_start
     return bsc.make_opts(dt=sc.dt, gravity=tuple(sc.gravity), precision=precision, rtol=args.rtol, atol=args.atol,
                          stop_mode=bsc.BSC_STOP_GRAD if stop == "grad" else bsc.BSC_STOP_STEP,
@@ -193,20 +206,23 @@ def timed_step(ctx, x, v, tgt, opts, torch):
 
 
 def paired_steps(ctx, sc, x, v, step0, steps, variants, advance, torch, bsc, log=None):
-    """From the same state every step, runs each (name, opts) variant; the trajectory then continues
-    from variant `advance`. Returns {name: [(seconds, stats, dx_rel_vs_first_variant)]}."""
-    out = {name: [] for name, _ in variants}
+    """From the same state every step, runs each (name, opts[, context]) variant (a variant with a
+    context of its own keeps its own previous Newton direction for the recycled warm start); the
+    trajectory then continues from variant `advance`. Returns {name: [(seconds, stats,
+    dx_rel_vs_first_variant)]}."""
+    variants = [(vt[0], vt[1], vt[2] if len(vt) > 2 else ctx) for vt in variants]
+    out = {name: [] for name, _, _ in variants}
     for k in range(steps):
         tgt = bsc.to_soa(sc.pin_targets(step0 + k))
         res = {}
-        for name, opts in variants:
+        for name, opts, vctx in variants:
             xs, vs = x.clone(), v.clone()
-            sec, s = timed_step(ctx, xs, vs, tgt, opts, torch)
+            sec, s = timed_step(vctx, xs, vs, tgt, opts, torch)
             res[name] = (xs, vs, sec, s)
         ref = variants[0][0]
         dref = res[ref][0] - x
         nref = float(torch.linalg.vector_norm(dref))
-        for name, _ in variants:
+        for name, _, _ in variants:
             err = float(torch.linalg.vector_norm(res[name][0] - res[ref][0])) / max(nref, 1e-300)
             out[name].append((res[name][2], res[name][3], err))
         x.copy_(res[advance][0])
@@ -214,7 +230,7 @@ def paired_steps(ctx, sc, x, v, step0, steps, variants, advance, torch, bsc, log
         if log and (k % 50 == 0 or k == steps - 1):
             log(f"[bench] {sc.name} step {step0 + k}: " +
                 " ".join(f"{n}: {1e3 * res[n][2]:.2f} ms {res[n][3]['newton_iters']}N/{res[n][3]['pcg_iters_total']}it"
-                         for n, _ in variants))
+                         for n, _, _ in variants))
     return out
 
 
@@ -328,10 +344,22 @@ def main():
     n, ne = sc.n_cp, sc.n_elem
     x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
 
-    # ---- headline: FP32-mixed steps at |g| <= rtol |g0|, FP64 from the identical state beside ----
+    # ---- headline: FP32-mixed steps at |g| <= rtol |g0| with the warm start, and from the
+    #      identical state beside them: plain FP64 (zero start), FP32-mixed with zero start and
+    #      FP64 with the same warm start, each on a context of its own ----
+    wm = warm_mode(bsc, args.warm)
+    lw = bsc.BSC_WARM_PREVIOUS if wm == bsc.BSC_WARM_PREVIOUS else bsc.BSC_WARM_NONE     # the other legs' start
+    if wm == bsc.BSC_WARM_NET:
+        from paper_2506_18867_amd import warmstart_eval as we
+        ctx.bsc_warmstart_load(torch.from_numpy(np.fromfile(we.DEFAULT_WEIGHTS, dtype=np.float32)).cuda())
     o32 = step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args)
-    o64 = step_opts(bsc, sc, bsc.BSC_FP64, args)
-    variants = [("fp32_mixed", o32), ("fp64", o64)]
+    o64 = step_opts(bsc, sc, bsc.BSC_FP64, args, warm=bsc.BSC_WARM_NONE)
+    variants = [("fp32_mixed", o32, ctx), ("fp64", o64, bsc.context_for_scene(sc))]
+    if wm != bsc.BSC_WARM_NONE:
+        variants += [("fp32_mixed_zero_start", step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, warm=bsc.BSC_WARM_NONE),
+                      bsc.context_for_scene(sc))]
+        if wm == bsc.BSC_WARM_PREVIOUS:
+            variants += [("fp64_warm", step_opts(bsc, sc, bsc.BSC_FP64, args), bsc.context_for_scene(sc))]
     paired_steps(ctx, sc, x, v, 0, args.warmup, variants, "fp32_mixed", torch, bsc)
     xs, vs = x.clone(), v.clone()
     head = paired_steps(ctx, sc, x, v, args.warmup, args.steps, variants, "fp32_mixed", torch, bsc, log)
@@ -339,14 +367,15 @@ def main():
     sec32 = sum(r[0] for r in r32)
     sec64 = sum(r[0] for r in r64)
     st32 = [r[1] for r in r32]
-    log(f"[bench] headline: fp32 {1e3 * sec32 / args.steps:.3f} ms/step, fp64 {1e3 * sec64 / args.steps:.3f} ms/step")
+    secs = {name: sum(r[0] for r in head[name]) for name in head}
+    log("[bench] headline: " + ", ".join(f"{name} {1e3 * secs[name] / args.steps:.3f} ms/step" for name in head))
 
     # ---- the same steps under the paper's stopping rule (|p|_inf / dt <= atol) ----
     step_rule = None
     if args.step_rule_steps > 0:
         xr, vr = xs.clone(), vs.clone()
-        rv = [("fp32_mixed", step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, stop="step")),
-              ("fp64", step_opts(bsc, sc, bsc.BSC_FP64, args, stop="step"))]
+        rv = [("fp32_mixed", step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, stop="step", warm=lw), bsc.context_for_scene(sc)),
+              ("fp64", step_opts(bsc, sc, bsc.BSC_FP64, args, stop="step", warm=lw), bsc.context_for_scene(sc))]
         rr = paired_steps(ctx, sc, xr, vr, args.warmup, args.step_rule_steps, rv, "fp32_mixed", torch, bsc)
         step_rule = {k: summarize(rr[k], ne) for k in rr}
         step_rule["stop"] = f"|p|inf/dt<={args.atol:g} m/s"
@@ -360,7 +389,8 @@ def main():
         sc2 = syn.compressed_sheet(100, seed=2)
         ctx2 = bsc.context_for_scene(sc2)
         x2, v2 = bsc.to_soa(sc2.x0), bsc.to_soa(sc2.v0)
-        v2s = [("fp64", step_opts(bsc, sc2, bsc.BSC_FP64, args)), ("fp32_mixed", step_opts(bsc, sc2, bsc.BSC_FP32_MIXED, args))]
+        v2s = [("fp64", step_opts(bsc, sc2, bsc.BSC_FP64, args, warm=lw), ctx2),
+               ("fp32_mixed", step_opts(bsc, sc2, bsc.BSC_FP32_MIXED, args, warm=lw), bsc.context_for_scene(sc2))]
         rr = paired_steps(ctx2, sc2, x2, v2, 0, args.c2_steps, v2s, "fp64", torch, bsc, log)
         errs = np.array([r[2] for r in rr["fp32_mixed"]])
         c2 = {"workload": "compressed drape 100x100 CPs (9604 elements), 10% compression, E=1e4 Pa, t=1 mm, "
@@ -380,7 +410,7 @@ def main():
             csc = syn.driven_sheet(args.n, seed=300 + cell)
             cctx = bsc.context_for_scene(csc)
             xc, vc = bsc.to_soa(csc.x0), bsc.to_soa(csc.v0)
-            oc = step_opts(bsc, csc, bsc.BSC_FP32_MIXED, args)
+            oc = step_opts(bsc, csc, bsc.BSC_FP32_MIXED, args, warm=lw)
             timed_step(cctx, xc, vc, bsc.to_soa(csc.pin_targets(0)), oc, torch)          # warm-up step
             runs = [timed_step(cctx, xc, vc, bsc.to_soa(csc.pin_targets(1 + k)), oc, torch) + (0.0,)
                     for k in range(args.sweep_steps)]
@@ -403,7 +433,7 @@ def main():
         for name, rule in (("reduced", bsc.BSC_QUAD_REDUCED), ("gauss2_interior", bsc.BSC_QUAD_GAUSS2)):
             qctx = bsc.context_for_scene(sc, quadrature=rule)
             xq, vq = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
-            oq = step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, stop="step")
+            oq = step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, stop="step", warm=lw)
             timed_step(qctx, xq, vq, bsc.to_soa(sc.pin_targets(0)), oq, torch)            # warm-up
             xq, vq = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
             runs = [timed_step(qctx, xq, vq, bsc.to_soa(sc.pin_targets(k)), oq, torch) for k in range(args.quad_steps)]
@@ -429,7 +459,7 @@ def main():
         for name, dom in (("square", None), ("bend_150deg", ("bend", 150.0)), ("annulus_0.5", ("annulus", 0.5))):
             gsc = syn.driven_sheet(args.n, seed=args.seed, noise=args.noise, domain=dom)
             gctx = bsc.context_for_scene(gsc)
-            og = step_opts(bsc, gsc, bsc.BSC_FP32_MIXED, args, stop="step")
+            og = step_opts(bsc, gsc, bsc.BSC_FP32_MIXED, args, stop="step", warm=lw)
             xq, vq = bsc.to_soa(gsc.x0), bsc.to_soa(gsc.v0)
             timed_step(gctx, xq, vq, bsc.to_soa(gsc.pin_targets(0)), og, torch)           # warm-up
             xq, vq = bsc.to_soa(gsc.x0), bsc.to_soa(gsc.v0)
@@ -607,15 +637,22 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"driven sheet {args.n}x{args.n} CPs ({ne} elements), E=1e4 Pa, t=1 mm, dt=0.01 s, "
-                               f"|g|<={args.rtol:g}|g0| every step, FP32-mixed; FP64 from the identical state beside it",
+                               f"|g|<={args.rtol:g}|g0| every step, FP32-mixed; plain FP64 (and the other start) "
+                               f"from the identical state beside it",
                    "n_cp": n, "n_elem": ne, "seed": args.seed, "noise": args.noise,
                    "pcg": ("multigrid V(1,1)" if args.precond == "mg" else "block-Jacobi") + " PCG, "
                           + ("Eisenstat-Walker tolerance in [%g, 0.1]" % args.pcg_rtol
                              if args.adaptive else "fixed tolerance %g" % args.pcg_rtol),
                    "newton_start": "inertial predictor x^n + dt v^n" if args.start == "predictor" else "x^n",
+                   "pcg_warm_start": {"previous": "previous Newton direction (energy-optimal multiple, kept when it "
+                                                  "lowers the initial residual)",
+                                      "none": "zero start", "net": "learned network prediction"}[args.warm],
                    "parallelism": "single GPU"},
-        "newton_step_ms": {"fp32_mixed": round(ms_step32, 3), "fp64": round(1e3 * sec64 / args.steps, 3)},
+        "newton_step_ms": {name: round(1e3 * secs[name] / args.steps, 3) for name in head},
         "speedup_vs_fp64": round(sec64 / sec32, 3),
+        "speedup_vs_fp64_same_start": round(secs["fp64_warm"] / sec32, 3) if "fp64_warm" in secs else None,
+        "speedup_vs_fp32_zero_start": (round(secs["fp32_mixed_zero_start"] / sec32, 3)
+                                       if "fp32_mixed_zero_start" in secs else None),
         "per_step": {"newton_fp32": [s["newton_iters"] for s in st32],
                      "newton_fp64": [r[1]["newton_iters"] for r in r64],
                      "pcg_fp32": [s["pcg_iters_total"] for s in st32],
@@ -628,6 +665,16 @@ def main():
                                        "fp64": sum(1 for r in r64 if r[1]["status"] != 0)}},
         "phases_ms_per_step_fp32": {k: round(sum(s[k] for s in st32) / args.steps, 3)
                                     for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_warmstart", "ms_total")},
+        "phases_ms_per_step_fp32_zero_start": ({k: round(sum(r[1][k] for r in head["fp32_mixed_zero_start"]) / args.steps, 3)
+                                               for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_total")}
+                                               if "fp32_mixed_zero_start" in head else None),
+        "iterations_per_step": {name: {"newton": round(sum(r[1]["newton_iters"] for r in head[name]) / args.steps, 2),
+                                       "pcg": round(sum(r[1]["pcg_iters_total"] for r in head[name]) / args.steps, 2),
+                                       "warm_used": round(sum(r[1]["warm_start_used"] for r in head[name]) / args.steps, 2),
+                                       "cg_launches": round(sum(r[1]["cg_launches"] for r in head[name]) / args.steps, 2),
+                                       "g_rel_max": float("%.3g" % max(g_rel(r[1]) for r in head[name])),
+                                       "not_converged": sum(1 for r in head[name] if r[1]["status"] != 0)}
+                                for name in head},
         "pcg_us_per_iter_fp32": round(1e3 * sum(s["ms_pcg"] for s in st32) / max(1, pcg32), 3),
         "cg_kernel": {"active_us": round(1e3 * cg_ms / max(1, cg_active), 3), "launches": cg_launches,
                       "active_launches": cg_active, "gb_s": round(cg_bytes32 * cg_active / max(cg_ms, 1e-9) / 1e6, 1)},

@@ -66,7 +66,7 @@ __host__ __device__ inline int upper_slot(int di, int dj) {
 // Solver scalars (doubles) and flags (int32) in the workspace, shared by the solvers and read
 // back by the host in one copy.
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
-       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_WSA, S_WSB, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
+       S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_WSA, S_WSB, S_G0, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
        S_XMAX = 47 };
 enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS, I_WS };   // I_WS: the warm start was used
 constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
@@ -269,12 +269,6 @@ struct bsc_ctx {
     // of 1..8 chunks of launches per precision (index [precision][chunks])
     hipGraphExec_t cg_graph[2][9] = {};
     hipGraphExec_t mg_graph[2][9] = {};      // the same for multigrid-preconditioned CG iterations
-    // captured kernel sequences of a Newton iteration, keyed by their launch parameters
-    struct SeqGraph {
-        unsigned char key[64];
-        hipGraphExec_t exec;
-    };
-    std::vector<SeqGraph> seq_graphs;
     bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
     // PCG iterations of the previous step's solves, by Newton iteration (sizes first bursts)
     int pcg_hist[64] = {};
@@ -302,7 +296,6 @@ struct bsc_ctx {
         for (auto &row : mg_graph)
             for (auto &g : row)
                 if (g) (void)hipGraphExecDestroy(g);
-        for (auto &g : seq_graphs) (void)hipGraphExecDestroy(g.exec);
         for (auto &e : ev_pool) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
     }

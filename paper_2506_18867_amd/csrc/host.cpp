@@ -608,8 +608,6 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     for (auto &row : c->mg_graph)
         for (auto &g : row)
             if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
-    for (auto &g : c->seq_graphs) (void)hipGraphExecDestroy(g.exec);
-    c->seq_graphs.clear();
     DevSheet &S = c->dev;
     S.mp_elem = B.mp_elem; S.mp_off = B.mp_off; S.mp_tu = B.mp_tu; S.mp_tv = B.mp_tv; S.mp_w = B.mp_w;
     S.be_elem = B.be_elem; S.be_off = B.be_off; S.be_tu = B.be_tu; S.be_tv = B.be_tv; S.be_w = B.be_w;

@@ -136,10 +136,13 @@ __device__ __forceinline__ void block_product(const DevSheet &S, const T *__rest
 }
 
 // w = H u for a tile of 64 rows; wave g computes block products g, g+8, g+16, g+24 and the
-// eight partial results are summed through LDS.
-template <typename T>
+// eight partial results are summed through LDS. DOTS (the warm start): the tile's partials of
+// g.u, u.w, g.w and w.w go to part[k * stride + block] (a fixed-order wave sum per tile).
+template <typename T, bool DOTS = false>
 __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S, const T *__restrict__ H,
-                                                                     const double *__restrict__ u, double *__restrict__ w) {
+                                                                     const double *__restrict__ u, double *__restrict__ w,
+                                                                     const double *__restrict__ gv = nullptr,
+                                                                     double *__restrict__ part = nullptr, int stride = 0) {
     __shared__ T ys[kGroups][3][kRowsPerTile];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -155,14 +158,30 @@ __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S
 #pragma unroll
     for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
     __syncthreads();
-    if (g == 0 && a < S.n_cp) {
-        const size_t n = S.n_cp;
+    if (g == 0) {
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+        if (a < S.n_cp) {
+            const size_t n = S.n_cp;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            T y = ys[0][c][lane];
+            for (int c = 0; c < 3; ++c) {
+                T y = ys[0][c][lane];
 #pragma unroll
-            for (int q = 1; q < kGroups; ++q) y += ys[q][c][lane];
-            w[c * n + a] = double(y);
+                for (int q = 1; q < kGroups; ++q) y += ys[q][c][lane];
+                const double wy = double(y);
+                w[c * n + a] = wy;
+                if (DOTS) {
+                    const double gc = gv[c * n + a], uc = u[c * n + a];
+                    d[0] += gc * uc; d[1] += uc * wy; d[2] += gc * wy; d[3] += wy * wy;
+                }
+            }
+        }
+        if (DOTS) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[k] = wave_sum_all(d[k]);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) part[k * stride + blockIdx.x] = d[k];
+            }
         }
     }
 }
@@ -319,22 +338,34 @@ __device__ double forcing_term(int mode, int first, double eta_host, double rtol
     return fmin(eta_max, fmax(rtol_min, e));
 }
 
-// r = b - q (q = A x0, or none), p = s = 0; per-block partials of b.b; the solve's tolerance.
-__global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ q,
+// r = b - A x0, p = s = 0; per-block partials of b.b; the solve's tolerance. Without a warm
+// start (ph null) x0 = 0 (set by the prep kernel) and r = b. With one, x0 = a ph and A x0 = a hq
+// for the multiple a at S_WSA that k_ws_finish decided (a = 0: x0 = 0 and r = b exactly).
+__global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ ph,
+                                                    const double *__restrict__ hq, double *__restrict__ x0,
                                                     double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
                                                     int eta_mode, int first, double eta_host, double rtol_min,
-                                                    double eta_max) {
+                                                    double eta_max, double grad_rtol) {
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
+    const double ws = ph ? scal[S_WSA] : 0.0;
     double bb = 0.0;
     if (a < S.n_cp) {
         for (int c = 0; c < 3; ++c) {
-            const double bc = b[c * n + a];
-            r[c * n + a] = q ? bc - q[c * n + a] : bc;
-            p[c * n + a] = 0.0;
-            sv[c * n + a] = 0.0;
+            const size_t k = c * n + a;
+            const double bc = b[k];
+            if (ws != 0.0) {
+                const double aq = ws * hq[k];
+                x0[k] = ws * ph[k];
+                r[k] = bc - aq;
+            } else {
+                if (ph) x0[k] = 0.0;
+                r[k] = bc;
+            }
+            p[k] = 0.0;
+            sv[k] = 0.0;
             bb += bc * bc;
         }
     }
@@ -347,6 +378,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
         scal[S_RTOL] = eta;
         scal[S_ETA] = eta;
         scal[S_GPREV] = gn;
+        // gradient rule with the solve enqueued before the host has read |g|: a Newton iterate
+        // that already meets |g| <= grad_rtol |g0| (or |g| = 0) solves nothing (the host stops)
+        if (first) scal[S_G0] = gn;
+        if (grad_rtol > 0.0 && (gn <= grad_rtol * scal[S_G0] || gn == 0.0)) isc[I_DONE] = 1;
     }
 }
 
@@ -689,39 +724,28 @@ __global__ void k_phat(int n_cp, const float *__restrict__ out, const int32_t *_
     for (int c = 0; c < 3; ++c) ph[c * n_cp + a] = pinned ? 0.0 : double(out[c * n_cp + a]);
 }
 
-// Partials of g.ph, ph.w, g.w, w.w (4 arrays of kReduceBlocks).
-__global__ void __launch_bounds__(kBlock) k_dots4_part(int n, const double *__restrict__ g, const double *__restrict__ ph,
-                                                       const double *__restrict__ w, double *__restrict__ part, int stride) {
-    __shared__ double sh[48];
-    double v[3] = {0.0, 0.0, 0.0}, ww = 0.0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        v[0] += g[t] * ph[t]; v[1] += ph[t] * w[t]; v[2] += g[t] * w[t]; ww += w[t] * w[t];
-    }
-    block_sum3(v, sh);
-    __syncthreads();
-    double u3[3] = {ww, 0.0, 0.0};
-    block_sum3(u3, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = v[0]; part[stride + blockIdx.x] = v[1];
-        part[2 * stride + blockIdx.x] = v[2]; part[3 * stride + blockIdx.x] = u3[0];
-    }
-}
-
-__global__ void k_finish4(const double *__restrict__ part, int stride, int n, double *__restrict__ out) {
-    if (threadIdx.x >= 4) return;
+// The warm start's decision, on the device: the sums of the four partial arrays (fixed order)
+// give gp = g.p, pw = p.Hp, gw = g.Hp, ww = |Hp|^2 (stored at S_WS0..3); with bb = |g|^2 the
+// energy-optimal multiple a = -gp / pw of the prediction p (either sign) gives the initial
+// residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g. The start x0 = a p is kept only when
+// that is below bb (the zero start's residual), else a = 0. S_WSA receives a, the flag I_WS
+// whether the start was kept.
+// One wave per partial array (launched with 256 threads): lane l sums entries l, l + 64, ... in
+// order, then the butterfly sum; the result does not depend on timing.
+__global__ void __launch_bounds__(256) k_ws_finish(const double *__restrict__ part, int stride, int nb, double *scal,
+                                                  int32_t *isc) {
+    __shared__ double tot[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double s = 0.0;
-    for (int t = 0; t < n; ++t) s += part[threadIdx.x * stride + t];
-    out[threadIdx.x] = s;
-}
-
-// The warm start's decision, on the device: with gp = g.p, pw = p.Hp, gw = g.Hp, ww = |Hp|^2 (at
-// S_WS0..3) and bb = |g|^2, the energy-optimal multiple a = -gp / pw of the prediction p (either
-// sign) gives the initial residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g; the start
-// x0 = a p is kept only when that is below bb (the zero start's residual), else a = 0. S_WSA
-// receives a, the flag I_WS whether the start was kept.
-__global__ void k_ws_decide(double *scal, int32_t *isc) {
+    for (int t = lane; t < nb; t += 64) s += part[w * stride + t];
+    s = wave_sum_all(s);
+    if (lane == 0) {
+        tot[w] = s;
+        scal[S_WS0 + w] = s;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    const double gp = scal[S_WS0], pw = scal[S_WS1], gw = scal[S_WS2], ww = scal[S_WS3], bb = scal[S_GG];
+    const double gp = tot[0], pw = tot[1], gw = tot[2], ww = tot[3], bb = scal[S_GG];
     double a = 0.0;
     if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw) && std::isfinite(gw) && std::isfinite(ww)) {
         const double as = -gp / pw;
@@ -730,17 +754,6 @@ __global__ void k_ws_decide(double *scal, int32_t *isc) {
     }
     scal[S_WSA] = a;
     isc[I_WS] = a != 0.0 ? 1 : 0;
-}
-
-// x0 = a p and q0 = H x0 = a Hp for the decided multiple a (exact zeros when a = 0, whatever p
-// holds).
-__global__ void k_ws_apply(int n, const double *__restrict__ scal, const double *__restrict__ p, double *__restrict__ hp,
-                           double *__restrict__ x0) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const double a = scal[S_WSA];
-    x0[t] = a != 0.0 ? a * p[t] : 0.0;
-    hp[t] = a != 0.0 ? a * hp[t] : 0.0;
 }
 
 // ---- line search -------------------------------------------------------------------------
@@ -1008,48 +1021,6 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     return BSC_OK;
 }
 
-// Runs the kernels that enqueue(stream) launches: from a graph captured the first time this key
-// is seen (on a private stream) and replayed on st, or directly on st when graphs are off or the
-// capture fails. The key holds every launch parameter that is not fixed by the workspace.
-template <typename F>
-hipError_t run_seq(bsc_ctx *ctx, const void *key, size_t klen, hipStream_t st, F &&enqueue) {
-    if (!ctx->use_graphs || klen > sizeof(bsc_ctx::SeqGraph::key)) {
-        enqueue(st);
-        return hipGetLastError();
-    }
-    unsigned char k[sizeof(bsc_ctx::SeqGraph::key)] = {};
-    std::memcpy(k, key, klen);
-    for (const auto &g : ctx->seq_graphs)
-        if (std::memcmp(g.key, k, sizeof(k)) == 0) return hipGraphLaunch(g.exec, st);
-    hipStream_t cs = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t ge = nullptr;
-    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-        enqueue(cs);
-        ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
-    }
-    ok = ok && hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) == hipSuccess;
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cs) (void)hipStreamDestroy(cs);
-    if (!ok) {
-        if (ge) (void)hipGraphExecDestroy(ge);
-        (void)hipGetLastError();
-        enqueue(st);
-        return hipGetLastError();
-    }
-    if (ctx->seq_graphs.size() >= 64) {          // bounded cache: drop the oldest
-        (void)hipGraphExecDestroy(ctx->seq_graphs.front().exec);
-        ctx->seq_graphs.erase(ctx->seq_graphs.begin());
-    }
-    bsc_ctx::SeqGraph g;
-    std::memcpy(g.key, k, sizeof(k));
-    g.exec = ge;
-    ctx->seq_graphs.push_back(g);
-    return hipGraphLaunch(ge, st);
-}
-
 }  // namespace
 
 bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *v, const double *pin_tgt,
@@ -1065,14 +1036,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
     const int stride = B.max_blocks;
     const bool step_rule = o->fixed_newton_iters <= 0 && o->stop_mode == BSC_STOP_STEP;
-    // With the step rule (and no warm start) nothing the host decides before the solve depends on
-    // the assembly: the PCG tolerance is formed on the device and E, |g| are read back with |p|
-    // and the line search's first trial after the solve, in one synchronisation.
-    // warm starts: the learned prediction needs the host (the net's forward pass runs outside the
-    // captured sequences); the recycled previous direction runs entirely on the device
+    // With the step rule nothing the host decides before the solve depends on the assembly: the
+    // PCG tolerance is formed on the device and E, |g| are read back with |p| and the line
+    // search's first trial after the solve, in one synchronisation. Both warm starts run on the
+    // device without a host decision.
     const int warm = o->warm_start;
-    const bool net_warm = warm == BSC_WARM_NET;
-    const bool deferred = step_rule && !net_warm;
+    const bool deferred = step_rule;
     const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !warm;
     bsc_step_stats s{};
     auto t_start = std::chrono::steady_clock::now();
@@ -1153,8 +1122,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? wait_pub(last) : e;
     };
-    // keys of the captured sequences: launch parameters as 64-bit words
-    auto bits = [](double d) { uint64_t u; std::memcpy(&u, &d, 8); return u; };
 
     HIPX(hipMemcpyAsync(B.xn, x, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "copy x");
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, 1.0, x, dt, v, B.xhat);
@@ -1176,12 +1143,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     for (;; ++it) {
         // ---- assembly: E, g, H at x ---------------------------------------------------------
         hipEvent_t e0 = rec();
+        // (plain launches: the short sequences of a Newton iteration measured faster enqueued
+        // directly than replayed as captured graphs, whose switches with plain launches on the
+        // stream each cost a gap; only the PCG bursts, 8-64 launches, are graphs)
         {
-            const uint64_t key[8] = {1, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
-                                     bits(gz), 0};
-            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     (void)assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, cs);
-                 }), "assembly");
+            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st);
+            if (sa != BSC_OK) return sa;
         }
         hipEvent_t e1 = rec();
         int eta_mode = ETA_EXPLICIT;
@@ -1189,7 +1156,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // is recomputed where it is needed)
         double *rb[2] = {B.r, B.r2}, *wb[2] = {B.q, B.q2}, *sb[2] = {B.p1, B.p2};
         double *p = B.p0;
-        double *hq = rb[1];                      // H p_hat and q0 = H x0 of the warm start (double)
+        double *hq = rb[1];                      // H p_hat of the warm start (free until the CG's first odd launch)
         const int nbi = blocks(S.n_cp), nbc = cg_blocks(S.n_u, S.n_v);
         double *part[2] = {B.partials, B.partials + 3 * stride}, *pbb = B.partials + 6 * stride;
         const bool presum = nbc > kCgPreSumBlocks;
@@ -1208,6 +1175,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         };
         const int first = it == 0 ? 1 : 0;
         double eta_arg = 0.0;                    // the explicit mode's tolerance (set before the solve)
+        double grad_rtol = 0.0;                  // the device-side gradient stop of the speculative solve
         // block-Jacobi inverse, b = -g, x0 = 0 (the recycled warm start keeps the previous direction)
         double *keep = warm == BSC_WARM_PREVIOUS ? B.pprev : nullptr;
         auto enqueue_prep = [&](hipStream_t cs) {
@@ -1218,19 +1186,23 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir,
                                                                      keep);
         };
-        // warm start from the prediction ph: Hp into hq, the four dot products, the decision and
-        // x0 = a ph, q0 = a Hp (zero when the start is not kept), all on the device
+        // warm start from the prediction ph: H ph into hq with the partials of its four dot
+        // products, then their sums and the decision, all on the device (k_cg_init applies it)
         auto enqueue_warm = [&](hipStream_t cs, const double *ph) {
-            (void)launch_spmv(S, prec, B.hess, ph, hq, cs);
-            k_dots4_part<<<kReduceBlocks, kBlock, 0, cs>>>(n3, B.g, ph, hq, B.partials + 4 * stride, stride);
-            k_finish4<<<1, 64, 0, cs>>>(B.partials + 4 * stride, stride, kReduceBlocks, B.scalars + S_WS0);
-            k_ws_decide<<<1, 64, 0, cs>>>(B.scalars, B.iscalars);
-            k_ws_apply<<<blocks(n3), kBlock, 0, cs>>>(n3, B.scalars, ph, hq, B.dir);
+            const int nb = spmv_blocks(S.n_cp);
+            if (prec == BSC_FP64)
+                k_spmv_tile<double, true><<<nb, kRowsPerTile * kGroups, 0, cs>>>(S, (const double *)B.hess, ph, hq, B.g,
+                                                                                B.partials + 4 * stride, stride);
+            else
+                k_spmv_tile<float, true><<<nb, kRowsPerTile * kGroups, 0, cs>>>(S, (const float *)B.hess, ph, hq, B.g,
+                                                                               B.partials + 4 * stride, stride);
+            k_ws_finish<<<1, 256, 0, cs>>>(B.partials + 4 * stride, stride, nb, B.scalars, B.iscalars);
         };
-        // r = b - q0, the tolerance, and the first CG launch (it forms w_0)
-        auto enqueue_init = [&](hipStream_t cs, const double *q0_) {
-            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, q0_, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode,
-                                               first, eta_arg, o->pcg_rtol, eta_max);
+        // r = b - A x0 (x0 = a ph with the decided multiple, when ph is given), the tolerance, and
+        // the first CG launch (it forms w_0)
+        auto enqueue_init = [&](hipStream_t cs, const double *ph) {
+            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, ph, hq, B.dir, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
+                                               eta_mode, first, eta_arg, o->pcg_rtol, eta_max, grad_rtol);
             if (prec == BSC_FP64)
                 k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
             else
@@ -1238,28 +1210,108 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
         };
         // the block-Jacobi solve's set-up (prep, the recycled warm start, init and the first
-        // launch) as one captured sequence
+        // launch), enqueued as plain launches: as a captured sequence it measured slower (each
+        // switch between a graph and plain launches on the stream costs a gap)
+        const double *ph = warm == BSC_WARM_PREVIOUS ? B.pprev : (warm == BSC_WARM_NET ? B.phat : nullptr);
         auto cg_setup = [&]() -> hipError_t {
-            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), (step_rule ? 2u : 0u) | (uint64_t(warm) << 4), bits(eta_max)};
-            return run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                enqueue_prep(cs);
-                if (warm == BSC_WARM_PREVIOUS) enqueue_warm(cs, B.pprev);
-                enqueue_init(cs, warm == BSC_WARM_PREVIOUS ? hq : nullptr);
-            });
+            enqueue_prep(st);
+            if (warm == BSC_WARM_NET) {
+                // the learned prediction p_hat = net(g), zero on pinned CPs
+                hipEvent_t w0 = rec();
+                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
+                const hipError_t e = net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0,
+                                                      B.net_act1, B.net_scale, B.net_w_fwd, true, st);
+                if (e != hipSuccess) return e;
+                k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
+                span(w0, rec(), &s.ms_warmstart);
+            }
+            if (ph) enqueue_warm(st, ph);
+            enqueue_init(st, ph);
+            return hipGetLastError();
         };
-        // Gradient rule (no learned warm start, no multigrid): the set-up is enqueued right behind
+        int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
+        // a chunk: 8 fused block-Jacobi CG launches (even: every chunk starts on an odd launch),
+        // or one multigrid-preconditioned CG iteration
+        const int chunk = use_mg ? 1 : 8;
+        auto enqueue_chunk = [&](hipStream_t cs) {
+            if (use_mg) {
+                (void)mg_cg_iteration(S, B, prec, rb[0], sb[0], p, wb[0], B.partials, B.partials + stride, pbb, cs);
+                return;
+            }
+            for (int c = 1; c <= chunk; ++c) {
+                if (prec == BSC_FP64)
+                    k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
+                else
+                    k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
+                if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[c & 1], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
+            }
+        };
+        // A burst of K chunks (K = 1..8) is one graph of 8K launches, captured the first time it
+        // is needed (on a private stream) and replayed on the context's stream; the kernel
+        // arguments depend only on the bound workspace. One graph launch per burst avoids the
+        // gap between successive graph launches.
+        auto graph_for = [&](int K) -> hipGraphExec_t {
+            hipGraphExec_t &gxe = (use_mg ? ctx->mg_graph : ctx->cg_graph)[prec == BSC_FP64 ? 0 : 1][K];
+            if (!gxe && ctx->use_graphs) {
+                hipStream_t cs = nullptr;
+                hipGraph_t graph = nullptr;
+                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    for (int k = 0; k < K; ++k) enqueue_chunk(cs);
+                    if (pub) publish(cs);
+                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+                }
+                ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+                if (cs) (void)hipStreamDestroy(cs);
+                if (!ok) {
+                    if (gxe) { (void)hipGraphExecDestroy(gxe); gxe = nullptr; }
+                    (void)hipGetLastError();
+                }
+            }
+            return gxe;
+        };
+        auto launch_burst = [&](int K) -> hipError_t {
+            hipGraphExec_t gx = graph_for(K);
+            if (gx) return hipGraphLaunch(gx, st);
+            for (int bi = 0; bi < K; ++bi) enqueue_chunk(st);
+            if (pub) publish(st);
+            return hipGetLastError();
+        };
+        // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
+        // exit at once, in about 3 us, while a burst boundary costs a host round trip). The first
+        // burst covers the iterations that the same Newton iteration of the previous step needed
+        // plus four (two chunks without such a record); after each burst the host extrapolates the
+        // residual's geometric decay to the stopping threshold and sizes the next burst to cover
+        // the iterations that remain plus half a chunk.
+        int burst = 2, done_prev = 0;
+        if (!use_mg && it < 64 && ctx->pcg_hist[it] > 0)
+            burst = std::max(1, std::min(8, (ctx->pcg_hist[it] + 4 + chunk) / chunk));
+        // Gradient rule (no multigrid): the set-up is enqueued right behind
         // the assembly with the forcing term formed on the device (the same formula as the
-        // host's), and the host reads E and |g| while the GPU runs it. A Newton iteration that
-        // turns out to have converged wastes only that set-up; x is not touched.
-        const bool early = !deferred && !net_warm && !use_mg;
-        hipEvent_t e2 = nullptr;
+        // host's), and the host reads E and |g| while the GPU runs it. Under the gradient stop the
+        // first burst follows at once (speculative): the set-up marks the solve done on the device
+        // when |g| already meets the stop, so a converged iterate costs only the set-up and a
+        // burst of launches that exit; x is not touched.
+        const bool early = !deferred && !use_mg;
+        hipEvent_t e2 = nullptr, burst_c0 = nullptr;
+        bool burst_pending = false;
+        int32_t burst_last = 0;
         if (early) {
             eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
+            const bool speculate = o->stop_mode == BSC_STOP_GRAD && o->fixed_newton_iters <= 0 && it < o->max_newton;
+            grad_rtol = speculate ? o->rtol : 0.0;
             const int32_t last = seen();
             if (pub) publish(st);
             e2 = rec();
             HIPX(cg_setup(), "cg init");
+            if (speculate) {
+                burst_c0 = rec();
+                HIPX(launch_burst(burst), "cg graph");
+                burst_last = last + 1;             // the burst publishes after the assembly's read-back
+                burst_pending = true;
+            }
             HIPX(pub ? wait_pub(last) : copy_sync(), "read norms");
         }
         if (!deferred) {
@@ -1316,99 +1368,25 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             // multigrid: Galerkin hierarchy and block-Jacobi inverses of every level, then r = b,
             // p = 0, the flags and the tolerance (the first iteration's stop test sets |b|-relative
             // tolerance from the partials of |b|^2)
-            const uint64_t key[9] = {2, uint64_t(prec), uint64_t(eta_mode), uint64_t(first), bits(eta_arg), bits(o->pcg_rtol),
-                                     uint64_t(o->max_pcg), 1 | (step_rule ? 2u : 0u), bits(eta_max)};
-            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     enqueue_prep(cs);
-                     (void)mg_setup(S, B, prec, cs);
-                     k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
-                                                        eta_mode, first, eta_arg, o->pcg_rtol, eta_max);
-                 }), "mg init");
-        } else if (!net_warm) {
-            HIPX(cg_setup(), "cg init");
-        } else {
-            // learned warm start: p_hat = net(g) masked at pins, then the same device-side
-            // decision as the recycled start (x0 = a p_hat with the energy-optimal a, kept only
-            // when it lowers the initial residual)
             enqueue_prep(st);
-            {
-                Timer tw(st);
-                k_to_float<<<blocks(n3), kBlock, 0, st>>>(n3, B.g, B.net_in);
-                HIPX(net_forward_impl(S.n_u, S.n_v, 1, B.net_w, B.net_in, B.net_out, nullptr, B.net_act0, B.net_act1,
-                                      B.net_scale, B.net_w_fwd, true, st), "warm start forward");
-                k_phat<<<blocks(S.n_cp), kBlock, 0, st>>>(S.n_cp, B.net_out, S.pinmask, B.phat);
-                HIPX(hipGetLastError(), "warm start");
-                s.ms_warmstart += tw.stop();
-            }
-            enqueue_warm(st, B.phat);
-            enqueue_init(st, hq);
-            HIPX(hipGetLastError(), "cg init");
+            HIPX(mg_setup(S, B, prec, st), "mg setup");
+            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
+                                               o->max_pcg, eta_mode, first, eta_arg, o->pcg_rtol, eta_max, 0.0);
+            HIPX(hipGetLastError(), "mg init");
+        } else {
+            HIPX(cg_setup(), "cg init");
         }
-        int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
-        // a chunk: 8 fused block-Jacobi CG launches (even: every chunk starts on an odd launch),
-        // or one multigrid-preconditioned CG iteration
-        const int chunk = use_mg ? 1 : 8;
-        auto enqueue_chunk = [&](hipStream_t cs) {
-            if (use_mg) {
-                (void)mg_cg_iteration(S, B, prec, rb[0], sb[0], p, wb[0], B.partials, B.partials + stride, pbb, cs);
-                return;
-            }
-            for (int c = 1; c <= chunk; ++c) {
-                if (prec == BSC_FP64)
-                    k_cg_fused<double, false><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(c), B.scalars, B.iscalars);
-                else
-                    k_cg_fused<float, false><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(c), B.scalars, B.iscalars);
-                if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[c & 1], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
-            }
-        };
-        // A burst of K chunks (K = 1..8) is one graph of 8K launches, captured the first time it
-        // is needed (on a private stream) and replayed on the context's stream; the kernel
-        // arguments depend only on the bound workspace. One graph launch per burst avoids the
-        // gap between successive graph launches.
-        auto graph_for = [&](int K) -> hipGraphExec_t {
-            hipGraphExec_t &gxe = (use_mg ? ctx->mg_graph : ctx->cg_graph)[prec == BSC_FP64 ? 0 : 1][K];
-            if (!gxe && ctx->use_graphs) {
-                hipStream_t cs = nullptr;
-                hipGraph_t graph = nullptr;
-                bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
-                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                if (ok) {
-                    for (int k = 0; k < K; ++k) enqueue_chunk(cs);
-                    if (pub) publish(cs);
-                    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
-                }
-                ok = ok && hipGraphInstantiate(&gxe, graph, nullptr, nullptr, 0) == hipSuccess;
-                if (graph) (void)hipGraphDestroy(graph);
-                if (cs) (void)hipStreamDestroy(cs);
-                if (!ok) {
-                    if (gxe) { (void)hipGraphExecDestroy(gxe); gxe = nullptr; }
-                    (void)hipGetLastError();
-                }
-            }
-            return gxe;
-        };
-        // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
-        // exit at once, in about 3 us, while a burst boundary costs a host round trip). The first
-        // burst covers the iterations that the same Newton iteration of the previous step needed
-        // plus four (two chunks without such a record); after each burst the host extrapolates the
-        // residual's geometric decay to the stopping threshold and sizes the next burst to cover
-        // the iterations that remain plus half a chunk.
-        int burst = 2, done_prev = 0;
-        if (!use_mg && it < 64 && ctx->pcg_hist[it] > 0)
-            burst = std::max(1, std::min(8, (ctx->pcg_hist[it] + 4 + chunk) / chunk));
         double lrho_prev = 0.0;
         bool have_prev = false;
         while (true) {
-            hipEvent_t c0 = rec();
-            const int32_t last = seen();
-            hipGraphExec_t gx = graph_for(burst);
-            if (gx) {
-                HIPX(hipGraphLaunch(gx, st), "cg graph");
-            } else {
-                for (int bi = 0; bi < burst; ++bi) enqueue_chunk(st);
-                if (pub) publish(st);
+            hipEvent_t c0 = burst_c0;
+            int32_t last = burst_last;
+            if (!burst_pending) {
+                c0 = rec();
+                last = seen();
+                HIPX(launch_burst(burst), "cg graph");
             }
-            HIPX(hipGetLastError(), "cg");
+            burst_pending = false;
             span(c0, rec(), &s.ms_cg_kernels);
             HIPX(pub ? wait_pub(last) : copy_sync(), "read cg state");
             for (int k = 0; k < 7; ++k) flags[k] = hf[k];
@@ -1459,19 +1437,15 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         {
             double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
             const int32_t last = seen();
-            const uint64_t key[8] = {3, uint64_t(prec), uint64_t(reinterpret_cast<uintptr_t>(x)), bits(inv_dt2), bits(gx), bits(gy),
-                                     bits(gz), uint64_t(step_rule ? 1 : 0) | (pub ? 2u : 0u)};
-            HIPX(run_seq(ctx, key, sizeof(key), st, [&](hipStream_t cs) {
-                     // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at
-                     // 7; the membrane difference at 0, free once PCG has finished)
-                     k_ls_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
-                                                                 B.partials + 7 * stride);
-                     k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pb, stride);
-                     k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials);
-                     k_ls_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
-                                                       B.partials, blocks(S.n_mp), B.scalars);
-                     if (pub) publish(cs);
-                 }), "line search setup");
+            // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at 7; the
+            // membrane difference at 0, free once PCG has finished)
+            k_ls_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride, B.partials + 7 * stride);
+            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, B.dir, pb, stride);
+            k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, 1.0, B.partials);
+            k_ls_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
+                                              B.partials, blocks(S.n_mp), B.scalars);
+            if (pub) publish(st);
+            HIPX(hipGetLastError(), "line search setup");
             e5 = rec();
             HIPX(pub ? wait_pub(last) : copy_sync(), "read scalars");
         }
@@ -1582,8 +1556,8 @@ bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, doubl
         k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir, nullptr);
     else
         k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir, nullptr);
-    k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
-                                       ETA_EXPLICIT, 1, rtol, rtol, rtol);
+    k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
+                                       ETA_EXPLICIT, 1, rtol, rtol, rtol, 0.0);
     fused(0);
     HIPX(hipGetLastError(), "stencil pcg");
     int32_t flags[8] = {};

@@ -1,10 +1,12 @@
 """Evaluates the learned PCG warm start on a held-out sheet (compression and drape).
 
-From the same state of an FP64 reference trajectory at every step, three solves are run:
+From the same state of an FP64 reference trajectory at every step, four solves are run:
 (i) FP64 zero-start PCG, (ii) FP32-mixed zero-start PCG, (iii) FP32-mixed PCG warm-started by
-the network (falling back to zero start when the prediction does not lower the residual). All
-use the same Newton stopping rule. The trajectory advances with (i). Reported per variant:
-ms per step, Newton and PCG iterations, warm-start use/fallbacks, the final |g|/|g0|.
+the network (falling back to zero start when the prediction does not lower the residual), and
+(iv) FP32-mixed PCG warm-started by the previous Newton direction of the same solve (the
+recycled start, with the same scaling and fallback). All use the same Newton stopping rule.
+The trajectory advances with (i). Reported per variant: ms per step, Newton and PCG
+iterations, warm-start use/fallbacks, the final |g|/|g0|.
 
 Usage: python -m paper_2506_18867_amd.warmstart_eval --weights paper_2506_18867_amd/weights/warmstart_c32.f32
 """
@@ -41,7 +43,9 @@ def evaluate(weights_path: str, n: int = 226, seed: int = 5001, steps: int = 20,
     w = torch.from_numpy(np.fromfile(weights_path, dtype=np.float32)).cuda()
     ctx.bsc_warmstart_load(w)
     x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
-    variants = [("fp64", bsc.BSC_FP64, 0), ("fp32_mixed", bsc.BSC_FP32_MIXED, 0), ("fp32_mixed_warm", bsc.BSC_FP32_MIXED, 1)]
+    variants = [("fp64", bsc.BSC_FP64, bsc.BSC_WARM_NONE), ("fp32_mixed", bsc.BSC_FP32_MIXED, bsc.BSC_WARM_NONE),
+                ("fp32_mixed_warm", bsc.BSC_FP32_MIXED, bsc.BSC_WARM_NET),
+                ("fp32_mixed_recycled", bsc.BSC_FP32_MIXED, bsc.BSC_WARM_PREVIOUS)]
     res = {name: {"ms": [], "newton": [], "pcg": [], "used": 0, "fallbacks": 0, "g_rel": [], "status": []}
            for name, _, _ in variants}
     for step in range(steps):
@@ -78,7 +82,10 @@ def evaluate(weights_path: str, n: int = 226, seed: int = 5001, steps: int = 20,
     base = summary["fp32_mixed"]
     summary["gain"] = {"pcg_iters_zero_over_warm": base["pcg_total"] / max(1, summary["fp32_mixed_warm"]["pcg_total"]),
                        "ms_zero_over_warm": base["ms_per_step"] / summary["fp32_mixed_warm"]["ms_per_step"],
-                       "ms_fp64_over_warm": summary["fp64"]["ms_per_step"] / summary["fp32_mixed_warm"]["ms_per_step"]}
+                       "ms_fp64_over_warm": summary["fp64"]["ms_per_step"] / summary["fp32_mixed_warm"]["ms_per_step"],
+                       "pcg_iters_zero_over_recycled": base["pcg_total"] / max(1, summary["fp32_mixed_recycled"]["pcg_total"]),
+                       "ms_zero_over_recycled": base["ms_per_step"] / summary["fp32_mixed_recycled"]["ms_per_step"],
+                       "ms_fp64_over_recycled": summary["fp64"]["ms_per_step"] / summary["fp32_mixed_recycled"]["ms_per_step"]}
     summary["config"] = {"n": n, "seed": seed, "steps": steps, "stop": stop, "rtol": rtol, "atol": atol,
                          "pcg_rtol": pcg_rtol, "compression": compression, "material": [sc.material.young, sc.material.thickness]}
     return summary
