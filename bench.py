@@ -106,6 +106,9 @@ def parse(argv=None):
     p.add_argument("--warm", choices=["previous", "none", "net"], default="previous",
                    help="PCG warm start of the FP32-mixed headline (and of the step-rule, sweep and ablation legs): "
                         "the previous Newton direction, none (zero start) or the learned network")
+    p.add_argument("--variants", choices=["all", "headline"], default="all",
+                   help="headline steps: FP32-mixed with the warm start beside plain FP64, FP32-mixed zero start and "
+                        "FP64 with the same start (all), or FP32-mixed alone (headline: for kernel traces of its launches)")
     p.add_argument("--precond", choices=["jacobi", "mg"], default="jacobi",
                    help="PCG preconditioner: block Jacobi (fused kernel) or the multigrid V-cycle")
     p.add_argument("--start", choices=["predictor", "previous"], default="previous",
@@ -354,8 +357,10 @@ def main():
         ctx.bsc_warmstart_load(torch.from_numpy(np.fromfile(we.DEFAULT_WEIGHTS, dtype=np.float32)).cuda())
     o32 = step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args)
     o64 = step_opts(bsc, sc, bsc.BSC_FP64, args, warm=bsc.BSC_WARM_NONE)
-    variants = [("fp32_mixed", o32, ctx), ("fp64", o64, bsc.context_for_scene(sc))]
-    if wm != bsc.BSC_WARM_NONE:
+    variants = [("fp32_mixed", o32, ctx)]
+    if args.variants == "all":
+        variants += [("fp64", o64, bsc.context_for_scene(sc))]
+    if wm != bsc.BSC_WARM_NONE and args.variants == "all":
         variants += [("fp32_mixed_zero_start", step_opts(bsc, sc, bsc.BSC_FP32_MIXED, args, warm=bsc.BSC_WARM_NONE),
                       bsc.context_for_scene(sc))]
         if wm == bsc.BSC_WARM_PREVIOUS:
@@ -363,7 +368,7 @@ def main():
     paired_steps(ctx, sc, x, v, 0, args.warmup, variants, "fp32_mixed", torch, bsc)
     xs, vs = x.clone(), v.clone()
     head = paired_steps(ctx, sc, x, v, args.warmup, args.steps, variants, "fp32_mixed", torch, bsc, log)
-    r32, r64 = head["fp32_mixed"], head["fp64"]
+    r32, r64 = head["fp32_mixed"], head.get("fp64", [])
     sec32 = sum(r[0] for r in r32)
     sec64 = sum(r[0] for r in r64)
     st32 = [r[1] for r in r32]
@@ -649,7 +654,7 @@ def main():
                                       "none": "zero start", "net": "learned network prediction"}[args.warm],
                    "parallelism": "single GPU"},
         "newton_step_ms": {name: round(1e3 * secs[name] / args.steps, 3) for name in head},
-        "speedup_vs_fp64": round(sec64 / sec32, 3),
+        "speedup_vs_fp64": round(sec64 / sec32, 3) if r64 else None,
         "speedup_vs_fp64_same_start": round(secs["fp64_warm"] / sec32, 3) if "fp64_warm" in secs else None,
         "speedup_vs_fp32_zero_start": (round(secs["fp32_mixed_zero_start"] / sec32, 3)
                                        if "fp32_mixed_zero_start" in secs else None),
