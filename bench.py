@@ -30,7 +30,7 @@ Further legs (each a field of the one JSON line):
                     intensities: the Gershgorin trigger, the series and the merged solve;
   quadrature_ablation, general_rest, contact_conversion, wrinkling_convergence.
 The roofline object covers the kernel with the largest share of the step (the fused PCG-iteration
-kernel), timed live by the library with HIP events around its graph chunks on its stream (the
+kernel), timed live by the library with HIP events around its bursts of launches on its stream (the
 torch current stream). cpu_baseline is the oracle's eval+assembly on the same 226 x 226 sheet.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 226] [--no-cpu]
@@ -63,7 +63,7 @@ ASM_FLOP_PER_ELEM = 8.5e3
 # was evicted first (`bench.py --copy-probe 1024`: FETCH_SIZE 0.500, WRITE_SIZE 1.000 of the
 # bytes). Summary and commands: profiles/k_cg_fused_226_traffic.md. Valid only for the kernel
 # source it was measured on (hash of its text in solve.hip); otherwise reported as null.
-CG_TRAFFIC = {"kernel_sha256_16": "9020f57fa3cbcbc5", "fetch_kib": 16388.2, "write_kib": 5441.9,
+CG_TRAFFIC = {"kernel_sha256_16": "9020f57fa3cbcbc5", "fetch_kib": 16505.3, "write_kib": 5443.1,
               "fetch_factor": 0.500, "write_factor": 1.000}
 
 

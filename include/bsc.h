@@ -133,11 +133,11 @@ typedef struct {
  * warm_start_used / warm_start_fallbacks count the Newton iterations whose prediction was kept /
  * dropped); ms_total is
  * the host wall-clock time of the call. The PCG iterations run as launches of one fused kernel (one per
- * iteration, replayed in fixed-size chunks; launches after convergence exit at once):
+ * iteration, enqueued in fixed-size chunks; launches after convergence exit at once):
  * cg_launches counts them, cg_active_launches those that performed an iteration, and
  * ms_cg_kernels is their GPU time from HIP events recorded on the context's stream around
- * each burst of chunks (one graph launch, which ends with the kernel that publishes the solver
- * state to the host). */
+ * each burst of chunks (which ends with the kernel that publishes the solver state to the
+ * host; with BSC_GRAPHS=1 in the environment at bsc_create a burst is one graph launch). */
 typedef struct {
     int32_t newton_iters, pcg_iters_total, ls_halvings, warm_start_used, warm_start_fallbacks;
     double g0_norm, g_norm, energy;

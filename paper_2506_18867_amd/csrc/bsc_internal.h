@@ -269,7 +269,7 @@ struct bsc_ctx {
     // of 1..8 chunks of launches per precision (index [precision][chunks])
     hipGraphExec_t cg_graph[2][9] = {};
     hipGraphExec_t mg_graph[2][9] = {};      // the same for multigrid-preconditioned CG iterations
-    bool use_graphs = true;          // BSC_NO_GRAPHS=1 in the environment at create disables them
+    bool use_graphs = false;         // BSC_GRAPHS=1 in the environment at create: bursts replayed from graphs
     // PCG iterations of the previous step's solves, by Newton iteration (sizes first bursts)
     int pcg_hist[64] = {};
     // (g, p) sample log of the Newton iterations (device float buffers owned by the caller)

@@ -360,7 +360,7 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
     c->n_cp = n_u * n_v; c->n_elem = c->Nu * c->Nv;
     c->mat = *mat;
     c->stream = (hipStream_t)hip_stream;
-    if (const char *ng = std::getenv("BSC_NO_GRAPHS")) c->use_graphs = !(ng[0] == '1');
+    if (const char *gr = std::getenv("BSC_GRAPHS")) c->use_graphs = gr[0] == '1';
     if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
 
     // The rest map X(u,v) = sum N_a X^a is affine iff the CPs are an affine image of the

@@ -10,7 +10,7 @@
 // preconditioner, the SpMV and the new partials); every block re-sums the partials in the same
 // fixed order (large grids: a one-block kernel sums them once per launch). Scalars live in
 // device memory, nothing uses atomics or in-kernel fences, results are deterministic, and the
-// host reads the solver state once per burst of graph-replayed launches.
+// host reads the solver state once per burst of launches.
 // Line search: the energy difference E(x + alpha p) - E(x) is evaluated in double without
 // forming the two energies: the inertia, gravity and bending terms are exact quadratics in
 // alpha (coefficients computed once), and each membrane point evaluates Psi(F + alpha dF) -
@@ -1143,9 +1143,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     for (;; ++it) {
         // ---- assembly: E, g, H at x ---------------------------------------------------------
         hipEvent_t e0 = rec();
-        // (plain launches: the short sequences of a Newton iteration measured faster enqueued
-        // directly than replayed as captured graphs, whose switches with plain launches on the
-        // stream each cost a gap; only the PCG bursts, 8-64 launches, are graphs)
+        // (plain launches: the sequences of a Newton iteration measured faster enqueued directly
+        // than replayed as captured graphs, whose switches with plain launches on the stream each
+        // cost a gap)
         {
             const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st);
             if (sa != BSC_OK) return sa;
@@ -1246,10 +1246,11 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                 if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[c & 1], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
             }
         };
-        // A burst of K chunks (K = 1..8) is one graph of 8K launches, captured the first time it
-        // is needed (on a private stream) and replayed on the context's stream; the kernel
-        // arguments depend only on the bound workspace. One graph launch per burst avoids the
-        // gap between successive graph launches.
+        // A burst of K chunks (K = 1..8) is enqueued as plain launches (the host keeps ahead of
+        // the GPU). With BSC_GRAPHS=1 at create it is one graph of 8K launches instead, captured
+        // the first time it is needed (on a private stream) and replayed on the context's stream
+        // (the kernel arguments depend only on the bound workspace); at 226^2 the graphs measured
+        // slower (a start-up gap per burst and gaps between their launches).
         auto graph_for = [&](int K) -> hipGraphExec_t {
             hipGraphExec_t &gxe = (use_mg ? ctx->mg_graph : ctx->cg_graph)[prec == BSC_FP64 ? 0 : 1][K];
             if (!gxe && ctx->use_graphs) {

@@ -400,7 +400,7 @@ def test_cg_graph_replays_match_eager_launches(monkeypatch):
     sc = syn.driven_sheet(48, seed=303)
     results = []
     for no_graph in ("1", "0"):
-        monkeypatch.setenv("BSC_NO_GRAPHS", no_graph)
+        monkeypatch.setenv("BSC_GRAPHS", "0" if no_graph == "1" else "1")
         ctx = _ctx(sc)
         x, v = bsc.to_soa(sc.x0), bsc.to_soa(sc.v0)
         for prec in (bsc.BSC_FP64, bsc.BSC_FP32_MIXED):
