@@ -95,9 +95,10 @@ typedef struct {
  *   under BSC_STOP_STEP and 0.1 under BSC_STOP_GRAD; with
  *   BSC_STOP_STEP a stop is only accepted on a direction solved to pcg_rtol. */
 /* PCG warm starts. NONE: x0 = 0. NET: the loaded network's prediction from the gradient (the
- * learned warm start; needs bsc_warmstart_load). PREVIOUS: the previous Newton direction of this
- * context (recycled: in the linearly converging phase of projected Newton successive directions
- * are close; not in the paper). Both decide on the device, with no host round trip. */
+ * learned warm start; needs bsc_warmstart_load). PREVIOUS: the previous Newton direction of the
+ * same step (recycled: in the linearly converging phase of projected Newton successive
+ * directions are close; the first Newton iteration of a step starts from zero; not in the
+ * paper). Both decide on the device, with no host round trip. */
 enum { BSC_WARM_NONE = 0, BSC_WARM_NET = 1, BSC_WARM_PREVIOUS = 2 };
 /* PCG preconditioners. JACOBI: 3x3 block Jacobi, one fused kernel per iteration. MULTIGRID: one
  * symmetric V(1,1) cycle on the hierarchy of the patch's knot halvings (exact B-spline

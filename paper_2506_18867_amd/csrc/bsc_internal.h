@@ -32,9 +32,9 @@ constexpr int kHessEntries = BSC_HESS_ENTRIES;
 constexpr int kCgTileU = 64, kCgTileV = 2;
 // Hessian blocks per wave that the FP32 CG kernel loads before its prologue reduction (3 or more
 // need more than the 128 VGPRs that keep two workgroups on a CU)
-constexpr int kCgPrefetch = 2;
 // CG grids of more workgroups than this have the previous launch's partials summed once, by a
 // one-block kernel between the launches, instead of by every workgroup (quadratic in the grid)
+constexpr int kCgPrefetch = 2;
 constexpr int kCgPreSumBlocks = 2048;
 
 // Upper-stencil slot offsets (di, dj); slot 0 is the diagonal.
@@ -68,7 +68,9 @@ __host__ __device__ inline int upper_slot(int di, int dj) {
 enum { S_TOL2 = 0, S_ALPHA0, S_ALPHA1, S_GAMMA0, S_GAMMA1, S_E, S_GG, S_C1, S_C2, S_DEM, S_PMAX, S_RTOL, S_ETA, S_GPREV,
        S_WS0, S_WS1, S_WS2, S_WS3, S_RHO, S_WSA, S_WSB, S_G0, S_MGRHO0 = 40, S_MGRHO1 = 41, S_CGSUM = 44 /* 3 slots */,
        S_XMAX = 47 };
-enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS, I_WS };   // I_WS: the warm start was used
+enum { I_DONE = 0, I_ITA, I_ITB, I_BREAK, I_MAXIT, I_ITERS, I_WS, I_LSACC };
+// I_WS: the warm start was kept; I_LSACC: the device's line-search trial at alpha = 1 (0 rejected,
+// 1 accepted and applied, 2 the direction is below the stagnation scale, x untouched)
 constexpr int I_PUBSEQ = 60;                 // sequence number of the last published read-back
 // Largest PCG relative tolerance of the Eisenstat-Walker forcing term (and its first value):
 // loose under the step-length stopping rule, tighter under the gradient rule, which has to reach

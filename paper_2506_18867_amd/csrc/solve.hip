@@ -221,6 +221,11 @@ __global__ void __launch_bounds__(kBlock) k_export_bsr(DevSheet S, const T *__re
 
 // ---- small vector kernels ------------------------------------------------------------------
 
+__global__ void k_zero(int n, double *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = 0.0;
+}
+
 __global__ void k_axpby(int n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
                         double *__restrict__ out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,7 +293,8 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // inverse of the 3x3 diagonal block, or its inverse diagonal where that block is not positive
 // definite), the right-hand side b = -g (written 0 - g, so that a zero gradient gives +0) and
 // the initial direction x0 = 0. With keep, the direction that x0 held (the previous Newton
-// direction) is saved there first, zero on pinned CPs.
+// direction of the step; zero at the step's first iteration) is saved there first, zero on
+// pinned CPs.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_prep(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv,
                                                     const double *__restrict__ g, double *__restrict__ b,
@@ -350,7 +356,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
-    const double ws = ph ? scal[S_WSA] : 0.0;
+    // the gradient stop (below) is known to every thread: a solve that will not run keeps x0 = 0
+    const double gn0 = sqrt(scal[S_GG]);
+    const bool gstop = grad_rtol > 0.0 && (gn0 == 0.0 || (!first && gn0 <= grad_rtol * scal[S_G0]));
+    const double ws = ph && !gstop ? scal[S_WSA] : 0.0;
     double bb = 0.0;
     if (a < S.n_cp) {
         for (int c = 0; c < 3; ++c) {
@@ -381,7 +390,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
         // gradient rule with the solve enqueued before the host has read |g|: a Newton iterate
         // that already meets |g| <= grad_rtol |g0| (or |g| = 0) solves nothing (the host stops)
         if (first) scal[S_G0] = gn;
-        if (grad_rtol > 0.0 && (gn <= grad_rtol * scal[S_G0] || gn == 0.0)) isc[I_DONE] = 1;
+        if (gstop) isc[I_DONE] = 1;
     }
 }
 
@@ -762,11 +771,11 @@ __global__ void __launch_bounds__(256) k_ws_finish(const double *__restrict__ pa
 // gravity and bending terms (quadratics in alpha) plus the membrane term, summed point by point.
 // Per CP, in one pass over p: partials of c1 and c2 of the inertia and gravity terms and of
 // max |p| (the stop tests).
-__global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
-                                                  const double *__restrict__ p, double inv_dt2, double gx, double gy,
-                                                  double gz, double *partials, int stride, double *__restrict__ pmax_part) {
+__device__ __forceinline__ void ls_cp_block(const DevSheet &S, const double *__restrict__ x, const double *__restrict__ xhat,
+                                            const double *__restrict__ p, double inv_dt2, double gx, double gy, double gz,
+                                            double *partials, int stride, double *__restrict__ pmax_part, int blk) {
     __shared__ double sh[kBlock / 64];
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blk * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
     double c1 = 0.0, c2 = 0.0, m = 0.0;
     if (a < S.n_cp) {
@@ -780,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__re
     }
     c1 = block_sum(c1, sh);
     c2 = block_sum(c2, sh);
-    if (threadIdx.x == 0) { partials[blockIdx.x] = c1; partials[stride + blockIdx.x] = c2; }
+    if (threadIdx.x == 0) { partials[blk] = c1; partials[stride + blk] = c2; }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
     __syncthreads();
@@ -788,16 +797,22 @@ __global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__re
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-        pmax_part[blockIdx.x] = m;
+        pmax_part[blk] = m;
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
+                                                  const double *__restrict__ p, double inv_dt2, double gx, double gy,
+                                                  double gz, double *partials, int stride, double *__restrict__ pmax_part) {
+    ls_cp_block(S, x, xhat, p, inv_dt2, gx, gy, gz, partials, stride, pmax_part, blockIdx.x);
+}
+
 // The line-search scalars in one block, each in a fixed order: max |p| (exact in any order),
-// c1 and c2 over the CP and bending partials, the membrane energy difference at alpha = 1.
-__global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa,
-                                                      const double *__restrict__ pb, int n_beb, int stride,
-                                                      const double *__restrict__ pd, int n_mpb, double *scal) {
-    __shared__ double sh[kBlock / 64];
+// c1 and c2 over the CP and bending partials, the membrane energy difference at alpha = 1;
+// out[0..3] = max |p|, c1, c2, dE_membrane, valid in every thread of the block.
+__device__ void ls_sums(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa, const double *__restrict__ pb,
+                        int n_beb, int stride, const double *__restrict__ pd, int n_mpb, double *sh, double out[4]) {
+    __shared__ double res[4];
     double m = 0.0;
     for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) m = fmax(m, pm[t]);
 #pragma unroll
@@ -806,27 +821,39 @@ __global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-        scal[S_PMAX] = m;
+        res[0] = m;
     }
     for (int k = 0; k < 2; ++k) {
         double v = 0.0;
         for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) v += pa[k * stride + t];
         for (int t = threadIdx.x; t < n_beb; t += blockDim.x) v += pb[k * stride + t];
         v = block_sum(v, sh);
-        if (threadIdx.x == 0) scal[S_C1 + k] = v;
+        if (threadIdx.x == 0) res[1 + k] = v;
     }
     double v = 0.0;
     for (int t = threadIdx.x; t < n_mpb; t += blockDim.x) v += pd[t];
     v = block_sum(v, sh);
-    if (threadIdx.x == 0) scal[S_DEM] = v;
+    if (threadIdx.x == 0) res[3] = v;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = res[k];
+}
+
+__global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa,
+                                                      const double *__restrict__ pb, int n_beb, int stride,
+                                                      const double *__restrict__ pd, int n_mpb, double *scal) {
+    __shared__ double sh[kBlock / 64];
+    double r[4];
+    ls_sums(pm, n_cpb, pa, pb, n_beb, stride, pd, n_mpb, sh, r);
+    if (threadIdx.x == 0) { scal[S_PMAX] = r[0]; scal[S_C1] = r[1]; scal[S_C2] = r[2]; scal[S_DEM] = r[3]; }
 }
 
 // Per bending evaluation: partials of c1 and c2 of the bending term, whose Laplacian is linear
 // in the CPs.
-__global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const double *__restrict__ beD, const double *__restrict__ p,
-                                                         double *partials, int stride) {
+__device__ __forceinline__ void ls_bend_block(const DevSheet &S, const double *__restrict__ beD, const double *__restrict__ p,
+                                              double *partials, int stride, int blk) {
     __shared__ double sh[kBlock / 64];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blk * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
     double c1 = 0.0, c2 = 0.0;
     if (q < S.n_be) {
@@ -847,14 +874,19 @@ __global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const doubl
     }
     c1 = block_sum(c1, sh);
     c2 = block_sum(c2, sh);
-    if (threadIdx.x == 0) { partials[blockIdx.x] = c1; partials[stride + blockIdx.x] = c2; }
+    if (threadIdx.x == 0) { partials[blk] = c1; partials[stride + blk] = c2; }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const double *__restrict__ beD, const double *__restrict__ p,
+                                                         double *partials, int stride) {
+    ls_bend_block(S, beD, p, partials, stride, blockIdx.x);
 }
 
 // Membrane energy difference sum_q w (Psi(F + alpha dF) - Psi(F)) in double.
-__global__ void __launch_bounds__(kBlock) k_ls_membrane(DevSheet S, const double *__restrict__ x, const double *__restrict__ p,
-                                                        double alpha, double *partials) {
+__device__ __forceinline__ void ls_membrane_block(const DevSheet &S, const double *__restrict__ x, const double *__restrict__ p,
+                                                  double alpha, double *partials, int blk) {
     __shared__ double sh[kBlock / 64];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blk * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
     double de = 0.0;
     if (q < S.n_mp) {
@@ -915,7 +947,27 @@ __global__ void __launch_bounds__(kBlock) k_ls_membrane(DevSheet S, const double
         de = S.mp_w[q] * dPsi;
     }
     const double s = block_sum(de, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[blk] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ls_membrane(DevSheet S, const double *__restrict__ x, const double *__restrict__ p,
+                                                        double alpha, double *partials) {
+    ls_membrane_block(S, x, p, alpha, partials, blockIdx.x);
+}
+
+// The line-search set-up in one launch, gated by the solve's done flag (the end of a PCG burst):
+// blocks [0, nbc) the CP terms, [nbc, nbc + nbb) the bending terms, the rest the membrane
+// energy difference at alpha = 1; each block writes the partial slot its own launch would.
+__global__ void __launch_bounds__(kBlock) k_ls_setup(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
+                                                     const double *__restrict__ p, double inv_dt2, double gx, double gy,
+                                                     double gz, double *pa, int stride, double *__restrict__ pmax_part,
+                                                     const double *__restrict__ beD, double *pbend, double *pmem, int nbc, int nbb,
+                                                     const int32_t *__restrict__ gate) {
+    if (!gate[I_DONE]) return;
+    const int b = blockIdx.x;
+    if (b < nbc) ls_cp_block(S, x, xhat, p, inv_dt2, gx, gy, gz, pa, stride, pmax_part, b);
+    else if (b < nbc + nbb) ls_bend_block(S, beD, p, pbend, stride, b - nbc);
+    else ls_membrane_block(S, x, p, 1.0, pmem, b - nbc - nbb);
 }
 
 __global__ void k_sum_into(const double *__restrict__ p, int n, double *scal, int slot) {
@@ -948,6 +1000,32 @@ __global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal,
 __global__ void k_update(int n, double alpha, const double *__restrict__ p, double *__restrict__ x) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) x[t] += alpha * p[t];
+}
+
+// The line search's first trial on the device, at the end of the burst in which the solve
+// finished (gated by its done flag; not after a breakdown). Every block re-sums the line-search
+// partials in k_ls_finish's order (block 0 stores the scalars), so every thread takes the same
+// decision: dE(1) = (c1 + c2 / 2) + dE_membrane in the host's order and rounding. A direction
+// below the stagnation scale (|p|_inf <= stag |x0|_inf, when stag > 0) leaves x untouched (flag
+// 2); dE(1) finite and <= 0 applies x += p, the same update as k_update with alpha = 1 (flag 1);
+// otherwise x is untouched (flag 0) and the host halves alpha.
+__global__ void __launch_bounds__(kBlock) k_ls_accept(int n, int32_t *isc, double *scal, const double *__restrict__ pm,
+                                                      int n_cpb, const double *__restrict__ pa, const double *__restrict__ pb,
+                                                      int n_beb, int stride, const double *__restrict__ pd, int n_mpb,
+                                                      const double *__restrict__ p, double *__restrict__ x, double stag) {
+    __shared__ double sh[kBlock / 64];
+    if (!isc[I_DONE] || isc[I_BREAK]) return;
+    double r[4];
+    ls_sums(pm, n_cpb, pa, pb, n_beb, stride, pd, n_mpb, sh, r);
+    const double dE = __dadd_rn(__dadd_rn(r[1], __dmul_rn(0.5, r[2])), r[3]);
+    int d = (std::isfinite(dE) && dE <= 0.0) ? 1 : 0;
+    if (stag > 0.0 && r[0] <= stag * scal[S_XMAX]) d = 2;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d == 1 && t < n) x[t] += 1.0 * p[t];
+    if (t == 0) {
+        scal[S_PMAX] = r[0]; scal[S_C1] = r[1]; scal[S_C2] = r[2]; scal[S_DEM] = r[3];
+        isc[I_LSACC] = d;
+    }
 }
 
 // dE(alpha) = alpha c1 + alpha^2 c2 / 2 + (membrane difference at alpha), the line search's
@@ -1044,6 +1122,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const bool deferred = step_rule;
     const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !warm;
     bsc_step_stats s{};
+    double ls_in_bursts = 0.0;   // line-search kernels timed inside the PCG bursts (moved from ms_pcg)
     auto t_start = std::chrono::steady_clock::now();
     // Phase timing: events from a pool, recorded as the step goes and read once at its end (a
     // read in the middle of the step would wait for the event and delay the next launch).
@@ -1128,6 +1207,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     if (o->start == BSC_START_PREDICTOR)
         HIPX(hipMemcpyAsync(x, B.xhat, 8 * size_t(n3), hipMemcpyDeviceToDevice, st), "predictor start");
     if (npins > 0) k_apply_pins<<<blocks(npins), kBlock, 0, st>>>(S.n_cp, npins, B.pin_idx, pin_tgt, x);
+    // the recycled warm start draws on the directions of this step only: its first Newton
+    // iteration sees p = 0 and starts from zero (a new step solves for a new inertia term)
+    if (o->warm_start == BSC_WARM_PREVIOUS) k_zero<<<blocks(n3), kBlock, 0, st>>>(n3, B.dir);
     // |x0|_inf: the scale below which a Newton update only moves x by rounding
     k_absmax_part<<<kReduceBlocks, kBlock, 0, st>>>(n3, x, B.partials + 7 * stride);
     k_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, kReduceBlocks, 1, B.scalars, S_XMAX);
@@ -1229,7 +1311,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             enqueue_init(st, ph);
             return hipGetLastError();
         };
-        int32_t flags[7] = {0, 0, 0, 0, 0, 0, 0};
+        int32_t flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         // a chunk: 8 fused block-Jacobi CG launches (even: every chunk starts on an odd launch),
         // or one multigrid-preconditioned CG iteration
         const int chunk = use_mg ? 1 : 8;
@@ -1273,10 +1355,39 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             }
             return gxe;
         };
+        // Gradient rule, plain launches: every burst ends with the line-search set-up and the
+        // trial at alpha = 1, gated by the solve's done flag (they exit at once while the solve
+        // runs), so that the burst that finishes the solve also returns |p|_inf, the energy
+        // difference and the decision, and x is updated without a host round trip.
+        const bool ls_dev = !deferred && !use_mg && !ctx->use_graphs;
+        double *pa = B.partials + 3 * stride, *pbend = B.partials + 5 * stride;
+        // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at 7; the
+        // membrane difference at 0, free once PCG has finished)
+        auto enqueue_ls = [&](hipStream_t cs) {
+            k_ls_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
+                                                        B.partials + 7 * stride);
+            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pbend, stride);
+            k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials);
+            k_ls_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pbend, blocks(S.n_be), stride,
+                                               B.partials, blocks(S.n_mp), B.scalars);
+        };
         auto launch_burst = [&](int K) -> hipError_t {
-            hipGraphExec_t gx = graph_for(K);
-            if (gx) return hipGraphLaunch(gx, st);
+            hipGraphExec_t ge = graph_for(K);
+            if (ge) return hipGraphLaunch(ge, st);
             for (int bi = 0; bi < K; ++bi) enqueue_chunk(st);
+            if (ls_dev) {
+                hipEvent_t la = rec();
+                const int nbc_ = blocks(S.n_cp), nbb_ = blocks(S.n_be), nbm_ = blocks(S.n_mp);
+                k_ls_setup<<<nbc_ + nbb_ + nbm_, kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
+                                                                  B.partials + 7 * stride, B.beD, pbend, B.partials, nbc_, nbb_,
+                                                                  B.iscalars);
+                k_ls_accept<<<blocks(n3), kBlock, 0, st>>>(n3, B.iscalars, B.scalars, B.partials + 7 * stride, nbc_, pa, pbend,
+                                                           nbb_, stride, B.partials, nbm_, B.dir, x,
+                                                           o->fixed_newton_iters <= 0 ? kStagnation : 0.0);
+                hipEvent_t lb = rec();
+                span(la, lb, &s.ms_linesearch);
+                span(la, lb, &ls_in_bursts);
+            }
             if (pub) publish(st);
             return hipGetLastError();
         };
@@ -1390,7 +1501,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             burst_pending = false;
             span(c0, rec(), &s.ms_cg_kernels);
             HIPX(pub ? wait_pub(last) : copy_sync(), "read cg state");
-            for (int k = 0; k < 7; ++k) flags[k] = hf[k];
+            for (int k = 0; k < 8; ++k) flags[k] = hf[k];
             const double *cgs = hs;
             s.cg_launches += chunk * burst;
             if (flags[I_DONE]) break;
@@ -1433,28 +1544,21 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
         // ---- |p|_inf for the stop tests, line-search coefficients and the trial at alpha = 1 ---
         // The energy difference along p: the inertia, gravity and bending terms are quadratics in
-        // alpha (coefficients c1, c2), the membrane term is summed point by point.
-        hipEvent_t e4 = rec(), e5 = nullptr;
-        {
-            double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
+        // alpha (coefficients c1, c2), the membrane term is summed point by point. With ls_dev they
+        // ran at the end of the last burst and the scalars are already here.
+        if (!ls_dev) {
+            hipEvent_t e4 = rec();
             const int32_t last = seen();
-            // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at 7; the
-            // membrane difference at 0, free once PCG has finished)
-            k_ls_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride, B.partials + 7 * stride);
-            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, B.dir, pb, stride);
-            k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, st>>>(S, x, B.dir, 1.0, B.partials);
-            k_ls_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
-                                              B.partials, blocks(S.n_mp), B.scalars);
+            enqueue_ls(st);
             if (pub) publish(st);
             HIPX(hipGetLastError(), "line search setup");
-            e5 = rec();
+            span(e4, rec(), &s.ms_linesearch);
             HIPX(pub ? wait_pub(last) : copy_sync(), "read scalars");
         }
         double sc[S_GPREV - S_E + 1];
         for (int k = S_E; k <= S_GPREV; ++k) sc[k - S_E] = hs[k];
         if (deferred) span(e0, e1, &s.ms_assemble);
         span(e2, e3, &s.ms_pcg);
-        span(e4, e5, &s.ms_linesearch);
         auto scal = [&](int i) { return sc[i - S_E]; };
         if (deferred) {
             const double E = scal(S_E), gn = std::sqrt(scal(S_GG));
@@ -1472,6 +1576,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // cannot improve x any further (e.g. a sheet at rest without forces, whose gradient is
         // rounding alone); the step has converged
         if (!step_rule && o->fixed_newton_iters <= 0 && scal(S_PMAX) <= kStagnation * hs[S_XMAX]) break;
+        // the device's trial at alpha = 1 was accepted and applied (else x is untouched and the
+        // host halves alpha below, from the same scalars)
+        if (ls_dev && flags[I_LSACC] == 1) continue;
 
         // ---- backtracking line search on the energy difference ------------------------------
         {
@@ -1509,6 +1616,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
         else (void)hipGetLastError();
     }
+    s.ms_pcg -= ls_in_bursts;
+    s.ms_cg_kernels -= ls_in_bursts;
     s.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (stats) *stats = s;
     return result;
