@@ -344,11 +344,41 @@ __device__ double forcing_term(int mode, int first, double eta_host, double rtol
     return fmin(eta_max, fmax(rtol_min, e));
 }
 
+// The warm start's decision, made by every block of the CG initialisation alike: the sums of
+// the four partial arrays of the SpMV with the prediction p (one wave per array: lane l sums
+// entries l, l + 64, ... in order, then the butterfly sum) give gp = g.p, pw = p.Hp, gw = g.Hp,
+// ww = |Hp|^2; with bb = |g|^2 the energy-optimal multiple a = -gp / pw (either sign) gives the
+// initial residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g. The start x0 = a p is kept
+// only when that is below bb (the zero start's residual), else a = 0. Needs 256 threads.
+static_assert(kBlock == 256, "the warm start's decision takes one wave per partial array");
+__device__ double ws_decide(const double *__restrict__ part, int stride, int nb, double bb, double tot[4]) {
+    __shared__ double sm[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int t = lane; t < nb; t += 64) s += part[w * stride + t];
+    s = wave_sum_all(s);
+    if (lane == 0) sm[w] = s;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k] = sm[k];
+    const double gp = tot[0], pw = tot[1], gw = tot[2], ww = tot[3];
+    double a = 0.0;
+    if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw) && std::isfinite(gw) && std::isfinite(ww)) {
+        const double as = -gp / pw;
+        const double rr = bb + 2.0 * as * gw + as * as * ww;
+        if (as != 0.0 && rr < bb) a = as;
+    }
+    return a;
+}
+
 // r = b - A x0, p = s = 0; per-block partials of b.b; the solve's tolerance. Without a warm
 // start (ph null) x0 = 0 (set by the prep kernel) and r = b. With one, x0 = a ph and A x0 = a hq
-// for the multiple a at S_WSA that k_ws_finish decided (a = 0: x0 = 0 and r = b exactly).
+// for the multiple a that every block decides from the partials wpart of the product hq = H ph
+// (a = 0: x0 = 0 and r = b exactly); block 0 stores the dots at S_WS0..3, a at S_WSA and the
+// flag I_WS.
 __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ ph,
-                                                    const double *__restrict__ hq, double *__restrict__ x0,
+                                                    const double *__restrict__ hq, const double *__restrict__ wpart,
+                                                    int wstride, int wnb, double *__restrict__ x0,
                                                     double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
                                                     int eta_mode, int first, double eta_host, double rtol_min,
@@ -359,7 +389,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__
     // the gradient stop (below) is known to every thread: a solve that will not run keeps x0 = 0
     const double gn0 = sqrt(scal[S_GG]);
     const bool gstop = grad_rtol > 0.0 && (gn0 == 0.0 || (!first && gn0 <= grad_rtol * scal[S_G0]));
-    const double ws = ph && !gstop ? scal[S_WSA] : 0.0;
+    double ws = 0.0;
+    if (ph && !gstop) {                          // uniform over the block
+        double tot[4];
+        ws = ws_decide(wpart, wstride, wnb, scal[S_GG], tot);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) scal[S_WS0 + k] = tot[k];
+        }
+    }
+    if (ph && blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_WSA] = ws;
+        isc[I_WS] = ws != 0.0 ? 1 : 0;
+    }
     double bb = 0.0;
     if (a < S.n_cp) {
         for (int c = 0; c < 3; ++c) {
@@ -731,38 +773,6 @@ __global__ void k_phat(int n_cp, const float *__restrict__ out, const int32_t *_
     if (a >= n_cp) return;
     const bool pinned = pinmask[a] != 0;
     for (int c = 0; c < 3; ++c) ph[c * n_cp + a] = pinned ? 0.0 : double(out[c * n_cp + a]);
-}
-
-// The warm start's decision, on the device: the sums of the four partial arrays (fixed order)
-// give gp = g.p, pw = p.Hp, gw = g.Hp, ww = |Hp|^2 (stored at S_WS0..3); with bb = |g|^2 the
-// energy-optimal multiple a = -gp / pw of the prediction p (either sign) gives the initial
-// residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g. The start x0 = a p is kept only when
-// that is below bb (the zero start's residual), else a = 0. S_WSA receives a, the flag I_WS
-// whether the start was kept.
-// One wave per partial array (launched with 256 threads): lane l sums entries l, l + 64, ... in
-// order, then the butterfly sum; the result does not depend on timing.
-__global__ void __launch_bounds__(256) k_ws_finish(const double *__restrict__ part, int stride, int nb, double *scal,
-                                                  int32_t *isc) {
-    __shared__ double tot[4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double s = 0.0;
-    for (int t = lane; t < nb; t += 64) s += part[w * stride + t];
-    s = wave_sum_all(s);
-    if (lane == 0) {
-        tot[w] = s;
-        scal[S_WS0 + w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const double gp = tot[0], pw = tot[1], gw = tot[2], ww = tot[3], bb = scal[S_GG];
-    double a = 0.0;
-    if (pw > 0.0 && std::isfinite(gp) && std::isfinite(pw) && std::isfinite(gw) && std::isfinite(ww)) {
-        const double as = -gp / pw;
-        const double rr = bb + 2.0 * as * gw + as * as * ww;
-        if (as != 0.0 && rr < bb) a = as;
-    }
-    scal[S_WSA] = a;
-    isc[I_WS] = a != 0.0 ? 1 : 0;
 }
 
 // ---- line search -------------------------------------------------------------------------
@@ -1269,7 +1279,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                                      keep);
         };
         // warm start from the prediction ph: H ph into hq with the partials of its four dot
-        // products, then their sums and the decision, all on the device (k_cg_init applies it)
+        // products (k_cg_init sums them, decides and applies the start, all on the device)
         auto enqueue_warm = [&](hipStream_t cs, const double *ph) {
             const int nb = spmv_blocks(S.n_cp);
             if (prec == BSC_FP64)
@@ -1278,13 +1288,13 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             else
                 k_spmv_tile<float, true><<<nb, kRowsPerTile * kGroups, 0, cs>>>(S, (const float *)B.hess, ph, hq, B.g,
                                                                                B.partials + 4 * stride, stride);
-            k_ws_finish<<<1, 256, 0, cs>>>(B.partials + 4 * stride, stride, nb, B.scalars, B.iscalars);
         };
         // r = b - A x0 (x0 = a ph with the decided multiple, when ph is given), the tolerance, and
         // the first CG launch (it forms w_0)
         auto enqueue_init = [&](hipStream_t cs, const double *ph) {
-            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, ph, hq, B.dir, rb[0], p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg,
-                                               eta_mode, first, eta_arg, o->pcg_rtol, eta_max, grad_rtol);
+            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, ph, hq, B.partials + 4 * stride, stride, spmv_blocks(S.n_cp), B.dir, rb[0],
+                                               p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode, first, eta_arg,
+                                               o->pcg_rtol, eta_max, grad_rtol);
             if (prec == BSC_FP64)
                 k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
             else
@@ -1482,7 +1492,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             // tolerance from the partials of |b|^2)
             enqueue_prep(st);
             HIPX(mg_setup(S, B, prec, st), "mg setup");
-            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
+            k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, 0, 0, nullptr, rb[0], p, sb[0], pbb, B.iscalars, B.scalars,
                                                o->max_pcg, eta_mode, first, eta_arg, o->pcg_rtol, eta_max, 0.0);
             HIPX(hipGetLastError(), "mg init");
         } else {
@@ -1666,7 +1676,7 @@ bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, doubl
         k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir, nullptr);
     else
         k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir, nullptr);
-    k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
+    k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, 0, 0, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
                                        ETA_EXPLICIT, 1, rtol, rtol, rtol, 0.0);
     fused(0);
     HIPX(hipGetLastError(), "stencil pcg");
