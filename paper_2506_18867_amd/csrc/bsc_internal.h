@@ -318,6 +318,28 @@ size_t contact_tmp_bytes(int max_pairs, int max_vpairs);
 void host_pieces(int type, double t, double N[3], double D[3], double D2[3]);
 DevSheet dev_sheet(const bsc_ctx *ctx);
 
+// Read-back into host-mapped pinned memory: the scalars and the first 8 flags, then the next
+// sequence number (kept in the device flags) stored with system-scope release, on which the host
+// spins. Run by one block (at least kScalars threads) once the values it copies are final in the
+// block's view; every thread of the block calls it.
+struct PubPtrs {
+    double *hs;          // host copy of the scalars
+    int32_t *hf;         // host copy of the flags
+    int32_t *hseq;       // host sequence number
+};
+__device__ __forceinline__ void publish_block(const double *scal, int32_t *flags, const PubPtrs &P) {
+    const int t = threadIdx.x;
+    if (t < kScalars) P.hs[t] = scal[t];
+    if (t < 8) P.hf[t] = flags[t];
+    const int32_t seq = flags[I_PUBSEQ] + 1;
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) {
+        flags[I_PUBSEQ] = seq;
+        __hip_atomic_store(P.hseq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // ---- launchers (eval.hip) ----
 // Membrane points (w Psi, w P and, with hess, w A+), bending evaluations; element gather;
 // tiled assembly of the per-CP gradient and (hess != NULL) the upper-stencil Hessian blocks
@@ -332,7 +354,7 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const 
                            double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st,
                            bool gnorm = false);
 hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out,
-                                hipStream_t st, double *out_gg = nullptr);
+                                hipStream_t st, double *out_gg = nullptr, const PubPtrs *pub = nullptr);
 hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,
                        hipStream_t st);
 

@@ -926,10 +926,13 @@ __global__ void __launch_bounds__(kBlock) k_elem_grad(DevSheet S, const T *__res
 
 // Sums three partial arrays in a fixed order into out[0] (the energy) and, if pg is given, the
 // partials pg (|g|^2 of the assembly tiles) into out_g[0].
+// With pub, the solver scalars (scal, which holds out and out_g) and flags are then read back to
+// the host in the same launch.
 __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ p0, int n0, const double *__restrict__ p1,
                                                    int n1, const double *__restrict__ p2, int n2,
                                                    double *__restrict__ out, const double *__restrict__ pg, int ng,
-                                                   double *__restrict__ out_g) {
+                                                   double *__restrict__ out_g, const double *scal, int32_t *flags,
+                                                   PubPtrs pub, int do_pub) {
     __shared__ double sh[kBlock / 64];
     double v = 0.0;
     for (int t = threadIdx.x; t < n0; t += blockDim.x) v += p0[t];
@@ -942,6 +945,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ p0
         for (int t = threadIdx.x; t < ng; t += blockDim.x) u += pg[t];
         const double sg = block_sum(u, sh);
         if (threadIdx.x == 0) out_g[0] = sg;
+    }
+    if (do_pub) {
+        __syncthreads();
+        publish_block(scal, flags, pub);
     }
 }
 
@@ -1025,10 +1032,12 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const 
 }
 
 hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out, hipStream_t st,
-                                double *out_gg) {
+                                double *out_gg, const PubPtrs *pub) {
+    static_assert(kBlock >= kScalars, "the read-back copies one scalar per thread");
     k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
                                    B.partials + 2 * B.max_blocks, n_cp_partials, out,
-                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_cp_partials, out_gg);
+                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_cp_partials, out_gg, B.scalars,
+                                   B.iscalars, pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -993,18 +993,8 @@ __global__ void k_sum_into(const double *__restrict__ p, int n, double *scal, in
 // next sequence number (kept in the device flags, so that the kernel can sit in a replayed
 // graph) behind a system-scope fence. The host polls that number instead of waiting for a
 // stream synchronisation, which wakes it sooner.
-__global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal, int32_t *__restrict__ flags,
-                                                double *host_scal, int32_t *host_flags, int32_t *host_seq) {
-    const int t = threadIdx.x;
-    if (t < kScalars) host_scal[t] = scal[t];
-    if (t < 8) host_flags[t] = flags[t];
-    const int32_t seq = flags[I_PUBSEQ] + 1;
-    __threadfence_system();
-    __syncthreads();
-    if (t == 0) {
-        flags[I_PUBSEQ] = seq;
-        __hip_atomic_store(host_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+__global__ void __launch_bounds__(64) k_publish(const double *__restrict__ scal, int32_t *__restrict__ flags, PubPtrs P) {
+    publish_block(scal, flags, P);
 }
 
 __global__ void k_update(int n, double alpha, const double *__restrict__ p, double *__restrict__ x) {
@@ -1018,23 +1008,30 @@ __global__ void k_update(int n, double alpha, const double *__restrict__ p, doub
 // decision: dE(1) = (c1 + c2 / 2) + dE_membrane in the host's order and rounding. A direction
 // below the stagnation scale (|p|_inf <= stag |x0|_inf, when stag > 0) leaves x untouched (flag
 // 2); dE(1) finite and <= 0 applies x += p, the same update as k_update with alpha = 1 (flag 1);
-// otherwise x is untouched (flag 0) and the host halves alpha.
+// otherwise x is untouched (flag 0) and the host halves alpha. With do_pub, block 0 then
+// publishes the scalars and flags to the host (gate open or not): the burst's read-back.
 __global__ void __launch_bounds__(kBlock) k_ls_accept(int n, int32_t *isc, double *scal, const double *__restrict__ pm,
                                                       int n_cpb, const double *__restrict__ pa, const double *__restrict__ pb,
                                                       int n_beb, int stride, const double *__restrict__ pd, int n_mpb,
-                                                      const double *__restrict__ p, double *__restrict__ x, double stag) {
+                                                      const double *__restrict__ p, double *__restrict__ x, double stag,
+                                                      PubPtrs pub, int do_pub) {
     __shared__ double sh[kBlock / 64];
-    if (!isc[I_DONE] || isc[I_BREAK]) return;
-    double r[4];
-    ls_sums(pm, n_cpb, pa, pb, n_beb, stride, pd, n_mpb, sh, r);
-    const double dE = __dadd_rn(__dadd_rn(r[1], __dmul_rn(0.5, r[2])), r[3]);
-    int d = (std::isfinite(dE) && dE <= 0.0) ? 1 : 0;
-    if (stag > 0.0 && r[0] <= stag * scal[S_XMAX]) d = 2;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d == 1 && t < n) x[t] += 1.0 * p[t];
-    if (t == 0) {
-        scal[S_PMAX] = r[0]; scal[S_C1] = r[1]; scal[S_C2] = r[2]; scal[S_DEM] = r[3];
-        isc[I_LSACC] = d;
+    if (isc[I_DONE] && !isc[I_BREAK]) {
+        double r[4];
+        ls_sums(pm, n_cpb, pa, pb, n_beb, stride, pd, n_mpb, sh, r);
+        const double dE = __dadd_rn(__dadd_rn(r[1], __dmul_rn(0.5, r[2])), r[3]);
+        int d = (std::isfinite(dE) && dE <= 0.0) ? 1 : 0;
+        if (stag > 0.0 && r[0] <= stag * scal[S_XMAX]) d = 2;
+        const int t = blockIdx.x * blockDim.x + threadIdx.x;
+        if (d == 1 && t < n) x[t] += 1.0 * p[t];
+        if (t == 0) {
+            scal[S_PMAX] = r[0]; scal[S_C1] = r[1]; scal[S_C2] = r[2]; scal[S_DEM] = r[3];
+            isc[I_LSACC] = d;
+        }
+    }
+    if (do_pub && blockIdx.x == 0) {
+        __syncthreads();
+        publish_block(scal, isc, pub);
     }
 }
 
@@ -1096,7 +1093,7 @@ struct Timer {
 
 // Assembles E, g (double), |g|^2 and H (working precision) at x for one Newton iteration.
 bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *xhat, double inv_dt2, const double *grav,
-                         hipStream_t st) {
+                         hipStream_t st, const PubPtrs *pub) {
     const DevSheet &S = ctx->dev;
     const DevBufs &B = ctx->buf;
     // FP32-mixed: the points in FP64 arithmetic, the Hessian stored in FP32 and the stresses (for
@@ -1105,7 +1102,7 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     else HIPX(launch_points_mixed(S, B, x, st), "points");
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
     HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st, true), "assemble");
-    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG), "energy");
+    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG, pub), "energy");
     return BSC_OK;
 }
 
@@ -1131,6 +1128,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const int warm = o->warm_start;
     const bool deferred = step_rule;
     const bool use_mg = o->preconditioner == BSC_PRECOND_MULTIGRID && B.mg_levels > 0 && !warm;
+    // gradient rule (no multigrid): the PCG set-up follows the assembly without a host decision
+    // (below), and the assembly's reduction publishes E and |g| in the same launch
+    const bool early = !deferred && !use_mg;
     bsc_step_stats s{};
     double ls_in_bursts = 0.0;   // line-search kernels timed inside the PCG bursts (moved from ms_pcg)
     auto t_start = std::chrono::steady_clock::now();
@@ -1183,9 +1183,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     int32_t *hseq = (int32_t *)(ctx->pinned + 8 * kScalars + 64);
     const bool pub = ctx->pinned_dev != nullptr;
     auto seen = [&]() { return __atomic_load_n(hseq, __ATOMIC_ACQUIRE); };
+    const PubPtrs pubp{(double *)ctx->pinned_dev, (int32_t *)(ctx->pinned_dev + 8 * kScalars),
+                       (int32_t *)(ctx->pinned_dev + 8 * kScalars + 64)};
     auto publish = [&](hipStream_t cs) {
-        k_publish<<<1, 64, 0, cs>>>(B.scalars, B.iscalars, (double *)ctx->pinned_dev, (int32_t *)(ctx->pinned_dev + 8 * kScalars),
-                                    (int32_t *)(ctx->pinned_dev + 8 * kScalars + 64));
+        k_publish<<<1, 64, 0, cs>>>(B.scalars, B.iscalars, pubp);
     };
     auto copy_sync = [&]() -> hipError_t {
         hipError_t e = hipMemcpyAsync(ctx->pinned, B.scalars, 8 * kScalars + 4 * 8, hipMemcpyDeviceToHost, st);
@@ -1238,8 +1239,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // (plain launches: the sequences of a Newton iteration measured faster enqueued directly
         // than replayed as captured graphs, whose switches with plain launches on the stream each
         // cost a gap)
+        const int32_t last_asm = seen();
         {
-            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st);
+            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st, early && pub ? &pubp : nullptr);
             if (sa != BSC_OK) return sa;
         }
         hipEvent_t e1 = rec();
@@ -1393,12 +1395,13 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                                   B.iscalars);
                 k_ls_accept<<<blocks(n3), kBlock, 0, st>>>(n3, B.iscalars, B.scalars, B.partials + 7 * stride, nbc_, pa, pbend,
                                                            nbb_, stride, B.partials, nbm_, B.dir, x,
-                                                           o->fixed_newton_iters <= 0 ? kStagnation : 0.0);
+                                                           o->fixed_newton_iters <= 0 ? kStagnation : 0.0, pubp, pub ? 1 : 0);
                 hipEvent_t lb = rec();
                 span(la, lb, &s.ms_linesearch);
                 span(la, lb, &ls_in_bursts);
+            } else if (pub) {
+                publish(st);
             }
-            if (pub) publish(st);
             return hipGetLastError();
         };
         // Chunks are enqueued in bursts with one flag read per burst (launches after convergence
@@ -1416,7 +1419,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // first burst follows at once (speculative): the set-up marks the solve done on the device
         // when |g| already meets the stop, so a converged iterate costs only the set-up and a
         // burst of launches that exit; x is not touched.
-        const bool early = !deferred && !use_mg;
         hipEvent_t e2 = nullptr, burst_c0 = nullptr;
         bool burst_pending = false;
         int32_t burst_last = 0;
@@ -1424,8 +1426,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
             const bool speculate = o->stop_mode == BSC_STOP_GRAD && o->fixed_newton_iters <= 0 && it < o->max_newton;
             grad_rtol = speculate ? o->rtol : 0.0;
-            const int32_t last = seen();
-            if (pub) publish(st);
+            const int32_t last = last_asm;           // the assembly's reduction published E and |g|
             e2 = rec();
             HIPX(cg_setup(), "cg init");
             if (speculate) {
