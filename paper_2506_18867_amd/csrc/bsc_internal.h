@@ -122,15 +122,15 @@ struct DevSheet {
 #ifndef BSC_ASM_THREADS
 #define BSC_ASM_THREADS 512
 #endif
-// Dynamic LDS per assembly workgroup: two workgroups (plus their small static arrays) share
-// a CU's 160 KB.
-#ifndef BSC_ASM_LDS_KB
-#define BSC_ASM_LDS_KB 78
+// Dynamic LDS per assembly workgroup: two workgroups (plus their small static arrays, under
+// 256 bytes) share a CU's 160 KB.
+#ifndef BSC_ASM_LDS_BYTES
+#define BSC_ASM_LDS_BYTES (80 * 1024 - 256)
 #endif
 constexpr int kAsmTileU = BSC_ASM_TILE_U;
 constexpr int kAsmThreads = BSC_ASM_THREADS;
 enum AsmKind { kAsmF32 = 0, kAsmF64 = 1, kAsmMixed = 2 };   // (A, P, g) = (f, f, f), (d, d, d), (f, d, d)
-constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
+constexpr size_t kAsmLdsMax = BSC_ASM_LDS_BYTES;
 
 // LDS layout of one assembly tile (offsets in bytes): local membrane point offsets of the
 // (tx + 2) x (ty + 2) elements, the first global point of each element row, the work counter,
@@ -142,18 +142,20 @@ constexpr size_t kAsmLdsMax = BSC_ASM_LDS_KB * 1024;
 //     the FP32 Hessian), then in double for the FP64 gradient P (from float 44), the span
 //     coordinates tu, tv (from 56) and, for a general rest map, the inverse Jacobian K (from 60):
 //     kAsmRecM / kAsmRecMC floats.
-//   FP64 (kAsmF64, doubles): A (21), tu, tv (21, 22; the gradients are recomputed), K (23..26
-//     for a general rest map), P (6, after them): kAsmRecD / kAsmRecDC doubles.
-// The record lengths in 16-byte units are odd or twice odd, so the neighbouring records that
-// the lanes of a wave read fall on different LDS banks.
-constexpr int kAsmRecF = 52, kAsmRecM = 60, kAsmRecMC = 68, kAsmRecD = 29, kAsmRecDC = 33;
+//   FP64 (kAsmF64, doubles): everything in the span's parametric coordinates (u, v), where the
+//     gradient of basis function (a, b) is (Du[a] Nv[b], Nu[a] Dv[b]): the density Hessian
+//     congruent to A under the inverse Jacobian K (21), the 1-D factors Nu, Du, Nv, Dv (21..32)
+//     and the stress P K^T (6, from 33): kAsmRecD doubles, for any rest map.
+// The float record lengths in 16-byte units are odd or twice odd, so the neighbouring records
+// that the lanes of a wave read fall on different LDS banks.
+constexpr int kAsmRecF = 52, kAsmRecM = 60, kAsmRecMC = 68, kAsmRecD = 39;
 struct AsmLds {
     size_t el_off, rows, counter, rec, rec_bytes, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 __host__ __device__ inline size_t asm_rec_bytes(int kind, bool curved) {
     return kind == kAsmF32 ? 4 * kAsmRecF
-                           : (kind == kAsmMixed ? 4 * (curved ? kAsmRecMC : kAsmRecM) : 8 * (curved ? kAsmRecDC : kAsmRecD));
+                           : (kind == kAsmMixed ? 4 * (curved ? kAsmRecMC : kAsmRecM) : 8 * kAsmRecD);
 }
 __host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int kind, bool curved) {
     AsmLds L;
@@ -219,6 +221,7 @@ struct DevBufs {
     // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
     double *g, *xn, *xhat, *dir, *r, *p0, *p1, *q, *pinv, *tmp, *phat;
     double *pprev;                               // the previous Newton direction (recycled warm start)
+    double *gpre;                                // per-CP gradient terms of the assembly (bending, inertia, gravity)
     double *r2, *q2, *p2;                    // second halves of the CG double buffers
     void *hess;                              // kHessEntries n_cp doubles
     // warm-start network
@@ -340,20 +343,33 @@ __device__ __forceinline__ void publish_block(const double *scal, int32_t *flags
     }
 }
 
+// The per-CP terms of an assembly that need no quadrature point: the bending gradient K_b d, the
+// inertia M (x - xhat) / dt^2 (when xhat is given) and the gravity load -M g, summed into gpre
+// ([3][n_cp], double), with their energies.
+struct CpTerms {
+    const double *xhat;
+    double inv_dt2, gx, gy, gz;
+    double *gpre;
+};
+
 // ---- launchers (eval.hip) ----
-// Membrane points (w Psi, w P and, with hess, w A+), bending evaluations; element gather;
-// tiled assembly of the per-CP gradient and (hess != NULL) the upper-stencil Hessian blocks
-// (kind: AsmKind; gnorm: also per-tile partials of |g|^2); energy reduction (n_cp_partials: the
-// assembly's tile count, or 0; out_gg: where |g|^2 goes, from an assembly run with gnorm). The
-// mixed-precision Newton points: FP64 arithmetic, FP32 Hessian and FP64 stresses in one pass.
+// Membrane points (w Psi, w P and, with hess, w A+), bending evaluations and, with cpt, the
+// per-CP terms (their energy partials in partial array 2, cp_blocks of them); element gather;
+// tiled assembly, after a points pass with cpt, of the per-CP gradient (membrane stresses plus
+// B.gpre) and (hess != NULL) the upper-stencil Hessian blocks (kind: AsmKind; gnorm: also
+// per-tile partials of |g|^2); energy reduction (n_cp_partials: cp_blocks after a points pass
+// with cpt, else 0; n_gg_partials: the tile count of an assembly run with gnorm, summed into
+// out_gg; with pub the solver scalars and flags are then published to the host in the same
+// launch). The mixed-precision Newton points: FP64 arithmetic, FP32 Hessian and FP64 stresses
+// in one pass.
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
-                         const double *x, hipStream_t st, bool bending);
-hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st);
+                         const double *x, hipStream_t st, bool bending, const CpTerms *cpt = nullptr);
+hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st, const CpTerms *cpt);
 int assemble_tiles(const DevSheet &S, int kind);
-hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
-                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st,
-                           bool gnorm = false);
-hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out,
+int cp_blocks(const DevSheet &S);
+hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
+                           hipStream_t st, bool gnorm = false);
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, int n_gg_partials, double *out,
                                 hipStream_t st, double *out_gg = nullptr, const PubPtrs *pub = nullptr);
 hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,
                        hipStream_t st);

@@ -535,24 +535,103 @@ __device__ __forceinline__ double bending_point(const DevSheet &S, const double 
     return e_loc;
 }
 
-// The membrane points and the bending evaluations in one launch: blocks [0, nbm) take membrane
-// points, the rest bending evaluations; each block writes the sum of its energies to its own
-// partial slot (membrane: pm[block], bending: pb[block - nbm]), so the sums keep the order of
-// separate launches. The two parts are independent, and one grid lets the light bending blocks
-// fill the slots that the register-heavy membrane blocks leave free.
+// Displacement component c of CP (i, j) from its rest position (the component of
+// displacement_t, in the same arithmetic).
+template <bool CURVED>
+__device__ __forceinline__ double displacement_c(const DevSheet &S, const double *__restrict__ x, int i, int j, int c) {
+    const int a = j * S.n_u + i;
+    double X = 0.0;
+    if (c < 2) {
+        if (CURVED) {
+            X = S.rest[c * S.n_cp + a];
+        } else {
+            const double gu = greville(i, S.n_u), gv = greville(j, S.n_v);
+            X = c == 0 ? S.A00 * gu + S.A01 * gv + S.b0 : S.A10 * gu + S.A11 * gv + S.b1;
+        }
+    }
+    return x[size_t(c) * S.n_cp + a] - X;
+}
+
+// The per-CP gradient terms that need no quadrature point, for CP a: the bending energy is
+// quadratic in the displacement d = x - X and zero at rest, so its gradient is exactly K_b d, the
+// constant bending stencil (a scalar times I3 per block, built at create from the same bending
+// evaluations) over the 25 neighbours; then the inertia M (x - xhat) / dt^2 and the gravity load
+// -M g (Sec. 3.2, the incremental potential). Returns the CP's inertia and gravity energy. Every
+// neighbour is read (an absent one reads CP a and its term is discarded by a select), so the
+// loads carry no branches and issue in a few batches.
+template <bool CURVED>
+__device__ __forceinline__ double cp_terms(const DevSheet &S, const double *__restrict__ x, const CpTerms &C, int a) {
+    double e_loc = 0.0;
+    if (a < S.n_cp) {
+        const size_t ncp = S.n_cp;
+        const int i = a % S.n_u, j = a / S.n_u;
+        double accb[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int s2 = 0; s2 < kSlots; ++s2) {
+            const int di = slot_di(s2), dj = slot_dj(s2);
+            const int ib = i + di, jb = j + dj;
+            const bool okb = ib >= 0 && ib < S.n_u && jb < S.n_v;
+            const double w = S.hbend[s2 * ncp + a];
+            double d[3];
+            displacement_t<CURVED>(S, x, okb ? ib : i, okb ? jb : j, d);
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) accb[cc] += okb ? w * d[cc] : 0.0;
+            if (s2 == 0) continue;
+            const int ic = i - di, jc = j - dj;
+            const bool okc = ic >= 0 && ic < S.n_u && jc >= 0;
+            const double w2 = S.hbend[s2 * ncp + (okc ? jc * S.n_u + ic : a)];
+            displacement_t<CURVED>(S, x, okc ? ic : i, okc ? jc : j, d);
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) accb[cc] += okc ? w2 * d[cc] : 0.0;
+        }
+        const double M = S.mass[a];
+        const double grav[3] = {C.gx, C.gy, C.gz};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            double gs = accb[cc];
+            const double xc = x[cc * ncp + a];
+            if (C.xhat) {
+                const double dlt = xc - C.xhat[cc * ncp + a];
+                gs += M * C.inv_dt2 * dlt;
+                e_loc += 0.5 * M * C.inv_dt2 * dlt * dlt;
+            }
+            gs -= M * grav[cc];
+            e_loc -= M * grav[cc] * xc;
+            C.gpre[cc * ncp + a] = gs;
+        }
+    }
+    return e_loc;
+}
+
+// The per-CP terms, the membrane points and the bending evaluations in one launch: blocks
+// [0, ncb) take CPs (ncb = 0 without them), the next nbm membrane points, the rest bending
+// evaluations; each block writes the sum of its energies to its own partial slot (CPs:
+// pc[block], membrane: pm[block - ncb], bending: pb[block - ncb - nbm]), so the sums keep the
+// order of separate launches. The parts are independent, and one grid lets the light bending
+// and CP blocks fill the slots that the register-heavy membrane blocks leave free; the CP
+// blocks, bound by the latency of their neighbour loads, come first so that it overlaps the rest.
 template <typename T, bool HESS, bool CURVED, typename TA = T, typename TP = T, bool BEND = true>
 __global__ void __launch_bounds__(kBlock) k_points(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
                                                    TP *__restrict__ ptP, double *__restrict__ ptE,
                                                    double *__restrict__ pm, double *__restrict__ beD,
-                                                   double *__restrict__ beE, double *__restrict__ pb, int nbm) {
+                                                   double *__restrict__ beE, double *__restrict__ pb, int ncb, int nbm,
+                                                   CpTerms C, double *__restrict__ pc) {
     __shared__ double sh[kBlock / 64];
-    const bool mem = !BEND || int(blockIdx.x) < nbm;
-    const int blk = mem ? int(blockIdx.x) : int(blockIdx.x) - nbm;
+    const int b = int(blockIdx.x);
+    const int role = b < ncb ? 2 : (b < ncb + nbm ? 0 : 1);
+    const int blk = role == 2 ? b : (role == 0 ? b - ncb : b - ncb - nbm);
     const int q = blk * kBlock + threadIdx.x;
-    const double e_loc = mem ? membrane_point<T, HESS, CURVED, TA, TP>(S, x, ptA, ptP, ptE, q)
-                             : bending_point<CURVED>(S, x, beD, beE, q);
+    double e_loc;
+    if (role == 0) {
+        e_loc = membrane_point<T, HESS, CURVED, TA, TP>(S, x, ptA, ptP, ptE, q);
+    } else if (role == 1) {
+        if constexpr (BEND) e_loc = bending_point<CURVED>(S, x, beD, beE, q);
+        else e_loc = 0.0;
+    } else {
+        e_loc = cp_terms<CURVED>(S, x, C, q);
+    }
     const double s = block_sum(e_loc, sh);
-    if (threadIdx.x == 0) (mem ? pm : pb)[blk] = s;
+    if (threadIdx.x == 0) (role == 2 ? pc : (role == 0 ? pm : pb))[blk] = s;
 }
 
 // ---- stage 2, tiled: Hessian blocks from LDS, gradient ------------------------------------------
@@ -569,18 +648,18 @@ __global__ void __launch_bounds__(kBlock) k_points(DevSheet S, const double *__r
 // which wave takes it.
 template <typename TA, typename TP, typename TG, bool CURVED>
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int kind, const TA *__restrict__ ptA,
-                                                               const TP *__restrict__ ptP,
-                                                               const double *__restrict__ x, const double *__restrict__ xhat,
-                                                               double inv_dt2, double gx, double gy, double gz,
-                                                               TA *__restrict__ hess, TG *__restrict__ gout,
-                                                               double *__restrict__ partials, double *__restrict__ gg_partials) {
+                                                               const TP *__restrict__ ptP, const double *__restrict__ gpre,
+                                                               double inv_dt2, TA *__restrict__ hess, TG *__restrict__ gout,
+                                                               double *__restrict__ gg_partials) {
     constexpr bool STAGE_DN = sizeof(TA) == 4;
     // kind of record (see AsmLds): FP32, mixed (float Hessian, double stress) or FP64
     constexpr int KIND = sizeof(TA) == 4 ? (sizeof(TP) == 4 ? kAsmF32 : kAsmMixed) : kAsmF64;
     constexpr int REC = KIND == kAsmF32 ? kAsmRecF
-                      : (KIND == kAsmMixed ? (CURVED ? kAsmRecMC : kAsmRecM) : (CURVED ? kAsmRecDC : kAsmRecD));
-    // offsets (units of TA) of the stress P and, in mixed records, of the double tu, tv and K
-    constexpr int OFF_P = KIND == kAsmF64 ? (CURVED ? 27 : 23) : 44;
+                      : (KIND == kAsmMixed ? (CURVED ? kAsmRecMC : kAsmRecM) : kAsmRecD);
+    // offsets (units of TA) of the stress P (FP64: P K^T) and, in mixed records, of the double
+    // tu, tv and K; FP64 records hold the 1-D factors Nu, Du, Nv, Dv from OFF_N
+    constexpr int OFF_P = KIND == kAsmF64 ? 33 : 44;
+    constexpr int OFF_N = 21;
     constexpr int OFF_T = 56, OFF_K = 60;
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
@@ -598,6 +677,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     const int tx0 = (tile % ntx) * kAsmTileU;
     int ty0 = 0, h = 0;
     asm_tile_row(S.n_v, ty, tile / ntx, ty0, h);
+    const int R = kAsmTileU * h;                 // CPs of the tile (some past the sheet's edge)
     const int k0 = max(0, tx0 - 2), k1 = min(S.Nu - 1, tx0 + kAsmTileU - 1);
     const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + h - 1);
     const int nk = k1 - k0 + 1, nl = l1 - l0 + 1, ne = nk * nl;
@@ -656,16 +736,59 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                     }
                 }
             } else {
-                rec[21] = TA(tu);
-                rec[22] = TA(tv);
-                if constexpr (CURVED) {
-                    const PtK K = mp_geo_t<true>(S, q);
-                    rec[23] = K.k00; rec[24] = K.k01; rec[25] = K.k10; rec[26] = K.k11;
-                }
-            }
-            TP *pp = (TP *)(rec + OFF_P);
+                // FP64: the gradient with respect to X of basis function (a, b) is K^T ghat with
+                // ghat = (Du[a] Nv[b], Nu[a] Dv[b]) in the span's parameters, so the items' sums
+                // of ga^T A^(gamma delta) gb equal those of ghat_a^T Ahat ghat_b with Ahat the
+                // congruence (K x I3) A (K x I3)^T, and P dN = (P K^T) ghat: formed once per point
+                int kk = 0;
+                while (kk + 1 < nk && el_off[r * nk + kk + 1] <= t) ++kk;
+                double Nu[3], Du[3], Nv[3], Dv[3];
+                pieces<double>(span_type(k0 + kk, S.Nu), tu, Nu, Du);
+                pieces<double>(span_type(l0 + r, S.Nv), tv, Nv, Dv);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) pp[c] = ptP[c * S.n_mp + q];
+                for (int m = 0; m < 3; ++m) {
+                    rec[OFF_N + m] = Nu[m];
+                    rec[OFF_N + 3 + m] = Du[m];
+                    rec[OFF_N + 6 + m] = Nv[m];
+                    rec[OFF_N + 9 + m] = Dv[m];
+                }
+                const PtK K = mp_geo_t<CURVED>(S, q);
+                const double Kg[2][2] = {{K.k00, K.k01}, {K.k10, K.k11}};
+                if (hess) {
+                    double A6[21];
+#pragma unroll
+                    for (int c = 0; c < 21; ++c) A6[c] = rec[c];
+                    // Ahat[3g' + i][3d' + j] = sum_{g,d} K[g'][g] K[d'][d] A[3g + i][3d + j]
+#pragma unroll
+                    for (int R = 0; R < 6; ++R)
+#pragma unroll
+                        for (int C = R; C < 6; ++C) {
+                            const int gp = R / 3, i = R % 3, dp = C / 3, jc = C % 3;
+                            double v = 0.0;
+#pragma unroll
+                            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                                for (int d = 0; d < 2; ++d) {
+                                    const int r6 = 3 * g + i, c6 = 3 * d + jc;
+                                    v += Kg[gp][g] * Kg[dp][d] * A6[u6(r6, c6)];
+                                }
+                            rec[u6(R, C)] = v;
+                        }
+                }
+                TP *pp = (TP *)(rec + OFF_P);
+                double P6[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) P6[c] = ptP[c * S.n_mp + q];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int gp = 0; gp < 2; ++gp) pp[2 * i + gp] = Kg[gp][0] * P6[2 * i] + Kg[gp][1] * P6[2 * i + 1];
+            }
+            if constexpr (STAGE_DN) {
+                TP *pp = (TP *)(rec + OFF_P);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) pp[c] = ptP[c * S.n_mp + q];
+            }
         }
     }
     __syncthreads();
@@ -675,12 +798,11 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     constexpr unsigned long long kPacked = kO[0] | kO[1] << 4 | kO[2] << 8 | kO[3] << 12 | kO[4] << 16 | kO[5] << 20 |
                                            kO[6] << 24 | kO[7] << 28 | kO[8] << 32 | kO[9] << 36 | kO[10] << 40 |
                                            kO[11] << 44 | kO[12] << 48 | kO[13] << 52;
-    const int R = kAsmTileU * h;
     const int nitems = (hess ? kSlots + 1 : 1) * R;
     const int nchunks = (nitems + 63) / 64;
     const size_t ncp = S.n_cp;
     const int lane = threadIdx.x & 63;
-    double e_loc = 0.0, gg_loc = 0.0;
+    double gg_loc = 0.0;
     for (;;) {
         int ch = 0;
         if (lane == 0) ch = atomicAdd(counter, 1);
@@ -729,12 +851,11 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                                         acc[r][cc] += c00 * Aq[u6(r, cc)] + c01 * Aq[u6(r, 3 + cc)] +
                                                       c10 * Aq[u6(3 + r, cc)] + c11 * Aq[u6(3 + r, 3 + cc)];
                             } else {
-                                const TA tu = rec[21], tv = rec[22];
-                                PtK K;
-                                if constexpr (CURVED) K = PtK{rec[23], rec[24], rec[25], rec[26]};
-                                else K = mp_geo_t<false>(S, 0);
-                                grad_at<TA>(S, K, k, l, la, lb, tu, tv, ga);
-                                grad_at<TA>(S, K, k, l, ma, mb, tu, tv, gb);
+                                // parametric gradients from the 1-D factors; rec holds Ahat
+                                ga[0] = rec[OFF_N + 3 + la] * rec[OFF_N + 6 + lb];
+                                ga[1] = rec[OFF_N + la] * rec[OFF_N + 9 + lb];
+                                gb[0] = rec[OFF_N + 3 + ma] * rec[OFF_N + 6 + mb];
+                                gb[1] = rec[OFF_N + ma] * rec[OFF_N + 9 + mb];
                                 const TA c00 = ga[0] * gb[0], c01 = ga[0] * gb[1], c10 = ga[1] * gb[0], c11 = ga[1] * gb[1];
 #pragma unroll
                                 for (int r = 0; r < 3; ++r)
@@ -767,9 +888,12 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                     for (int cc = 0; cc < 3; ++cc) hess[(e0 + 3 * r + cc) * ncp + a] = acc[r][cc];
             }
         } else {
-            // gradient: membrane stresses and bending terms of the CP's elements, inertia, gravity
+            // gradient: the membrane stresses of the CP's points (staged records) plus the per-CP
+            // terms (bending, inertia, gravity) formed by the points pass
+            double gp[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) gp[cc] = gpre[cc * ncp + a];
             TG acc[3] = {TG(0), TG(0), TG(0)};
-            double accb[3] = {0.0, 0.0, 0.0};
             // the stresses and basis gradients of the CP's points, all from the staged records
             for (int l = max(0, j - 2); l <= min(j, S.Nv - 1); ++l) {
                 const int r = l - l0;
@@ -793,10 +917,9 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                             }
                             grad_at<TG>(S, K, k, l, la, lb, TG(d[0]), TG(d[1]), dn);
                         } else {
-                            PtK K;
-                            if constexpr (CURVED) K = PtK{rec[23], rec[24], rec[25], rec[26]};
-                            else K = mp_geo_t<false>(S, 0);
-                            grad_at<TG>(S, K, k, l, la, lb, TG(rec[21]), TG(rec[22]), dn);
+                            // parametric gradient; the staged stress is P K^T
+                            dn[0] = rec[OFF_N + 3 + la] * rec[OFF_N + 6 + lb];
+                            dn[1] = rec[OFF_N + la] * rec[OFF_N + 9 + lb];
                         }
                         const TP *pp = (const TP *)(rec + OFF_P);
 #pragma unroll
@@ -804,52 +927,16 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                     }
                 }
             }
-            // bending: the energy is quadratic with the constant stencil K_b (a scalar times I3 per
-            // block, built at create from the same bending evaluations), so its gradient is K_b d
-            // over the 25 stencil neighbours (d: displacement from the rest position)
-#pragma unroll
-            for (int s2 = 0; s2 < kSlots; ++s2) {
-                const int di = slot_di(s2), dj = slot_dj(s2);
-                const int ib = i + di, jb = j + dj;
-                if (ib >= 0 && ib < S.n_u && jb < S.n_v) {
-                    const double w = S.hbend[s2 * ncp + a];
-                    double d[3];
-                    displacement_t<CURVED>(S, x, ib, jb, d);
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
-                }
-                if (s2 == 0) continue;
-                const int ic = i - di, jc = j - dj;
-                if (ic >= 0 && ic < S.n_u && jc >= 0) {
-                    const double w = S.hbend[s2 * ncp + jc * S.n_u + ic];
-                    double d[3];
-                    displacement_t<CURVED>(S, x, ic, jc, d);
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) accb[cc] += w * d[cc];
-                }
-            }
-            const double M = S.mass[a];
-            const double grav[3] = {gx, gy, gz};
             const bool pin = S.pinmask[a] != 0;
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                double gs = double(acc[cc]) + accb[cc];
-                const double xc = x[cc * ncp + a];
-                if (xhat) {
-                    const double dlt = xc - xhat[cc * ncp + a];
-                    gs += M * inv_dt2 * dlt;
-                    e_loc += 0.5 * M * inv_dt2 * dlt * dlt;
-                }
-                gs -= M * grav[cc];
-                e_loc -= M * grav[cc] * xc;
+                const double gs = double(acc[cc]) + gp[cc];
                 const TG gv = pin ? TG(0) : TG(gs);
                 gout[cc * ncp + a] = gv;
                 gg_loc += double(gv) * double(gv);
             }
         }
     }
-    const double tot = block_sum(e_loc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
     if (gg_partials) {
         const double gg = block_sum(gg_loc, sh);
         if (threadIdx.x == 0) gg_partials[blockIdx.x] = gg;
@@ -956,28 +1043,32 @@ inline int blocks(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
 
+int cp_blocks(const DevSheet &S) { return blocks(S.n_cp); }
+
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
-                         const double *x, hipStream_t st, bool bending) {
-    // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch.
-    double *pm = B.partials, *pb = B.partials + B.max_blocks;
-    const int nbm = blocks(S.n_mp), nb = nbm + (bending ? blocks(S.n_be) : 0);
+                         const double *x, hipStream_t st, bool bending, const CpTerms *cpt) {
+    // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch, [4] assembly
+    // tiles (|g|^2).
+    double *pm = B.partials, *pb = B.partials + B.max_blocks, *pc = B.partials + 2 * B.max_blocks;
+    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + (bending ? blocks(S.n_be) : 0);
+    const CpTerms Ct = cpt ? *cpt : CpTerms{nullptr, 0.0, 0.0, 0.0, 0.0, nullptr};
     auto go = [&](auto curved, auto bend) {
         constexpr bool C = decltype(curved)::value, BE = decltype(bend)::value;
         if (grad64 || precision == BSC_FP64) {
             double *P = grad64 ? B.ptP64 : (double *)B.ptP;
             if (hess && !grad64)
                 k_points<double, true, C, double, double, BE><<<nb, kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm, B.beD,
-                                                                                      B.beE, pb, nbm);
+                                                                                      B.beE, pb, ncb, nbm, Ct, pc);
             else
                 k_points<double, false, C, double, double, BE><<<nb, kBlock, 0, st>>>(S, x, (double *)B.ptA, P, B.ptE, pm, B.beD,
-                                                                                       B.beE, pb, nbm);
+                                                                                       B.beE, pb, ncb, nbm, Ct, pc);
         } else {
             if (hess)
                 k_points<float, true, C, float, float, BE><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm,
-                                                                                  B.beD, B.beE, pb, nbm);
+                                                                                  B.beD, B.beE, pb, ncb, nbm, Ct, pc);
             else
                 k_points<float, false, C, float, float, BE><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, (float *)B.ptP, B.ptE, pm,
-                                                                                   B.beD, B.beE, pb, nbm);
+                                                                                   B.beD, B.beE, pb, ncb, nbm, Ct, pc);
         }
     };
     auto go2 = [&](auto curved) {
@@ -991,13 +1082,14 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
 
 // The Newton step's mixed-precision points in one pass: FP64 arithmetic, the stresses (for the
 // FP64 gradient) stored in double and the projected density Hessian stored in float.
-hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st) {
-    double *pm = B.partials, *pb = B.partials + B.max_blocks;
-    const int nbm = blocks(S.n_mp), nb = nbm + blocks(S.n_be);
+hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st, const CpTerms *cpt) {
+    double *pm = B.partials, *pb = B.partials + B.max_blocks, *pc = B.partials + 2 * B.max_blocks;
+    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + blocks(S.n_be);
+    const CpTerms Ct = cpt ? *cpt : CpTerms{nullptr, 0.0, 0.0, 0.0, 0.0, nullptr};
     auto go = [&](auto curved) {
         constexpr bool C = decltype(curved)::value;
         k_points<double, true, C, float, double><<<nb, kBlock, 0, st>>>(S, x, (float *)B.ptA, B.ptP64, B.ptE, pm, B.beD, B.beE,
-                                                                         pb, nbm);
+                                                                         pb, ncb, nbm, Ct, pc);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
@@ -1008,35 +1100,34 @@ int assemble_tiles(const DevSheet &S, int kind) {
     return ((S.n_u + kAsmTileU - 1) / kAsmTileU) * asm_tile_rows(S.n_v, S.asm_ty[kind]);
 }
 
-hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, const double *x, const double *xhat,
-                           double inv_dt2, const double *grav, void *g, void *hess, hipStream_t st, bool gnorm) {
-    double *pc = B.partials + 2 * B.max_blocks, *pg = gnorm ? B.partials + 4 * B.max_blocks : nullptr;
-    const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
+hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
+                           hipStream_t st, bool gnorm) {
+    double *pg = gnorm ? B.partials + 4 * B.max_blocks : nullptr;
     const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], kind, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
     auto go = [&](auto curved) {
-        constexpr bool C = decltype(curved)::value;
+        constexpr bool CV = decltype(curved)::value;
         if (kind == kAsmF32)
-            k_assemble_tile<float, float, float, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, (const float *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (float *)g, pc, pg);
+            k_assemble_tile<float, float, float, CV><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const float *)B.ptA, (const float *)B.ptP, B.gpre, inv_dt2, (float *)hess, (float *)g, pg);
         else if (kind == kAsmF64)
-            k_assemble_tile<double, double, double, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const double *)B.ptA, (const double *)B.ptP, x, xhat, inv_dt2, gx, gy, gz, (double *)hess, (double *)g, pc, pg);
+            k_assemble_tile<double, double, double, CV><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const double *)B.ptA, (const double *)B.ptP, B.gpre, inv_dt2, (double *)hess, (double *)g, pg);
         else
-            k_assemble_tile<float, double, double, C><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, B.ptP64, x, xhat, inv_dt2, gx, gy, gz, (float *)hess, (double *)g, pc, pg);
+            k_assemble_tile<float, double, double, CV><<<nt, kAsmThreads, lds, st>>>(
+                S, kind, (const float *)B.ptA, B.ptP64, B.gpre, inv_dt2, (float *)hess, (double *)g, pg);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
     return hipGetLastError();
 }
 
-hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, double *out, hipStream_t st,
-                                double *out_gg, const PubPtrs *pub) {
+hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, int n_gg_partials, double *out,
+                                hipStream_t st, double *out_gg, const PubPtrs *pub) {
     static_assert(kBlock >= kScalars, "the read-back copies one scalar per thread");
     k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
                                    B.partials + 2 * B.max_blocks, n_cp_partials, out,
-                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_cp_partials, out_gg, B.scalars,
+                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_gg_partials, out_gg, B.scalars,
                                    B.iscalars, pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0);
     return hipGetLastError();
 }
@@ -1069,7 +1160,7 @@ bsc_status bsc_eval_egh(bsc_ctx *c, int32_t precision, const double *d_x, double
     const DevSheet &S = c->dev;
     bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_elem_hess != nullptr, false, d_x, c->stream, true), "eval points");
     if (st != BSC_OK) return st;
-    st = hip_check(c, launch_energy_reduce(S, c->buf, 0, d_energy, c->stream), "energy reduce");
+    st = hip_check(c, launch_energy_reduce(S, c->buf, 0, 0, d_energy, c->stream), "energy reduce");
     if (st != BSC_OK) return st;
     return hip_check(c, launch_elem(S, c->buf, precision, d_elem_energy, d_elem_grad, d_elem_hess, c->stream), "element gather");
 }
@@ -1086,12 +1177,15 @@ bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const 
         inv_dt2 = 1.0 / (dt * dt);
     }
     const DevSheet &S = c->dev;
-    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream, true), "eval points");
+    const CpTerms cpt{d_xhat, inv_dt2, gravity ? gravity[0] : 0.0, gravity ? gravity[1] : 0.0, gravity ? gravity[2] : 0.0,
+                      c->buf.gpre};
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream, true, &cpt),
+                              "eval points");
     if (st != BSC_OK) return st;
     const int kind = precision == BSC_FP64 ? kAsmF64 : kAsmF32;
-    st = hip_check(c, launch_assemble(S, c->buf, kind, d_x, d_xhat, inv_dt2, gravity, d_grad, d_hess, c->stream), "assemble");
+    st = hip_check(c, launch_assemble(S, c->buf, kind, inv_dt2, d_grad, d_hess, c->stream), "assemble");
     if (st != BSC_OK) return st;
-    return hip_check(c, launch_energy_reduce(S, c->buf, assemble_tiles(S, kind), d_energy, c->stream), "energy reduce");
+    return hip_check(c, launch_energy_reduce(S, c->buf, cp_blocks(S), 0, d_energy, c->stream), "energy reduce");
 }
 
 }  // extern "C"

@@ -1098,11 +1098,13 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     const DevBufs &B = ctx->buf;
     // FP32-mixed: the points in FP64 arithmetic, the Hessian stored in FP32 and the stresses (for
     // the FP64 gradient and energy) in FP64
-    if (prec == BSC_FP64) HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true), "points");
-    else HIPX(launch_points_mixed(S, B, x, st), "points");
+    const CpTerms cpt{xhat, inv_dt2, grav ? grav[0] : 0.0, grav ? grav[1] : 0.0, grav ? grav[2] : 0.0, B.gpre};
+    if (prec == BSC_FP64) HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true, &cpt), "points");
+    else HIPX(launch_points_mixed(S, B, x, st, &cpt), "points");
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
-    HIPX(launch_assemble(S, B, kind, x, xhat, inv_dt2, grav, B.g, B.hess, st, true), "assemble");
-    HIPX(launch_energy_reduce(S, B, assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG, pub), "energy");
+    HIPX(launch_assemble(S, B, kind, inv_dt2, B.g, B.hess, st, true), "assemble");
+    HIPX(launch_energy_reduce(S, B, cp_blocks(S), assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG, pub),
+         "energy");
     return BSC_OK;
 }
 
