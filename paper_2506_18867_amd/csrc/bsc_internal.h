@@ -139,23 +139,23 @@ constexpr size_t kAsmLdsMax = BSC_ASM_LDS_BYTES;
 //     to 24), the gradients of the 9 local basis functions (18, from 24), the weighted first
 //     Piola stress P (6, from 44): kAsmRecF floats.
 //   mixed (kAsmMixed, floats, 16-byte aligned): A and the basis gradients as in FP32 (float, for
-//     the FP32 Hessian), then in double for the FP64 gradient P (from float 44), the span
-//     coordinates tu, tv (from 56) and, for a general rest map, the inverse Jacobian K (from 60):
-//     kAsmRecM / kAsmRecMC floats.
+//     the FP32 Hessian; the gradients rounded from FP64), then for the FP64 gradient P in double
+//     (from float 44) and the rounding remainders of the 18 basis gradients (from 56; the float
+//     pair holds each FP64 gradient to about 48 bits): kAsmRecM floats, for any rest map.
 //   FP64 (kAsmF64, doubles): everything in the span's parametric coordinates (u, v), where the
 //     gradient of basis function (a, b) is (Du[a] Nv[b], Nu[a] Dv[b]): the density Hessian
 //     congruent to A under the inverse Jacobian K (21), the 1-D factors Nu, Du, Nv, Dv (21..32)
 //     and the stress P K^T (6, from 33): kAsmRecD doubles, for any rest map.
 // The float record lengths in 16-byte units are odd or twice odd, so the neighbouring records
 // that the lanes of a wave read fall on different LDS banks.
-constexpr int kAsmRecF = 52, kAsmRecM = 60, kAsmRecMC = 68, kAsmRecD = 39;
+constexpr int kAsmRecF = 52, kAsmRecM = 76, kAsmRecD = 39;
 struct AsmLds {
     size_t el_off, rows, counter, rec, rec_bytes, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 __host__ __device__ inline size_t asm_rec_bytes(int kind, bool curved) {
     return kind == kAsmF32 ? 4 * kAsmRecF
-                           : (kind == kAsmMixed ? 4 * (curved ? kAsmRecMC : kAsmRecM) : 8 * kAsmRecD);
+                           : (kind == kAsmMixed ? 4 * kAsmRecM : 8 * kAsmRecD);
 }
 __host__ __device__ inline AsmLds asm_lds_layout(int tx, int ty, int maxp, int kind, bool curved) {
     AsmLds L;

@@ -655,12 +655,11 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     // kind of record (see AsmLds): FP32, mixed (float Hessian, double stress) or FP64
     constexpr int KIND = sizeof(TA) == 4 ? (sizeof(TP) == 4 ? kAsmF32 : kAsmMixed) : kAsmF64;
     constexpr int REC = KIND == kAsmF32 ? kAsmRecF
-                      : (KIND == kAsmMixed ? (CURVED ? kAsmRecMC : kAsmRecM) : kAsmRecD);
-    // offsets (units of TA) of the stress P (FP64: P K^T) and, in mixed records, of the double
-    // tu, tv and K; FP64 records hold the 1-D factors Nu, Du, Nv, Dv from OFF_N
+                      : (KIND == kAsmMixed ? kAsmRecM : kAsmRecD);
+    // offsets (units of TA) of the stress P (FP64: P K^T) and, in mixed records, of the basis
+    // gradients' rounding remainders; FP64 records hold the 1-D factors Nu, Du, Nv, Dv from OFF_N
     constexpr int OFF_P = KIND == kAsmF64 ? 33 : 44;
-    constexpr int OFF_N = 21;
-    constexpr int OFF_T = 56, OFF_K = 60;
+    constexpr int OFF_N = 21, OFF_LO = 56;
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
     __shared__ int s_rowlen[16];                 // points per element row of the tile (ty + 2 rows)
@@ -718,21 +717,25 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 // the element from the tile layout: row r, column k0 + (offset of t within the row)
                 int kk = 0;
                 while (kk + 1 < nk && el_off[r * nk + kk + 1] <= t) ++kk;
-                TA dN[9][2];
-                local_grads<TA>(S, mp_geo_t<CURVED>(S, q), k0 + kk, l0 + r, TA(tu), TA(tv), dN);
-#pragma unroll
-                for (int m = 0; m < 9; ++m) {
-                    rec[24 + 2 * m] = dN[m][0];
-                    rec[24 + 2 * m + 1] = dN[m][1];
-                }
                 if constexpr (KIND == kAsmMixed) {
-                    double *d = (double *)(rec + OFF_T);
-                    d[0] = tu;
-                    d[1] = tv;
-                    if constexpr (CURVED) {
-                        const PtK K = mp_geo_t<true>(S, q);
-                        double *kq = (double *)(rec + OFF_K);
-                        kq[0] = K.k00; kq[1] = K.k01; kq[2] = K.k10; kq[3] = K.k11;
+                    // the gradients in FP64, stored as float plus float remainder
+                    double dN[9][2];
+                    local_grads<double>(S, mp_geo_t<CURVED>(S, q), k0 + kk, l0 + r, tu, tv, dN);
+#pragma unroll
+                    for (int m = 0; m < 9; ++m)
+#pragma unroll
+                        for (int g = 0; g < 2; ++g) {
+                            const float hi = float(dN[m][g]);
+                            rec[24 + 2 * m + g] = hi;
+                            rec[OFF_LO + 2 * m + g] = float(dN[m][g] - double(hi));
+                        }
+                } else {
+                    TA dN[9][2];
+                    local_grads<TA>(S, mp_geo_t<CURVED>(S, q), k0 + kk, l0 + r, TA(tu), TA(tv), dN);
+#pragma unroll
+                    for (int m = 0; m < 9; ++m) {
+                        rec[24 + 2 * m] = dN[m][0];
+                        rec[24 + 2 * m + 1] = dN[m][1];
                     }
                 }
             } else {
@@ -907,15 +910,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                             dn[0] = g2.x;
                             dn[1] = g2.y;
                         } else if constexpr (KIND == kAsmMixed) {
-                            const double *d = (const double *)(rec + OFF_T);
-                            PtK K;
-                            if constexpr (CURVED) {
-                                const double *kq = (const double *)(rec + OFF_K);
-                                K = PtK{kq[0], kq[1], kq[2], kq[3]};
-                            } else {
-                                K = mp_geo_t<false>(S, 0);
-                            }
-                            grad_at<TG>(S, K, k, l, la, lb, TG(d[0]), TG(d[1]), dn);
+                            const int o = 2 * (3 * lb + la);
+                            const float2 h2 = *(const float2 *)(rec + 24 + o), l2 = *(const float2 *)(rec + OFF_LO + o);
+                            dn[0] = double(h2.x) + double(l2.x);
+                            dn[1] = double(h2.y) + double(l2.y);
                         } else {
                             // parametric gradient; the staged stress is P K^T
                             dn[0] = rec[OFF_N + 3 + la] * rec[OFF_N + 6 + lb];
