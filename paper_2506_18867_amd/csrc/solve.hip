@@ -819,34 +819,51 @@ __global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__re
 
 // The line-search scalars in one block, each in a fixed order: max |p| (exact in any order),
 // c1 and c2 over the CP and bending partials, the membrane energy difference at alpha = 1;
-// out[0..3] = max |p|, c1, c2, dE_membrane, valid in every thread of the block.
+// out[0..3] = max |p|, c1, c2, dE_membrane, valid in every thread of the block. Each thread
+// reads its elements of all the partial arrays in one loop (the loads issue together), then
+// the four values are reduced across the block at once.
 __device__ void ls_sums(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa, const double *__restrict__ pb,
                         int n_beb, int stride, const double *__restrict__ pd, int n_mpb, double *sh, double out[4]) {
-    __shared__ double res[4];
-    double m = 0.0;
-    for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) m = fmax(m, pm[t]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-        res[0] = m;
+    __shared__ double res[4][kBlock / 64];
+    double m = 0.0, c1 = 0.0, c2 = 0.0, dm = 0.0;
+    const int n = max(max(n_cpb, n_beb), n_mpb);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        if (t < n_cpb) {
+            m = fmax(m, pm[t]);
+            c1 += pa[t];
+            c2 += pa[stride + t];
+        }
+        if (t < n_beb) {
+            c1 += pb[t];
+            c2 += pb[stride + t];
+        }
+        if (t < n_mpb) dm += pd[t];
     }
-    for (int k = 0; k < 2; ++k) {
-        double v = 0.0;
-        for (int t = threadIdx.x; t < n_cpb; t += blockDim.x) v += pa[k * stride + t];
-        for (int t = threadIdx.x; t < n_beb; t += blockDim.x) v += pb[k * stride + t];
-        v = block_sum(v, sh);
-        if (threadIdx.x == 0) res[1 + k] = v;
-    }
-    double v = 0.0;
-    for (int t = threadIdx.x; t < n_mpb; t += blockDim.x) v += pd[t];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) res[3] = v;
-    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k] = res[k];
+    for (int off = 32; off > 0; off >>= 1) {
+        m = fmax(m, __shfl_down(m, off));
+        c1 += __shfl_down(c1, off);
+        c2 += __shfl_down(c2, off);
+        dm += __shfl_down(dm, off);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        res[0][wid] = m;
+        res[1][wid] = c1;
+        res[2][wid] = c2;
+        res[3][wid] = dm;
+    }
+    __syncthreads();
+    double r[4] = {res[0][0], res[1][0], res[2][0], res[3][0]};
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) {
+        r[0] = fmax(r[0], res[0][w]);
+        r[1] += res[1][w];
+        r[2] += res[2][w];
+        r[3] += res[3][w];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = r[k];
+    (void)sh;
 }
 
 __global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__ pm, int n_cpb, const double *__restrict__ pa,
