@@ -220,7 +220,6 @@ struct DevBufs {
     int32_t *iscalars;
     // solver vectors (3 n_cp doubles each) and the block-Jacobi inverse (6 n_cp)
     double *g, *xn, *xhat, *dir, *r, *p0, *p1, *q, *pinv, *tmp, *phat;
-    double *pprev;                               // the previous Newton direction (recycled warm start)
     double *gpre;                                // per-CP gradient terms of the assembly (bending, inertia, gravity)
     double *r2, *q2, *p2;                    // second halves of the CG double buffers
     void *hess;                              // kHessEntries n_cp doubles

@@ -1045,8 +1045,8 @@ int cp_blocks(const DevSheet &S) { return blocks(S.n_cp); }
 
 hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, bool hess, bool grad64,
                          const double *x, hipStream_t st, bool bending, const CpTerms *cpt) {
-    // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] scratch, [4] assembly
-    // tiles (|g|^2).
+    // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] assembly tiles (|g|^2);
+    // [4..7] are free for the kernels that follow (the warm start's dot products).
     double *pm = B.partials, *pb = B.partials + B.max_blocks, *pc = B.partials + 2 * B.max_blocks;
     const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + (bending ? blocks(S.n_be) : 0);
     const CpTerms Ct = cpt ? *cpt : CpTerms{nullptr, 0.0, 0.0, 0.0, 0.0, nullptr};
@@ -1100,7 +1100,7 @@ int assemble_tiles(const DevSheet &S, int kind) {
 
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
                            hipStream_t st, bool gnorm) {
-    double *pg = gnorm ? B.partials + 4 * B.max_blocks : nullptr;
+    double *pg = gnorm ? B.partials + 3 * B.max_blocks : nullptr;
     const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], kind, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
     auto go = [&](auto curved) {
@@ -1125,7 +1125,7 @@ hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_pa
     static_assert(kBlock >= kScalars, "the read-back copies one scalar per thread");
     k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
                                    B.partials + 2 * B.max_blocks, n_cp_partials, out,
-                                   out_gg ? B.partials + 4 * B.max_blocks : nullptr, n_gg_partials, out_gg, B.scalars,
+                                   out_gg ? B.partials + 3 * B.max_blocks : nullptr, n_gg_partials, out_gg, B.scalars,
                                    B.iscalars, pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0);
     return hipGetLastError();
 }

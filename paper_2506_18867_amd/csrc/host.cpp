@@ -268,7 +268,7 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.bsr_rowptr = (int32_t *)take(4 * (ncp + 1));
     t.scalars = (double *)take(8 * kScalars);
     t.iscalars = (int32_t *)take(4 * 64);          // directly after the scalars (kScalars * 8 is a multiple of 256)
-    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2, &t.pprev, &t.gpre};
+    double **vecs[] = {&t.g, &t.xn, &t.xhat, &t.dir, &t.r, &t.p0, &t.p1, &t.q, &t.tmp, &t.phat, &t.r2, &t.q2, &t.p2, &t.gpre};
     for (double **v : vecs) *v = (double *)take(8 * 3 * ncp);
     t.pinv = (double *)take(8 * 6 * ncp);
     t.mg_x0 = t.r2;                                // unused by the multigrid solver otherwise

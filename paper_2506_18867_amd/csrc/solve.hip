@@ -135,6 +135,61 @@ __device__ __forceinline__ void block_product(const DevSheet &S, const T *__rest
     }
 }
 
+// Per-CP set-up of a block-Jacobi PCG solve: b = -g and the inverse of the diagonal block
+// (the inverse diagonal where the block is not positive definite).
+template <typename T>
+__device__ __forceinline__ void prep_row(const DevSheet &S, const T *__restrict__ H, T *__restrict__ pinv,
+                                         const double *__restrict__ g, double *__restrict__ b, int a) {
+    const size_t n = S.n_cp;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[c * n + a] = 0.0 - g[c * n + a];
+    const double a00 = H[a], a01 = H[n + a], a02 = H[2 * n + a], a11 = H[3 * n + a], a12 = H[4 * n + a], a22 = H[5 * n + a];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    double inv[6];
+    if (det > 0.0 && a00 > 0.0) {
+        const double id = 1.0 / det;
+        inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
+        inv[3] = (a00 * a22 - a02 * a02) * id; inv[4] = (a02 * a01 - a00 * a12) * id; inv[5] = (a00 * a11 - a01 * a01) * id;
+    } else {   // not positive definite: fall back to the inverse diagonal
+        inv[0] = a00 > 0.0 ? 1.0 / a00 : 1.0; inv[1] = inv[2] = 0.0;
+        inv[3] = a11 > 0.0 ? 1.0 / a11 : 1.0; inv[4] = 0.0; inv[5] = a22 > 0.0 ? 1.0 / a22 : 1.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) pinv[t * n + a] = T(inv[t]);
+}
+
+// The energy and |g|^2 of an assembly from its partial sums, formed by one block of the first
+// kernel after it (so that no launch of its own separates the assembly from the solve): the
+// points pass's energy partials p0, p1, p2 and the tiles' |g|^2 partials pg, each summed in a
+// fixed order, then with do_pub the read-back of the solver scalars and flags. out == nullptr:
+// nothing to do.
+struct EnergyRed {
+    const double *p0, *p1, *p2, *pg;
+    int n0, n1, n2, ng;
+    double *out, *out_g;
+    PubPtrs pub;
+    int do_pub;
+};
+
+__device__ void energy_reduce_block(const EnergyRed &R, const double *scal, int32_t *flags, double *sh) {
+    double v = 0.0, u = 0.0;
+    for (int t = threadIdx.x; t < R.n0; t += blockDim.x) v += R.p0[t];
+    for (int t = threadIdx.x; t < R.n1; t += blockDim.x) v += R.p1[t];
+    for (int t = threadIdx.x; t < R.n2; t += blockDim.x) v += R.p2[t];
+    for (int t = threadIdx.x; t < R.ng; t += blockDim.x) u += R.pg[t];
+    const double se = block_sum(v, sh);
+    const double sg = block_sum(u, sh);
+    if (threadIdx.x == 0) {
+        R.out[0] = se;
+        R.out_g[0] = sg;
+    }
+    if (R.do_pub) {
+        __syncthreads();
+        publish_block(scal, flags, R.pub);
+    }
+}
+
 // w = H u for a tile of 64 rows; wave g computes block products g, g+8, g+16, g+24 and the
 // eight partial results are summed through LDS. DOTS (the warm start): the tile's partials of
 // g.u, u.w, g.w and w.w go to part[k * stride + block] (a fixed-order wave sum per tile).
@@ -142,8 +197,13 @@ template <typename T, bool DOTS = false>
 __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S, const T *__restrict__ H,
                                                                      const double *__restrict__ u, double *__restrict__ w,
                                                                      const double *__restrict__ gv = nullptr,
-                                                                     double *__restrict__ part = nullptr, int stride = 0) {
+                                                                     double *__restrict__ part = nullptr, int stride = 0,
+                                                                     T *__restrict__ pinv = nullptr,
+                                                                     double *__restrict__ bvec = nullptr,
+                                                                     EnergyRed red = EnergyRed{}, const double *scal = nullptr,
+                                                                     int32_t *flags = nullptr) {
     __shared__ T ys[kGroups][3][kRowsPerTile];
+    __shared__ double shr[kRowsPerTile * kGroups / 64];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = tile * kRowsPerTile + lane;
@@ -154,6 +214,8 @@ __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S
             const int pid = g + kGroups * m;
             if (pid < 25) block_product<T>(S, H, u, a, i, j, pid, acc);
         }
+        // with pinv: the PCG set-up of the tile's rows, by the last wave (one product fewer)
+        if (pinv && g == kGroups - 1) prep_row<T>(S, H, pinv, gv, bvec, a);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) ys[g][c][lane] = acc[c];
@@ -184,6 +246,7 @@ __global__ void __launch_bounds__(kRowsPerTile * kGroups) k_spmv_tile(DevSheet S
             }
         }
     }
+    if (red.out && blockIdx.x == 0) energy_reduce_block(red, scal, flags, shr);
 }
 
 template <typename T>
@@ -295,34 +358,21 @@ __global__ void __launch_bounds__(kBlock) k_finish(const double *__restrict__ pa
 // the initial direction x0 = 0. With keep, the direction that x0 held (the previous Newton
 // direction of the step; zero at the step's first iteration) is saved there first, zero on
 // pinned CPs.
+// The set-up without a warm start: prep_row and x0 = 0.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_prep(DevSheet S, const T *__restrict__ H, T *__restrict__ pinv,
                                                     const double *__restrict__ g, double *__restrict__ b,
-                                                    double *__restrict__ x0, double *__restrict__ keep) {
+                                                    double *__restrict__ x0, EnergyRed red = EnergyRed{},
+                                                    const double *scal = nullptr, int32_t *flags = nullptr) {
+    __shared__ double sh[kBlock / 64];
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= S.n_cp) return;
-    const size_t n = S.n_cp;
-    const bool pinned = S.pinmask[a] != 0;
+    if (a < S.n_cp) {
+        const size_t n = S.n_cp;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        b[c * n + a] = 0.0 - g[c * n + a];
-        if (keep) keep[c * n + a] = pinned ? 0.0 : x0[c * n + a];
-        x0[c * n + a] = 0.0;
+        for (int c = 0; c < 3; ++c) x0[c * n + a] = 0.0;
+        prep_row<T>(S, H, pinv, g, b, a);
     }
-    const double a00 = H[a], a01 = H[n + a], a02 = H[2 * n + a], a11 = H[3 * n + a], a12 = H[4 * n + a], a22 = H[5 * n + a];
-    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
-    const double det = a00 * c00 + a01 * c01 + a02 * c02;
-    double inv[6];
-    if (det > 0.0 && a00 > 0.0) {
-        const double id = 1.0 / det;
-        inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
-        inv[3] = (a00 * a22 - a02 * a02) * id; inv[4] = (a02 * a01 - a00 * a12) * id; inv[5] = (a00 * a11 - a01 * a01) * id;
-    } else {   // not positive definite: fall back to the inverse diagonal
-        inv[0] = a00 > 0.0 ? 1.0 / a00 : 1.0; inv[1] = inv[2] = 0.0;
-        inv[3] = a11 > 0.0 ? 1.0 / a11 : 1.0; inv[4] = 0.0; inv[5] = a22 > 0.0 ? 1.0 / a22 : 1.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 6; ++t) pinv[t * n + a] = T(inv[t]);
+    if (red.out && blockIdx.x == 0) energy_reduce_block(red, scal, flags, sh);
 }
 
 // PCG tolerance of a Newton iteration. EXPLICIT: given by the host. FIXED / TIGHT: pcg_rtol.
@@ -376,9 +426,9 @@ __device__ double ws_decide(const double *__restrict__ part, int stride, int nb,
 // for the multiple a that every block decides from the partials wpart of the product hq = H ph
 // (a = 0: x0 = 0 and r = b exactly); block 0 stores the dots at S_WS0..3, a at S_WSA and the
 // flag I_WS.
-__global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *__restrict__ ph,
+__global__ void __launch_bounds__(kBlock) k_cg_init(DevSheet S, const double *__restrict__ b, const double *ph,
                                                     const double *__restrict__ hq, const double *__restrict__ wpart,
-                                                    int wstride, int wnb, double *__restrict__ x0,
+                                                    int wstride, int wnb, double *x0,
                                                     double *__restrict__ r, double *__restrict__ p, double *__restrict__ sv,
                                                     double *__restrict__ pbb, int32_t *isc, double *scal, int maxit,
                                                     int eta_mode, int first, double eta_host, double rtol_min,
@@ -1108,9 +1158,10 @@ struct Timer {
         if (e_ != hipSuccess) return hip_check(ctx, e_, what);      \
     } while (0)
 
-// Assembles E, g (double), |g|^2 and H (working precision) at x for one Newton iteration.
+// Assembles E, g (double), |g|^2 and H (working precision) at x for one Newton iteration. With
+// red, E and |g|^2 are left to the next kernel (energy_reduce_block), whose arguments go to red.
 bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *xhat, double inv_dt2, const double *grav,
-                         hipStream_t st, const PubPtrs *pub) {
+                         hipStream_t st, const PubPtrs *pub, EnergyRed *red = nullptr) {
     const DevSheet &S = ctx->dev;
     const DevBufs &B = ctx->buf;
     // FP32-mixed: the points in FP64 arithmetic, the Hessian stored in FP32 and the stresses (for
@@ -1120,6 +1171,14 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     else HIPX(launch_points_mixed(S, B, x, st, &cpt), "points");
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
     HIPX(launch_assemble(S, B, kind, inv_dt2, B.g, B.hess, st, true), "assemble");
+    if (red) {
+        // the same arrays and counts as launch_energy_reduce
+        const int mb = B.max_blocks;
+        *red = EnergyRed{B.partials, B.partials + mb, B.partials + 2 * mb, B.partials + 3 * mb, blocks(S.n_mp), blocks(S.n_be),
+                         cp_blocks(S), assemble_tiles(S, kind), B.scalars + S_E, B.scalars + S_GG,
+                         pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0};
+        return BSC_OK;
+    }
     HIPX(launch_energy_reduce(S, B, cp_blocks(S), assemble_tiles(S, kind), B.scalars + S_E, st, B.scalars + S_GG, pub),
          "energy");
     return BSC_OK;
@@ -1259,8 +1318,10 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // than replayed as captured graphs, whose switches with plain launches on the stream each
         // cost a gap)
         const int32_t last_asm = seen();
+        EnergyRed red{};                 // early: E and |g|^2 summed (and published) by the PCG set-up's first kernel
         {
-            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st, early && pub ? &pubp : nullptr);
+            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st, early && pub ? &pubp : nullptr,
+                                                early ? &red : nullptr);
             if (sa != BSC_OK) return sa;
         }
         hipEvent_t e1 = rec();
@@ -1289,26 +1350,32 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         const int first = it == 0 ? 1 : 0;
         double eta_arg = 0.0;                    // the explicit mode's tolerance (set before the solve)
         double grad_rtol = 0.0;                  // the device-side gradient stop of the speculative solve
-        // block-Jacobi inverse, b = -g, x0 = 0 (the recycled warm start keeps the previous direction)
-        double *keep = warm == BSC_WARM_PREVIOUS ? B.pprev : nullptr;
+        // block-Jacobi inverse, b = -g, x0 = 0
         auto enqueue_prep = [&](hipStream_t cs) {
             if (prec == BSC_FP64)
                 k_cg_prep<double><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir,
-                                                                      keep);
+                                                                      red, B.scalars, B.iscalars);
             else
                 k_cg_prep<float><<<blocks(S.n_cp), kBlock, 0, cs>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir,
-                                                                     keep);
+                                                                     red, B.scalars, B.iscalars);
+            red.out = nullptr;
         };
         // warm start from the prediction ph: H ph into hq with the partials of its four dot
-        // products (k_cg_init sums them, decides and applies the start, all on the device)
+        // products (k_cg_init sums them, decides and applies the start, all on the device), and
+        // the set-up of enqueue_prep except x0 = 0 (k_cg_init writes every entry of x0)
         auto enqueue_warm = [&](hipStream_t cs, const double *ph) {
             const int nb = spmv_blocks(S.n_cp);
             if (prec == BSC_FP64)
                 k_spmv_tile<double, true><<<nb, kRowsPerTile * kGroups, 0, cs>>>(S, (const double *)B.hess, ph, hq, B.g,
-                                                                                B.partials + 4 * stride, stride);
+                                                                                B.partials + 4 * stride, stride,
+                                                                                (double *)B.pinv, B.tmp, red, B.scalars,
+                                                                                B.iscalars);
             else
                 k_spmv_tile<float, true><<<nb, kRowsPerTile * kGroups, 0, cs>>>(S, (const float *)B.hess, ph, hq, B.g,
-                                                                               B.partials + 4 * stride, stride);
+                                                                               B.partials + 4 * stride, stride,
+                                                                               (float *)B.pinv, B.tmp, red, B.scalars,
+                                                                               B.iscalars);
+            red.out = nullptr;
         };
         // r = b - A x0 (x0 = a ph with the decided multiple, when ph is given), the tolerance, and
         // the first CG launch (it forms w_0)
@@ -1325,9 +1392,12 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // the block-Jacobi solve's set-up (prep, the recycled warm start, init and the first
         // launch), enqueued as plain launches: as a captured sequence it measured slower (each
         // switch between a graph and plain launches on the stream costs a gap)
-        const double *ph = warm == BSC_WARM_PREVIOUS ? B.pprev : (warm == BSC_WARM_NET ? B.phat : nullptr);
+        // The recycled start reads the previous direction in place (k_cg_init scales it into x0
+        // elementwise); it is zero at pinned CPs, whose rows of H are the identity with a zero
+        // right-hand side, so PCG never moves them.
+        const double *ph = warm == BSC_WARM_PREVIOUS ? B.dir : (warm == BSC_WARM_NET ? B.phat : nullptr);
         auto cg_setup = [&]() -> hipError_t {
-            enqueue_prep(st);
+            if (!ph) enqueue_prep(st);
             if (warm == BSC_WARM_NET) {
                 // the learned prediction p_hat = net(g), zero on pinned CPs
                 hipEvent_t w0 = rec();
@@ -1445,7 +1515,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
             const bool speculate = o->stop_mode == BSC_STOP_GRAD && o->fixed_newton_iters <= 0 && it < o->max_newton;
             grad_rtol = speculate ? o->rtol : 0.0;
-            const int32_t last = last_asm;           // the assembly's reduction published E and |g|
+            const int32_t last = last_asm;           // the set-up.s first kernel publishes E and |g|
             e2 = rec();
             HIPX(cg_setup(), "cg init");
             if (speculate) {
@@ -1693,9 +1763,9 @@ bsc_status stencil_pcg(bsc_ctx *ctx, int prec, const double *b, double *x, doubl
     // block-Jacobi inverse of the matrix, b (as 0 - (-b)) into B.tmp, x0 = 0 into B.dir
     k_axpby<<<blocks(n3), kBlock, 0, st>>>(n3, -1.0, b, 0.0, b, B.g);
     if (prec == BSC_FP64)
-        k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir, nullptr);
+        k_cg_prep<double><<<nbi, kBlock, 0, st>>>(S, (const double *)B.hess, (double *)B.pinv, B.g, B.tmp, B.dir);
     else
-        k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir, nullptr);
+        k_cg_prep<float><<<nbi, kBlock, 0, st>>>(S, (const float *)B.hess, (float *)B.pinv, B.g, B.tmp, B.dir);
     k_cg_init<<<nbi, kBlock, 0, st>>>(S, B.tmp, nullptr, nullptr, nullptr, 0, 0, nullptr, rb[0], B.p0, sb[0], pbb, B.iscalars, B.scalars, max_iter,
                                        ETA_EXPLICIT, 1, rtol, rtol, rtol, 0.0);
     fused(0);
