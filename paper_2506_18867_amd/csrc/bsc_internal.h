@@ -110,8 +110,10 @@ struct DevSheet {
     const double *mass, *hbend;
     const int32_t *pinmask;
     // tiled assembly (k_assemble_tile): tile height and the per-tile maximum of the membrane
-    // points of the elements a tile touches, per precision combination (AsmKind)
-    int asm_ty[3], asm_maxp[3];
+    // points of the elements a tile touches, per precision combination (AsmKind), and each
+    // kind's tile table (asm_tile_table; asm_stride ints per tile)
+    int asm_ty[3], asm_maxp[3], asm_stride[3];
+    const int32_t *asm_tab[3];
 };
 
 // Tiled assembly: tiles of kAsmTileU x ty CPs; the precision combinations of the per-point
@@ -196,6 +198,22 @@ __host__ __device__ inline void asm_tile_row(int n_v, int ty, int tr, int &y0, i
     }
 }
 
+// Tile table of the tiled assembly, built at create: tile t (t = tile row * tiles per row +
+// tile column) owns asm_stride ints from t * asm_stride: the number np of staged points, then
+// for each record r < np the global membrane point (np ints) and the tile-local element
+// (l - l0) nk + (k - k0) it belongs to (np ints; both padded to the kind's maxp), then one int
+// per tile-local element: point count | first record << 4 | further records << 18. A span's
+// first point goes to region 0 (the first points of the tile's spans in element order), its
+// further points, in order, to region 1 (contiguous per span, after region 0): every interior
+// span carries exactly two points under the paper's rule, so the lanes of a wave that read the
+// s-th point of neighbouring spans read neighbouring records.
+__host__ __device__ inline int asm_tab_stride(int ty, int maxp) {
+    return 1 + 2 * maxp + (BSC_ASM_TILE_U + 2) * (ty + 2);
+}
+__host__ __device__ inline int asm_el_count(int info) { return info & 15; }
+__host__ __device__ inline int asm_el_first(int info) { return (info >> 4) & 0x3fff; }
+__host__ __device__ inline int asm_el_rest(int info) { return (info >> 18) & 0x3fff; }
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Give every
 // XCD a contiguous range of tiles so that neighbouring tiles, which read each other's halo
 // (stencil neighbours, shared elements), are usually in the same L2.
@@ -210,6 +228,7 @@ struct DevBufs {
     int32_t *mp_elem, *mp_off, *be_elem, *be_off, *pinmask, *pin_idx;
     double *mp_tu, *mp_tv, *mp_w, *be_tu, *be_tv, *be_w, *mass, *hbend;
     double *mp_K, *be_L, *rest;              // general rest map only (zero bytes when affine)
+    int32_t *asm_tab;                        // assembly tile tables (asm_tile_table)
     // per-point intermediates (sized for double; float uses the front half)
     void *ptA, *ptP;
     double *ptE, *ptP64, *beD, *beE;
@@ -263,6 +282,10 @@ struct bsc_ctx {
     std::vector<double> mp_tu, mp_tv, mp_w, be_tu, be_tv, be_w, mass, hbend;
     std::vector<double> mp_K, be_L, rest;    // general rest map: SoA per-point geometry, rest CPs
     std::vector<int32_t> pins;
+    // assembly tile tables (AsmKind kinds with the same tile height share one): offset of each
+    // kind's table in asm_tab and the ints per tile; layout in asm_tile_table
+    std::vector<int32_t> asm_tab;
+    size_t asm_tab_off[3] = {0, 0, 0};
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;

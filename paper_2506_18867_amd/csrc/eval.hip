@@ -662,11 +662,9 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     constexpr int OFF_N = 21, OFF_LO = 56;
     extern __shared__ __align__(16) char lds[];
     __shared__ double sh[kAsmThreads / 64];
-    __shared__ int s_rowlen[16];                 // points per element row of the tile (ty + 2 rows)
     const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
     const AsmLds L = asm_lds_layout(kAsmTileU, ty, maxp, KIND, CURVED);
-    int *el_off = (int *)(lds + L.el_off);
-    int *mrow = (int *)(lds + L.rows);
+    int *el_info = (int *)(lds + L.el_off);      // per tile-local element: count, first and further records
     int *counter = (int *)(lds + L.counter);
     TA *prec = (TA *)(lds + L.rec);
 
@@ -681,32 +679,18 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
     const int l0 = max(0, ty0 - 2), l1 = min(S.Nv - 1, ty0 + h - 1);
     const int nk = k1 - k0 + 1, nl = l1 - l0 + 1, ne = nk * nl;
 
-    // Local point offsets of the tile's elements (element (k, l) -> (l - l0) nk + (k - k0)): the
-    // points of one element row are contiguous in the global tables, so an offset is the points
-    // of the rows before plus the offset within the row. One round of independent global loads
-    // (row starts and lengths, each element's first point), then the row prefix from LDS.
-    for (int r = threadIdx.x; r < nl; r += blockDim.x) {
-        const int e0 = (l0 + r) * S.Nu;
-        const int s0 = S.mp_off[e0 + k0];
-        mrow[r] = s0;
-        s_rowlen[r] = S.mp_off[e0 + k1 + 1] - s0;
-    }
-    for (int t = threadIdx.x; t < ne; t += blockDim.x) el_off[t] = S.mp_off[(l0 + t / nk) * S.Nu + k0 + t % nk];
+    // The tile's table (built at create): its point count, the global point and tile-local
+    // element of each record, and the per-element record indices, all read in one round of
+    // independent loads (the record lists are padded to maxp).
+    const int32_t *T = S.asm_tab[kind] + size_t(tile) * S.asm_stride[kind];
+    const int32_t *tq = T + 1, *te = T + 1 + maxp;
+    for (int t = threadIdx.x; t < ne; t += blockDim.x) el_info[t] = T[1 + 2 * maxp + t];
     if (threadIdx.x == 0) *counter = 0;
-    __syncthreads();
-    for (int t = threadIdx.x; t <= ne; t += blockDim.x) {
-        const int r = t < ne ? t / nk : nl;
-        int base = 0;
-        for (int q = 0; q < r; ++q) base += s_rowlen[q];
-        el_off[t] = t < ne ? base + (el_off[t] - mrow[r]) : base;
-    }
-    __syncthreads();
     {
-        const int np = el_off[ne];
+        const int np = T[0];
         for (int t = threadIdx.x; t < np; t += blockDim.x) {
-            int r = 0;
-            while (r + 1 < nl && el_off[(r + 1) * nk] <= t) ++r;
-            const int q = mrow[r] + (t - el_off[r * nk]);
+            const int q = tq[t], elr = te[t];
+            const int r = elr / nk, kk = elr - r * nk;
             TA *rec = prec + size_t(t) * REC;
             if (hess) {
 #pragma unroll
@@ -714,9 +698,6 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
             }
             const double tu = S.mp_tu[q], tv = S.mp_tv[q];
             if constexpr (STAGE_DN) {
-                // the element from the tile layout: row r, column k0 + (offset of t within the row)
-                int kk = 0;
-                while (kk + 1 < nk && el_off[r * nk + kk + 1] <= t) ++kk;
                 if constexpr (KIND == kAsmMixed) {
                     // the gradients in FP64, stored as float plus float remainder
                     double dN[9][2];
@@ -743,8 +724,6 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 // ghat = (Du[a] Nv[b], Nu[a] Dv[b]) in the span's parameters, so the items' sums
                 // of ga^T A^(gamma delta) gb equal those of ghat_a^T Ahat ghat_b with Ahat the
                 // congruence (K x I3) A (K x I3)^T, and P dN = (P K^T) ghat: formed once per point
-                int kk = 0;
-                while (kk + 1 < nk && el_off[r * nk + kk + 1] <= t) ++kk;
                 double Nu[3], Du[3], Nv[3], Dv[3];
                 pieces<double>(span_type(k0 + kk, S.Nu), tu, Nu, Du);
                 pieces<double>(span_type(l0 + r, S.Nv), tv, Nv, Dv);
@@ -831,8 +810,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                         const int el = (l - l0) * nk + (k - k0);
                         const int la = i - k, lb = j - l, ma = ib - k, mb = jb - l;
                         const int oa = 24 + 2 * (3 * lb + la), ob = 24 + 2 * (3 * mb + ma);
-                        for (int q = el_off[el]; q < el_off[el + 1]; ++q) {
-                            const TA *rec = prec + size_t(q) * REC;
+                        const int info = el_info[el], cnt = asm_el_count(info);
+                        const int r0 = asm_el_first(info), r1 = asm_el_rest(info) - 1;
+                        for (int sq = 0; sq < cnt; ++sq) {
+                            const TA *rec = prec + size_t(sq == 0 ? r0 : r1 + sq) * REC;
                             TA ga[2], gb[2];
                             if constexpr (STAGE_DN) {
                                 TA Aq[21];
@@ -902,8 +883,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
                 const int r = l - l0;
                 for (int k = max(0, i - 2); k <= min(i, S.Nu - 1); ++k) {
                     const int el = r * nk + (k - k0), la = i - k, lb = j - l;
-                    for (int t = el_off[el]; t < el_off[el + 1]; ++t) {
-                        const TA *rec = prec + size_t(t) * REC;
+                    const int info = el_info[el], cnt = asm_el_count(info);
+                    const int r0 = asm_el_first(info), r1 = asm_el_rest(info) - 1;
+                    for (int sq = 0; sq < cnt; ++sq) {
+                        const TA *rec = prec + size_t(sq == 0 ? r0 : r1 + sq) * REC;
                         TG dn[2];
                         if constexpr (KIND == kAsmF32) {
                             const float2 g2 = *(const float2 *)(rec + 24 + 2 * (3 * lb + la));

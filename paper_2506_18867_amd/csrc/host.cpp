@@ -257,6 +257,7 @@ size_t layout_workspace(const bsc_ctx *c, DevBufs *b, char *base) {
     t.be_L = (double *)take(8 * c->be_L.size());
     t.rest = (double *)take(8 * c->rest.size());
     t.pinmask = (int32_t *)take(4 * ncp);
+    t.asm_tab = (int32_t *)take(4 * c->asm_tab.size());
     t.pin_idx = (int32_t *)take(4 * ncp);
     t.ptA = take(8 * 21 * nmp);
     t.ptP = take(8 * 6 * nmp);
@@ -537,6 +538,50 @@ bsc_status bsc_create(bsc_ctx **out, int32_t n_u, int32_t n_v, const double *kno
         }
         if (S.asm_ty[kind] == 0) { delete c; return BSC_E_INVAL; }
     }
+    // the tile tables, one per distinct (tile height, point bound)
+    c->asm_tab.clear();
+    for (int kind = 0; kind < 3; ++kind) {
+        const int ty = S.asm_ty[kind], maxp = S.asm_maxp[kind];
+        S.asm_stride[kind] = asm_tab_stride(ty, maxp);
+        int same = -1;
+        for (int k2 = 0; k2 < kind; ++k2)
+            if (S.asm_ty[k2] == ty && S.asm_maxp[k2] == maxp) same = k2;
+        if (same >= 0) { c->asm_tab_off[kind] = c->asm_tab_off[same]; continue; }
+        if (maxp >= (1 << 14)) { delete c; return BSC_E_INVAL; }
+        const int ntx = (n_u + kAsmTileU - 1) / kAsmTileU, nt = ntx * asm_tile_rows(n_v, ty), stride = S.asm_stride[kind];
+        c->asm_tab_off[kind] = c->asm_tab.size();
+        c->asm_tab.resize(c->asm_tab.size() + size_t(nt) * stride, 0);
+        int32_t *base = c->asm_tab.data() + c->asm_tab_off[kind];
+        for (int tile = 0; tile < nt; ++tile) {
+            const int tx0 = (tile % ntx) * kAsmTileU;
+            int ty0 = 0, h = 0;
+            asm_tile_row(n_v, ty, tile / ntx, ty0, h);
+            const int k0 = std::max(0, tx0 - 2), k1 = std::min(Nu - 1, tx0 + kAsmTileU - 1);
+            const int l0 = std::max(0, ty0 - 2), l1 = std::min(Nv - 1, ty0 + h - 1);
+            const int nk = k1 - k0 + 1, ne = nk * (l1 - l0 + 1);
+            int32_t *T = base + size_t(tile) * stride;
+            int n0 = 0, np = 0;
+            for (int el = 0; el < ne; ++el) {
+                const int e = (l0 + el / nk) * Nu + k0 + el % nk, cnt = c->mp_off[e + 1] - c->mp_off[e];
+                if (cnt > 15) { delete c; return BSC_E_INVAL; }
+                n0 += cnt > 0;
+                np += cnt;
+            }
+            int32_t *rq = T + 1, *re = T + 1 + maxp, *info = T + 1 + 2 * maxp;
+            T[0] = np;
+            int i0 = 0, i1 = n0;
+            for (int el = 0; el < ne; ++el) {
+                const int e = (l0 + el / nk) * Nu + k0 + el % nk, q0 = c->mp_off[e], cnt = c->mp_off[e + 1] - q0;
+                info[el] = cnt | (i0 << 4) | (i1 << 18);
+                for (int s = 0; s < cnt; ++s) {
+                    const int r = s == 0 ? i0 : i1 + s - 1;
+                    rq[r] = q0 + s;
+                    re[r] = el;
+                }
+                if (cnt > 0) { ++i0; i1 += cnt - 1; }
+            }
+        }
+    }
     c->hu = hu;
     c->hv = hv;
     *out = c;
@@ -577,6 +622,7 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
         {B.mass, c->mass.data(), 8 * c->mass.size()}, {B.hbend, c->hbend.data(), 8 * c->hbend.size()},
         {B.mp_K, c->mp_K.data(), 8 * c->mp_K.size()}, {B.be_L, c->be_L.data(), 8 * c->be_L.size()},
         {B.rest, c->rest.data(), 8 * c->rest.size()},
+        {B.asm_tab, c->asm_tab.data(), 4 * c->asm_tab.size()},
     };
     for (const Up &u : ups) {
         if (u.n == 0) continue;
@@ -615,6 +661,7 @@ bsc_status bsc_bind_workspace(bsc_ctx *c, void *d_ws, size_t bytes) {
     S.mp_K = S.curved ? B.mp_K : nullptr;
     S.be_L = S.curved ? B.be_L : nullptr;
     S.rest = S.curved ? B.rest : nullptr;
+    for (int kind = 0; kind < 3; ++kind) S.asm_tab[kind] = B.asm_tab + c->asm_tab_off[kind];
     return BSC_OK;
 }
 
