@@ -404,8 +404,19 @@ static_assert(kBlock == 256, "the warm start's decision takes one wave per parti
 __device__ double ws_decide(const double *__restrict__ part, int stride, int nb, double bb, double tot[4]) {
     __shared__ double sm[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the lane's elements t = lane, lane + 64, ... added in that order; loaded eight at a time so
+    // that their latencies overlap
+    const double *pw_ = part + size_t(w) * stride;
     double s = 0.0;
-    for (int t = lane; t < nb; t += 64) s += part[w * stride + t];
+    int t = lane;
+    for (; t + 7 * 64 < nb; t += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = pw_[t + 64 * k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; t < nb; t += 64) s += pw_[t];
     s = wave_sum_all(s);
     if (lane == 0) sm[w] = s;
     __syncthreads();
