@@ -379,7 +379,8 @@ struct CpTerms {
 // per-CP terms (their energy partials in partial array 2, cp_blocks of them); element gather;
 // tiled assembly, after a points pass with cpt, of the per-CP gradient (membrane stresses plus
 // B.gpre) and (hess != NULL) the upper-stencil Hessian blocks (kind: AsmKind; gnorm: also
-// per-tile partials of |g|^2); energy reduction (n_cp_partials: cp_blocks after a points pass
+// per-tile partials of |g|^2; out_e: the energy of the points pass, summed by the tile kernel's
+// block 0, where no |g|^2 is needed); energy reduction (n_cp_partials: cp_blocks after a points pass
 // with cpt, else 0; n_gg_partials: the tile count of an assembly run with gnorm, summed into
 // out_gg; with pub the solver scalars and flags are then published to the host in the same
 // launch). The mixed-precision Newton points: FP64 arithmetic, FP32 Hessian and FP64 stresses
@@ -390,7 +391,7 @@ hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double
 int assemble_tiles(const DevSheet &S, int kind);
 int cp_blocks(const DevSheet &S);
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
-                           hipStream_t st, bool gnorm = false);
+                           hipStream_t st, bool gnorm = false, double *out_e = nullptr);
 hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, int n_gg_partials, double *out,
                                 hipStream_t st, double *out_gg = nullptr, const PubPtrs *pub = nullptr);
 hipError_t launch_elem(const DevSheet &S, const DevBufs &B, int precision, void *eE, void *eg, void *eH,

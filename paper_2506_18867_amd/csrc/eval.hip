@@ -634,6 +634,14 @@ __global__ void __launch_bounds__(kBlock) k_points(DevSheet S, const double *__r
     if (threadIdx.x == 0) (role == 2 ? pc : (role == 0 ? pm : pb))[blk] = s;
 }
 
+// The energy of an assembly without |g|^2 (bsc_assemble), summed by the tile kernel's block 0
+// from the points pass's partials (membrane, bending, CPs) in a fixed order; out null: none.
+struct EnergySum {
+    const double *p0, *p1, *p2;
+    int n0, n1, n2;
+    double *out;
+};
+
 // ---- stage 2, tiled: Hessian blocks from LDS, gradient ------------------------------------------
 //
 // One workgroup per tile of kAsmTileU x ty CPs. The membrane points of the elements that the
@@ -650,7 +658,7 @@ template <typename TA, typename TP, typename TG, bool CURVED>
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int kind, const TA *__restrict__ ptA,
                                                                const TP *__restrict__ ptP, const double *__restrict__ gpre,
                                                                double inv_dt2, TA *__restrict__ hess, TG *__restrict__ gout,
-                                                               double *__restrict__ gg_partials) {
+                                                               double *__restrict__ gg_partials, EnergySum esum) {
     constexpr bool STAGE_DN = sizeof(TA) == 4;
     // kind of record (see AsmLds): FP32, mixed (float Hessian, double stress) or FP64
     constexpr int KIND = sizeof(TA) == 4 ? (sizeof(TP) == 4 ? kAsmF32 : kAsmMixed) : kAsmF64;
@@ -922,6 +930,15 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_tile(DevSheet S, int k
         const double gg = block_sum(gg_loc, sh);
         if (threadIdx.x == 0) gg_partials[blockIdx.x] = gg;
     }
+    // the energy from the points pass's partials, complete before this launch began
+    if (esum.out && blockIdx.x == 0) {
+        double v = 0.0;
+        for (int t = threadIdx.x; t < esum.n0; t += blockDim.x) v += esum.p0[t];
+        for (int t = threadIdx.x; t < esum.n1; t += blockDim.x) v += esum.p1[t];
+        for (int t = threadIdx.x; t < esum.n2; t += blockDim.x) v += esum.p2[t];
+        const double e = block_sum(v, sh);
+        if (threadIdx.x == 0) esum.out[0] = e;
+    }
 }
 
 // ---- per-element outputs -------------------------------------------------------------------
@@ -1082,21 +1099,23 @@ int assemble_tiles(const DevSheet &S, int kind) {
 }
 
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
-                           hipStream_t st, bool gnorm) {
+                           hipStream_t st, bool gnorm, double *out_e) {
     double *pg = gnorm ? B.partials + 3 * B.max_blocks : nullptr;
+    const EnergySum esum{B.partials, B.partials + B.max_blocks, B.partials + 2 * B.max_blocks, blocks(S.n_mp), blocks(S.n_be),
+                         cp_blocks(S), out_e};
     const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], kind, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
     auto go = [&](auto curved) {
         constexpr bool CV = decltype(curved)::value;
         if (kind == kAsmF32)
             k_assemble_tile<float, float, float, CV><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, (const float *)B.ptP, B.gpre, inv_dt2, (float *)hess, (float *)g, pg);
+                S, kind, (const float *)B.ptA, (const float *)B.ptP, B.gpre, inv_dt2, (float *)hess, (float *)g, pg, esum);
         else if (kind == kAsmF64)
             k_assemble_tile<double, double, double, CV><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const double *)B.ptA, (const double *)B.ptP, B.gpre, inv_dt2, (double *)hess, (double *)g, pg);
+                S, kind, (const double *)B.ptA, (const double *)B.ptP, B.gpre, inv_dt2, (double *)hess, (double *)g, pg, esum);
         else
             k_assemble_tile<float, double, double, CV><<<nt, kAsmThreads, lds, st>>>(
-                S, kind, (const float *)B.ptA, B.ptP64, B.gpre, inv_dt2, (float *)hess, (double *)g, pg);
+                S, kind, (const float *)B.ptA, B.ptP64, B.gpre, inv_dt2, (float *)hess, (double *)g, pg, esum);
     };
     if (S.curved) go(std::true_type{});
     else go(std::false_type{});
@@ -1164,9 +1183,7 @@ bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const 
                               "eval points");
     if (st != BSC_OK) return st;
     const int kind = precision == BSC_FP64 ? kAsmF64 : kAsmF32;
-    st = hip_check(c, launch_assemble(S, c->buf, kind, inv_dt2, d_grad, d_hess, c->stream), "assemble");
-    if (st != BSC_OK) return st;
-    return hip_check(c, launch_energy_reduce(S, c->buf, cp_blocks(S), 0, d_energy, c->stream), "energy reduce");
+    return hip_check(c, launch_assemble(S, c->buf, kind, inv_dt2, d_grad, d_hess, c->stream, false, d_energy), "assemble");
 }
 
 }  // extern "C"
