@@ -367,7 +367,7 @@ __device__ __forceinline__ void publish_block(const double *scal, int32_t *flags
 
 // The per-CP terms of an assembly that need no quadrature point: the bending gradient K_b d, the
 // inertia M (x - xhat) / dt^2 (when xhat is given) and the gravity load -M g, summed into gpre
-// ([3][n_cp], double), with their energies.
+// ([3][n_cp], double), with their energies (the bending energy as d^T K_b d / 2).
 struct CpTerms {
     const double *xhat;
     double inv_dt2, gx, gy, gz;
@@ -375,8 +375,9 @@ struct CpTerms {
 };
 
 // ---- launchers (eval.hip) ----
-// Membrane points (w Psi, w P and, with hess, w A+), bending evaluations and, with cpt, the
-// per-CP terms (their energy partials in partial array 2, cp_blocks of them); element gather;
+// Membrane points (w Psi, w P and, with hess, w A+) and either the bending evaluations or, with
+// cpt, the per-CP terms (bending energy included; their energy partials in partial array 2,
+// cp_blocks of them); element gather;
 // tiled assembly, after a points pass with cpt, of the per-CP gradient (membrane stresses plus
 // B.gpre) and (hess != NULL) the upper-stencil Hessian blocks (kind: AsmKind; gnorm: also
 // per-tile partials of |g|^2; out_e: the energy of the points pass, summed by the tile kernel's

@@ -556,9 +556,11 @@ __device__ __forceinline__ double displacement_c(const DevSheet &S, const double
 // quadratic in the displacement d = x - X and zero at rest, so its gradient is exactly K_b d, the
 // constant bending stencil (a scalar times I3 per block, built at create from the same bending
 // evaluations) over the 25 neighbours; then the inertia M (x - xhat) / dt^2 and the gravity load
-// -M g (Sec. 3.2, the incremental potential). Returns the CP's inertia and gravity energy. Every
-// neighbour is read (an absent one reads CP a and its term is discarded by a select), so the
-// loads carry no branches and issue in a few batches.
+// -M g (Sec. 3.2, the incremental potential). Returns the CP's share of the energy of these terms:
+// inertia, gravity and d_a . (K_b d)_a / 2, so that the CPs' shares sum to the bending energy
+// (the bending evaluations are then not needed in an assembly). Every neighbour is read (an
+// absent one reads CP a and its term is discarded by a select), so the loads carry no branches
+// and issue in a few batches.
 template <bool CURVED>
 __device__ __forceinline__ double cp_terms(const DevSheet &S, const double *__restrict__ x, const CpTerms &C, int a) {
     double e_loc = 0.0;
@@ -584,6 +586,10 @@ __device__ __forceinline__ double cp_terms(const DevSheet &S, const double *__re
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) accb[cc] += okc ? w2 * d[cc] : 0.0;
         }
+        // the bending energy: quadratic in d with the same stencil, 1/2 d^T K_b d, this CP's share
+        double dself[3];
+        displacement_t<CURVED>(S, x, i, j, dself);
+        e_loc += 0.5 * (dself[0] * accb[0] + dself[1] * accb[1] + dself[2] * accb[2]);
         const double M = S.mass[a];
         const double grav[3] = {C.gx, C.gy, C.gz};
 #pragma unroll
@@ -1048,7 +1054,8 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
     // Partials layout: [0] membrane, [1] bending, [2] per-CP terms, [3] assembly tiles (|g|^2);
     // [4..7] are free for the kernels that follow (the warm start's dot products).
     double *pm = B.partials, *pb = B.partials + B.max_blocks, *pc = B.partials + 2 * B.max_blocks;
-    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + (bending ? blocks(S.n_be) : 0);
+    // with the per-CP terms the bending energy comes from the stencil: no bending blocks
+    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + (bending && !cpt ? blocks(S.n_be) : 0);
     const CpTerms Ct = cpt ? *cpt : CpTerms{nullptr, 0.0, 0.0, 0.0, 0.0, nullptr};
     auto go = [&](auto curved, auto bend) {
         constexpr bool C = decltype(curved)::value, BE = decltype(bend)::value;
@@ -1082,7 +1089,7 @@ hipError_t launch_points(const DevSheet &S, const DevBufs &B, int precision, boo
 // FP64 gradient) stored in double and the projected density Hessian stored in float.
 hipError_t launch_points_mixed(const DevSheet &S, const DevBufs &B, const double *x, hipStream_t st, const CpTerms *cpt) {
     double *pm = B.partials, *pb = B.partials + B.max_blocks, *pc = B.partials + 2 * B.max_blocks;
-    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + blocks(S.n_be);
+    const int ncb = cpt ? cp_blocks(S) : 0, nbm = blocks(S.n_mp), nb = ncb + nbm + (cpt ? 0 : blocks(S.n_be));
     const CpTerms Ct = cpt ? *cpt : CpTerms{nullptr, 0.0, 0.0, 0.0, 0.0, nullptr};
     auto go = [&](auto curved) {
         constexpr bool C = decltype(curved)::value;
@@ -1101,8 +1108,8 @@ int assemble_tiles(const DevSheet &S, int kind) {
 hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double inv_dt2, void *g, void *hess,
                            hipStream_t st, bool gnorm, double *out_e) {
     double *pg = gnorm ? B.partials + 3 * B.max_blocks : nullptr;
-    const EnergySum esum{B.partials, B.partials + B.max_blocks, B.partials + 2 * B.max_blocks, blocks(S.n_mp), blocks(S.n_be),
-                         cp_blocks(S), out_e};
+    const EnergySum esum{B.partials, B.partials + B.max_blocks, B.partials + 2 * B.max_blocks, blocks(S.n_mp), 0, cp_blocks(S),
+                         out_e};
     const size_t lds = asm_lds_layout(kAsmTileU, S.asm_ty[kind], S.asm_maxp[kind], kind, S.curved != 0).total;
     const int nt = assemble_tiles(S, kind);
     auto go = [&](auto curved) {
@@ -1125,7 +1132,7 @@ hipError_t launch_assemble(const DevSheet &S, const DevBufs &B, int kind, double
 hipError_t launch_energy_reduce(const DevSheet &S, const DevBufs &B, int n_cp_partials, int n_gg_partials, double *out,
                                 hipStream_t st, double *out_gg, const PubPtrs *pub) {
     static_assert(kBlock >= kScalars, "the read-back copies one scalar per thread");
-    k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, blocks(S.n_be),
+    k_reduce<<<1, kBlock, 0, st>>>(B.partials, blocks(S.n_mp), B.partials + B.max_blocks, n_cp_partials ? 0 : blocks(S.n_be),
                                    B.partials + 2 * B.max_blocks, n_cp_partials, out,
                                    out_gg ? B.partials + 3 * B.max_blocks : nullptr, n_gg_partials, out_gg, B.scalars,
                                    B.iscalars, pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0);
@@ -1179,7 +1186,7 @@ bsc_status bsc_assemble(bsc_ctx *c, int32_t precision, const double *d_x, const 
     const DevSheet &S = c->dev;
     const CpTerms cpt{d_xhat, inv_dt2, gravity ? gravity[0] : 0.0, gravity ? gravity[1] : 0.0, gravity ? gravity[2] : 0.0,
                       c->buf.gpre};
-    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream, true, &cpt),
+    bsc_status st = hip_check(c, launch_points(S, c->buf, precision, d_hess != nullptr, false, d_x, c->stream, false, &cpt),
                               "eval points");
     if (st != BSC_OK) return st;
     const int kind = precision == BSC_FP64 ? kAsmF64 : kAsmF32;

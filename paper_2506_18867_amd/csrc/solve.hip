@@ -840,20 +840,22 @@ __global__ void k_phat(int n_cp, const float *__restrict__ out, const int32_t *_
 
 // The energy difference along p is dE(alpha) = alpha c1 + alpha^2 c2 / 2 for the inertia,
 // gravity and bending terms (quadratics in alpha) plus the membrane term, summed point by point.
-// Per CP, in one pass over p: partials of c1 and c2 of the inertia and gravity terms and of
-// max |p| (the stop tests).
-__device__ __forceinline__ void ls_cp_block(const DevSheet &S, const double *__restrict__ x, const double *__restrict__ xhat,
-                                            const double *__restrict__ p, double inv_dt2, double gx, double gy, double gz,
-                                            double *partials, int stride, double *__restrict__ pmax_part, int blk) {
+// Per CP, in one pass over p: partials of c1 = gpre . p over the quadratic terms (gpre: the
+// assembly's per-CP gradient terms at x, bending included), of the inertia's part of c2,
+// M p . p / dt^2, and of max |p| (the stop tests). The bending part of c2 comes from the
+// bending evaluations (ls_bend_block).
+__device__ __forceinline__ void ls_cp_block(const DevSheet &S, const double *__restrict__ gpre, const double *__restrict__ p,
+                                            double inv_dt2, double *partials, int stride, double *__restrict__ pmax_part,
+                                            int blk) {
     __shared__ double sh[kBlock / 64];
     const int a = blk * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
     double c1 = 0.0, c2 = 0.0, m = 0.0;
     if (a < S.n_cp) {
-        const double M = S.mass[a], g[3] = {gx, gy, gz};
+        const double M = S.mass[a];
         for (int c = 0; c < 3; ++c) {
             const double pc = p[c * n + a];
-            c1 += M * inv_dt2 * pc * (x[c * n + a] - xhat[c * n + a]) - M * g[c] * pc;
+            c1 += gpre[c * n + a] * pc;
             c2 += M * inv_dt2 * pc * pc;
             m = fmax(m, fabs(pc));
         }
@@ -872,10 +874,9 @@ __device__ __forceinline__ void ls_cp_block(const DevSheet &S, const double *__r
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
-                                                  const double *__restrict__ p, double inv_dt2, double gx, double gy,
-                                                  double gz, double *partials, int stride, double *__restrict__ pmax_part) {
-    ls_cp_block(S, x, xhat, p, inv_dt2, gx, gy, gz, partials, stride, pmax_part, blockIdx.x);
+__global__ void __launch_bounds__(kBlock) k_ls_cp(DevSheet S, const double *__restrict__ gpre, const double *__restrict__ p,
+                                                  double inv_dt2, double *partials, int stride, double *__restrict__ pmax_part) {
+    ls_cp_block(S, gpre, p, inv_dt2, partials, stride, pmax_part, blockIdx.x);
 }
 
 // The line-search scalars in one block, each in a fixed order: max |p| (exact in any order),
@@ -936,14 +937,14 @@ __global__ void __launch_bounds__(kBlock) k_ls_finish(const double *__restrict__
     if (threadIdx.x == 0) { scal[S_PMAX] = r[0]; scal[S_C1] = r[1]; scal[S_C2] = r[2]; scal[S_DEM] = r[3]; }
 }
 
-// Per bending evaluation: partials of c1 and c2 of the bending term, whose Laplacian is linear
-// in the CPs.
-__device__ __forceinline__ void ls_bend_block(const DevSheet &S, const double *__restrict__ beD, const double *__restrict__ p,
-                                              double *partials, int stride, int blk) {
+// Per bending evaluation: partials of the bending term's c2 = sum_q w mu |Laplacian(p)|^2 (its
+// Laplacian is linear in the CPs); its c1 is part of gpre . p. The c1 partial is zero.
+__device__ __forceinline__ void ls_bend_block(const DevSheet &S, const double *__restrict__ p, double *partials, int stride,
+                                              int blk) {
     __shared__ double sh[kBlock / 64];
     const int q = blk * blockDim.x + threadIdx.x;
     const size_t n = S.n_cp;
-    double c1 = 0.0, c2 = 0.0;
+    double c2 = 0.0;
     if (q < S.n_be) {
         const int e = S.be_elem[q], k = e % S.Nu, l = e / S.Nu;
         // Laplacian weights of the 9 local CPs (the same as the bending kernel's)
@@ -955,19 +956,14 @@ __device__ __forceinline__ void ls_bend_block(const DevSheet &S, const double *_
             for (int c = 0; c < 3; ++c) lp[c] += L[m] * p[c * n + cp];
         }
         const double wm = S.be_w[q] * S.mu_bend;
-        for (int c = 0; c < 3; ++c) {
-            c1 += beD[c * S.n_be + q] * lp[c];     // beD = w mu Laplacian(phi(x))
-            c2 += wm * lp[c] * lp[c];
-        }
+        for (int c = 0; c < 3; ++c) c2 += wm * lp[c] * lp[c];
     }
-    c1 = block_sum(c1, sh);
     c2 = block_sum(c2, sh);
-    if (threadIdx.x == 0) { partials[blk] = c1; partials[stride + blk] = c2; }
+    if (threadIdx.x == 0) { partials[blk] = 0.0; partials[stride + blk] = c2; }
 }
 
-__global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const double *__restrict__ beD, const double *__restrict__ p,
-                                                         double *partials, int stride) {
-    ls_bend_block(S, beD, p, partials, stride, blockIdx.x);
+__global__ void __launch_bounds__(kBlock) k_ls_quad_bend(DevSheet S, const double *__restrict__ p, double *partials, int stride) {
+    ls_bend_block(S, p, partials, stride, blockIdx.x);
 }
 
 // Membrane energy difference sum_q w (Psi(F + alpha dF) - Psi(F)) in double.
@@ -1046,15 +1042,14 @@ __global__ void __launch_bounds__(kBlock) k_ls_membrane(DevSheet S, const double
 // The line-search set-up in one launch, gated by the solve's done flag (the end of a PCG burst):
 // blocks [0, nbc) the CP terms, [nbc, nbc + nbb) the bending terms, the rest the membrane
 // energy difference at alpha = 1; each block writes the partial slot its own launch would.
-__global__ void __launch_bounds__(kBlock) k_ls_setup(DevSheet S, const double *__restrict__ x, const double *__restrict__ xhat,
-                                                     const double *__restrict__ p, double inv_dt2, double gx, double gy,
-                                                     double gz, double *pa, int stride, double *__restrict__ pmax_part,
-                                                     const double *__restrict__ beD, double *pbend, double *pmem, int nbc, int nbb,
+__global__ void __launch_bounds__(kBlock) k_ls_setup(DevSheet S, const double *__restrict__ x, const double *__restrict__ gpre,
+                                                     const double *__restrict__ p, double inv_dt2, double *pa, int stride,
+                                                     double *__restrict__ pmax_part, double *pbend, double *pmem, int nbc, int nbb,
                                                      const int32_t *__restrict__ gate) {
     if (!gate[I_DONE]) return;
     const int b = blockIdx.x;
-    if (b < nbc) ls_cp_block(S, x, xhat, p, inv_dt2, gx, gy, gz, pa, stride, pmax_part, b);
-    else if (b < nbc + nbb) ls_bend_block(S, beD, p, pbend, stride, b - nbc);
+    if (b < nbc) ls_cp_block(S, gpre, p, inv_dt2, pa, stride, pmax_part, b);
+    else if (b < nbc + nbb) ls_bend_block(S, p, pbend, stride, b - nbc);
     else ls_membrane_block(S, x, p, 1.0, pmem, b - nbc - nbb);
 }
 
@@ -1178,14 +1173,14 @@ bsc_status assemble_iter(bsc_ctx *ctx, int prec, const double *x, const double *
     // FP32-mixed: the points in FP64 arithmetic, the Hessian stored in FP32 and the stresses (for
     // the FP64 gradient and energy) in FP64
     const CpTerms cpt{xhat, inv_dt2, grav ? grav[0] : 0.0, grav ? grav[1] : 0.0, grav ? grav[2] : 0.0, B.gpre};
-    if (prec == BSC_FP64) HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, true, &cpt), "points");
+    if (prec == BSC_FP64) HIPX(launch_points(S, B, BSC_FP64, true, false, x, st, false, &cpt), "points");
     else HIPX(launch_points_mixed(S, B, x, st, &cpt), "points");
     const int kind = prec == BSC_FP64 ? kAsmF64 : kAsmMixed;
     HIPX(launch_assemble(S, B, kind, inv_dt2, B.g, B.hess, st, true), "assemble");
     if (red) {
         // the same arrays and counts as launch_energy_reduce
         const int mb = B.max_blocks;
-        *red = EnergyRed{B.partials, B.partials + mb, B.partials + 2 * mb, B.partials + 3 * mb, blocks(S.n_mp), blocks(S.n_be),
+        *red = EnergyRed{B.partials, B.partials + mb, B.partials + 2 * mb, B.partials + 3 * mb, blocks(S.n_mp), 0,
                          cp_blocks(S), assemble_tiles(S, kind), B.scalars + S_E, B.scalars + S_GG,
                          pub ? *pub : PubPtrs{nullptr, nullptr, nullptr}, pub ? 1 : 0};
         return BSC_OK;
@@ -1207,7 +1202,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     const int prec = o->precision;
     const double dt = o->dt, inv_dt2 = 1.0 / (dt * dt);
     const double *grav = o->gravity;
-    const double gx = grav ? grav[0] : 0.0, gy = grav ? grav[1] : 0.0, gz = grav ? grav[2] : 0.0;
     const int stride = B.max_blocks;
     const bool step_rule = o->fixed_newton_iters <= 0 && o->stop_mode == BSC_STOP_STEP;
     // With the step rule nothing the host decides before the solve depends on the assembly: the
@@ -1476,9 +1470,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // (partial arrays: c1, c2 of the CPs at 3, 4; of the bending at 5, 6; max |p| at 7; the
         // membrane difference at 0, free once PCG has finished)
         auto enqueue_ls = [&](hipStream_t cs) {
-            k_ls_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
-                                                        B.partials + 7 * stride);
-            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.beD, B.dir, pbend, stride);
+            k_ls_cp<<<blocks(S.n_cp), kBlock, 0, cs>>>(S, B.gpre, B.dir, inv_dt2, pa, stride, B.partials + 7 * stride);
+            k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, cs>>>(S, B.dir, pbend, stride);
             k_ls_membrane<<<blocks(S.n_mp), kBlock, 0, cs>>>(S, x, B.dir, 1.0, B.partials);
             k_ls_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pbend, blocks(S.n_be), stride,
                                                B.partials, blocks(S.n_mp), B.scalars);
@@ -1490,8 +1483,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             if (ls_dev) {
                 hipEvent_t la = rec();
                 const int nbc_ = blocks(S.n_cp), nbb_ = blocks(S.n_be), nbm_ = blocks(S.n_mp);
-                k_ls_setup<<<nbc_ + nbb_ + nbm_, kBlock, 0, st>>>(S, x, B.xhat, B.dir, inv_dt2, gx, gy, gz, pa, stride,
-                                                                  B.partials + 7 * stride, B.beD, pbend, B.partials, nbc_, nbb_,
+                k_ls_setup<<<nbc_ + nbb_ + nbm_, kBlock, 0, st>>>(S, x, B.gpre, B.dir, inv_dt2, pa, stride,
+                                                                  B.partials + 7 * stride, pbend, B.partials, nbc_, nbb_,
                                                                   B.iscalars);
                 k_ls_accept<<<blocks(n3), kBlock, 0, st>>>(n3, B.iscalars, B.scalars, B.partials + 7 * stride, nbc_, pa, pbend,
                                                            nbb_, stride, B.partials, nbm_, B.dir, x,
@@ -1860,14 +1853,14 @@ bsc_status bsc_energy_difference(bsc_ctx *c, const double *d_x, const double *d_
     const DevBufs &B = c->buf;
     hipStream_t st = c->stream;
     const int stride = B.max_blocks;
-    // the bending term's coefficients need w mu Laplacian(phi(x)) at every bending evaluation
-    bsc_status r = hip_check(c, launch_points(S, B, BSC_FP64, false, false, d_x, st, true), "energy difference points");
+    // c1 of the quadratic terms needs their gradient at x: the per-CP terms of the points pass
+    // (without xhat the inertia term is dropped: inv_dt2 = 0)
+    const CpTerms cpt{d_xhat, inv_dt2, gx, gy, gz, B.gpre};
+    bsc_status r = hip_check(c, launch_points(S, B, BSC_FP64, false, false, d_x, st, false, &cpt), "energy difference points");
     if (r != BSC_OK) return r;
     double *pa = B.partials + 3 * stride, *pb = B.partials + 5 * stride;
-    // without xhat the inertia term is dropped: inv_dt2 = 0 and x stands in for xhat
-    k_ls_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, d_x, d_xhat ? d_xhat : d_x, d_p, inv_dt2, gx, gy, gz, pa, stride,
-                                                B.partials + 7 * stride);
-    k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, B.beD, d_p, pb, stride);
+    k_ls_cp<<<blocks(S.n_cp), kBlock, 0, st>>>(S, B.gpre, d_p, inv_dt2, pa, stride, B.partials + 7 * stride);
+    k_ls_quad_bend<<<blocks(S.n_be), kBlock, 0, st>>>(S, d_p, pb, stride);
     k_ls_finish<<<1, kBlock, 0, st>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pb, blocks(S.n_be), stride,
                                       B.partials, 0, B.scalars);
     for (int k = 0; k < n_alpha; ++k) {
