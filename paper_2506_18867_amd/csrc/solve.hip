@@ -399,16 +399,17 @@ __device__ double forcing_term(int mode, int first, double eta_host, double rtol
 // entries l, l + 64, ... in order, then the butterfly sum) give gp = g.p, pw = p.Hp, gw = g.Hp,
 // ww = |Hp|^2; with bb = |g|^2 the energy-optimal multiple a = -gp / pw (either sign) gives the
 // initial residual |b - a Hp|^2 = bb + 2 a gw + a^2 ww with b = -g. The start x0 = a p is kept
-// only when that is below bb (the zero start's residual), else a = 0. Needs 256 threads.
-static_assert(kBlock == 256, "the warm start's decision takes one wave per partial array");
+// only when that is below bb (the zero start's residual), else a = 0. Needs at least 256
+// threads (waves after the fourth add nothing).
+static_assert(kBlock >= 256, "the warm start's decision takes one wave per partial array");
 __device__ double ws_decide(const double *__restrict__ part, int stride, int nb, double bb, double tot[4]) {
     __shared__ double sm[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // the lane's elements t = lane, lane + 64, ... added in that order; loaded eight at a time so
     // that their latencies overlap
-    const double *pw_ = part + size_t(w) * stride;
+    const double *pw_ = part + size_t(w < 4 ? w : 0) * stride;
     double s = 0.0;
-    int t = lane;
+    int t = w < 4 ? lane : nb;                    // one wave per array; further waves add nothing
     for (; t + 7 * 64 < nb; t += 8 * 64) {
         double v[8];
 #pragma unroll
@@ -418,7 +419,7 @@ __device__ double ws_decide(const double *__restrict__ part, int stride, int nb,
     }
     for (; t < nb; t += 64) s += pw_[t];
     s = wave_sum_all(s);
-    if (lane == 0) sm[w] = s;
+    if (lane == 0 && w < 4) sm[w] = s;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) tot[k] = sm[k];
@@ -528,6 +529,13 @@ struct CgBufs {
     const double *pre;                            // the sums of part_in (large grids), or null
     int stride, nb_init;
     int slot_in, slot_out;                        // iteration-counter slots (alternate)
+    // K_0 with the set-up folded in (fold != 0; otherwise k_cg_init ran before it): r_0 = b - a hq
+    // formed on every footprint and x_0 = a ph, with the multiple a decided in every block from
+    // the warm start's dot-product partials (wpart; ph null: a = 0), then the gradient stop, the
+    // forcing term, the tolerance rtol^2 |g|^2 (b = -g) and the flags by block 0
+    const double *b, *hq, *ph, *wpart;
+    int fold, wstride, wnb, maxit, eta_mode, first;
+    double eta_host, rtol_min, eta_max, grad_rtol;
 };
 
 template <typename T, bool FIRST>
@@ -541,7 +549,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     __shared__ double u64[3][R];
     __shared__ T ys[8][3][64];
     __shared__ double sh[48];
-    if (isc[I_DONE]) return;
+    const bool fold = FIRST && B.fold;
+    if (!fold && isc[I_DONE]) return;
     const T *__restrict__ w_in = (const T *)B.w_in;
     const T *__restrict__ pinv = (const T *)B.pinv;
     T *__restrict__ w_out = (T *)B.w_out;
@@ -576,7 +585,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                 v[2] += B.part_in[2 * B.stride + t];
             }
         }
-    } else if (blockIdx.x == 0) {
+    } else if (blockIdx.x == 0 && !fold) {
         for (int t = threadIdx.x; t < B.nb_init; t += blockDim.x) v[0] += B.pbb[t];
     }
     // wave sums now, so that only the partials are waited for; the cross-wave half of the
@@ -602,9 +611,24 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     double rin[3] = {0.0, 0.0, 0.0}, sin_[3] = {0.0, 0.0, 0.0};
     double po[3] = {0.0, 0.0, 0.0}, xo[3] = {0.0, 0.0, 0.0};
     T win_t[3] = {T(0), T(0), T(0)}, pv_t[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    double hqf[3] = {0.0, 0.0, 0.0}, phf[3] = {0.0, 0.0, 0.0};
     if (fp) {
+        if (fold) {
+            // r_0 = b - a hq once a is known (below); b into rin for now
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rin[c] = B.r_in[c * n + fa];
+            for (int c = 0; c < 3; ++c) rin[c] = B.b[c * n + fa];
+            if (B.ph) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hqf[c] = B.hq[c * n + fa];
+                if (own) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) phf[c] = B.ph[c * n + fa];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rin[c] = B.r_in[c * n + fa];
+        }
 #pragma unroll
         for (int k = 0; k < 6; ++k) pv_t[k] = pinv[k * n + fa];
         if (!FIRST) {
@@ -672,11 +696,45 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             scal[S_RHO] = rho;                    // |r|^2 of iteration j-1: read by the host between bursts
             isc[B.slot_out] = it + 1;
         }
-    } else if (blockIdx.x == 0) {                 // uniform per block
-        wave_totals3(v, sh);
-        if (threadIdx.x == 0) {
-            scal[S_TOL2] = scal[S_RTOL] * scal[S_RTOL] * v[0];
-            isc[B.slot_out] = 0;
+    } else if (!fold) {
+        if (blockIdx.x == 0) {                    // uniform per block
+            wave_totals3(v, sh);
+            if (threadIdx.x == 0) {
+                scal[S_TOL2] = scal[S_RTOL] * scal[S_RTOL] * v[0];
+                isc[B.slot_out] = 0;
+            }
+        }
+    }
+    // the folded set-up (the same decisions as k_cg_init, made by every block alike)
+    double ws = 0.0;
+    bool gstop = false;
+    if (fold) {
+        const double gg = scal[S_GG], gn0 = sqrt(gg);
+        gstop = B.grad_rtol > 0.0 && (gn0 == 0.0 || (!B.first && gn0 <= B.grad_rtol * scal[S_G0]));
+        double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        if (B.ph && !gstop) ws = ws_decide(B.wpart, B.wstride, B.wnb, gg, tot);
+        if (lead) {
+            if (B.ph) {
+                if (!gstop) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) scal[S_WS0 + k] = tot[k];
+                }
+                scal[S_WSA] = ws;
+                isc[I_WS] = ws != 0.0 ? 1 : 0;
+            }
+            isc[I_ITA] = 0; isc[I_ITB] = 0; isc[I_BREAK] = 0; isc[I_MAXIT] = B.maxit; isc[I_ITERS] = 0;
+            const double eta = forcing_term(B.eta_mode, B.first, B.eta_host, B.rtol_min, B.eta_max, gn0, scal[S_GPREV],
+                                            scal[S_ETA]);
+            scal[S_RTOL] = eta;
+            scal[S_ETA] = eta;
+            scal[S_GPREV] = gn0;
+            scal[S_TOL2] = eta * eta * gg;        // b = -g: |b|^2 = |g|^2
+            if (B.first) scal[S_G0] = gn0;
+            isc[I_DONE] = gstop ? 1 : 0;
+        }
+        if (ws != 0.0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rin[c] = rin[c] - ws * hqf[c];
         }
     }
 
@@ -699,6 +757,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             uv[1] = pv[1] * rv[0] + pv[3] * rv[1] + pv[4] * rv[2];
             uv[2] = pv[2] * rv[0] + pv[4] * rv[1] + pv[5] * rv[2];
             if (own) {
+                if (fold) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const size_t k = c * n + fa;
+                        B.x[k] = ws * phf[c];
+                        B.r_out[k] = rv[c];
+                        B.p[k] = 0.0;
+                        B.s_out[k] = 0.0;
+                    }
+                }
                 if (!FIRST) {
                     double uo[3];
                     uo[0] = pv[0] * rin[0] + pv[1] * rin[1] + pv[2] * rin[2];
@@ -727,6 +795,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int c = 0; c < 3; ++c) us[c][hy][hx] = T(uv[c]);
     }
     __syncthreads();
+    if (gstop) return;                            // uniform: the iterate already meets the stop
 
     // (4) w = A u for the wave's block products, u from LDS. In FP32, out-of-grid neighbours read
     //     a valid row and take u = 0, so the body has no data-dependent branch and the compiler
@@ -1382,16 +1451,19 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                                                B.iscalars);
             red.out = nullptr;
         };
-        // r = b - A x0 (x0 = a ph with the decided multiple, when ph is given), the tolerance, and
-        // the first CG launch (it forms w_0)
+        // the first CG launch (it forms w_0) with the set-up folded in: r_0 = b - A x_0 (x_0 = a ph
+        // with the decided multiple, when ph is given), the gradient stop, the tolerance and the flags
         auto enqueue_init = [&](hipStream_t cs, const double *ph) {
-            k_cg_init<<<nbi, kBlock, 0, cs>>>(S, B.tmp, ph, hq, B.partials + 4 * stride, stride, spmv_blocks(S.n_cp), B.dir, rb[0],
-                                               p, sb[0], pbb, B.iscalars, B.scalars, o->max_pcg, eta_mode, first, eta_arg,
-                                               o->pcg_rtol, eta_max, grad_rtol);
+            CgBufs c0 = bufs(0);
+            c0.fold = 1;
+            c0.b = B.tmp; c0.hq = hq; c0.ph = ph;
+            c0.wpart = B.partials + 4 * stride; c0.wstride = stride; c0.wnb = spmv_blocks(S.n_cp);
+            c0.maxit = o->max_pcg; c0.eta_mode = eta_mode; c0.first = first; c0.eta_host = eta_arg;
+            c0.rtol_min = o->pcg_rtol; c0.eta_max = eta_max; c0.grad_rtol = grad_rtol;
             if (prec == BSC_FP64)
-                k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, bufs(0), B.scalars, B.iscalars);
+                k_cg_fused<double, true><<<nbc, 512, 0, cs>>>(S, (const double *)B.hess, c0, B.scalars, B.iscalars);
             else
-                k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, bufs(0), B.scalars, B.iscalars);
+                k_cg_fused<float, true><<<nbc, 512, 0, cs>>>(S, (const float *)B.hess, c0, B.scalars, B.iscalars);
             if (presum) k_cg_sum<<<1, 1024, 0, cs>>>(part[0], stride, nbc, B.iscalars, B.scalars + S_CGSUM);
         };
         // the block-Jacobi solve's set-up (prep, the recycled warm start, init and the first
