@@ -63,7 +63,7 @@ ASM_FLOP_PER_ELEM = 8.5e3
 # was evicted first (`bench.py --copy-probe 1024`: FETCH_SIZE 0.500, WRITE_SIZE 1.000 of the
 # bytes). Summary and commands: profiles/k_cg_fused_226_traffic.md. Valid only for the kernel
 # source it was measured on (hash of its text in solve.hip); otherwise reported as null.
-CG_TRAFFIC = {"kernel_sha256_16": "9020f57fa3cbcbc5", "fetch_kib": 16505.3, "write_kib": 5443.1,
+CG_TRAFFIC = {"kernel_sha256_16": "0899f3d6f38822e8", "fetch_kib": 16697.6, "write_kib": 5443.2,
               "fetch_factor": 0.500, "write_factor": 1.000}
 
 
