@@ -192,6 +192,14 @@ def step_opts(bsc, sc, precision, args, stop="grad", warm=None):
                          start=bsc.BSC_START_PREVIOUS if start == "previous" else bsc.BSC_START_PREDICTOR)
 
 
+def phase_opts(bsc, opts):
+    """A copy of opts that times every phase of the step (GPU events, about 14 per Newton
+    iteration)."""
+    o = type(opts).from_buffer_copy(opts)
+    o.timing = bsc.BSC_TIMING_PHASES
+    return o
+
+
 def timed_step(ctx, x, v, tgt, opts, torch):
     """One implicit-Euler step in place, bracketed by device syncs; returns (seconds, stats dict).
     The stats carry the step's status: a step that did not converge leaves its last iterate in
@@ -374,6 +382,13 @@ def main():
     st32 = [r[1] for r in r32]
     secs = {name: sum(r[0] for r in head[name]) for name in head}
     log("[bench] headline: " + ", ".join(f"{name} {1e3 * secs[name] / args.steps:.3f} ms/step" for name in head))
+    # The headline steps record timing events only around the CG launches (the roofline's kernel
+    # time); the per-phase breakdown needs about 14 events per Newton iteration, each a gap between
+    # two kernels, so it comes from a few more steps of the FP32-mixed legs from the same state.
+    phase_legs = [(name, phase_opts(bsc, o), c) for name, o, c in variants
+                  if name in ("fp32_mixed", "fp32_mixed_zero_start")]
+    n_phase = min(args.steps, 5)
+    phases = paired_steps(ctx, sc, xs.clone(), vs.clone(), args.warmup, n_phase, phase_legs, "fp32_mixed", torch, bsc)
 
     # ---- the same steps under the paper's stopping rule (|p|_inf / dt <= atol) ----
     step_rule = None
@@ -605,8 +620,8 @@ def main():
     pcg32 = sum(s["pcg_iters_total"] for s in st32)
     ms_step32 = 1e3 * sec32 / args.steps
     share_asm = newton32 * ms_asm32 / (1e3 * sec32)
-    share_pcg = sum(s["ms_pcg"] for s in st32) / (1e3 * sec32)
     cg_ms = sum(s["ms_cg_kernels"] for s in st32)
+    share_pcg = cg_ms / (1e3 * sec32)                 # the CG launches' GPU time
     cg_launches = sum(s["cg_launches"] for s in st32)
     cg_active = sum(s["cg_active_launches"] for s in st32)
     if share_pcg >= share_asm and cg_ms > 0:
@@ -621,7 +636,8 @@ def main():
                "avg_ms": ms_asm32}
     roof = {"bound": dom["bound"], "achieved": round(dom["achieved"], 2), "peak": dom["peak"], "unit": dom["unit"],
             "frac": round(dom["achieved"] / dom["peak"], 4), "traffic": None, "kernel": dom["kernel"],
-            "avg_ms": round(dom["avg_ms"], 5), "share_of_step": {"assembly": round(share_asm, 3), "pcg": round(share_pcg, 3)},
+            "avg_ms": round(dom["avg_ms"], 5),
+            "share_of_step": {"assembly": round(share_asm, 3), "cg_launches": round(share_pcg, 3)},
             "frac_of_measured_hbm_copy": round(dom["achieved"] / ceilings["hbm_copy_1gib_gb_s"], 4),
             "frac_of_measured_cache_copy_64mb": round(dom["achieved"] / ceilings["cache_copy_64mb_gb_s"], 4)}
     for k in ("launches", "active_launches", "bytes_per_active_launch"):
@@ -668,11 +684,13 @@ def main():
                      "dx_rel_fp64_vs_fp32": [float("%.3g" % r[2]) for r in r64],
                      "not_converged": {"fp32_mixed": sum(1 for s in st32 if s["status"] != 0),
                                        "fp64": sum(1 for r in r64 if r[1]["status"] != 0)}},
-        "phases_ms_per_step_fp32": {k: round(sum(s[k] for s in st32) / args.steps, 3)
-                                    for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_warmstart", "ms_total")},
-        "phases_ms_per_step_fp32_zero_start": ({k: round(sum(r[1][k] for r in head["fp32_mixed_zero_start"]) / args.steps, 3)
+        "phases_ms_per_step_fp32": dict({k: round(sum(r[1][k] for r in phases["fp32_mixed"]) / n_phase, 3)
+                                         for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_warmstart", "ms_total")},
+                                        steps=n_phase, note="separate steps from the headline's start state with "
+                                                            "every phase timed (events add to ms_total)"),
+        "phases_ms_per_step_fp32_zero_start": ({k: round(sum(r[1][k] for r in phases["fp32_mixed_zero_start"]) / n_phase, 3)
                                                for k in ("ms_assemble", "ms_pcg", "ms_linesearch", "ms_total")}
-                                               if "fp32_mixed_zero_start" in head else None),
+                                               if "fp32_mixed_zero_start" in phases else None),
         "iterations_per_step": {name: {"newton": round(sum(r[1]["newton_iters"] for r in head[name]) / args.steps, 2),
                                        "pcg": round(sum(r[1]["pcg_iters_total"] for r in head[name]) / args.steps, 2),
                                        "warm_used": round(sum(r[1]["warm_start_used"] for r in head[name]) / args.steps, 2),
@@ -680,7 +698,8 @@ def main():
                                        "g_rel_max": float("%.3g" % max(g_rel(r[1]) for r in head[name])),
                                        "not_converged": sum(1 for r in head[name] if r[1]["status"] != 0)}
                                 for name in head},
-        "pcg_us_per_iter_fp32": round(1e3 * sum(s["ms_pcg"] for s in st32) / max(1, pcg32), 3),
+        "pcg_us_per_iter_fp32": round(1e3 * sum(r[1]["ms_pcg"] for r in phases["fp32_mixed"])
+                                      / max(1, sum(r[1]["pcg_iters_total"] for r in phases["fp32_mixed"])), 3),
         "cg_kernel": {"active_us": round(1e3 * cg_ms / max(1, cg_active), 3), "launches": cg_launches,
                       "active_launches": cg_active, "gb_s": round(cg_bytes32 * cg_active / max(cg_ms, 1e-9) / 1e6, 1)},
         "step_rule": step_rule,

@@ -126,10 +126,18 @@ typedef struct {
     int32_t start;              /* BSC_START_PREVIOUS (default) or BSC_START_PREDICTOR */
     double pcg_eta_max;         /* cap of the adaptive PCG tolerance; 0 = 0.5 under BSC_STOP_STEP,
                                    0.1 under BSC_STOP_GRAD; else in [pcg_rtol, 0.9] */
+    int32_t timing;             /* BSC_TIMING_CG (default), BSC_TIMING_PHASES or BSC_TIMING_OFF */
 } bsc_step_opts;
+/* GPU timing of a step (bsc_step_stats). Every timing event is a marker between two kernels on the
+ * context's stream and delays the second by a few microseconds, so the default records only what
+ * ms_cg_kernels needs. CG: one event at the start of each burst of PCG launches and one after its
+ * last CG launch. PHASES: also ms_assemble, ms_pcg, ms_linesearch and ms_warmstart (about 14
+ * events per Newton iteration; diagnostics). OFF: none (the GPU fields of the stats stay 0). */
+enum { BSC_TIMING_CG = 0, BSC_TIMING_PHASES = 1, BSC_TIMING_OFF = 2 };
 
 /* Statistics of one step. ms_assemble, ms_pcg, ms_linesearch and ms_warmstart are GPU phase
- * times from HIP events on the context's stream (read once at the end of the step; ms_warmstart
+ * times from HIP events on the context's stream, recorded under BSC_TIMING_PHASES only (else 0;
+ * read once at the end of the step; ms_warmstart
  * is the network's forward pass, the warm start's product, dots and decision count in ms_pcg;
  * warm_start_used / warm_start_fallbacks count the Newton iterations whose prediction was kept /
  * dropped); ms_total is
@@ -137,8 +145,9 @@ typedef struct {
  * iteration, enqueued in fixed-size chunks; launches after convergence exit at once):
  * cg_launches counts them, cg_active_launches those that performed an iteration, and
  * ms_cg_kernels is their GPU time from HIP events recorded on the context's stream around
- * each burst of chunks (which ends with the kernel that publishes the solver state to the
- * host; with BSC_GRAPHS=1 in the environment at bsc_create a burst is one graph launch). */
+ * the CG launches of each burst of chunks (not under BSC_TIMING_OFF; with BSC_GRAPHS=1 in the
+ * environment at bsc_create a burst is one graph launch, which ends with the kernel that
+ * publishes the solver state to the host). */
 typedef struct {
     int32_t newton_iters, pcg_iters_total, ls_halvings, warm_start_used, warm_start_fallbacks;
     double g0_norm, g_norm, energy;

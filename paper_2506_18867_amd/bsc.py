@@ -36,6 +36,9 @@ BSC_START_PREDICTOR = 1
 BSC_WARM_NONE = 0
 BSC_WARM_NET = 1
 BSC_WARM_PREVIOUS = 2
+BSC_TIMING_CG = 0
+BSC_TIMING_PHASES = 1
+BSC_TIMING_OFF = 2
 BSC_HESS_ENTRIES = 114
 BSC_NET_PARAMS = 38592
 BSC_NET_NOALLOC_SCRATCH_BYTES = 32 << 20   # static scratch of bsc_net_backward_noalloc, per GPU
@@ -65,7 +68,7 @@ class StepOpts(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("max_pcg", ctypes.c_int32), ("pcg_rtol", ctypes.c_double),
                 ("warm_start", ctypes.c_int32), ("fixed_newton_iters", ctypes.c_int32),
                 ("pcg_adaptive", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("start", ctypes.c_int32),
-                ("pcg_eta_max", ctypes.c_double)]
+                ("pcg_eta_max", ctypes.c_double), ("timing", ctypes.c_int32)]
 
 
 class PfOpts(ctypes.Structure):
@@ -206,9 +209,10 @@ def make_material(membrane=0, young=0.0, poisson=0.0, thickness=0.0, mu_st1=0.0,
 
 def make_opts(dt=0.01, gravity=(0.0, 0.0, -9.81), precision=BSC_FP64, stop_mode=BSC_STOP_GRAD, rtol=1e-6,
               atol=1e-2, max_newton=50, max_pcg=2000, pcg_rtol=1e-4, warm_start=0, fixed_newton_iters=0,
-              pcg_adaptive=0, preconditioner=0, start=0, pcg_eta_max=0.0) -> StepOpts:
+              pcg_adaptive=0, preconditioner=0, start=0, pcg_eta_max=0.0, timing=BSC_TIMING_CG) -> StepOpts:
     return StepOpts(dt, (ctypes.c_double * 3)(*gravity), precision, stop_mode, rtol, atol, max_newton, max_pcg,
-                    pcg_rtol, warm_start, fixed_newton_iters, pcg_adaptive, preconditioner, start, pcg_eta_max)
+                    pcg_rtol, warm_start, fixed_newton_iters, pcg_adaptive, preconditioner, start, pcg_eta_max,
+                    timing)
 
 
 @dataclass

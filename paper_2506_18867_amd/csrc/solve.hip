@@ -1210,9 +1210,13 @@ struct Timer {
     hipStream_t st;
     hipEvent_t a, b;
     bool ok;
-    explicit Timer(hipStream_t s) : st(s) {
-        ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    explicit Timer(hipStream_t s, bool on = true) : st(s), a(nullptr), b(nullptr), ok(false) {
+        if (!on) return;
+        if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) b = nullptr;
+        ok = a && b;
         if (ok) (void)hipEventRecord(a, st);
+        else (void)hipGetLastError();
     }
     double stop() {
         if (!ok) return 0.0;
@@ -1223,7 +1227,8 @@ struct Timer {
         return ms;
     }
     ~Timer() {
-        if (ok) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
 };
 
@@ -1286,14 +1291,17 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
     bsc_step_stats s{};
     double ls_in_bursts = 0.0;   // line-search kernels timed inside the PCG bursts (moved from ms_pcg)
     auto t_start = std::chrono::steady_clock::now();
-    // Phase timing: events from a pool, recorded as the step goes and read once at its end (a
-    // read in the middle of the step would wait for the event and delay the next launch).
+    // Timing: events from a pool, recorded as the step goes and read once at its end (a read in
+    // the middle of the step would wait for the event and delay the next launch). Each event sits
+    // between two kernels and delays the second by a few microseconds (without the system-scope
+    // fence, which a timestamp read after the stream's synchronisation does not need, by less), so
+    // rec_cg() (the CG spans) records unless timing is off and rec() (the phases) only on request.
     size_t ev_used = 0;
-    auto rec = [&]() -> hipEvent_t {
-        if (ctx->ev_failed) return nullptr;
+    auto rec_any = [&](bool on) -> hipEvent_t {
+        if (!on || ctx->ev_failed) return nullptr;
         if (ev_used == ctx->ev_pool.size()) {
             hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) {
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
                 (void)hipGetLastError();
                 ctx->ev_failed = true;
                 return nullptr;
@@ -1307,6 +1315,9 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         }
         return e;
     };
+    const bool time_phases = o->timing == BSC_TIMING_PHASES, time_cg = o->timing != BSC_TIMING_OFF;
+    auto rec = [&]() { return rec_any(time_phases); };
+    auto rec_cg = [&]() { return rec_any(time_cg); };
     struct Span {
         hipEvent_t a, b;
         double *acc;
@@ -1548,12 +1559,18 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             k_ls_finish<<<1, kBlock, 0, cs>>>(B.partials + 7 * stride, blocks(S.n_cp), pa, pbend, blocks(S.n_be), stride,
                                                B.partials, blocks(S.n_mp), B.scalars);
         };
-        auto launch_burst = [&](int K) -> hipError_t {
+        // cg_end: an event right behind the burst's CG launches (the line-search kernels follow it)
+        auto launch_burst = [&](int K, hipEvent_t *cg_end) -> hipError_t {
             hipGraphExec_t ge = graph_for(K);
-            if (ge) return hipGraphLaunch(ge, st);
+            if (ge) {
+                const hipError_t e = hipGraphLaunch(ge, st);
+                *cg_end = rec_cg();
+                return e;
+            }
             for (int bi = 0; bi < K; ++bi) enqueue_chunk(st);
+            *cg_end = rec_cg();
             if (ls_dev) {
-                hipEvent_t la = rec();
+                hipEvent_t la = time_phases ? *cg_end : nullptr;
                 const int nbc_ = blocks(S.n_cp), nbb_ = blocks(S.n_be), nbm_ = blocks(S.n_mp);
                 k_ls_setup<<<nbc_ + nbb_ + nbm_, kBlock, 0, st>>>(S, x, B.gpre, B.dir, inv_dt2, pa, stride,
                                                                   B.partials + 7 * stride, pbend, B.partials, nbc_, nbb_,
@@ -1563,7 +1580,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
                                                            o->fixed_newton_iters <= 0 ? kStagnation : 0.0, pubp, pub ? 1 : 0);
                 hipEvent_t lb = rec();
                 span(la, lb, &s.ms_linesearch);
-                span(la, lb, &ls_in_bursts);
+                span(la, lb, &ls_in_bursts);     // inside the span of ms_pcg
             } else if (pub) {
                 publish(st);
             }
@@ -1584,7 +1601,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // first burst follows at once (speculative): the set-up marks the solve done on the device
         // when |g| already meets the stop, so a converged iterate costs only the set-up and a
         // burst of launches that exit; x is not touched.
-        hipEvent_t e2 = nullptr, burst_c0 = nullptr;
+        hipEvent_t e2 = nullptr, burst_c0 = nullptr, burst_c1 = nullptr;
         bool burst_pending = false;
         int32_t burst_last = 0;
         if (early) {
@@ -1595,8 +1612,8 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             e2 = rec();
             HIPX(cg_setup(), "cg init");
             if (speculate) {
-                burst_c0 = rec();
-                HIPX(launch_burst(burst), "cg graph");
+                burst_c0 = rec_cg();
+                HIPX(launch_burst(burst, &burst_c1), "cg graph");
                 burst_last = last + 1;             // the burst publishes after the assembly's read-back
                 burst_pending = true;
             }
@@ -1667,15 +1684,15 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         double lrho_prev = 0.0;
         bool have_prev = false;
         while (true) {
-            hipEvent_t c0 = burst_c0;
+            hipEvent_t c0 = burst_c0, c1 = burst_c1;
             int32_t last = burst_last;
             if (!burst_pending) {
-                c0 = rec();
+                c0 = rec_cg();
                 last = seen();
-                HIPX(launch_burst(burst), "cg graph");
+                HIPX(launch_burst(burst, &c1), "cg graph");
             }
             burst_pending = false;
-            span(c0, rec(), &s.ms_cg_kernels);
+            span(c0, c1, &s.ms_cg_kernels);
             HIPX(pub ? wait_pub(last) : copy_sync(), "read cg state");
             for (int k = 0; k < 8; ++k) flags[k] = hf[k];
             const double *cgs = hs;
@@ -1758,7 +1775,7 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
 
         // ---- backtracking line search on the energy difference ------------------------------
         {
-            Timer t(st);
+            Timer t(st, time_phases);
             const double c1 = scal(S_C1), c2 = scal(S_C2);
             double dem = scal(S_DEM);
             double alpha = 1.0;
@@ -1793,7 +1810,6 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         else (void)hipGetLastError();
     }
     s.ms_pcg -= ls_in_bursts;
-    s.ms_cg_kernels -= ls_in_bursts;
     s.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (stats) *stats = s;
     return result;
@@ -1899,6 +1915,7 @@ bsc_status bsc_newton_step(bsc_ctx *c, const bsc_step_opts *o, double *d_x, doub
     if (!c->pins.empty() && !d_pin_targets) return fail(c, BSC_E_INVAL, "pins set but no targets");
     if (o->warm_start < BSC_WARM_NONE || o->warm_start > BSC_WARM_PREVIOUS) return fail(c, BSC_E_INVAL, "bad warm start");
     if (o->warm_start == BSC_WARM_NET && !c->net_loaded) return fail(c, BSC_E_STATE, "warm start requested but no network loaded");
+    if (o->timing < BSC_TIMING_CG || o->timing > BSC_TIMING_OFF) return fail(c, BSC_E_INVAL, "bad timing mode");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(o->gravity[k])) return fail(c, BSC_E_INVAL, "gravity must be finite");
     bsc_status st = newton_step(c, o, d_x, d_v, d_pin_targets, stats);
