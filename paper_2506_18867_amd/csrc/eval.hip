@@ -481,7 +481,11 @@ __device__ __forceinline__ double membrane_point(const DevSheet &S, const double
             }
         }
         T psi, P[3][2], A[6][6];
-        if (S.membrane == BSC_MEMBRANE_STVK) stvk<T>(G, T(S.mu), T(S.lam), psi, P, A, HESS);
+        // StVK: the projected density Hessian comes in closed form from the structured projection
+        // (exact for definite and indefinite points alike), so the full 6x6 and its Cholesky test
+        // are only formed for a degenerate F (parallel columns), where that projection declines
+        const bool direct = HESS && S.membrane == BSC_MEMBRANE_STVK;
+        if (S.membrane == BSC_MEMBRANE_STVK) stvk<T>(G, T(S.mu), T(S.lam), psi, P, A, HESS && !direct);
         else fbw<T>(G, T(S.mu1), T(S.mu2), T(S.msh), psi, P, A, HESS);
         e_loc = w * double(psi);
         ptE[q] = e_loc;
@@ -490,16 +494,19 @@ __device__ __forceinline__ double membrane_point(const DevSheet &S, const double
 #pragma unroll
             for (int i = 0; i < 3; ++i) ptP[(2 * i + g) * S.n_mp + q] = TP(w * double(P[i][g]));
         if (HESS) {
-            double Ad[6][6];
+            double Ad[6][6], Gd[3][2];
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 3; ++c) { Gd[c][0] = double(G[c][0]); Gd[c][1] = double(G[c][1]); }
+            if (!direct || !project_structured(S, Gd, Ad)) {
+                if (direct) {
+                    T psi2, P2[3][2];
+                    stvk<T>(G, T(S.mu), T(S.lam), psi2, P2, A, true);
+                }
 #pragma unroll
-                for (int c = 0; c < 6; ++c) Ad[r][c] = 0.5 * (double(A[r][c]) + double(A[c][r]));
-            if (!cholesky_pd(Ad)) {
-                double Gd[3][2];
+                for (int r = 0; r < 6; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) { Gd[c][0] = double(G[c][0]); Gd[c][1] = double(G[c][1]); }
-                if (!project_structured(S, Gd, Ad)) project_psd(Ad);
+                    for (int c = 0; c < 6; ++c) Ad[r][c] = 0.5 * (double(A[r][c]) + double(A[c][r]));
+                if (!cholesky_pd(Ad) && (direct || !project_structured(S, Gd, Ad))) project_psd(Ad);
             }
 #pragma unroll
             for (int r = 0; r < 6; ++r)
