@@ -616,6 +616,11 @@ __device__ __forceinline__ double cp_terms(const DevSheet &S, const double *__re
     return e_loc;
 }
 
+// Minimum waves per SIMD of the points pass: the FP32 instantiation (FP32 arithmetic and records)
+// runs faster with its registers capped for three waves; the FP64 ones keep all their registers.
+template <typename T, typename TP>
+constexpr int kPointsWaves = (sizeof(T) == 4 && sizeof(TP) == 4) ? 3 : 1;
+
 // The per-CP terms, the membrane points and the bending evaluations in one launch: blocks
 // [0, ncb) take CPs (ncb = 0 without them), the next nbm membrane points, the rest bending
 // evaluations; each block writes the sum of its energies to its own partial slot (CPs:
@@ -624,7 +629,8 @@ __device__ __forceinline__ double cp_terms(const DevSheet &S, const double *__re
 // and CP blocks fill the slots that the register-heavy membrane blocks leave free; the CP
 // blocks, bound by the latency of their neighbour loads, come first so that it overlaps the rest.
 template <typename T, bool HESS, bool CURVED, typename TA = T, typename TP = T, bool BEND = true>
-__global__ void __launch_bounds__(kBlock) k_points(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kPointsWaves<T, TP>)))
+k_points(DevSheet S, const double *__restrict__ x, TA *__restrict__ ptA,
                                                    TP *__restrict__ ptP, double *__restrict__ ptE,
                                                    double *__restrict__ pm, double *__restrict__ beD,
                                                    double *__restrict__ beE, double *__restrict__ pb, int ncb, int nbm,
