@@ -301,19 +301,20 @@ __device__ void project_psd4(double A[4][4]) {
         }
 }
 
-// Symmetric 2x2 [[a, b], [b, c]] projected to PSD in closed form.
-__device__ void project_psd2(double &a, double &b, double &c) {
-    const double h = 0.5 * (a - c), m = 0.5 * (a + c);
-    const double r = sqrt(h * h + b * b);
-    const double l1 = m + r, l2 = m - r;          // l1 >= l2
-    if (l2 >= 0.0) return;
-    if (l1 <= 0.0) { a = b = c = 0.0; return; }
+// Symmetric 2x2 [[a, b], [b, c]] projected to PSD in closed form (R: the arithmetic).
+template <typename R>
+__device__ void project_psd2(R &a, R &b, R &c) {
+    const R h = R(0.5) * (a - c), m = R(0.5) * (a + c);
+    const R r = sqrt(h * h + b * b);
+    const R l1 = m + r, l2 = m - r;               // l1 >= l2
+    if (l2 >= R(0)) return;
+    if (l1 <= R(0)) { a = b = c = R(0); return; }
     // keep l1 v v^T, v the unit eigenvector of l1
-    double vx, vy;
-    if (h >= 0.0) { vx = h + r; vy = b; } else { vx = b; vy = r - h; }
-    const double nn = vx * vx + vy * vy;
-    if (nn == 0.0) { a = fmax(a, 0.0); c = fmax(c, 0.0); b = 0.0; return; }
-    const double k = l1 / nn;
+    R vx, vy;
+    if (h >= R(0)) { vx = h + r; vy = b; } else { vx = b; vy = r - h; }
+    const R nn = vx * vx + vy * vy;
+    if (nn == R(0)) { a = fmax(a, R(0)); c = fmax(c, R(0)); b = R(0); return; }
+    const R k = l1 / nn;
     a = k * vx * vx; b = k * vx * vy; c = k * vy * vy;
 }
 
@@ -326,25 +327,26 @@ __device__ void project_psd2(double &a, double &b, double &c) {
 // (psi_1 - psi_2)/(s1 - s2) (Smith, de Goes and Kim 2019, analytic eigensystems of isotropic
 // energies). For StVK, psi = mu/4 sum (s_i^2 - 1)^2 + lam/8 (s1^2 + s2^2 - 2)^2, both
 // quotients are polynomials, so equal singular values need no special case.
-__device__ void stvk_inplane_projected(double a, double b, double d, double mu, double lam, double P[4][4]) {
-    const double p = a * a, q = a * b, r = b * b + d * d;          // C = F^T F
-    const double h = 0.5 * (p - r), m = 0.5 * (p + r), rad = sqrt(h * h + q * q);
-    const double s1 = sqrt(m + rad), s2 = a * d / s1;
-    double vx, vy;                                                  // eigenvector of C for s1^2
-    if (h >= 0.0) { vx = h + rad; vy = q; } else { vx = q; vy = rad - h; }
-    const double nn = sqrt(vx * vx + vy * vy);
-    if (nn > 0.0) { vx /= nn; vy /= nn; } else { vx = 1.0; vy = 0.0; }
-    const double v1[2] = {vx, vy}, v2[2] = {-vy, vx};
-    const double u1[2] = {(a * vx + b * vy) / s1, (d * vy) / s1}, u2[2] = {-u1[1], u1[0]};
-    const double I = s1 * s1 + s2 * s2;
-    double b11 = mu * (3.0 * s1 * s1 - 1.0) + 0.5 * lam * (I - 2.0) + lam * s1 * s1;
-    double b22 = mu * (3.0 * s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0) + lam * s2 * s2;
-    double b12 = lam * s1 * s2;
-    project_psd2(b11, b12, b22);
-    const double lt = fmax(mu * (s1 * s1 - s1 * s2 + s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0), 0.0);
-    const double ll = fmax(mu * (s1 * s1 + s1 * s2 + s2 * s2 - 1.0) + 0.5 * lam * (I - 2.0), 0.0);
-    double D1[4], D2[4], T[4], L[4];                                // vec index 2 gamma + i
-    const double k = 0.70710678118654752440;
+template <typename R>
+__device__ void stvk_inplane_projected(R a, R b, R d, R mu, R lam, R P[4][4]) {
+    const R p = a * a, q = a * b, r = b * b + d * d;                // C = F^T F
+    const R h = R(0.5) * (p - r), m = R(0.5) * (p + r), rad = sqrt(h * h + q * q);
+    const R s1 = sqrt(m + rad), s2 = a * d / s1;
+    R vx, vy;                                                       // eigenvector of C for s1^2
+    if (h >= R(0)) { vx = h + rad; vy = q; } else { vx = q; vy = rad - h; }
+    const R nn = sqrt(vx * vx + vy * vy);
+    if (nn > R(0)) { vx /= nn; vy /= nn; } else { vx = R(1); vy = R(0); }
+    const R v1[2] = {vx, vy}, v2[2] = {-vy, vx};
+    const R u1[2] = {(a * vx + b * vy) / s1, (d * vy) / s1}, u2[2] = {-u1[1], u1[0]};
+    const R I = s1 * s1 + s2 * s2;
+    R b11 = mu * (R(3) * s1 * s1 - R(1)) + R(0.5) * lam * (I - R(2)) + lam * s1 * s1;
+    R b22 = mu * (R(3) * s2 * s2 - R(1)) + R(0.5) * lam * (I - R(2)) + lam * s2 * s2;
+    R b12 = lam * s1 * s2;
+    project_psd2<R>(b11, b12, b22);
+    const R lt = fmax(mu * (s1 * s1 - s1 * s2 + s2 * s2 - R(1)) + R(0.5) * lam * (I - R(2)), R(0));
+    const R ll = fmax(mu * (s1 * s1 + s1 * s2 + s2 * s2 - R(1)) + R(0.5) * lam * (I - R(2)), R(0));
+    R D1[4], D2[4], T[4], L[4];                                     // vec index 2 gamma + i
+    const R k = R(0.70710678118654752440);
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
@@ -363,43 +365,48 @@ __device__ void stvk_inplane_projected(double a, double b, double d, double mu, 
 }
 
 // Builds the projected 6x6 density Hessian of the membrane model at displacement gradient G
-// (double) into A. Returns false when f1 and f2 are (nearly) parallel.
-__device__ bool project_structured(const DevSheet &S, const double G[3][2], double A[6][6]) {
-    double f[2][3];
+// into A, in the arithmetic R. Returns false when f1 and f2 are (nearly) parallel: within a
+// relative 1e-8 in FP64; in FP32 (StVK only, whose Hessian is then stored in FP32) within 1e-3,
+// where the frame would carry too much rounding.
+template <typename R>
+__device__ bool project_structured(const DevSheet &S, const R G[3][2], R A[6][6]) {
+    R f[2][3];
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) f[g][i] = G[i][g] + ((i == g) ? 1.0 : 0.0);
-    const double l1 = sqrt(f[0][0] * f[0][0] + f[0][1] * f[0][1] + f[0][2] * f[0][2]);
-    double n[3] = {f[0][1] * f[1][2] - f[0][2] * f[1][1], f[0][2] * f[1][0] - f[0][0] * f[1][2], f[0][0] * f[1][1] - f[0][1] * f[1][0]};
-    const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    const double l2 = sqrt(f[1][0] * f[1][0] + f[1][1] * f[1][1] + f[1][2] * f[1][2]);
-    if (!(l1 > 0.0) || !(ln > 1e-8 * l1 * l2)) return false;
-    double e[3][3];                                 // e[0] = e1, e[1] = e2, e[2] = e3
+        for (int i = 0; i < 3; ++i) f[g][i] = G[i][g] + ((i == g) ? R(1) : R(0));
+    const R l1 = sqrt(f[0][0] * f[0][0] + f[0][1] * f[0][1] + f[0][2] * f[0][2]);
+    R n[3] = {f[0][1] * f[1][2] - f[0][2] * f[1][1], f[0][2] * f[1][0] - f[0][0] * f[1][2], f[0][0] * f[1][1] - f[0][1] * f[1][0]};
+    const R ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const R l2 = sqrt(f[1][0] * f[1][0] + f[1][1] * f[1][1] + f[1][2] * f[1][2]);
+    const R par = sizeof(R) == 8 ? R(1e-8) : R(1e-3);
+    if (!(l1 > R(0)) || !(ln > par * l1 * l2)) return false;
+    R e[3][3];                                      // e[0] = e1, e[1] = e2, e[2] = e3
 #pragma unroll
     for (int i = 0; i < 3; ++i) { e[0][i] = f[0][i] / l1; e[2][i] = n[i] / ln; }
     e[1][0] = e[2][1] * e[0][2] - e[2][2] * e[0][1];
     e[1][1] = e[2][2] * e[0][0] - e[2][0] * e[0][2];
     e[1][2] = e[2][0] * e[0][1] - e[2][1] * e[0][0];
     // in-plane components: F2[i][g] = f_g . e_i (i, g in {0,1}); f1 . e2 = 0
-    double F2[2][2];
-    F2[0][0] = l1; F2[1][0] = 0.0;
+    R F2[2][2];
+    F2[0][0] = l1; F2[1][0] = R(0);
     F2[0][1] = f[1][0] * e[0][0] + f[1][1] * e[0][1] + f[1][2] * e[0][2];
     F2[1][1] = ln / l1;
-    double P4[4][4], Na, Nb, Nc;                    // P4 index 2*gamma + i
+    R P4[4][4], Na, Nb, Nc;                         // P4 index 2*gamma + i
     if (S.membrane == BSC_MEMBRANE_STVK) {
-        double E[2][2];
+        const R mu = R(S.mu), lam = R(S.lam);
+        R E[2][2];
 #pragma unroll
         for (int g = 0; g < 2; ++g)
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                E[g][d] = 0.5 * (G[g][d] + G[d][g] + G[0][g] * G[0][d] + G[1][g] * G[1][d] + G[2][g] * G[2][d]);
-        const double tr = E[0][0] + E[1][1];
-        Na = 2.0 * S.mu * E[0][0] + S.lam * tr;     // normal block: the second Piola-Kirchhoff stress
-        Nb = 2.0 * S.mu * E[0][1];
-        Nc = 2.0 * S.mu * E[1][1] + S.lam * tr;
-        stvk_inplane_projected(F2[0][0], F2[0][1], F2[1][1], S.mu, S.lam, P4);
-    } else {
+                E[g][d] = R(0.5) * (G[g][d] + G[d][g] + G[0][g] * G[0][d] + G[1][g] * G[1][d] + G[2][g] * G[2][d]);
+        const R tr = E[0][0] + E[1][1];
+        Na = R(2) * mu * E[0][0] + lam * tr;        // normal block: the second Piola-Kirchhoff stress
+        Nb = R(2) * mu * E[0][1];
+        Nc = R(2) * mu * E[1][1] + lam * tr;
+        stvk_inplane_projected<R>(F2[0][0], F2[0][1], F2[1][1], mu, lam, P4);
+    } else if constexpr (sizeof(R) == 8) {
         const double mus[2] = {S.mu1, S.mu2};
         double len[2], q[2];
 #pragma unroll
@@ -427,10 +434,12 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
                         P4[2 * g + i][2 * d + j] = a;
                     }
         Na = 2.0 * mus[0] * q[0]; Nb = 2.0 * S.msh * I6; Nc = 2.0 * mus[1] * q[1];
+        project_psd4(P4);
+    } else {
+        return false;                               // FBW is projected in FP64 only
     }
-    if (S.membrane != BSC_MEMBRANE_STVK) project_psd4(P4);
-    project_psd2(Na, Nb, Nc);
-    const double N2[2][2] = {{Na, Nb}, {Nb, Nc}};
+    project_psd2<R>(Na, Nb, Nc);
+    const R N2[2][2] = {{Na, Nb}, {Nb, Nc}};
     // rotate back: A[(g,i),(d,j)] = sum_{a,b<2} e_a[i] P4[(g,a),(d,b)] e_b[j] + N[g][d] e3[i] e3[j]
 #pragma unroll
     for (int g = 0; g < 2; ++g)
@@ -440,7 +449,7 @@ __device__ bool project_structured(const DevSheet &S, const double G[3][2], doub
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    double v = N2[g][d] * e[2][i] * e[2][j];
+                    R v = N2[g][d] * e[2][i] * e[2][j];
 #pragma unroll
                     for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
@@ -497,7 +506,23 @@ __device__ __forceinline__ double membrane_point(const DevSheet &S, const double
             double Ad[6][6], Gd[3][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c) { Gd[c][0] = double(G[c][0]); Gd[c][1] = double(G[c][1]); }
-            if (!direct || !project_structured(S, Gd, Ad)) {
+            if constexpr (sizeof(TA) == 4) {
+                // stored in FP32: the StVK projection in FP32 arithmetic; a (nearly) degenerate F
+                // takes the FP64 path below
+                if (direct) {
+                    float Gf[3][2], Af[6][6];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { Gf[c][0] = float(G[c][0]); Gf[c][1] = float(G[c][1]); }
+                    if (project_structured<float>(S, Gf, Af)) {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r)
+#pragma unroll
+                            for (int c = r; c < 6; ++c) ptA[u6(r, c) * S.n_mp + q] = TA(w * double(Af[r][c]));
+                        return e_loc;
+                    }
+                }
+            }
+            if (!direct || !project_structured<double>(S, Gd, Ad)) {
                 if (direct) {
                     T psi2, P2[3][2];
                     stvk<T>(G, T(S.mu), T(S.lam), psi2, P2, A, true);
@@ -506,7 +531,7 @@ __device__ __forceinline__ double membrane_point(const DevSheet &S, const double
                 for (int r = 0; r < 6; ++r)
 #pragma unroll
                     for (int c = 0; c < 6; ++c) Ad[r][c] = 0.5 * (double(A[r][c]) + double(A[c][r]));
-                if (!cholesky_pd(Ad) && (direct || !project_structured(S, Gd, Ad))) project_psd(Ad);
+                if (!cholesky_pd(Ad) && (direct || !project_structured<double>(S, Gd, Ad))) project_psd(Ad);
             }
 #pragma unroll
             for (int r = 0; r < 6; ++r)
