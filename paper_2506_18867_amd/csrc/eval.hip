@@ -365,9 +365,10 @@ __device__ void stvk_inplane_projected(R a, R b, R d, R mu, R lam, R P[4][4]) {
 }
 
 // Builds the projected 6x6 density Hessian of the membrane model at displacement gradient G
-// into A, in the arithmetic R. Returns false when f1 and f2 are (nearly) parallel: within a
-// relative 1e-8 in FP64; in FP32 (StVK only, whose Hessian is then stored in FP32) within 1e-3,
-// where the frame would carry too much rounding.
+// into A, in the arithmetic R. The rounding of n = f1 x f2 tilts the frame by about 2 eps / r,
+// r = |f1 x f2| / (|f1| |f2|), so the projection declines (returns false) below r = 1e-5 in FP64
+// (tilt <= 4e-11) and r = 0.1 in FP32 (StVK only, whose Hessian is then stored in FP32; tilt
+// <= 2.4e-6); the caller then projects the full 6x6 matrix.
 template <typename R>
 __device__ bool project_structured(const DevSheet &S, const R G[3][2], R A[6][6]) {
     R f[2][3];
@@ -379,7 +380,7 @@ __device__ bool project_structured(const DevSheet &S, const R G[3][2], R A[6][6]
     R n[3] = {f[0][1] * f[1][2] - f[0][2] * f[1][1], f[0][2] * f[1][0] - f[0][0] * f[1][2], f[0][0] * f[1][1] - f[0][1] * f[1][0]};
     const R ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     const R l2 = sqrt(f[1][0] * f[1][0] + f[1][1] * f[1][1] + f[1][2] * f[1][2]);
-    const R par = sizeof(R) == 8 ? R(1e-8) : R(1e-3);
+    const R par = sizeof(R) == 8 ? R(1e-5) : R(0.1);
     if (!(l1 > R(0)) || !(ln > par * l1 * l2)) return false;
     R e[3][3];                                      // e[0] = e1, e[1] = e2, e[2] = e3
 #pragma unroll
@@ -507,8 +508,8 @@ __device__ __forceinline__ double membrane_point(const DevSheet &S, const double
 #pragma unroll
             for (int c = 0; c < 3; ++c) { Gd[c][0] = double(G[c][0]); Gd[c][1] = double(G[c][1]); }
             if constexpr (sizeof(TA) == 4) {
-                // stored in FP32: the StVK projection in FP32 arithmetic; a (nearly) degenerate F
-                // takes the FP64 path below
+                // stored in FP32: the StVK projection in FP32 arithmetic; columns of F within
+                // r = 0.1 of parallel take the FP64 path below
                 if (direct) {
                     float Gf[3][2], Af[6][6];
 #pragma unroll

@@ -189,6 +189,34 @@ def test_fp32_gradient_and_hessian_within_bounds(kind, n):
     assert relerr(E.item(), rE) < 1e-5
 
 
+@pytest.mark.parametrize("delta", [0.15, 0.05, 1e-6])
+def test_nearly_parallel_columns_match_oracle(delta):
+    """Every element sheared and flattened to F = [[1, 1/2], [0, delta], [0, 0]], so that
+    r = |f1 x f2| / (|f1| |f2|) is about 1.9 delta: at 0.15 the FP32 structured projection takes
+    the points, at 0.05 it declines (r < 0.1) and the FP64 one does, at 1e-6 that declines too
+    (r < 1e-5) and the full 6x6 matrix is projected. FP64 at the FP64 bar, FP32-mixed at its own."""
+    sc = syn.hanging_sheet(12, seed=3)
+    sh = oracle_sheet(sc)
+    X = np.asarray(sc.rest, dtype=np.float64).reshape(-1, 2)     # CP rest positions: F is exact
+    x = np.stack([X[:, 0] + 0.5 * X[:, 1], delta * X[:, 1], np.zeros(X.shape[0])], axis=1)
+    mask = np.zeros(sc.n_cp, dtype=bool)
+    mask[sc.pins] = True
+    rE, rg, rH = oracle.assemble(sh, x, sc.x0, sc.dt, sc.gravity, mask)
+    rHu = oracle_stencil_to_upper(rH, sc.n_u, sc.n_v)
+    ctx = _ctx(sc)
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(sc.x0), sc.dt, tuple(sc.gravity), bsc.BSC_FP64)
+    torch.cuda.synchronize()
+    print(f"[parallel columns] delta={delta:g}", flush=True)
+    assert relerr(E.item(), rE) < TOL64
+    check64(bsc.to_aos(g), rg, 0, "gradient")
+    check64(H, rHu, 1, "Hessian")
+    E, g, H = ctx.bsc_assemble(bsc.to_soa(x), bsc.to_soa(sc.x0), sc.dt, tuple(sc.gravity), bsc.BSC_FP32_MIXED)
+    eg, eh = relerr(bsc.to_aos(g), rg), relerr(H.cpu().numpy(), rHu)
+    print(f"  fp32: grad rel err {eg:.2e}, hessian rel err {eh:.2e}")
+    assert eg < 1e-4
+    assert eh < 1e-5
+
+
 def test_compressed_100_sheet_matches_oracle():
     """The 100 x 100 CP sheet with 10% in-plane compression and +-2 mm z-noise, both side
     columns held (the workload of the FP64 against FP32 comparison): FP64 assembly within 1e-10
