@@ -170,3 +170,32 @@ def test_binding_refuses_mistyped_or_short_buffers():
     with pytest.raises(bsc.BscError) as e:
         bsc._need(None, torch.float64, 6, "x")
     assert e.value.status == bsc.BSC_E_INVAL
+
+
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """Every struct the binding passes by pointer has the C header's size and field offsets:
+    a small C program built against include/bsc.h prints them (gcc, host only)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = {"bsc_material": bsc.Material, "bsc_step_opts": bsc.StepOpts, "bsc_step_stats": bsc.StepStats,
+               "bsc_pf_opts": bsc.PfOpts, "bsc_pf_stats": bsc.PfStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bsc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
