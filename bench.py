@@ -15,6 +15,10 @@ result.
 value = elements advanced per second (n_elem * steps / timed seconds of the FP32-mixed steps) in
 Melem/s; ms_per_step is the mean FP32-mixed step time (each step bracketed by device syncs).
 
+The timed steps record HIP events only around the PCG launches (the roofline's kernel time);
+phases_ms_per_step_fp32 comes from 5 more steps from the headline's start state with every phase
+timed (about 14 events per Newton iteration, each a gap between two kernels).
+
 Further legs (each a field of the one JSON line):
   step_rule         the same steps under the paper's stopping rule |p|_inf / dt <= 1e-2 m/s;
   fp32_vs_fp64_100  the 100 x 100 compressed drape, 200 steps, FP32-mixed and FP64 from the
@@ -30,8 +34,8 @@ Further legs (each a field of the one JSON line):
                     intensities: the Gershgorin trigger, the series and the merged solve;
   quadrature_ablation, general_rest, contact_conversion, wrinkling_convergence.
 The roofline object covers the kernel with the largest share of the step (the fused PCG-iteration
-kernel), timed live by the library with HIP events around its bursts of launches on its stream (the
-torch current stream). cpu_baseline is the oracle's eval+assembly on the same 226 x 226 sheet.
+kernel), timed live by the library with HIP events before the first and after the last CG launch of
+each burst on its stream (the torch current stream). cpu_baseline is the oracle's eval+assembly on the same 226 x 226 sheet.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 226] [--no-cpu]
 """
