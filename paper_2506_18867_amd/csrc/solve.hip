@@ -1403,10 +1403,13 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
         // than replayed as captured graphs, whose switches with plain launches on the stream each
         // cost a gap)
         const int32_t last_asm = seen();
+        // Under the gradient stop the first burst follows the set-up at once (speculative, below)
+        // and its read-back carries E and |g| too, so the set-up publishes nothing of its own.
+        const bool speculate = early && o->stop_mode == BSC_STOP_GRAD && o->fixed_newton_iters <= 0 && it < o->max_newton;
         EnergyRed red{};                 // early: E and |g|^2 summed (and published) by the PCG set-up's first kernel
         {
-            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st, early && pub ? &pubp : nullptr,
-                                                early ? &red : nullptr);
+            const bsc_status sa = assemble_iter(ctx, prec, x, B.xhat, inv_dt2, grav, st,
+                                                early && pub && !speculate ? &pubp : nullptr, early ? &red : nullptr);
             if (sa != BSC_OK) return sa;
         }
         hipEvent_t e1 = rec();
@@ -1597,24 +1600,24 @@ bsc_status newton_step(bsc_ctx *ctx, const bsc_step_opts *o, double *x, double *
             burst = std::max(1, std::min(8, (ctx->pcg_hist[it] + 4 + chunk) / chunk));
         // Gradient rule (no multigrid): the set-up is enqueued right behind
         // the assembly with the forcing term formed on the device (the same formula as the
-        // host's), and the host reads E and |g| while the GPU runs it. Under the gradient stop the
-        // first burst follows at once (speculative): the set-up marks the solve done on the device
-        // when |g| already meets the stop, so a converged iterate costs only the set-up and a
-        // burst of launches that exit; x is not touched.
+        // host's). Under the gradient stop the first burst follows at once (speculative): the
+        // set-up marks the solve done on the device when |g| already meets the stop, so a
+        // converged iterate costs only the set-up and a burst of launches that exit (x is not
+        // touched), and the host reads E and |g| with the burst's read-back. Otherwise the set-up
+        // publishes them and the host reads them while the GPU runs it.
         hipEvent_t e2 = nullptr, burst_c0 = nullptr, burst_c1 = nullptr;
         bool burst_pending = false;
         int32_t burst_last = 0;
         if (early) {
             eta_mode = o->pcg_adaptive ? ETA_ADAPTIVE : ETA_FIXED;
-            const bool speculate = o->stop_mode == BSC_STOP_GRAD && o->fixed_newton_iters <= 0 && it < o->max_newton;
             grad_rtol = speculate ? o->rtol : 0.0;
-            const int32_t last = last_asm;           // the set-up.s first kernel publishes E and |g|
+            const int32_t last = last_asm;           // E and |g| come with the next read-back
             e2 = rec();
             HIPX(cg_setup(), "cg init");
             if (speculate) {
                 burst_c0 = rec_cg();
                 HIPX(launch_burst(burst, &burst_c1), "cg graph");
-                burst_last = last + 1;             // the burst publishes after the assembly's read-back
+                burst_last = last;                 // the burst's read-back is the first after the assembly
                 burst_pending = true;
             }
             HIPX(pub ? wait_pub(last) : copy_sync(), "read norms");
